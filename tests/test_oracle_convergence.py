@@ -1,0 +1,43 @@
+"""Discretisation pins: V-norm convergence of order p - 1 (Theorem 2 and the remark after it).
+
+For smooth solutions with p_t = p_s = p and h_t = h_s = h the error in
+||v||_V^2 = ||v||^2 + ||S v||^2 decays like h^{p-1}.  The potential case
+(S_V = S + V) has no statement in the paper; it is checked against the same
+rate ("parity unpinned" by the paper; pinned here by the rate only).
+"""
+import numpy as np
+import pytest
+
+from oracle.operators import FastDiagonalization, Problem
+from oracle.pcg import pcg
+from oracle.rhs import SpaceTimeBasis, assemble_rhs, errors, full_coefficients
+from paper_2311_18461_amd.inputs import GaussianSum, SineMode1D, uniform_open_knots
+
+
+def _solve(p, n, nu, V=None, T=1.0):
+    m = SineMode1D(nu)
+    f = m.f if V is None else (lambda t, x: m.f(t, x) + V(x) * m.u(t, x))
+    kt, ks = uniform_open_knots(n, p, T), [uniform_open_knots(n, p)]
+    pr = Problem(kt, ks, p, p, nu, V)
+    stb = SpaceTimeBasis(kt, ks, p, p)
+    fb, G = assemble_rhs(stb, nu, f=f, u0=m.u0, V=V)
+    x, info = pcg(pr.matvec, FastDiagonalization(pr).apply, fb, tol=1e-12, maxit=300)
+    assert info["converged"]
+    C = full_coefficients(G, x, pr.n_s, pr.n_t)
+    return errors(kt, ks, p, p, C, nu, m.u, f, V)
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+@pytest.mark.parametrize("with_V", [False, True])
+def test_v_norm_rate(p, with_V):
+    V = GaussianSum(np.array([[0.4]]), np.array([0.15]), np.array([30.0])) if with_V else None
+    ns = [8, 16, 32]
+    ev = [_solve(p, n, 1.0, V)[1] for n in ns]
+    rates = np.log2(np.array(ev[:-1]) / np.array(ev[1:]))
+    assert rates[-1] > (p - 1) - 0.2, rates
+
+
+def test_config1_sine_solution_accuracy():
+    """1D, p = 2, 16 x 16 elements, u = sin(pi x) exp(-i pi^2 t), tol 1e-10."""
+    l2, vn = _solve(2, 16, 1.0)
+    assert l2 < 1e-2 and vn < 1.0
