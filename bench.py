@@ -1,0 +1,203 @@
+"""Benchmark: FD-preconditioned space-time PCG on one MI355X.
+
+One step = one complete preconditioned CG solve of A u = f to a relative
+residual of 1e-8 from a zero initial guess (matvec, FD preconditioner apply
+and PCG updates every iteration), inputs already resident in HBM.
+Workload: 2D space (unit square) + time, p = 3, 64^3 elements
+(n_t = 66, n_s = 65 per direction, N = 278,850 free complex dofs), potential
+V = sum of 8 seeded Gaussians (the preconditioner keeps V = 0).
+
+Printed JSON line: value = N / (seconds per solve) / 1e6 [Mdof/s], plus the
+preconditioner-apply throughput per precision, the time to 1e-8 per
+preconditioner precision, the roofline of the dominant kernel (live HIP-event
+timing) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FD precond apply Mdof/s + PCG time to 1e-8: FP64 vs mixed/batched/warm-start"
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def build_workload(sample=0, n_el=64, p=3):
+    from paper_2311_18461_amd import inputs, stfd
+    w = inputs.gaussian_potential_2d_workload(sample, n_el=n_el, p=p)
+    kt, ks = w.knots_t(), [w.knots_s()] * 2
+    Vq = stfd.sample_on_quad_grid(w.potential, ks, p)
+    prob = stfd.Problem(kt, ks, p, p, w.T, w.nu, V_quad=Vq, max_nrhs=1)
+    return w, prob
+
+
+def time_events(fn, reps, stream):
+    import torch
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        fn()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / reps  # ms
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The oracle's PCG (FP64 NumPy/SciPy, all host cores) on the same workload and right-hand side."""
+    from threadpoolctl import threadpool_info
+    from oracle.operators import FastDiagonalization, Problem as OProblem
+    from oracle.pcg import pcg
+    from paper_2311_18461_amd import inputs
+    ks = [w.knots_s()] * 2
+    ref = OProblem(w.knots_t(), ks, w.p, w.p, w.nu, w.potential)
+    fd = FastDiagonalization(ref)
+    f = inputs.random_complex(ref.N, 2999)
+    times, iters = [], []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        _, info = pcg(ref.matvec, fd.apply, f, tol=1e-8, maxit=1000)
+        times.append(time.perf_counter() - t0)
+        iters.append(info["iters"])
+        if time.perf_counter() - t_start > budget_s * 0.5 or len(times) >= 5:
+            break
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    t = float(np.median(times))
+    return {"value": ref.N / t / 1e6, "unit": "Mdof/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(times)} complete FP64 PCG solves to 1e-8 of the same workload and right-hand side "
+                      f"(setup excluded), median {t:.3f} s, {iters[0]} iterations"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3: one solve, 20 applies and matvecs, and a device copy of "
+                         "known size (64 MiB read + 64 MiB written) to calibrate FETCH_SIZE / WRITE_SIZE")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2311_18461_amd import inputs, stfd
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w, prob = build_workload()
+    N = prob.N
+    f = torch.from_numpy(inputs.random_complex(N, 2999)).to(dev)
+    u = torch.empty_like(f)
+
+    def solve(prec=args.precision):
+        return prob.pcg_solve(f, u, rtol=1e-8, maxit=1000, precision=prec, stream=stream)
+
+    if args.profile:
+        solve()
+        rc, info = solve()
+        r = torch.from_numpy(inputs.random_complex(N, 2998)).to(dev)
+        s = torch.empty_like(r)
+        for _ in range(20):
+            prob.apply_preconditioner(r, s, stream=stream)
+        for _ in range(20):
+            prob.matvec(r, s, stream=stream)
+        src = torch.ones(8 << 20, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "iterations": info[0]["iters"], "copy_bytes": src.numel() * 8}))
+        return
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    iters = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, info = solve()
+        iters.append(info[0]["iters"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = N / (ms_per_step / 1e3) / 1e6
+
+    # time to 1e-8 per preconditioner precision (a few solves each)
+    pcg_ms, pcg_iters, pcg_true = {}, {}, {}
+    for prec in ("fp64", "fp32", "bf16"):
+        solve(prec)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            rc, info = solve(prec)
+        torch.cuda.synchronize()
+        pcg_ms[prec] = (time.perf_counter() - t1) / 5 * 1e3
+        pcg_iters[prec] = info[0]["iters"]
+        pcg_true[prec] = info[0]["true_rel_res"]
+
+    # apply and matvec throughput with HIP events on the launch stream
+    r = torch.from_numpy(inputs.random_complex(N, 2998)).to(dev)
+    s = torch.empty_like(r)
+    apply_ms = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        prob.apply_preconditioner(r, s, precision=prec, stream=stream)
+        apply_ms[prec] = time_events(lambda: prob.apply_preconditioner(r, s, precision=prec, stream=stream), 50,
+                                     stream)
+    prob.matvec(r, s, stream=stream)
+    matvec_ms = time_events(lambda: prob.matvec(r, s, stream=stream), 50, stream)
+
+    # dominant kernel: the system matvec (one launch per call); algorithmic FP64 work per dof:
+    # 3 real (2p+1)^d-point stencils on complex data + 3 complex-by-real (2p+1)-band time products
+    p, d = w.p, 2
+    flops_per_dof = 12 * ((2 * p + 1) ** d + 2 * p + 1)
+    achieved = flops_per_dof * N / (matvec_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "matvec_kernel<2,3>", "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": None, "avg_launch_us": round(matvec_ms * 1e3, 2),
+                "flops_per_dof": flops_per_dof}
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Mdof/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else f"f64+{args.precision}",
+        "data": "synthetic",
+        "config": {"workload": "2D space + time, p=3, 64^3 elements, 8-Gaussian potential (seed 2000), "
+                               "PCG to 1e-8 from x0=0",
+                   "n_dof_free": N, "n_t": prob.n_t, "n_s": prob.n_s, "rhs": "seeded CN(0,1) (seed 2999)",
+                   "preconditioner_precision": args.precision},
+        "iterations": int(np.median(iters)),
+        "pcg_ms_to_1e-8": {k: round(v, 4) for k, v in pcg_ms.items()},
+        "pcg_iterations": pcg_iters,
+        "pcg_true_rel_res": {k: float(f"{v:.3e}") for k, v in pcg_true.items()},
+        "fd_apply_mdofs": {k: round(N / (v * 1e-3) / 1e6, 1) for k, v in apply_ms.items()},
+        "fd_apply_us": {k: round(v * 1e3, 2) for k, v in apply_ms.items()},
+        "matvec_us": round(matvec_ms * 1e3, 2),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * stfd.h - C ABI of the MI355X space-time fast-diagonalisation solver for the
+ * linear Schrodinger equation  i u_t - nu Lap u + V u = f  on (0,T) x (0,1)^d,
+ * discretised by the least-squares space-time isogeometric method of
+ * Bressan, Kushova, Sangalli, Tani, "Space-time least squares approximation
+ * for Schrodinger equation and efficient solver" (arXiv 2311.18461).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Vectors.  A space-time coefficient vector is complex FP64, stored as
+ *   interleaved (re, im) doubles (the memory layout of std::complex<double>
+ *   and torch.complex128).  Entry (i_t, i_1, ..., i_d) of the coefficient
+ *   tensor sits at index i_t + n_t * (i_1 + n_1 * (i_2 + n_2 * i_3)): time is
+ *   the fastest index, as in the vec operator of Section 3.3 (eq.
+ *   kron_vec_multi) and the ordering "space (x) time" of eq. syst_mat.
+ *   With nrhs > 1 the vectors are stacked, right-hand side slowest.
+ * Degrees of freedom.  n_t = m_t - 1 (the first time function is removed,
+ *   u(0) = 0) and n_l = m_l - 2 (first and last spatial functions removed,
+ *   homogeneous Dirichlet), Section 3.2; N = n_t * n_1 * ... * n_d.
+ * Memory.  Pointers named *_dev are device (HIP) pointers owned by the caller;
+ *   the library never frees them.  Every other pointer is host memory.  All
+ *   device memory the library needs is allocated in stfd_setup and freed in
+ *   stfd_destroy; apply/matvec/pcg allocate nothing.
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ *   stream).  apply and matvec are asynchronous and stream-ordered; pcg
+ *   returns when the solve has finished because it fills host-side info.
+ *   One handle must not be used by two streams at the same time (it owns one
+ *   set of work buffers).
+ * Errors.  Every int-returning function returns a stfd_status; no exception
+ *   crosses the ABI.  On STFD_EHIP the HIP error code is available from
+ *   stfd_last_hip_error().
+ */
+#ifndef STFD_H
+#define STFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stfd_problem stfd_problem; /* opaque handle, immutable after setup */
+
+typedef enum {
+  STFD_OK = 0,
+  STFD_NOT_CONVERGED = 1, /* pcg hit maxit; u holds the last iterate */
+  STFD_EINVAL = -1,       /* invalid argument (see each function) */
+  STFD_ENOTSPD = -2,      /* a pencil or time block is not (Hermitian) positive definite */
+  STFD_EBREAKDOWN = -3,   /* pcg: non-finite value, <p,Ap> <= 0 or <r,z> <= 0 */
+  STFD_ENOMEM = -4,       /* host or device allocation failed */
+  STFD_EHIP = -5          /* HIP runtime error */
+} stfd_status;
+
+/* Arithmetic of the preconditioner's mode products and time solves.
+ * The matvec, residuals, inner products and PCG updates are always FP64. */
+typedef enum {
+  STFD_FP64 = 0, /* FP64 MFMA mode products, FP64 time solves */
+  STFD_FP32 = 1, /* FP32 MFMA mode products, FP32 intermediates and time solves */
+  STFD_BF16 = 2  /* BF16 MFMA mode products with FP32 accumulation, FP32 time solves */
+} stfd_precision;
+
+enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1 };
+
+/* Problem description (Sections 2, 3.1-3.2, 4.3).
+ * knots_t / knots_s[l]: open knot vectors on [0,1] (first and last p+1 knots
+ *   repeated, non-decreasing), length m + p + 1.  The time basis is
+ *   b_i(t) = b_hat_i(t / T).  Interior multiplicity must keep the time space
+ *   C^0 (<= p_t) and the spatial spaces C^1 (<= p_s - 1) (Assumption 2).
+ * p_t >= 1, p_s >= 2 (Assumption 2).  T > 0, nu > 0.
+ * V_quad: NULL (V = 0) or the potential sampled at the spatial tensor Gauss
+ *   grid returned by stfd_quad_points for each direction (n_quad points per
+ *   element), stored x_1 fastest: V_quad[q_1 + Q_1 (q_2 + Q_2 q_3)].  The
+ *   system operator uses S_V = i d_t - nu Lap + V; the preconditioner always
+ *   uses V = 0 (it is defined for the parametric domain, Section 5).
+ * n_quad: Gauss points per element and direction; 0 means p + 1.
+ * max_nrhs: largest nrhs any later call will pass (work buffers are sized now).
+ */
+typedef struct {
+  int d;
+  int p_t, p_s;
+  const double *knots_t;
+  int n_knots_t;
+  const double *knots_s[3];
+  int n_knots_s[3];
+  double T, nu;
+  const double *V_quad;
+  int n_quad;
+  int max_nrhs;
+} stfd_setup_desc;
+
+typedef struct {
+  int iters;           /* PCG iterations performed */
+  int status;          /* stfd_status of this right-hand side */
+  double rel_res;      /* ||r_k||_2 / ||f||_2 of the recursively updated residual */
+  double true_rel_res; /* ||f - A u||_2 / ||f||_2 recomputed with the FP64 matvec */
+} stfd_pcg_info;
+
+/* Element-wise Gauss-Legendre rule on the non-empty knot spans of an open
+ * knot vector scaled by `scale` (pass T for the time direction, 1 in space).
+ * Writes *n_out = n_el * n_quad points and weights (pts/wts may be NULL to
+ * query the size).  n_quad = 0 means degree + 1.  Returns STFD_EINVAL for an
+ * invalid knot vector. */
+int stfd_quad_points(const double *knots, int n_knots, int degree, int n_quad, double scale,
+                     double *pts, double *wts, int *n_out);
+
+/* Setup (Algorithm 1 step 1 and the assembly of eq. syst_mat):
+ *  - 1D B-spline Gram matrices in space and time (eqs. space_mat, time_mat),
+ *  - generalised eigendecompositions L_l U_l = M_l U_l Lambda_l,
+ *    U_l^T M_l U_l = I (eq. space_eig), lambda_i = sum_l lambda_{l,i_l},
+ *  - factors of the Hermitian banded blocks
+ *    H_i = L_t + nu^2 lambda_i^2 M_t + nu lambda_i (W_t + W_t^*) (Section 5.2),
+ *  - the spatial factors S_1 = M_s, S_2 = nu^2 B_s - nu (K_V + K_V^T) + M_{V^2},
+ *    S_3 = nu L_s + M_V of A = sum_k S_k (x) T_k, T = (L_t, M_t, W_t + W_t^*).
+ * Everything is computed in FP64 on the host and uploaded once.
+ * Errors: STFD_EINVAL (see stfd_setup_desc), STFD_ENOTSPD, STFD_ENOMEM, STFD_EHIP.
+ * On success *out owns all host and device data of the problem. */
+int stfd_setup(const stfd_setup_desc *desc, stfd_problem **out);
+
+/* Sizes: n_t, n_s[0..2] (unused directions = 1), N = n_t * prod n_s. */
+int stfd_sizes(const stfd_problem *P, int64_t *n_t, int64_t n_s[3], int64_t *n_dof);
+
+/* s = P-hat^{-1} r by fast diagonalisation (Algorithm 1 steps 2-4,
+ * eq. preconditioner_str2): mode products with U_l^T, N_s independent banded
+ * time solves with H_i, mode products with U_l.  r_dev, s_dev: nrhs stacked
+ * complex FP64 vectors (may alias).  precision: stfd_precision.
+ * Errors: STFD_EINVAL (nrhs < 1 or > max_nrhs, bad precision), STFD_EHIP. */
+int stfd_apply_preconditioner(const stfd_problem *P, const void *r_dev, void *s_dev, int64_t nrhs,
+                              int precision, void *stream);
+
+/* y = A x with A = sum_k S_k (x) T_k applied matrix-free (Section 5.3, eq.
+ * syst_mat with the potential terms): spatial tensor-banded stencils with
+ * (2p_s+1)^d coefficients per row, then the banded time factors.  FP64.
+ * x_dev and y_dev must not overlap.  Errors: STFD_EINVAL, STFD_EHIP. */
+int stfd_matvec(const stfd_problem *P, const void *x_dev, void *y_dev, int64_t nrhs, void *stream);
+
+/* Preconditioned CG for A u = f (Section 5.3: CG since A is Hermitian positive
+ * definite, P-hat applied by Algorithm 1).  Stops when
+ * ||f - A u_k||_2 <= rtol ||f||_2 (recursive residual) or after maxit
+ * iterations; beta uses the Polak-Ribiere form <r_k+1, z_k+1 - z_k>/<r_k, z_k>.
+ * flags: STFD_X0_ZERO (u_dev is overwritten) or STFD_X0_GIVEN (u_dev holds
+ * the initial guess).  Each right-hand side converges independently (a
+ * converged system is frozen).  info: host array of nrhs entries (may be NULL).
+ * precision: arithmetic of the preconditioner (stfd_precision); everything
+ * else is FP64.  Returns STFD_OK if all systems converged, STFD_NOT_CONVERGED
+ * if some hit maxit, STFD_EBREAKDOWN on breakdown, STFD_EINVAL, STFD_EHIP. */
+int stfd_pcg_solve(const stfd_problem *P, const void *f_dev, void *u_dev, int64_t nrhs, double rtol,
+                   int maxit, int flags, int precision, stfd_pcg_info *info, void *stream);
+
+/* Host copies of setup data for inspection: U_l (n_l x n_l, row-major,
+ * U[j*n_l + k] = entry (j,k), column k = k-th eigenvector) and Lambda_l.
+ * Errors: STFD_EINVAL for l outside [0, d). */
+int stfd_get_pencil(const stfd_problem *P, int l, double *U, double *lambda);
+
+/* Diagnostic: runs one v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32 and
+ * v_mfma_f32_16x16x16bf16_1k with A[m][k] = m + 16 k and B[k][n] = (k == n mod K)
+ * on the current device and copies lane l's 4 result registers to
+ * out[4 l + v] (host arrays of 256 entries).  Used by tests to pin the
+ * operand/result lane layout the mode-product kernel relies on.
+ * Errors: STFD_EINVAL (NULL pointer), STFD_EHIP. */
+int stfd_debug_mfma_layout(double *out64, float *out32, float *outbf);
+
+void stfd_destroy(stfd_problem *P);
+const char *stfd_strerror(int code);
+int stfd_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STFD_H */

@@ -1,0 +1,75 @@
+// Host-side setup data of one problem (FP64), shared by host_setup.cpp and stfd.hip.
+#pragma once
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+namespace stfd {
+
+using cplx = std::complex<double>;
+
+// One knot vector and its element-wise Gauss rule with basis data.
+struct Direction {
+  std::vector<double> knots;  // scaled to the physical interval
+  int p = 0;
+  int m = 0;                  // number of B-splines
+  int n_el = 0;               // non-empty spans
+  int q = 0;                  // Gauss points per element
+  std::vector<int> first;     // first non-zero function on each element
+  std::vector<double> x, w;   // n_el * q points and weights
+  // basis[((e*q + g)*3 + r)*(p+1) + a]: derivative r of function first[e]+a at point g of element e
+  std::vector<double> basis;
+  double b(int e, int g, int r, int a) const { return basis[((size_t(e) * q + g) * 3 + r) * (p + 1) + a]; }
+};
+
+// Dense full m x m Gram matrices X[i*m+j] = int b_i^(a) b_j^(b).
+struct Gram1D {
+  int m = 0;
+  std::vector<double> M, L, J, G;  // G[i][j] = int b_j' b_i
+};
+
+struct HostProblem {
+  int d = 0, p_t = 0, p_s = 0;
+  double T = 1, nu = 1;
+  Direction dir_t;
+  Direction dir_s[3];
+  int n_t = 0;
+  int n_s[3] = {1, 1, 1};
+  int64_t N_s = 0, N = 0;
+  // reduced 1D matrices
+  std::vector<double> Mt, Lt, Kt;  // n_t x n_t; W_t + W_t^* = i Kt
+  std::vector<double> Ms1[3], Ls1[3], Js1[3];
+  // generalised eigendecomposition per direction: U[j*n + k], lambda[k]
+  std::vector<double> U[3], lam1[3];
+  std::vector<double> lam;  // Kronecker sum, N_s
+  // LDL^H factors of H_i, layout [t][k-1][mode] (complex) and [t][mode] (real)
+  std::vector<cplx> Lfac;
+  std::vector<double> Dinv;
+  // time bands T_k[t][dt + p_t], dt = -p_t..p_t  (k = 0: L_t, 1: M_t, 2: K_t)
+  std::vector<double> Tband;
+  // spatial stencils S_k[i][s], s = sum_l (o_l + p_s) (2p_s+1)^l, k = 0..2
+  int stencil = 0;  // (2 p_s + 1)^d
+  std::vector<double> Sc;  // 3 * N_s * stencil
+};
+
+// Returns 0 or a negative stfd_status.
+int validate_knots(const double* kn, int nk, int p, int max_interior_mult);
+int build_direction(const double* kn, int nk, int p, int q, double scale, Direction& out);
+void gram_1d(const Direction& dir, Gram1D& g);
+int gauss_legendre(int q, double* x, double* w);  // on (-1,1)
+int gen_eig(int n, const double* L, const double* M, double* U, double* lam);  // 0 or -2
+int host_setup(const struct stfd_setup_desc_view& v, HostProblem& hp);
+
+// Flat view of the public descriptor (keeps this header free of the C ABI).
+struct stfd_setup_desc_view {
+  int d, p_t, p_s;
+  const double* knots_t;
+  int n_knots_t;
+  const double* knots_s[3];
+  int n_knots_s[3];
+  double T, nu;
+  const double* V_quad;
+  int n_quad;
+};
+
+}  // namespace stfd

@@ -1,0 +1,1388 @@
+// MI355X (gfx950) implementation of the C ABI in include/stfd.h.
+//
+// Hot path per PCG iteration (Section 5.3):
+//   matvec  q = A p           : stencil x band kernel (FP64), fused <p,q> partials
+//   update  x += a p, r -= a q: BLAS-1 with fused ||r||^2 partials
+//   apply   z = P-hat^{-1} r  : 2d MFMA mode products + one banded time-solve kernel
+//                                (Algorithm 1 steps 2-4)
+//   dots / p-update           : Polak-Ribiere beta, p = z + beta p
+// Reductions are deterministic: every block writes one partial per reduction
+// and consumers sum the partials in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/stfd.h"
+#include "host_setup.h"
+#include "kernels.h"
+
+namespace stfd {
+
+static thread_local int g_last_hip_error = 0;
+
+#define STFD_HIP(expr)                          \
+  do {                                          \
+    hipError_t e_ = (expr);                     \
+    if (e_ != hipSuccess) {                     \
+      g_last_hip_error = int(e_);               \
+      return STFD_EHIP;                         \
+    }                                           \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ short f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return short(u >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum (fixed tree order); result valid in all threads.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < NT / 64; ++i) s += sh[i];
+  return s;
+}
+
+// Sum of nparts partials (fixed order per thread, then block tree); all threads get it.
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double* parts, int nparts, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += NT) s += parts[i];
+  return block_sum<NT>(s, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Mode product (Algorithm 1 steps 2 and 4): one block = one outer slice o and
+// one tile of `row_tile` rows; wave w owns output columns a in [16w, 16w+16).
+// The block stages In[o][0..n)[tile rows] in LDS (operand precision, zero
+// padded to the MFMA K step); each wave keeps its 16 columns of U' in
+// registers.  MFMA computes C^T = U'^T A^T so that the 16 rows of a result
+// fragment are contiguous in memory (coalesced stores).
+//   FP64: v_mfma_f64_16x16x4f64, K step 4
+//   FP32: v_mfma_f32_16x16x4f32, K step 4
+//   BF16: v_mfma_f32_16x16x16bf16_1k, K step 16, FP32 accumulation
+// Operand layouts (16x16xK, one block): lane l supplies A[m = l%16][k = (K/4)(l/16) + e]
+// and B[k = (K/4)(l/16) + e][n = l%16].  Result register v of lane l holds
+// D[m = 4(l/16) + v][n = l%16] for the FP32-accumulating instructions and
+// D[m = 4v + l/16][n = l%16] for v_mfma_f64_16x16x4f64 (checked by the
+// stfd_debug_mfma_layout probe).
+// ---------------------------------------------------------------------------
+template <int PREC>
+struct MPTraits;
+template <>
+struct MPTraits<MP_F64> {
+  using op_t = double;
+  using acc_t = d4_t;
+  static constexpr int K = 4;
+};
+template <>
+struct MPTraits<MP_F32> {
+  using op_t = float;
+  using acc_t = f4_t;
+  static constexpr int K = 4;
+};
+template <>
+struct MPTraits<MP_BF16> {
+  using op_t = short;  // bf16 bits
+  using acc_t = f4_t;
+  static constexpr int K = 16;
+};
+
+template <int PREC>
+__device__ __forceinline__ typename MPTraits<PREC>::op_t to_op(double v) {
+  if constexpr (PREC == MP_F64) return v;
+  else if constexpr (PREC == MP_F32) return float(v);
+  else return f32_to_bf16(float(v));
+}
+template <int PREC>
+__device__ __forceinline__ typename MPTraits<PREC>::op_t to_op(float v) {
+  if constexpr (PREC == MP_F64) return double(v);
+  else if constexpr (PREC == MP_F32) return v;
+  else return f32_to_bf16(v);
+}
+
+template <int PREC, typename Tin, typename Tout>
+__global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
+  using Tr = MPTraits<PREC>;
+  using op_t = typename Tr::op_t;
+  constexpr int K = Tr::K;
+  constexpr int KSTEPS_MAX = kMaxModeN / K;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  op_t* tile = reinterpret_cast<op_t*>(smem_raw);
+
+  const int n = a.n;
+  const int kpad = (n + K - 1) / K * K;
+  const int nks = kpad / K;
+  const int RT = a.row_tile;
+  const int64_t o = blockIdx.x / a.n_row_tiles;
+  const int64_t rt = blockIdx.x - o * a.n_row_tiles;
+  if (a.done && a.done[o / a.outer_per_rhs]) return;
+  const int64_t row0 = rt * RT;
+  const int rows_here = int(min<int64_t>(RT, a.inner - row0));
+  const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
+  Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
+
+  // stage the input tile tile[j*RT + r] = In[o][j][row0 + r]: batches of loads from clamped
+  // (always in-bounds) addresses are issued before any is consumed; padding is zeroed after
+  constexpr int kBatch = 8;
+  const int ntile = kpad * RT;
+  for (int b0 = 0; b0 < ntile; b0 += int(blockDim.x) * kBatch) {
+    Tin v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int idx = b0 + u * int(blockDim.x) + int(threadIdx.x);
+      const int j = idx / RT, r = idx - j * RT;
+      v[u] = src[int64_t(min(j, n - 1)) * a.inner + min(r, rows_here - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int idx = b0 + u * int(blockDim.x) + int(threadIdx.x);
+      const int j = idx / RT, r = idx - j * RT;
+      if (idx < ntile) tile[idx] = (j < n && r < rows_here) ? to_op<PREC>(v[u]) : op_t(0);
+    }
+  }
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int a0 = wave * 16;
+  const int col = lane & 15, grp = lane >> 4;
+  // this wave's operand fragments of U'^T: element (m = col, k = K/4*grp + e) of each K step
+  op_t ua[KSTEPS_MAX][K / 4];
+#pragma unroll
+  for (int ks = 0; ks < KSTEPS_MAX; ++ks)
+#pragma unroll
+    for (int e = 0; e < K / 4; ++e) {
+      const int j = ks * K + (K / 4) * grp + e;
+      const int aa = a0 + col;
+      const double v = a.U[min(j, n - 1) * n + min(aa, n - 1)];
+      ua[ks][e] = to_op<PREC>((ks < nks && j < n && aa < n) ? v : 0.0);
+    }
+  __syncthreads();
+
+  double dot_a = 0.0, dot_b = 0.0;
+  for (int r0 = 0; r0 < RT; r0 += 16) {
+    typename Tr::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS_MAX; ++ks) {
+      if (ks < nks) {
+      if constexpr (PREC == MP_F64) {
+        const double b = tile[(ks * K + grp) * RT + r0 + col];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b, acc, 0, 0, 0);
+      } else if constexpr (PREC == MP_F32) {
+        const float b = tile[(ks * K + grp) * RT + r0 + col];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[ks][0], b, acc, 0, 0, 0);
+      } else {
+        s4_t av, bv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          av[e] = ua[ks][e];
+          bv[e] = tile[(ks * K + 4 * grp + e) * RT + r0 + col];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+      }
+    }
+    const int r = r0 + col;
+    if (r < rows_here) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int aa = a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
+        if (aa < n) {
+          const int64_t off = int64_t(aa) * a.inner + r;
+          dst[off] = Tout(acc[v]);
+          if (a.part_a) {
+            const int64_t g = o * int64_t(n) * a.inner + row0 + off;
+            const double rv = a.dot_r[g];
+            dot_a += rv * double(Tout(acc[v]));
+            dot_b += rv * a.dot_z[g];
+          }
+        }
+      }
+    }
+  }
+  if (a.part_a) {
+    __shared__ double red[2][8];
+    dot_a = wave_sum(dot_a);
+    dot_b = wave_sum(dot_b);
+    if (lane == 0) {
+      red[0][wave] = dot_a;
+      red[1][wave] = dot_b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sa = 0.0, sb = 0.0;
+      const int nw = blockDim.x >> 6;
+      for (int w = 0; w < nw; ++w) {
+        sa += red[0][w];
+        sb += red[1][w];
+      }
+      a.part_a[blockIdx.x] = sa;
+      a.part_b[blockIdx.x] = sb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Banded time solves (Algorithm 1 step 3): for every spatial mode i solve
+// H_i x_i = y_i, H_i = L_t + mu_i^2 M_t + i mu_i K_t (Section 5.2), Hermitian
+// positive definite with half-bandwidth P, factorised at setup as L D L^H
+// (unit lower band L, real D > 0).  The recurrence over t is latency-bound,
+// so a block of `mpb` modes first copies everything it needs into LDS with
+// batched loads (no load waits inside the copy loops), then one lane per
+// mode sweeps forward (z_t = y_t - sum_k L[t][t-k] z_{t-k}, w_t = z_t / D_t)
+// and backward (x_t = w_t - sum_k conj(L[t+k][t]) x_{t+k}) reading LDS only,
+// four steps of operands at a time.  Arithmetic is FP64 for every precision
+// of the surrounding mode products (T is the storage type of y).
+// Factor layout (global and LDS, per block of mpb modes):
+//   Lb[blk][t][k-1][m] complex = L[t][t-k] of mode blk*mpb + m,  Db[blk][t][m] = 1 / D[t].
+// LDS y layout: ys[t][m] complex (lane-contiguous).
+// ---------------------------------------------------------------------------
+constexpr int kTsThreads = 256;
+constexpr int kTsBatch = 8;
+
+template <typename T, int P>
+__global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const double* Lb, const double* Db, int n_t,
+                                                              int64_t N_s, int64_t blocks_per_rhs, int mpb,
+                                                              const int* done) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Ls = reinterpret_cast<double*>(smem_raw);        // [n_t][P][mpb][2]
+  double* Ds = Ls + size_t(n_t) * P * mpb * 2;             // [n_t][mpb]
+  double* ys = Ds + size_t(n_t) * mpb;                     // [n_t][mpb][2]
+  const int64_t rhs = blockIdx.x / blocks_per_rhs;
+  if (done && done[rhs]) return;
+  const int64_t blk = blockIdx.x - rhs * blocks_per_rhs;
+  const int64_t i0 = blk * mpb;
+  const int nm = int(min<int64_t>(mpb, N_s - i0));
+  T* base = y + (rhs * N_s + i0) * int64_t(2 * n_t);
+  const int tid = threadIdx.x;
+  // factors of this block: one contiguous chunk
+  {
+    const int nl = n_t * P * mpb * 2, nd = n_t * mpb;
+    const double* gl = Lb + blk * int64_t(nl);
+    const double* gd = Db + blk * int64_t(nd);
+    for (int b0 = 0; b0 < nl; b0 += kTsThreads * kTsBatch) {
+      double v[kTsBatch];
+#pragma unroll
+      for (int u = 0; u < kTsBatch; ++u) v[u] = gl[min(b0 + u * kTsThreads + tid, nl - 1)];
+#pragma unroll
+      for (int u = 0; u < kTsBatch; ++u)
+        if (b0 + u * kTsThreads + tid < nl) Ls[b0 + u * kTsThreads + tid] = v[u];
+    }
+    for (int b0 = 0; b0 < nd; b0 += kTsThreads * kTsBatch) {
+      double v[kTsBatch];
+#pragma unroll
+      for (int u = 0; u < kTsBatch; ++u) v[u] = gd[min(b0 + u * kTsThreads + tid, nd - 1)];
+#pragma unroll
+      for (int u = 0; u < kTsBatch; ++u)
+        if (b0 + u * kTsThreads + tid < nd) Ds[b0 + u * kTsThreads + tid] = v[u];
+    }
+  }
+  // right-hand sides: global [m][t] (complex) -> LDS [t][m]
+  const int two_nt = 2 * n_t;
+  const int ny = nm * two_nt;
+  for (int b0 = 0; b0 < ny; b0 += kTsThreads * kTsBatch) {
+    T v[kTsBatch];
+#pragma unroll
+    for (int u = 0; u < kTsBatch; ++u) v[u] = base[min(b0 + u * kTsThreads + tid, ny - 1)];
+#pragma unroll
+    for (int u = 0; u < kTsBatch; ++u) {
+      const int idx = b0 + u * kTsThreads + tid;
+      if (idx < ny) {
+        const int m = idx / two_nt, rem = idx - m * two_nt;
+        ys[((rem >> 1) * mpb + m) * 2 + (rem & 1)] = double(v[u]);
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < nm) {
+    const int m = tid;
+    auto Lre = [&](int t, int k) { return Ls[((t * P + k - 1) * mpb + m) * 2]; };
+    auto Lim = [&](int t, int k) { return Ls[((t * P + k - 1) * mpb + m) * 2 + 1]; };
+    double hr[P], hi[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
+    int t = 0;
+    for (; t + 4 <= n_t; t += 4) {
+      double yr4[4], yi4[4], d4[4], l4[4][P][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        yr4[u] = ys[((t + u) * mpb + m) * 2];
+        yi4[u] = ys[((t + u) * mpb + m) * 2 + 1];
+        d4[u] = Ds[(t + u) * mpb + m];
+#pragma unroll
+        for (int k = 1; k <= P; ++k) {
+          l4[u][k - 1][0] = Lre(t + u, k);
+          l4[u][k - 1][1] = Lim(t + u, k);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double zr = yr4[u], zi = yi4[u];
+#pragma unroll
+        for (int k = P; k >= 1; --k) {
+          zr -= l4[u][k - 1][0] * hr[k - 1] - l4[u][k - 1][1] * hi[k - 1];
+          zi -= l4[u][k - 1][0] * hi[k - 1] + l4[u][k - 1][1] * hr[k - 1];
+        }
+#pragma unroll
+        for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
+        hr[0] = zr;
+        hi[0] = zi;
+        ys[((t + u) * mpb + m) * 2] = zr * d4[u];
+        ys[((t + u) * mpb + m) * 2 + 1] = zi * d4[u];
+      }
+    }
+    for (; t < n_t; ++t) {
+      double zr = ys[(t * mpb + m) * 2], zi = ys[(t * mpb + m) * 2 + 1];
+#pragma unroll
+      for (int k = P; k >= 1; --k) {
+        zr -= Lre(t, k) * hr[k - 1] - Lim(t, k) * hi[k - 1];
+        zi -= Lre(t, k) * hi[k - 1] + Lim(t, k) * hr[k - 1];
+      }
+#pragma unroll
+      for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
+      hr[0] = zr;
+      hi[0] = zi;
+      const double dv = Ds[t * mpb + m];
+      ys[(t * mpb + m) * 2] = zr * dv;
+      ys[(t * mpb + m) * 2 + 1] = zi * dv;
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
+    t = n_t - 1;
+    for (; t - 3 >= 0; t -= 4) {
+      double wr4[4], wi4[4], l4[4][P][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int tt = t - u;
+        wr4[u] = ys[(tt * mpb + m) * 2];
+        wi4[u] = ys[(tt * mpb + m) * 2 + 1];
+#pragma unroll
+        for (int k = 1; k <= P; ++k) {
+          const int row = min(tt + k, n_t - 1);
+          const bool ok = tt + k < n_t;
+          l4[u][k - 1][0] = ok ? Lre(row, k) : 0.0;
+          l4[u][k - 1][1] = ok ? Lim(row, k) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double xr = wr4[u], xi = wi4[u];
+#pragma unroll
+        for (int k = P; k >= 1; --k) {
+          xr -= l4[u][k - 1][0] * hr[k - 1] + l4[u][k - 1][1] * hi[k - 1];
+          xi -= l4[u][k - 1][0] * hi[k - 1] - l4[u][k - 1][1] * hr[k - 1];
+        }
+#pragma unroll
+        for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
+        hr[0] = xr;
+        hi[0] = xi;
+        ys[((t - u) * mpb + m) * 2] = xr;
+        ys[((t - u) * mpb + m) * 2 + 1] = xi;
+      }
+    }
+    for (; t >= 0; --t) {
+      double xr = ys[(t * mpb + m) * 2], xi = ys[(t * mpb + m) * 2 + 1];
+#pragma unroll
+      for (int k = P; k >= 1; --k) {
+        if (t + k < n_t) {
+          xr -= Lre(t + k, k) * hr[k - 1] + Lim(t + k, k) * hi[k - 1];
+          xi -= Lre(t + k, k) * hi[k - 1] - Lim(t + k, k) * hr[k - 1];
+        }
+      }
+#pragma unroll
+      for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
+      hr[0] = xr;
+      hi[0] = xi;
+      ys[(t * mpb + m) * 2] = xr;
+      ys[(t * mpb + m) * 2 + 1] = xi;
+    }
+  }
+  __syncthreads();
+  // write back [t][m] -> global [m][t]
+  for (int b0 = 0; b0 < ny; b0 += kTsThreads) {
+    const int idx = b0 + tid;
+    if (idx < ny) {
+      const int m = idx / two_nt, rem = idx - m * two_nt;
+      base[idx] = T(ys[((rem >> 1) * mpb + m) * 2 + (rem & 1)]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-free system matvec (Section 5.3, eq. syst_mat with potential terms):
+//   Y = sum_k T_k X S_k^T, X viewed as n_t x N_s (time fastest).
+// One wave per spatial point i, lanes over time (up to 4 chunks of 64).
+// Phase 1: Z_k(t, i) = sum_s S_k[i][s] X(t, i + o(s)) for the (2p+1)^d
+//          neighbours; the coefficients are wave-uniform (scalar loads),
+//          each neighbour column X(:, j) is one coalesced vector load.
+// Phase 2: Y(t, i) = sum_k sum_dt T_k[t][dt] Z_k(t + dt, i) with T_3 = i K_t,
+//          reading Z from the wave's LDS slice.
+// Optionally writes one partial of Re <x, y> per block (PCG's <p, A p>).
+// ---------------------------------------------------------------------------
+constexpr int kMvWaves = 4;
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kMvMaxChunks = 2;  // n_t <= 128
+
+struct MatvecArgs {
+  const double* x;
+  double* y;
+  const double* Sc;     // [N_s][stencil][3] interleaved spatial coefficients
+  const double* Tband;  // [3][n_t][2 pt + 1]
+  int n_t, pt;
+  int n1, n2, n3;
+  int64_t N_s;
+  int64_t blocks_per_rhs;
+  int64_t nrhs;
+  int64_t xcd_span;     // logical blocks per XCD
+  double* partial;      // [rhs][blocks_per_rhs] or nullptr
+  const int* done;
+};
+
+template <int D, int PS, int NCH>
+__global__ __launch_bounds__(64 * kMvWaves) void matvec_kernel(MatvecArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ double red[kMvWaves];
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous range of spatial points so that its L2 holds one slab of X.
+  const int64_t lb = int64_t(blockIdx.x % kXcds) * a.xcd_span + blockIdx.x / kXcds;
+  if (lb >= a.blocks_per_rhs * a.nrhs) return;
+  const int64_t rhs = lb / a.blocks_per_rhs;
+  const int64_t blk = lb - rhs * a.blocks_per_rhs;
+  if (a.done && a.done[rhs]) return;
+  const int n_t = a.n_t;
+  constexpr int nch = NCH;
+  const int64_t i = blk * kMvWaves + wv;
+  const bool active = i < a.N_s;
+  const int wt = 2 * a.pt + 1;
+  double* Tb = reinterpret_cast<double*>(smem_raw);                    // [3][n_t][wt]
+  double* Zw = Tb + size_t(3) * n_t * wt + size_t(wv) * 6 * n_t;        // [3][n_t][2] per wave
+  for (int idx = threadIdx.x; idx < 3 * n_t * wt; idx += 64 * kMvWaves) Tb[idx] = a.Tband[idx];
+  const double* X = a.x + rhs * a.N_s * int64_t(2 * n_t);
+  constexpr int W = 2 * PS + 1;
+  if (active) {
+    double z[NCH][6];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+      for (int e = 0; e < 6; ++e) z[c][e] = 0.0;
+    const int i1 = int(i % a.n1);
+    const int64_t rr = i / a.n1;
+    const int i2 = (D >= 2) ? int(rr % a.n2) : 0;
+    const int i3 = (D >= 3) ? int(rr / a.n2) : 0;
+    constexpr int ST = (D == 1 ? W : (D == 2 ? W * W : W * W * W));
+    const double* C = a.Sc + i * (ST * 3);
+    // time index of each chunk, clamped so that every load is in bounds
+    int tl[NCH];
+    bool tv[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      tv[c] = c * 64 + lane < n_t;
+      tl[c] = min(c * 64 + lane, n_t - 1);
+    }
+    for (int o3 = (D >= 3 ? -PS : 0); o3 <= (D >= 3 ? PS : 0); ++o3) {
+      const int j3 = i3 + o3;
+      if (D >= 3 && (j3 < 0 || j3 >= a.n3)) continue;
+      for (int o2 = (D >= 2 ? -PS : 0); o2 <= (D >= 2 ? PS : 0); ++o2) {
+        const int j2 = i2 + o2;
+        if (D >= 2 && (j2 < 0 || j2 >= a.n2)) continue;
+        const int sbase = (D >= 3 ? (o3 + PS) * W * W : 0) + (D >= 2 ? (o2 + PS) * W : 0);
+        const double* Xrow = X + (int64_t(a.n1) * (j2 + int64_t(a.n2) * j3)) * (2 * n_t);
+        // one row of W neighbours: issue every load first (clamped column), then accumulate;
+        // out-of-range neighbours get zero coefficients
+        double xr[W][NCH], xi[W][NCH];
+#pragma unroll
+        for (int o1 = 0; o1 < W; ++o1) {
+          const int j1 = min(max(i1 + o1 - PS, 0), a.n1 - 1);
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const double* q = Xrow + (int64_t(j1) * n_t + tl[c]) * 2;
+            xr[o1][c] = q[0];
+            xi[o1][c] = q[1];
+          }
+        }
+#pragma unroll
+        for (int o1 = 0; o1 < W; ++o1) {
+          const bool ok = (i1 + o1 - PS >= 0) && (i1 + o1 - PS < a.n1);
+          const int s = sbase + o1;
+          const double c0 = ok ? C[3 * s] : 0.0, c1 = ok ? C[3 * s + 1] : 0.0, c2 = ok ? C[3 * s + 2] : 0.0;
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) {
+            const double vr = ok ? xr[o1][c] : 0.0, vi = ok ? xi[o1][c] : 0.0;
+            z[c][0] += c0 * vr; z[c][1] += c0 * vi;
+            z[c][2] += c1 * vr; z[c][3] += c1 * vi;
+            z[c][4] += c2 * vr; z[c][5] += c2 * vi;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      if (tv[c]) {
+        const int t = tl[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          Zw[(k * n_t + t) * 2] = z[c][2 * k];
+          Zw[(k * n_t + t) * 2 + 1] = z[c][2 * k + 1];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double part = 0.0;
+  if (active) {
+    for (int c = 0; c < nch; ++c) {
+      const int t = c * 64 + lane;
+      if (t >= n_t) continue;
+      double yr = 0, yi = 0;
+      for (int dt = -a.pt; dt <= a.pt; ++dt) {
+        const int tt = t + dt;
+        if (tt < 0 || tt >= n_t) continue;
+        const double tl = Tb[(0 * n_t + t) * wt + dt + a.pt];
+        const double tm = Tb[(1 * n_t + t) * wt + dt + a.pt];
+        const double tk = Tb[(2 * n_t + t) * wt + dt + a.pt];
+        yr += tl * Zw[(0 * n_t + tt) * 2] + tm * Zw[(1 * n_t + tt) * 2] - tk * Zw[(2 * n_t + tt) * 2 + 1];
+        yi += tl * Zw[(0 * n_t + tt) * 2 + 1] + tm * Zw[(1 * n_t + tt) * 2 + 1] + tk * Zw[(2 * n_t + tt) * 2];
+      }
+      const int64_t g = (rhs * a.N_s + i) * n_t + t;
+      a.y[2 * g] = yr;
+      a.y[2 * g + 1] = yi;
+      if (a.partial) part += a.x[2 * g] * yr + a.x[2 * g + 1] * yi;  // Re(conj(x) y)
+    }
+  }
+  if (a.partial) {
+    part = wave_sum(part);
+    if (lane == 0) red[wv] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMvWaves; ++k) s += red[k];
+      a.partial[rhs * a.blocks_per_rhs + blk] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BLAS-1 kernels of PCG.  Vectors are complex FP64 [rhs][N]; grid = (kVecGrid, nrhs).
+// Scalar state per right-hand side lives in PcgScalars.
+// ---------------------------------------------------------------------------
+struct PcgScalars {
+  double nf2;       // ||f||^2
+  double rz[2];     // <r_k, z_k> by iteration parity
+  double res;       // ||r_k|| / ||f||
+  double true_res;
+  int iters;
+  int status;
+  int done;
+  int pad;
+};
+
+// partial sums of Re<a, b> (and optionally Re<a, c>) over this block's range
+__global__ __launch_bounds__(kVecBlock) void dot2_kernel(const double* a, const double* b, const double* c,
+                                                          int64_t n2, double* pb, double* pc, const int* done) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.y;
+  if (done && done[rhs]) return;
+  const double* A = a + rhs * n2;
+  const double* B = b + rhs * n2;
+  const double* C = c ? c + rhs * n2 : nullptr;
+  double sb = 0.0, sc = 0.0;
+  for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
+    const double ar = A[k], ai = A[k + 1];
+    sb += ar * B[k] + ai * B[k + 1];
+    if (C) sc += ar * C[k] + ai * C[k + 1];
+  }
+  sb = block_sum<kVecBlock>(sb, sh);
+  if (threadIdx.x == 0) pb[rhs * gridDim.x + blockIdx.x] = sb;
+  if (C) {
+    sc = block_sum<kVecBlock>(sc, sh);
+    if (threadIdx.x == 0) pc[rhs * gridDim.x + blockIdx.x] = sc;
+  }
+}
+
+// r = f - q (given x0) or r = f (zero x0, also zeroes x); partial ||f||^2
+__global__ __launch_bounds__(kVecBlock) void pcg_init_kernel(const double* f, const double* q, double* r,
+                                                              double* x, int64_t n2, double* pf) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.y;
+  const double* F = f + rhs * n2;
+  double* R = r + rhs * n2;
+  double s = 0.0;
+  for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
+    const double fr = F[k], fi = F[k + 1];
+    s += fr * fr + fi * fi;
+    if (q) {
+      R[k] = fr - q[rhs * n2 + k];
+      R[k + 1] = fi - q[rhs * n2 + k + 1];
+    } else {
+      R[k] = fr;
+      R[k + 1] = fi;
+      x[rhs * n2 + k] = 0.0;
+      x[rhs * n2 + k + 1] = 0.0;
+    }
+  }
+  s = block_sum<kVecBlock>(s, sh);
+  if (threadIdx.x == 0) pf[rhs * gridDim.x + blockIdx.x] = s;
+}
+
+// scalar bookkeeping after the initial residual: ||f||^2, ||r_0||, convergence at k = 0
+__global__ __launch_bounds__(kVecBlock) void pcg_start_kernel(const double* pf, const double* prr, int nparts,
+                                                               PcgScalars* sc, int* done, double tol) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.x;
+  const double nf2 = sum_partials<kVecBlock>(pf + rhs * nparts, nparts, sh);
+  const double rr = prr ? sum_partials<kVecBlock>(prr + rhs * nparts, nparts, sh) : nf2;
+  if (threadIdx.x == 0) {
+    PcgScalars& s = sc[rhs];
+    s.nf2 = nf2;
+    s.iters = 0;
+    s.status = STFD_OK;
+    s.done = 0;
+    s.rz[0] = s.rz[1] = 0.0;
+    s.true_res = 0.0;
+    if (!(nf2 > 0.0) || !std::isfinite(nf2)) {
+      // f = 0: the solution is u = 0 (already in x for a zero start)
+      s.res = 0.0;
+      s.done = 1;
+      if (!std::isfinite(nf2)) s.status = STFD_EBREAKDOWN;
+    } else {
+      s.res = sqrt(rr / nf2);
+      if (!std::isfinite(s.res)) { s.status = STFD_EBREAKDOWN; s.done = 1; }
+      else if (s.res <= tol) s.done = 1;
+    }
+    done[rhs] = s.done;
+  }
+}
+
+// p = z; rz[0] = <r, z>
+__global__ __launch_bounds__(kVecBlock) void pcg_first_p_kernel(const double* z, double* p, int64_t n2,
+                                                                 const double* prz, int nparts, PcgScalars* sc,
+                                                                 int* done) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.y;
+  if (done[rhs]) return;
+  const double rz = sum_partials<kVecBlock>(prz + rhs * nparts, nparts, sh);
+  for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
+    p[rhs * n2 + k] = z[rhs * n2 + k];
+    p[rhs * n2 + k + 1] = z[rhs * n2 + k + 1];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[rhs].rz[0] = rz;
+    if (!(rz > 0.0) || !std::isfinite(rz)) {
+      sc[rhs].status = STFD_EBREAKDOWN;
+      sc[rhs].done = 1;
+      done[rhs] = 1;
+    }
+  }
+}
+
+// alpha = rz / <p, q>; x += alpha p; r -= alpha q; partial ||r||^2
+__global__ __launch_bounds__(kVecBlock) void pcg_update_xr_kernel(const double* p, const double* q, double* x,
+                                                                   double* r, int64_t n2, const double* ppq,
+                                                                   int npq, const PcgScalars* sc, int parity,
+                                                                   double* prr, const int* done) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.y;
+  if (done[rhs]) return;
+  const double pq = sum_partials<kVecBlock>(ppq + rhs * npq, npq, sh);
+  const double rz = sc[rhs].rz[parity];
+  const bool ok = (pq > 0.0) && std::isfinite(pq);
+  const double alpha = ok ? rz / pq : 0.0;
+  double s = 0.0;
+  for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
+    const int64_t g = rhs * n2 + k;
+    const double rr = r[g] - alpha * q[g], ri = r[g + 1] - alpha * q[g + 1];
+    if (ok) {
+      x[g] += alpha * p[g];
+      x[g + 1] += alpha * p[g + 1];
+      r[g] = rr;
+      r[g + 1] = ri;
+    }
+    s += rr * rr + ri * ri;
+  }
+  s = block_sum<kVecBlock>(s, sh);
+  if (threadIdx.x == 0) prr[rhs * gridDim.x + blockIdx.x] = ok ? s : NAN;
+}
+
+// End of iteration k for one right-hand side: convergence / breakdown /
+// iteration-limit test on ||r_{k+1}|| (partials of pcg_update_xr), then
+// beta = (<r, z_new> - <r, z_old>) / rz_k (partials of the last mode product)
+// and p = z_new + beta p.  Every block computes the same scalars from the same
+// partials in the same order, so they all take the same decision; block 0
+// records the state, the per-rhs done flag and a copy in host-mapped memory.
+__global__ __launch_bounds__(kVecBlock) void pcg_end_iter_kernel(const double* znew, double* p, int64_t n2,
+                                                                  const double* prr, int nrr, const double* pa,
+                                                                  const double* pb, int nab, PcgScalars* sc,
+                                                                  int parity, int* done, int k, int maxit, double tol,
+                                                                  PcgScalars* host_slot) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.y;
+  if (done[rhs]) return;
+  const double rr = sum_partials<kVecBlock>(prr + rhs * nrr, nrr, sh);
+  const double nf2 = sc[rhs].nf2;
+  const double res = sqrt(rr / nf2);
+  int status = STFD_OK;
+  bool finished = false;
+  double rzn = 0.0;
+  if (!std::isfinite(res)) {
+    status = STFD_EBREAKDOWN;
+    finished = true;
+  } else if (res <= tol) {
+    finished = true;
+  } else if (k + 1 >= maxit) {
+    status = STFD_NOT_CONVERGED;
+    finished = true;
+  } else {
+    rzn = sum_partials<kVecBlock>(pa + rhs * nab, nab, sh);
+    const double rzm = sum_partials<kVecBlock>(pb + rhs * nab, nab, sh);
+    const double rz = sc[rhs].rz[parity];
+    if (!(rzn > 0.0) || !std::isfinite(rzn) || !std::isfinite(rzm)) {
+      status = STFD_EBREAKDOWN;
+      finished = true;
+    } else {
+      const double beta = (rzn - rzm) / rz;
+      for (int64_t q = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; q < n2;
+           q += int64_t(gridDim.x) * kVecBlock * 2) {
+        const int64_t g = rhs * n2 + q;
+        p[g] = znew[g] + beta * p[g];
+        p[g + 1] = znew[g + 1] + beta * p[g + 1];
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    PcgScalars& st = sc[rhs];
+    st.iters = k + 1;
+    if (std::isfinite(res)) st.res = res;
+    st.rz[parity ^ 1] = rzn;
+    st.status = status;
+    st.done = finished ? 1 : 0;
+    done[rhs] = st.done;
+    if (host_slot) host_slot[rhs] = st;
+  }
+}
+
+// ||f - q||^2 partials (true residual with q = A x)
+__global__ __launch_bounds__(kVecBlock) void resid_norm_kernel(const double* f, const double* q, int64_t n2, double* pr) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.y;
+  double s = 0.0;
+  for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
+    const int64_t g = rhs * n2 + k;
+    const double a = f[g] - q[g], b = f[g + 1] - q[g + 1];
+    s += a * a + b * b;
+  }
+  s = block_sum<kVecBlock>(s, sh);
+  if (threadIdx.x == 0) pr[rhs * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kVecBlock) void pcg_finish_kernel(const double* pr, int nparts, PcgScalars* sc) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.x;
+  const double rr = sum_partials<kVecBlock>(pr + rhs * nparts, nparts, sh);
+  if (threadIdx.x == 0) sc[rhs].true_res = (sc[rhs].nf2 > 0.0) ? sqrt(rr / sc[rhs].nf2) : 0.0;
+}
+
+// diagnostic: one MFMA of each kind with A[m][k] = m + 16 k, B[k][n] = (k == n % K)
+__global__ void mfma_layout_kernel(double* o64, float* o32, float* obf) {
+  const int l = threadIdx.x;
+  const int m = l & 15, g = l >> 4;
+  d4_t a64 = {0, 0, 0, 0};
+  a64 = __builtin_amdgcn_mfma_f64_16x16x4f64(double(m + 16 * g), double(g == (m & 3)), a64, 0, 0, 0);
+  f4_t a32 = {0, 0, 0, 0};
+  a32 = __builtin_amdgcn_mfma_f32_16x16x4f32(float(m + 16 * g), float(g == (m & 3)), a32, 0, 0, 0);
+  s4_t av, bv;
+  for (int e = 0; e < 4; ++e) {
+    const int k = 4 * g + e;
+    av[e] = f32_to_bf16(float(m + 16 * k));
+    bv[e] = f32_to_bf16(float(k == (m & 15)));
+  }
+  f4_t abf = {0, 0, 0, 0};
+  abf = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, abf, 0, 0, 0);
+  for (int v = 0; v < 4; ++v) {
+    o64[l * 4 + v] = a64[v];
+    o32[l * 4 + v] = a32[v];
+    obf[l * 4 + v] = abf[v];
+  }
+}
+
+}  // namespace stfd
+
+// ===========================================================================
+// Host side: the problem handle and the C ABI
+// ===========================================================================
+struct stfd_problem {
+  stfd::HostProblem hp;
+  int max_nrhs = 1;
+  int64_t n2 = 0;  // reals per vector (2 N)
+  // device data
+  double* U_fwd[3] = {nullptr, nullptr, nullptr};  // U'[j][a] = U[j][a]  (apply U^T)
+  double* U_bwd[3] = {nullptr, nullptr, nullptr};  // U'[j][a] = U[a][j]  (apply U)
+  double* Lb = nullptr;     // time-block factors [blk][t][k][m] (complex), see time_solve_kernel
+  double* Db = nullptr;     // inverse pivots [blk][t][m]
+  int ts_mpb = 16;          // modes per time-solve block
+  double* Tband = nullptr;  // [3][n_t][2 p_t + 1]: L_t, M_t, K_t bands
+  double* Sc = nullptr;
+  double* work64[2] = {nullptr, nullptr};
+  float* work32[2] = {nullptr, nullptr};
+  double* vec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // r, z, z2, p, q
+  double* parts = nullptr;  // 6 partial arrays of max_nrhs * max_parts
+  int64_t max_parts = 0;
+  stfd::PcgScalars* sc = nullptr;
+  int* done = nullptr;
+  stfd::PcgScalars* sc_host = nullptr;  // pinned host ring [kLag][max_nrhs], written by kernels
+  stfd::PcgScalars* sc_host_dev = nullptr;  // device address of sc_host
+  int64_t mp_last_blocks = 0;            // blocks per rhs of the last mode product (dot partials)
+  int64_t mv_blocks = 0;
+  size_t max_lds = 65536;  // per-block LDS limit of the device used at setup
+  std::vector<void*> allocs;
+};
+
+namespace stfd {
+
+constexpr int kLag = 3;  // iterations the host lets the device run ahead of its convergence check
+
+template <typename T>
+static int dev_alloc(stfd_problem* P, T** ptr, size_t count) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    return STFD_ENOMEM;
+  }
+  P->allocs.push_back(p);
+  *ptr = static_cast<T*>(p);
+  return STFD_OK;
+}
+
+template <typename T>
+static int upload(stfd_problem* P, T** ptr, const T* src, size_t count) {
+  int rc = dev_alloc(P, ptr, count);
+  if (rc) return rc;
+  STFD_HIP(hipMemcpy(*ptr, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return STFD_OK;
+}
+
+// Row tile for a mode product: at most 64 rows, balanced so that the last
+// tile is not mostly padding; smaller tiles when one right-hand side alone
+// would not give the launch enough blocks.  Depends only on per-rhs sizes so
+// that the number of blocks per right-hand side is fixed for a problem.
+static int pick_row_tile(int64_t inner, int64_t outer_per_rhs) {
+  int64_t ntile = (inner + 63) / 64;
+  int rt = int(16 * ((inner + 16 * ntile - 1) / (16 * ntile)));
+  while (rt > 16 && outer_per_rhs * ((inner + rt - 1) / rt) < 512) rt -= 16;
+  return std::max(rt, 16);
+}
+
+static int64_t mode_product_blocks_per_rhs(int64_t inner, int64_t outer_per_rhs) {
+  const int rt = pick_row_tile(inner, outer_per_rhs);
+  return outer_per_rhs * ((inner + rt - 1) / rt);
+}
+
+struct DotEpilogue {
+  const double* r = nullptr;
+  const double* zold = nullptr;
+  double* part_a = nullptr;
+  double* part_b = nullptr;
+};
+
+template <int PREC, typename Tin, typename Tout>
+static int launch_mode_product(const void* in, void* out, const double* U, int n, int64_t inner, int64_t outer,
+                               int64_t outer_per_rhs, const int* done, hipStream_t s,
+                               const DotEpilogue& ep = DotEpilogue()) {
+  ModeProductArgs a;
+  a.in = in;
+  a.out = out;
+  a.U = U;
+  a.n = n;
+  a.inner = inner;
+  a.outer = outer;
+  a.outer_per_rhs = outer_per_rhs;
+  a.row_tile = pick_row_tile(inner, outer_per_rhs);
+  a.n_row_tiles = (inner + a.row_tile - 1) / a.row_tile;
+  a.done = done;
+  a.dot_r = ep.r;
+  a.dot_z = ep.zold;
+  a.part_a = ep.part_a;
+  a.part_b = ep.part_b;
+  const int K = MPTraits<PREC>::K;
+  const int kpad = (n + K - 1) / K * K;
+  const size_t lds = size_t(kpad) * a.row_tile * sizeof(typename MPTraits<PREC>::op_t);
+  const int waves = (n + 15) / 16;
+  const int64_t blocks = outer * a.n_row_tiles;
+  if (blocks <= 0) return STFD_OK;
+  hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout>), dim3(unsigned(blocks)), dim3(64 * waves), lds, s, a);
+  STFD_HIP(hipGetLastError());
+  return STFD_OK;
+}
+
+template <typename T>
+static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* done, hipStream_t s) {
+  const HostProblem& hp = P->hp;
+  const int mpb = P->ts_mpb;
+  const int64_t bpr = (hp.N_s + mpb - 1) / mpb;
+  const size_t lds = size_t(mpb) * hp.n_t * (2 * hp.p_t + 1 + 2) * sizeof(double);
+  const dim3 grid(unsigned(bpr * nrhs)), block(kTsThreads);
+#define STFD_TS(PV)                                                                                          \
+  case PV:                                                                                                   \
+    hipLaunchKernelGGL((time_solve_kernel<T, PV>), grid, block, lds, s, y, P->Lb, P->Db, hp.n_t, hp.N_s,    \
+                       bpr, mpb, done);                                                                      \
+    break;
+  switch (hp.p_t) {
+    STFD_TS(1)
+    STFD_TS(2)
+    STFD_TS(3)
+    STFD_TS(4)
+    STFD_TS(5)
+    STFD_TS(6)
+    default:
+      return STFD_EINVAL;
+  }
+#undef STFD_TS
+  STFD_HIP(hipGetLastError());
+  return STFD_OK;
+}
+
+// Algorithm 1 steps 2-4 on nrhs stacked vectors.  TW = working precision of
+// intermediates (double for FP64, float otherwise).
+template <int PREC, typename TW>
+static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t nrhs, const int* done, hipStream_t s,
+                      TW* w0, TW* w1, const DotEpilogue& ep) {
+  const HostProblem& hp = P->hp;
+  const int d = hp.d;
+  // inner / outer sizes of each direction (reals)
+  int64_t inner[3], outer[3], outer_rhs[3];
+  int64_t below = 2 * int64_t(hp.n_t);
+  for (int l = 0; l < d; ++l) {
+    inner[l] = below;
+    int64_t above = 1;
+    for (int k = l + 1; k < d; ++k) above *= hp.n_s[k];
+    outer_rhs[l] = above;
+    outer[l] = above * nrhs;
+    below *= hp.n_s[l];
+  }
+  int rc;
+  // step 2: y = (U_s^T (x) I) r, directions 1..d; r (FP64) -> w0 -> w1 -> ...
+  TW* bufs[2] = {w0, w1};
+  int cur = 0;
+  rc = launch_mode_product<PREC, double, TW>(r, bufs[cur], P->U_fwd[0], hp.n_s[0], inner[0], outer[0], outer_rhs[0],
+                                             done, s);
+  if (rc) return rc;
+  for (int l = 1; l < d; ++l) {
+    rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], P->U_fwd[l], hp.n_s[l], inner[l], outer[l],
+                                           outer_rhs[l], done, s);
+    if (rc) return rc;
+    cur ^= 1;
+  }
+  // step 3: N_s independent banded time solves, in place
+  rc = launch_time_solve<TW>(P, bufs[cur], nrhs, done, s);
+  if (rc) return rc;
+  // step 4: s = (U_s (x) I) x, directions d..1, last product writes FP64 output
+  for (int l = d - 1; l >= 1; --l) {
+    rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], P->U_bwd[l], hp.n_s[l], inner[l], outer[l],
+                                           outer_rhs[l], done, s);
+    if (rc) return rc;
+    cur ^= 1;
+  }
+  return launch_mode_product<PREC, TW, double>(bufs[cur], s_out, P->U_bwd[0], hp.n_s[0], inner[0], outer[0],
+                                               outer_rhs[0], done, s, ep);
+}
+
+static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64_t nrhs, int precision,
+                          const int* done, hipStream_t s, const DotEpilogue& ep = DotEpilogue()) {
+  switch (precision) {
+    case STFD_FP64:
+      return apply_impl<MP_F64, double>(P, r, s_out, nrhs, done, s, P->work64[0], P->work64[1], ep);
+    case STFD_FP32:
+      return apply_impl<MP_F32, float>(P, r, s_out, nrhs, done, s, P->work32[0], P->work32[1], ep);
+    case STFD_BF16:
+      return apply_impl<MP_BF16, float>(P, r, s_out, nrhs, done, s, P->work32[0], P->work32[1], ep);
+    default:
+      return STFD_EINVAL;
+  }
+}
+
+static int matvec_dispatch(stfd_problem* P, const double* x, double* y, int64_t nrhs, double* partial,
+                           const int* done, hipStream_t s) {
+  const HostProblem& hp = P->hp;
+  MatvecArgs a;
+  a.x = x;
+  a.y = y;
+  a.Sc = P->Sc;
+  a.Tband = P->Tband;
+  a.n_t = hp.n_t;
+  a.pt = hp.p_t;
+  a.n1 = hp.n_s[0];
+  a.n2 = hp.n_s[1];
+  a.n3 = hp.n_s[2];
+  a.N_s = hp.N_s;
+  a.blocks_per_rhs = P->mv_blocks;
+  a.nrhs = nrhs;
+  a.xcd_span = (P->mv_blocks * nrhs + kXcds - 1) / kXcds;
+  a.partial = partial;
+  a.done = done;
+  const size_t lds = (size_t(3) * hp.n_t * (2 * hp.p_t + 1) + size_t(kMvWaves) * 6 * hp.n_t) * sizeof(double);
+  const dim3 grid(unsigned(a.xcd_span * kXcds)), block(64 * kMvWaves);
+#define STFD_MV(DV, PV)                                                                    \
+  if (hp.d == DV && hp.p_s == PV) {                                                       \
+    if (hp.n_t <= 64)                                                                     \
+      hipLaunchKernelGGL((matvec_kernel<DV, PV, 1>), grid, block, lds, s, a);             \
+    else                                                                                  \
+      hipLaunchKernelGGL((matvec_kernel<DV, PV, 2>), grid, block, lds, s, a);             \
+    STFD_HIP(hipGetLastError());                                                          \
+    return STFD_OK;                                                                       \
+  }
+  STFD_MV(1, 2) STFD_MV(1, 3) STFD_MV(1, 4) STFD_MV(1, 5) STFD_MV(1, 6)
+  STFD_MV(2, 2) STFD_MV(2, 3) STFD_MV(2, 4) STFD_MV(2, 5)
+  STFD_MV(3, 2) STFD_MV(3, 3) STFD_MV(3, 4)
+#undef STFD_MV
+  return STFD_EINVAL;
+}
+
+}  // namespace stfd
+
+using namespace stfd;
+
+extern "C" {
+
+const char* stfd_strerror(int code) {
+  switch (code) {
+    case STFD_OK: return "ok";
+    case STFD_NOT_CONVERGED: return "PCG did not converge within maxit iterations";
+    case STFD_EINVAL: return "invalid argument";
+    case STFD_ENOTSPD: return "matrix not (Hermitian) positive definite";
+    case STFD_EBREAKDOWN: return "PCG breakdown (non-finite value or non-positive curvature)";
+    case STFD_ENOMEM: return "allocation failed";
+    case STFD_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int stfd_last_hip_error(void) { return g_last_hip_error; }
+
+int stfd_quad_points(const double* knots, int n_knots, int degree, int n_quad, double scale, double* pts,
+                     double* wts, int* n_out) {
+  if (!n_out || degree < 1 || n_quad < 0 || !(scale > 0.0)) return STFD_EINVAL;
+  if (validate_knots(knots, n_knots, degree, degree)) return STFD_EINVAL;
+  Direction D;
+  if (build_direction(knots, n_knots, degree, n_quad ? n_quad : degree + 1, scale, D)) return STFD_EINVAL;
+  *n_out = int(D.x.size());
+  if (pts) std::memcpy(pts, D.x.data(), D.x.size() * sizeof(double));
+  if (wts) std::memcpy(wts, D.w.data(), D.w.size() * sizeof(double));
+  return STFD_OK;
+}
+
+void stfd_destroy(stfd_problem* P) {
+  if (!P) return;
+  for (void* p : P->allocs) (void)hipFree(p);
+  if (P->sc_host) (void)hipHostFree(P->sc_host);
+  delete P;
+}
+
+int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
+  if (!desc || !out) return STFD_EINVAL;
+  *out = nullptr;
+  if (desc->max_nrhs < 1 || desc->d < 1 || desc->d > 3) return STFD_EINVAL;
+  stfd_setup_desc_view v;
+  v.d = desc->d;
+  v.p_t = desc->p_t;
+  v.p_s = desc->p_s;
+  v.knots_t = desc->knots_t;
+  v.n_knots_t = desc->n_knots_t;
+  for (int l = 0; l < 3; ++l) {
+    v.knots_s[l] = desc->knots_s[l];
+    v.n_knots_s[l] = desc->n_knots_s[l];
+  }
+  v.T = desc->T;
+  v.nu = desc->nu;
+  v.V_quad = desc->V_quad;
+  v.n_quad = desc->n_quad;
+  stfd_problem* P = new (std::nothrow) stfd_problem;
+  if (!P) return STFD_ENOMEM;
+  int rc = host_setup(v, P->hp);
+  if (rc == 0) {
+    const HostProblem& hp = P->hp;
+    for (int l = 0; l < hp.d; ++l)
+      if (hp.n_s[l] > kMaxModeN) rc = -1;
+    if (hp.p_t > 6) rc = -1;
+    bool mv_ok = (hp.d == 1 && hp.p_s <= 6) || (hp.d == 2 && hp.p_s <= 5) || (hp.d == 3 && hp.p_s <= 4);
+    if (!mv_ok) rc = -1;
+    if (hp.n_t > 128) rc = -1;
+  }
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  const HostProblem& hp = P->hp;
+  P->max_nrhs = desc->max_nrhs;
+  P->n2 = 2 * hp.N;
+  // pencils: forward operand U, backward operand U^T
+  for (int l = 0; l < hp.d; ++l) {
+    const int n = hp.n_s[l];
+    std::vector<double> Ut(size_t(n) * n);
+    for (int j = 0; j < n; ++j)
+      for (int a = 0; a < n; ++a) Ut[size_t(j) * n + a] = hp.U[l][size_t(a) * n + j];
+    if ((rc = upload(P, &P->U_fwd[l], hp.U[l].data(), hp.U[l].size())) ||
+        (rc = upload(P, &P->U_bwd[l], Ut.data(), Ut.size()))) {
+      stfd_destroy(P);
+      return rc;
+    }
+  }
+  {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
+      P->max_lds = size_t(lds);
+    const size_t ts_bytes = size_t(hp.n_t) * (2 * hp.p_t + 1 + 2) * sizeof(double);
+    if (ts_bytes > P->max_lds || hp.n_t > 64 * kMvMaxChunks) {
+      stfd_destroy(P);
+      return STFD_EINVAL;
+    }
+  }
+  // time-block factors in the per-block layout of time_solve_kernel, time bands, spatial coefficients
+  {
+    const int nt = hp.n_t, pt = hp.p_t;
+    const size_t per_mode = size_t(nt) * (2 * pt + 1 + 2) * sizeof(double);
+    int mpb = int(std::min<size_t>(64, P->max_lds / per_mode));
+    // the sweep is a latency-bound recurrence: spread small problems over more blocks
+    while (mpb > 16 && (hp.N_s + mpb - 1) / mpb < 512) mpb /= 2;
+    P->ts_mpb = mpb;
+    const int64_t nblk = (hp.N_s + mpb - 1) / mpb;
+    std::vector<double> Lb(size_t(nblk) * nt * pt * mpb * 2, 0.0), Db(size_t(nblk) * nt * mpb, 1.0);
+    for (int64_t i = 0; i < hp.N_s; ++i) {
+      const int64_t b = i / mpb;
+      const int m = int(i - b * mpb);
+      for (int t = 0; t < nt; ++t) {
+        Db[(size_t(b) * nt + t) * mpb + m] = hp.Dinv[size_t(t) * hp.N_s + i];
+        for (int k = 1; k <= pt; ++k) {
+          const std::complex<double> v = hp.Lfac[(size_t(t) * pt + (k - 1)) * hp.N_s + i];
+          const size_t o = (((size_t(b) * nt + t) * pt + (k - 1)) * mpb + m) * 2;
+          Lb[o] = v.real();
+          Lb[o + 1] = v.imag();
+        }
+      }
+    }
+    // spatial coefficients interleaved per row and stencil offset: [N_s][stencil][3]
+    std::vector<double> ScI(hp.Sc.size());
+    const size_t ns = size_t(hp.N_s) * hp.stencil;
+    for (size_t is = 0; is < ns; ++is)
+      for (int k = 0; k < 3; ++k) ScI[is * 3 + k] = hp.Sc[k * ns + is];
+    if ((rc = upload(P, &P->Lb, Lb.data(), Lb.size())) || (rc = upload(P, &P->Db, Db.data(), Db.size())) ||
+        (rc = upload(P, &P->Tband, hp.Tband.data(), hp.Tband.size())) ||
+        (rc = upload(P, &P->Sc, ScI.data(), ScI.size()))) {
+      stfd_destroy(P);
+      return rc;
+    }
+  }
+  const size_t nvec = size_t(P->n2) * P->max_nrhs;
+  for (int k = 0; k < 2; ++k)
+    if ((rc = dev_alloc(P, &P->work64[k], nvec)) || (rc = dev_alloc(P, &P->work32[k], nvec))) {
+      stfd_destroy(P);
+      return rc;
+    }
+  for (int k = 0; k < 5; ++k)
+    if ((rc = dev_alloc(P, &P->vec[k], nvec))) {
+      stfd_destroy(P);
+      return rc;
+    }
+  // matvec launch shape: one wave per spatial point, kMvWaves points per block
+  P->mv_blocks = (hp.N_s + kMvWaves - 1) / kMvWaves;
+  {
+    int64_t outer0 = 1;
+    for (int l = 1; l < hp.d; ++l) outer0 *= hp.n_s[l];
+    P->mp_last_blocks = mode_product_blocks_per_rhs(2 * int64_t(hp.n_t), outer0);
+  }
+  P->max_parts = std::max<int64_t>(std::max<int64_t>(P->mv_blocks, P->mp_last_blocks), kVecGrid);
+  if ((rc = dev_alloc(P, &P->parts, size_t(6) * P->max_parts * P->max_nrhs)) ||
+      (rc = dev_alloc(P, &P->sc, size_t(P->max_nrhs))) || (rc = dev_alloc(P, &P->done, size_t(P->max_nrhs)))) {
+    stfd_destroy(P);
+    return rc;
+  }
+  hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&P->sc_host), sizeof(PcgScalars) * kLag * P->max_nrhs);
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    P->sc_host = nullptr;
+    stfd_destroy(P);
+    return STFD_ENOMEM;
+  }
+  e = hipHostGetDevicePointer(reinterpret_cast<void**>(&P->sc_host_dev), P->sc_host, 0);
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    stfd_destroy(P);
+    return STFD_EHIP;
+  }
+  *out = P;
+  return STFD_OK;
+}
+
+int stfd_sizes(const stfd_problem* P, int64_t* n_t, int64_t n_s[3], int64_t* n_dof) {
+  if (!P) return STFD_EINVAL;
+  if (n_t) *n_t = P->hp.n_t;
+  if (n_s)
+    for (int l = 0; l < 3; ++l) n_s[l] = (l < P->hp.d) ? P->hp.n_s[l] : 1;
+  if (n_dof) *n_dof = P->hp.N;
+  return STFD_OK;
+}
+
+int stfd_get_pencil(const stfd_problem* P, int l, double* U, double* lambda) {
+  if (!P || l < 0 || l >= P->hp.d) return STFD_EINVAL;
+  if (U) std::memcpy(U, P->hp.U[l].data(), P->hp.U[l].size() * sizeof(double));
+  if (lambda) std::memcpy(lambda, P->hp.lam1[l].data(), P->hp.lam1[l].size() * sizeof(double));
+  return STFD_OK;
+}
+
+int stfd_apply_preconditioner(const stfd_problem* Pc, const void* r_dev, void* s_dev, int64_t nrhs, int precision,
+                              void* stream) {
+  stfd_problem* P = const_cast<stfd_problem*>(Pc);
+  if (!P || !r_dev || !s_dev || nrhs < 1 || nrhs > P->max_nrhs) return STFD_EINVAL;
+  if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
+  return apply_dispatch(P, static_cast<const double*>(r_dev), static_cast<double*>(s_dev), nrhs, precision, nullptr,
+                        static_cast<hipStream_t>(stream));
+}
+
+int stfd_matvec(const stfd_problem* Pc, const void* x_dev, void* y_dev, int64_t nrhs, void* stream) {
+  stfd_problem* P = const_cast<stfd_problem*>(Pc);
+  if (!P || !x_dev || !y_dev || nrhs < 1 || nrhs > P->max_nrhs || x_dev == y_dev) return STFD_EINVAL;
+  return matvec_dispatch(P, static_cast<const double*>(x_dev), static_cast<double*>(y_dev), nrhs, nullptr, nullptr,
+                         static_cast<hipStream_t>(stream));
+}
+
+int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64_t nrhs, double rtol, int maxit,
+                   int flags, int precision, stfd_pcg_info* info, void* stream) {
+  stfd_problem* P = const_cast<stfd_problem*>(Pc);
+  if (!P || !f_dev || !u_dev || nrhs < 1 || nrhs > P->max_nrhs || maxit < 0 || !(rtol >= 0.0)) return STFD_EINVAL;
+  if (flags != STFD_X0_ZERO && flags != STFD_X0_GIVEN) return STFD_EINVAL;
+  if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double* f = static_cast<const double*>(f_dev);
+  double* x = static_cast<double*>(u_dev);
+  double* r = P->vec[0];
+  double* z = P->vec[1];
+  double* z2 = P->vec[2];
+  double* p = P->vec[3];
+  double* q = P->vec[4];
+  const int64_t n2 = P->n2;
+  const int64_t mp = P->max_parts;
+  double* pa = P->parts;                 // <r, z_new> partials (last mode product) / scratch
+  double* pb = pa + mp * P->max_nrhs;    // <r, z_old> partials / scratch
+  double* pc = pb + mp * P->max_nrhs;    // ||r||^2 partials (pcg_update_xr)
+  double* pd = pc + mp * P->max_nrhs;    // <p, A p> partials (matvec)
+  const dim3 vgrid(kVecGrid, unsigned(nrhs)), vblock(kVecBlock);
+  const int nab = int(P->mp_last_blocks);
+  int rc;
+  // r_0 = f - A x_0 and ||f||
+  if (flags == STFD_X0_GIVEN) {
+    if ((rc = matvec_dispatch(P, x, q, nrhs, nullptr, nullptr, s))) return rc;
+    hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, f, q, r, x, n2, pa);
+    hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, r, r, nullptr, n2, pb, nullptr, nullptr);
+    hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(nrhs)), vblock, 0, s, pa, pb, kVecGrid, P->sc, P->done, rtol);
+  } else {
+    hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, f, nullptr, r, x, n2, pa);
+    hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(nrhs)), vblock, 0, s, pa, nullptr, kVecGrid, P->sc, P->done,
+                       rtol);
+  }
+  STFD_HIP(hipGetLastError());
+  // z_0 = P^{-1} r_0, p_0 = z_0, rz_0 = <r_0, z_0>
+  if ((rc = apply_dispatch(P, r, z, nrhs, precision, P->done, s))) return rc;
+  hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, r, z, nullptr, n2, pa, nullptr, P->done);
+  hipLaunchKernelGGL(pcg_first_p_kernel, vgrid, vblock, 0, s, z, p, n2, pa, kVecGrid, P->sc, P->done);
+  STFD_HIP(hipGetLastError());
+  std::vector<hipEvent_t> ev(kLag);
+  for (int k = 0; k < kLag; ++k) STFD_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
+  auto cleanup = [&]() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  };
+  // Iteration k: q = A p (+<p,q>), x/r update (+||r||^2), z_new = P^{-1} r (+<r,z_new>, <r,z_old>),
+  // end-of-iteration test and p update.  The host runs up to kLag iterations ahead of the
+  // device-side test; iterations launched after convergence see done[rhs] and return at once.
+  for (int k = 0; k < maxit; ++k) {
+    if (k >= kLag) {
+      const int slot = (k - kLag) % kLag;
+      if (hipEventSynchronize(ev[slot]) != hipSuccess) { cleanup(); return STFD_EHIP; }
+      bool all = true;
+      for (int64_t rr = 0; rr < nrhs; ++rr) all = all && P->sc_host[slot * P->max_nrhs + rr].done;
+      if (all) break;
+    }
+    const int par = k & 1;
+    const int slot = k % kLag;
+    if ((rc = matvec_dispatch(P, p, q, nrhs, pd, P->done, s))) { cleanup(); return rc; }
+    hipLaunchKernelGGL(pcg_update_xr_kernel, vgrid, vblock, 0, s, p, q, x, r, n2, pd, int(P->mv_blocks), P->sc, par,
+                       pc, P->done);
+    DotEpilogue ep;
+    ep.r = r;
+    ep.zold = z;
+    ep.part_a = pa;
+    ep.part_b = pb;
+    if ((rc = apply_dispatch(P, r, z2, nrhs, precision, P->done, s, ep))) { cleanup(); return rc; }
+    hipLaunchKernelGGL(pcg_end_iter_kernel, vgrid, vblock, 0, s, z2, p, n2, pc, kVecGrid, pa, pb, nab, P->sc, par,
+                       P->done, k, maxit, rtol, P->sc_host_dev + slot * P->max_nrhs);
+    STFD_HIP(hipGetLastError());
+    std::swap(z, z2);
+    if (hipEventRecord(ev[slot], s) != hipSuccess) { cleanup(); return STFD_EHIP; }
+  }
+  cleanup();
+  // true residual ||f - A x|| / ||f||
+  if ((rc = matvec_dispatch(P, x, q, nrhs, nullptr, nullptr, s))) return rc;
+  hipLaunchKernelGGL(resid_norm_kernel, vgrid, vblock, 0, s, f, q, n2, pa);
+  hipLaunchKernelGGL(pcg_finish_kernel, dim3(unsigned(nrhs)), vblock, 0, s, pa, kVecGrid, P->sc);
+  STFD_HIP(hipGetLastError());
+  std::vector<PcgScalars> fin(nrhs);
+  STFD_HIP(hipMemcpyAsync(fin.data(), P->sc, sizeof(PcgScalars) * nrhs, hipMemcpyDeviceToHost, s));
+  STFD_HIP(hipStreamSynchronize(s));
+  int status = STFD_OK;
+  for (int64_t rr = 0; rr < nrhs; ++rr) {
+    const PcgScalars& sc = fin[rr];
+    int st = sc.status;
+    if (!sc.done && st == STFD_OK) st = STFD_NOT_CONVERGED;  // maxit == 0 with a non-converged start
+    if (info) {
+      info[rr].iters = sc.iters;
+      info[rr].status = st;
+      info[rr].rel_res = sc.res;
+      info[rr].true_rel_res = sc.true_res;
+    }
+    if (st == STFD_EBREAKDOWN) status = STFD_EBREAKDOWN;
+    else if (st == STFD_NOT_CONVERGED && status == STFD_OK) status = STFD_NOT_CONVERGED;
+  }
+  return status;
+}
+
+int stfd_debug_mfma_layout(double* out64, float* out32, float* outbf) {
+  if (!out64 || !out32 || !outbf) return STFD_EINVAL;
+  double* d64 = nullptr;
+  float* d32 = nullptr;
+  float* dbf = nullptr;
+  STFD_HIP(hipMalloc(&d64, 256 * sizeof(double)));
+  STFD_HIP(hipMalloc(&d32, 256 * sizeof(float)));
+  STFD_HIP(hipMalloc(&dbf, 256 * sizeof(float)));
+  hipLaunchKernelGGL(mfma_layout_kernel, dim3(1), dim3(64), 0, 0, d64, d32, dbf);
+  STFD_HIP(hipGetLastError());
+  STFD_HIP(hipMemcpy(out64, d64, 256 * sizeof(double), hipMemcpyDeviceToHost));
+  STFD_HIP(hipMemcpy(out32, d32, 256 * sizeof(float), hipMemcpyDeviceToHost));
+  STFD_HIP(hipMemcpy(outbf, dbf, 256 * sizeof(float), hipMemcpyDeviceToHost));
+  (void)hipFree(d64);
+  (void)hipFree(d32);
+  (void)hipFree(dbf);
+  return STFD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,208 @@
+"""Thin ctypes binding of libstfd.so (include/stfd.h): argument marshalling only.
+
+Device vectors are torch.complex128 CUDA tensors (interleaved re/im doubles,
+time index fastest, right-hand sides stacked slowest); streams are torch
+streams.  Every computation happens in the library's HIP kernels; if the
+library is missing this module raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstfd.so")
+
+OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EHIP = 0, 1, -1, -2, -3, -4, -5
+FP64, FP32, BF16 = 0, 1, 2
+X0_ZERO, X0_GIVEN = 0, 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+
+
+class SetupDesc(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("p_t", ctypes.c_int), ("p_s", ctypes.c_int),
+                ("knots_t", ctypes.POINTER(ctypes.c_double)), ("n_knots_t", ctypes.c_int),
+                ("knots_s", ctypes.POINTER(ctypes.c_double) * 3), ("n_knots_s", ctypes.c_int * 3),
+                ("T", ctypes.c_double), ("nu", ctypes.c_double),
+                ("V_quad", ctypes.POINTER(ctypes.c_double)), ("n_quad", ctypes.c_int),
+                ("max_nrhs", ctypes.c_int)]
+
+
+class PcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res", ctypes.c_double),
+                ("true_rel_res", ctypes.c_double)]
+
+
+class StfdError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = _lib().stfd_strerror(code).decode()
+        if code == EHIP:
+            msg += f" (hip error {_lib().stfd_last_hip_error()})"
+        super().__init__(f"{where}: {msg} [{code}]")
+
+
+_LIB = None
+
+# exported symbols and their signatures (mirrors include/stfd.h)
+_VP, _DP, _IP, _I64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_int64
+SIGNATURES = {
+    "stfd_quad_points": (ctypes.c_int, [_DP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _DP, _DP, _IP]),
+    "stfd_setup": (ctypes.c_int, [ctypes.POINTER(SetupDesc), ctypes.POINTER(_VP)]),
+    "stfd_sizes": (ctypes.c_int, [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    "stfd_apply_preconditioner": (ctypes.c_int, [_VP, _VP, _VP, _I64, ctypes.c_int, _VP]),
+    "stfd_matvec": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP]),
+    "stfd_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _I64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, ctypes.POINTER(PcgInfo), _VP]),
+    "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
+    "stfd_destroy": (None, [_VP]),
+    "stfd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "stfd_last_hip_error": (ctypes.c_int, []),
+    "stfd_debug_mfma_layout": (ctypes.c_int, [_DP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+}
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_18461_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(code, where, allow=(OK,)):
+    if code not in allow:
+        raise StfdError(code, where)
+    return code
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+def quad_points(knots, degree: int, n_quad: int = 0, scale: float = 1.0):
+    """Element-wise Gauss points/weights of the library on an open knot vector (scaled)."""
+    kn = np.ascontiguousarray(knots, dtype=np.float64)
+    n = ctypes.c_int(0)
+    _check(_lib().stfd_quad_points(_dptr(kn), len(kn), degree, n_quad, scale, None, None, ctypes.byref(n)),
+           "stfd_quad_points")
+    pts, wts = np.empty(n.value), np.empty(n.value)
+    _check(_lib().stfd_quad_points(_dptr(kn), len(kn), degree, n_quad, scale, _dptr(pts), _dptr(wts),
+                                   ctypes.byref(n)), "stfd_quad_points")
+    return pts, wts
+
+
+def sample_on_quad_grid(fn, knots_s, p_s: int, n_quad: int = 0) -> np.ndarray:
+    """fn(x_1, ..., x_d) on the library's spatial tensor Gauss grid, flattened x_1 fastest."""
+    pts = [quad_points(k, p_s, n_quad)[0] for k in knots_s]
+    grids = np.meshgrid(*reversed(pts), indexing="ij")
+    vals = np.asarray(fn(*reversed(grids)), dtype=np.float64)
+    return np.ascontiguousarray(vals.ravel())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, n_expected, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous complex128 CUDA tensor")
+    if t.numel() != n_expected:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n_expected}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """Handle of one set-up problem (stfd_setup / stfd_destroy)."""
+
+    def __init__(self, knots_t, knots_s, p_t: int, p_s: int, T: float = 1.0, nu: float = 1.0,
+                 V_quad=None, n_quad: int = 0, max_nrhs: int = 1):
+        d = len(knots_s)
+        self._keep = [np.ascontiguousarray(knots_t, dtype=np.float64)]
+        desc = SetupDesc()
+        desc.d, desc.p_t, desc.p_s = d, p_t, p_s
+        desc.knots_t, desc.n_knots_t = _dptr(self._keep[0]), len(self._keep[0])
+        for l in range(3):
+            if l < d:
+                k = np.ascontiguousarray(knots_s[l], dtype=np.float64)
+                self._keep.append(k)
+                desc.knots_s[l], desc.n_knots_s[l] = _dptr(k), len(k)
+            else:
+                desc.knots_s[l], desc.n_knots_s[l] = None, 0
+        desc.T, desc.nu = T, nu
+        if V_quad is not None:
+            v = np.ascontiguousarray(V_quad, dtype=np.float64)
+            self._keep.append(v)
+            desc.V_quad = _dptr(v)
+        else:
+            desc.V_quad = None
+        desc.n_quad, desc.max_nrhs = n_quad, max_nrhs
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(_lib().stfd_setup(ctypes.byref(desc), ctypes.byref(h)), "stfd_setup")
+        self._h = h
+        nt, ns, nd = ctypes.c_int64(), (ctypes.c_int64 * 3)(), ctypes.c_int64()
+        _check(_lib().stfd_sizes(self._h, ctypes.byref(nt), ns, ctypes.byref(nd)), "stfd_sizes")
+        self.d, self.n_t, self.n_s, self.N = d, nt.value, [ns[i] for i in range(d)], nd.value
+        self.N_s = self.N // self.n_t
+        self.max_nrhs = max_nrhs
+
+    def close(self):
+        if self._h is not None and _LIB is not None:
+            _LIB.stfd_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_pencil(self, l: int):
+        n = self.n_s[l]
+        U, lam = np.empty((n, n)), np.empty(n)
+        _check(_lib().stfd_get_pencil(self._h, l, _dptr(U), _dptr(lam)), "stfd_get_pencil")
+        return U, lam
+
+    def apply_preconditioner(self, r, s, nrhs: int = 1, precision=FP64, stream=None):
+        precision = PRECISIONS.get(precision, precision)
+        return _check(_lib().stfd_apply_preconditioner(self._h, _dev_ptr(r, self.N * nrhs, "r"),
+                                                       _dev_ptr(s, self.N * nrhs, "s"), nrhs, precision,
+                                                       _stream_ptr(stream)), "stfd_apply_preconditioner")
+
+    def matvec(self, x, y, nrhs: int = 1, stream=None):
+        return _check(_lib().stfd_matvec(self._h, _dev_ptr(x, self.N * nrhs, "x"), _dev_ptr(y, self.N * nrhs, "y"),
+                                         nrhs, _stream_ptr(stream)), "stfd_matvec")
+
+    def pcg_solve(self, f, u, nrhs: int = 1, rtol: float = 1e-8, maxit: int = 200, x0_given: bool = False,
+                  precision=FP64, stream=None, check=True):
+        precision = PRECISIONS.get(precision, precision)
+        info = (PcgInfo * nrhs)()
+        rc = _lib().stfd_pcg_solve(self._h, _dev_ptr(f, self.N * nrhs, "f"), _dev_ptr(u, self.N * nrhs, "u"),
+                                   nrhs, rtol, maxit, X0_GIVEN if x0_given else X0_ZERO, precision, info,
+                                   _stream_ptr(stream))
+        if check:
+            _check(rc, "stfd_pcg_solve", allow=(OK, NOT_CONVERGED))
+        return rc, [dict(iters=i.iters, status=i.status, rel_res=i.rel_res, true_rel_res=i.true_rel_res)
+                    for i in info]
+
+
+def debug_mfma_layout():
+    o64 = np.empty(256)
+    o32 = np.empty(256, dtype=np.float32)
+    obf = np.empty(256, dtype=np.float32)
+    _check(_lib().stfd_debug_mfma_layout(_dptr(o64), o32.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         obf.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+           "stfd_debug_mfma_layout")
+    return o64, o32, obf

@@ -1,0 +1,102 @@
+"""Host-only checks of the C ABI library: it loads, exports every declared
+symbol, its Gauss rule matches the oracle's, and invalid setups are rejected
+before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.bspline import gauss_rule
+from paper_2311_18461_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2311_18461_amd import stfd
+    return stfd
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "stfd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(stfd_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    stfd = _lib()
+    lib = stfd._lib()
+    names = _declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+        assert name in stfd.SIGNATURES, name
+
+
+def test_strerror():
+    stfd = _lib()
+    assert stfd._lib().stfd_strerror(stfd.EINVAL) == b"invalid argument"
+    assert stfd._lib().stfd_strerror(1234) == b"unknown status"
+
+
+@pytest.mark.parametrize("n_el,p,q,scale", [(5, 2, 0, 1.0), (7, 3, 0, 2.0), (4, 4, 6, 1.0)])
+def test_quad_points_match_oracle(n_el, p, q, scale):
+    stfd = _lib()
+    kn = inputs.uniform_open_knots(n_el, p)
+    pts, wts = stfd.quad_points(kn, p, q, scale)
+    x, w, _ = gauss_rule(kn * scale, q or p + 1)
+    np.testing.assert_allclose(pts, x, atol=1e-15 * scale)
+    np.testing.assert_allclose(wts, w, rtol=1e-13)
+
+
+def test_quad_points_graded_and_repeated():
+    stfd = _lib()
+    kn = np.array([0, 0, 0, 0.2, 0.5, 0.5, 0.8, 1, 1, 1.0])
+    pts, wts = stfd.quad_points(kn, 2)
+    x, w, _ = gauss_rule(kn, 3)
+    np.testing.assert_allclose(pts, x, atol=1e-15)
+    np.testing.assert_allclose(wts, w, rtol=1e-13)
+
+
+BAD = {
+    "p_s < 2": dict(p_s=1),
+    "p_t < 1": dict(p_t=0),
+    "nu <= 0": dict(nu=0.0),
+    "T <= 0": dict(T=-1.0),
+    "non-open knots": dict(knots_s=[np.array([0, 0, 0.1, 0.5, 1, 1, 1.0])]),
+    "decreasing knots": dict(knots_s=[np.array([0, 0, 0, 0.6, 0.4, 1, 1, 1.0])]),
+    "space not C1": dict(knots_s=[np.array([0, 0, 0, 0.5, 0.5, 1, 1, 1.0])]),
+    "time not C0": dict(knots_t=np.array([0, 0, 0, 0.5, 0.5, 0.5, 1, 1, 1.0])),
+    "knots outside [0,1]": dict(knots_t=np.array([0, 0, 0, 0.5, 1.5, 1.5, 1.5])),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BAD))
+def test_setup_rejects_invalid(case):
+    stfd = _lib()
+    args = dict(knots_t=inputs.uniform_open_knots(3, 2), knots_s=[inputs.uniform_open_knots(3, 2)],
+                p_t=2, p_s=2, T=1.0, nu=1.0)
+    args.update(BAD[case])
+    with pytest.raises(stfd.StfdError) as ei:
+        stfd.Problem(args["knots_t"], args["knots_s"], args["p_t"], args["p_s"], args["T"], args["nu"])
+    assert ei.value.code == stfd.EINVAL
+
+
+def test_setup_rejects_bad_d_and_nrhs():
+    stfd = _lib()
+    kn = inputs.uniform_open_knots(3, 2)
+    with pytest.raises(stfd.StfdError):
+        stfd.Problem(kn, [kn] * 4, 2, 2)
+    with pytest.raises(stfd.StfdError):
+        stfd.Problem(kn, [kn], 2, 2, max_nrhs=0)
+
+
+def test_setup_rejects_direction_above_mode_product_limit():
+    """The MFMA mode product keeps one 16-column block of U_l per wave for n_l <= 128."""
+    stfd = _lib()
+    kn = inputs.uniform_open_knots(130, 2)
+    with pytest.raises(stfd.StfdError) as ei:
+        stfd.Problem(inputs.uniform_open_knots(4, 2), [kn], 2, 2)
+    assert ei.value.code == stfd.EINVAL
