@@ -24,6 +24,22 @@
 
 namespace stfd {
 
+#ifdef STFD_PHASE_TIMING
+__device__ unsigned long long g_phase[4096][8];
+__device__ unsigned long long g_cycles[4096][8];
+#define STFD_STAMP(slot, k)                                                           \
+  do {                                                                                \
+    if (threadIdx.x == 0 && blockIdx.x < 4096) {                                      \
+      g_phase[blockIdx.x][k] = __builtin_amdgcn_s_memrealtime();                      \
+      g_cycles[blockIdx.x][k] = __builtin_amdgcn_s_memtime();                         \
+    }                                                                                 \
+  } while (0)
+#else
+#define STFD_STAMP(slot, k) \
+  do {                      \
+  } while (0)
+#endif
+
 static thread_local int g_last_hip_error = 0;
 
 #define STFD_HIP(expr)                          \
@@ -130,6 +146,7 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   op_t* tile = reinterpret_cast<op_t*>(smem_raw);
 
+  STFD_STAMP(0, 0);
   const int n = a.n;
   const int kpad = (n + K - 1) / K * K;
   const int nks = kpad / K;
@@ -142,6 +159,21 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
   const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
   Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
 
+  STFD_STAMP(0, 1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int a0 = wave * 16;
+  const int col = lane & 15, grp = lane >> 4;
+  // this wave's operand fragments of U'^T: element (m = col, k = K/4*grp + e) of each K step
+  op_t ua[KSTEPS_MAX][K / 4];
+#pragma unroll
+  for (int ks = 0; ks < KSTEPS_MAX; ++ks)
+#pragma unroll
+    for (int e = 0; e < K / 4; ++e) {
+      const int j = ks * K + (K / 4) * grp + e;
+      const int aa = a0 + col;
+      const double v = a.U[min(j, n - 1) * n + min(aa, n - 1)];
+      ua[ks][e] = to_op<PREC>((ks < nks && j < n && aa < n) ? v : 0.0);
+    }
   // stage the input tile tile[j*RT + r] = In[o][j][row0 + r]: batches of loads from clamped
   // (always in-bounds) addresses are issued before any is consumed; padding is zeroed after
   constexpr int kBatch = 8;
@@ -161,22 +193,8 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
       if (idx < ntile) tile[idx] = (j < n && r < rows_here) ? to_op<PREC>(v[u]) : op_t(0);
     }
   }
-
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int a0 = wave * 16;
-  const int col = lane & 15, grp = lane >> 4;
-  // this wave's operand fragments of U'^T: element (m = col, k = K/4*grp + e) of each K step
-  op_t ua[KSTEPS_MAX][K / 4];
-#pragma unroll
-  for (int ks = 0; ks < KSTEPS_MAX; ++ks)
-#pragma unroll
-    for (int e = 0; e < K / 4; ++e) {
-      const int j = ks * K + (K / 4) * grp + e;
-      const int aa = a0 + col;
-      const double v = a.U[min(j, n - 1) * n + min(aa, n - 1)];
-      ua[ks][e] = to_op<PREC>((ks < nks && j < n && aa < n) ? v : 0.0);
-    }
   __syncthreads();
+  STFD_STAMP(0, 2);
 
   double dot_a = 0.0, dot_b = 0.0;
   for (int r0 = 0; r0 < RT; r0 += 16) {
@@ -184,21 +202,21 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
 #pragma unroll
     for (int ks = 0; ks < KSTEPS_MAX; ++ks) {
       if (ks < nks) {
-      if constexpr (PREC == MP_F64) {
-        const double b = tile[(ks * K + grp) * RT + r0 + col];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b, acc, 0, 0, 0);
-      } else if constexpr (PREC == MP_F32) {
-        const float b = tile[(ks * K + grp) * RT + r0 + col];
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[ks][0], b, acc, 0, 0, 0);
-      } else {
-        s4_t av, bv;
+        if constexpr (PREC == MP_F64) {
+          const double b = tile[(ks * K + grp) * RT + r0 + col];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b, acc, 0, 0, 0);
+        } else if constexpr (PREC == MP_F32) {
+          const float b = tile[(ks * K + grp) * RT + r0 + col];
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[ks][0], b, acc, 0, 0, 0);
+        } else {
+          s4_t av, bv;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          av[e] = ua[ks][e];
-          bv[e] = tile[(ks * K + 4 * grp + e) * RT + r0 + col];
+          for (int e = 0; e < 4; ++e) {
+            av[e] = ua[ks][e];
+            bv[e] = tile[(ks * K + 4 * grp + e) * RT + r0 + col];
+          }
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-      }
       }
     }
     const int r = r0 + col;
@@ -219,6 +237,7 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
       }
     }
   }
+  STFD_STAMP(0, 3);
   if (a.part_a) {
     __shared__ double red[2][8];
     dot_a = wave_sum(dot_a);
@@ -274,6 +293,7 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
   const int nm = int(min<int64_t>(mpb, N_s - i0));
   T* base = y + (rhs * N_s + i0) * int64_t(2 * n_t);
   const int tid = threadIdx.x;
+  STFD_STAMP(0, 4);
   // factors of this block: one contiguous chunk
   {
     const int nl = n_t * P * mpb * 2, nd = n_t * mpb;
@@ -313,6 +333,7 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
     }
   }
   __syncthreads();
+  STFD_STAMP(0, 5);
   if (tid < nm) {
     const int m = tid;
     auto Lre = [&](int t, int k) { return Ls[((t * P + k - 1) * mpb + m) * 2]; };
@@ -320,6 +341,8 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
     double hr[P], hi[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
+    // forward: z_t = y_t - sum_k L[t][t-k] z_{t-k} (z_{t-1} term last), w_t = z_t / D_t,
+    // four steps of operands read from LDS at a time
     int t = 0;
     for (; t + 4 <= n_t; t += 4) {
       double yr4[4], yi4[4], d4[4], l4[4][P][2];
@@ -338,10 +361,16 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
       for (int u = 0; u < 4; ++u) {
         double zr = yr4[u], zi = yi4[u];
 #pragma unroll
-        for (int k = P; k >= 1; --k) {
-          zr -= l4[u][k - 1][0] * hr[k - 1] - l4[u][k - 1][1] * hi[k - 1];
-          zi -= l4[u][k - 1][0] * hi[k - 1] + l4[u][k - 1][1] * hr[k - 1];
+        for (int k = P; k >= 2; --k) {
+          zr = fma(-l4[u][k - 1][0], hr[k - 1], zr);
+          zr = fma(l4[u][k - 1][1], hi[k - 1], zr);
+          zi = fma(-l4[u][k - 1][0], hi[k - 1], zi);
+          zi = fma(-l4[u][k - 1][1], hr[k - 1], zi);
         }
+        zr = fma(-l4[u][0][0], hr[0], zr);
+        zi = fma(-l4[u][0][0], hi[0], zi);
+        zr = fma(l4[u][0][1], hi[0], zr);
+        zi = fma(-l4[u][0][1], hr[0], zi);
 #pragma unroll
         for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
         hr[0] = zr;
@@ -354,8 +383,10 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
       double zr = ys[(t * mpb + m) * 2], zi = ys[(t * mpb + m) * 2 + 1];
 #pragma unroll
       for (int k = P; k >= 1; --k) {
-        zr -= Lre(t, k) * hr[k - 1] - Lim(t, k) * hi[k - 1];
-        zi -= Lre(t, k) * hi[k - 1] + Lim(t, k) * hr[k - 1];
+        zr = fma(-Lre(t, k), hr[k - 1], zr);
+        zr = fma(Lim(t, k), hi[k - 1], zr);
+        zi = fma(-Lre(t, k), hi[k - 1], zi);
+        zi = fma(-Lim(t, k), hr[k - 1], zi);
       }
 #pragma unroll
       for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
@@ -365,6 +396,7 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
       ys[(t * mpb + m) * 2] = zr * dv;
       ys[(t * mpb + m) * 2 + 1] = zi * dv;
     }
+    // backward: x_t = w_t - sum_k conj(L[t+k][t]) x_{t+k} (x_{t+1} term last)
 #pragma unroll
     for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
     t = n_t - 1;
@@ -387,10 +419,16 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
       for (int u = 0; u < 4; ++u) {
         double xr = wr4[u], xi = wi4[u];
 #pragma unroll
-        for (int k = P; k >= 1; --k) {
-          xr -= l4[u][k - 1][0] * hr[k - 1] + l4[u][k - 1][1] * hi[k - 1];
-          xi -= l4[u][k - 1][0] * hi[k - 1] - l4[u][k - 1][1] * hr[k - 1];
+        for (int k = P; k >= 2; --k) {
+          xr = fma(-l4[u][k - 1][0], hr[k - 1], xr);
+          xr = fma(-l4[u][k - 1][1], hi[k - 1], xr);
+          xi = fma(-l4[u][k - 1][0], hi[k - 1], xi);
+          xi = fma(l4[u][k - 1][1], hr[k - 1], xi);
         }
+        xr = fma(-l4[u][0][0], hr[0], xr);
+        xi = fma(-l4[u][0][0], hi[0], xi);
+        xr = fma(-l4[u][0][1], hi[0], xr);
+        xi = fma(l4[u][0][1], hr[0], xi);
 #pragma unroll
         for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
         hr[0] = xr;
@@ -404,8 +442,10 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
 #pragma unroll
       for (int k = P; k >= 1; --k) {
         if (t + k < n_t) {
-          xr -= Lre(t + k, k) * hr[k - 1] + Lim(t + k, k) * hi[k - 1];
-          xi -= Lre(t + k, k) * hi[k - 1] - Lim(t + k, k) * hr[k - 1];
+          xr = fma(-Lre(t + k, k), hr[k - 1], xr);
+          xr = fma(-Lim(t + k, k), hi[k - 1], xr);
+          xi = fma(-Lre(t + k, k), hi[k - 1], xi);
+          xi = fma(Lim(t + k, k), hr[k - 1], xi);
         }
       }
 #pragma unroll
@@ -417,6 +457,7 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
     }
   }
   __syncthreads();
+  STFD_STAMP(0, 6);
   // write back [t][m] -> global [m][t]
   for (int b0 = 0; b0 < ny; b0 += kTsThreads) {
     const int idx = b0 + tid;
@@ -425,6 +466,7 @@ __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const doub
       base[idx] = T(ys[((rem >> 1) * mpb + m) * 2 + (rem & 1)]);
     }
   }
+  STFD_STAMP(0, 7);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,6 +519,7 @@ __global__ __launch_bounds__(64 * kMvWaves) void matvec_kernel(MatvecArgs a) {
   const int wt = 2 * a.pt + 1;
   double* Tb = reinterpret_cast<double*>(smem_raw);                    // [3][n_t][wt]
   double* Zw = Tb + size_t(3) * n_t * wt + size_t(wv) * 6 * n_t;        // [3][n_t][2] per wave
+  STFD_STAMP(0, 0);
   for (int idx = threadIdx.x; idx < 3 * n_t * wt; idx += 64 * kMvWaves) Tb[idx] = a.Tband[idx];
   const double* X = a.x + rhs * a.N_s * int64_t(2 * n_t);
   constexpr int W = 2 * PS + 1;
@@ -500,39 +543,45 @@ __global__ __launch_bounds__(64 * kMvWaves) void matvec_kernel(MatvecArgs a) {
       tv[c] = c * 64 + lane < n_t;
       tl[c] = min(c * 64 + lane, n_t - 1);
     }
-    for (int o3 = (D >= 3 ? -PS : 0); o3 <= (D >= 3 ? PS : 0); ++o3) {
-      const int j3 = i3 + o3;
-      if (D >= 3 && (j3 < 0 || j3 >= a.n3)) continue;
-      for (int o2 = (D >= 2 ? -PS : 0); o2 <= (D >= 2 ? PS : 0); ++o2) {
-        const int j2 = i2 + o2;
-        if (D >= 2 && (j2 < 0 || j2 >= a.n2)) continue;
-        const int sbase = (D >= 3 ? (o3 + PS) * W * W : 0) + (D >= 2 ? (o2 + PS) * W : 0);
-        const double* Xrow = X + (int64_t(a.n1) * (j2 + int64_t(a.n2) * j3)) * (2 * n_t);
-        // one row of W neighbours: issue every load first (clamped column), then accumulate;
-        // out-of-range neighbours get zero coefficients
-        double xr[W][NCH], xi[W][NCH];
+    // Stencil rows r = (o3, o2) flattened (x_2 offset fastest).  Rows outside the grid are
+    // clamped (loads stay in bounds) and their coefficients zeroed.
+    constexpr int NROWS = (D == 1 ? 1 : (D == 2 ? W : W * W));
+    auto row_ptr = [&](int r, bool& ok) {
+      const int o2 = (D >= 2) ? r % W - PS : 0;
+      const int o3 = (D >= 3) ? r / W - PS : 0;
+      const int j2 = i2 + o2, j3 = i3 + o3;
+      ok = (D < 2 || (j2 >= 0 && j2 < a.n2)) && (D < 3 || (j3 >= 0 && j3 < a.n3));
+      const int c2 = (D >= 2) ? min(max(j2, 0), a.n2 - 1) : 0;
+      const int c3 = (D >= 3) ? min(max(j3, 0), a.n3 - 1) : 0;
+      return X + (int64_t(a.n1) * (c2 + int64_t(a.n2) * c3)) * (2 * n_t);
+    };
+    // one row of W neighbours at a time: all of its loads are issued before any is used
+#pragma unroll 1
+    for (int r = 0; r < NROWS; ++r) {
+      bool row_ok;
+      const double* Xrow = row_ptr(r, row_ok);
+      double xr[W][NCH], xi[W][NCH];
 #pragma unroll
-        for (int o1 = 0; o1 < W; ++o1) {
-          const int j1 = min(max(i1 + o1 - PS, 0), a.n1 - 1);
+      for (int o1 = 0; o1 < W; ++o1) {
+        const int j1 = min(max(i1 + o1 - PS, 0), a.n1 - 1);
 #pragma unroll
-          for (int c = 0; c < NCH; ++c) {
-            const double* q = Xrow + (int64_t(j1) * n_t + tl[c]) * 2;
-            xr[o1][c] = q[0];
-            xi[o1][c] = q[1];
-          }
+        for (int c = 0; c < NCH; ++c) {
+          const double* q = Xrow + (int64_t(j1) * n_t + tl[c]) * 2;
+          xr[o1][c] = q[0];
+          xi[o1][c] = q[1];
         }
+      }
 #pragma unroll
-        for (int o1 = 0; o1 < W; ++o1) {
-          const bool ok = (i1 + o1 - PS >= 0) && (i1 + o1 - PS < a.n1);
-          const int s = sbase + o1;
-          const double c0 = ok ? C[3 * s] : 0.0, c1 = ok ? C[3 * s + 1] : 0.0, c2 = ok ? C[3 * s + 2] : 0.0;
+      for (int o1 = 0; o1 < W; ++o1) {
+        const bool ok = row_ok && (i1 + o1 - PS >= 0) && (i1 + o1 - PS < a.n1);
+        const int s = r * W + o1;
+        const double c0 = ok ? C[3 * s] : 0.0, c1 = ok ? C[3 * s + 1] : 0.0, c2 = ok ? C[3 * s + 2] : 0.0;
 #pragma unroll
-          for (int c = 0; c < NCH; ++c) {
-            const double vr = ok ? xr[o1][c] : 0.0, vi = ok ? xi[o1][c] : 0.0;
-            z[c][0] += c0 * vr; z[c][1] += c0 * vi;
-            z[c][2] += c1 * vr; z[c][3] += c1 * vi;
-            z[c][4] += c2 * vr; z[c][5] += c2 * vi;
-          }
+        for (int c = 0; c < NCH; ++c) {
+          const double vr = ok ? xr[o1][c] : 0.0, vi = ok ? xi[o1][c] : 0.0;
+          z[c][0] = fma(c0, vr, z[c][0]); z[c][1] = fma(c0, vi, z[c][1]);
+          z[c][2] = fma(c1, vr, z[c][2]); z[c][3] = fma(c1, vi, z[c][3]);
+          z[c][4] = fma(c2, vr, z[c][4]); z[c][5] = fma(c2, vi, z[c][5]);
         }
       }
     }
@@ -549,6 +598,7 @@ __global__ __launch_bounds__(64 * kMvWaves) void matvec_kernel(MatvecArgs a) {
     }
   }
   __syncthreads();
+  STFD_STAMP(0, 1);
   double part = 0.0;
   if (active) {
     for (int c = 0; c < nch; ++c) {
@@ -570,6 +620,7 @@ __global__ __launch_bounds__(64 * kMvWaves) void matvec_kernel(MatvecArgs a) {
       if (a.partial) part += a.x[2 * g] * yr + a.x[2 * g + 1] * yi;  // Re(conj(x) y)
     }
   }
+  STFD_STAMP(0, 2);
   if (a.partial) {
     part = wave_sum(part);
     if (lane == 0) red[wv] = part;
@@ -1325,7 +1376,11 @@ int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64
     }
     const int par = k & 1;
     const int slot = k % kLag;
-    if ((rc = matvec_dispatch(P, p, q, nrhs, pd, P->done, s))) { cleanup(); return rc; }
+    // With one right-hand side the matvec and apply kernels skip the done-flag test: the few
+    // iterations launched after convergence only overwrite q and z2, while x, r and p are
+    // guarded by the flag in pcg_update_xr / pcg_end_iter.
+    const int* dflag = nrhs > 1 ? P->done : nullptr;
+    if ((rc = matvec_dispatch(P, p, q, nrhs, pd, dflag, s))) { cleanup(); return rc; }
     hipLaunchKernelGGL(pcg_update_xr_kernel, vgrid, vblock, 0, s, p, q, x, r, n2, pd, int(P->mv_blocks), P->sc, par,
                        pc, P->done);
     DotEpilogue ep;
@@ -1333,7 +1388,7 @@ int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64
     ep.zold = z;
     ep.part_a = pa;
     ep.part_b = pb;
-    if ((rc = apply_dispatch(P, r, z2, nrhs, precision, P->done, s, ep))) { cleanup(); return rc; }
+    if ((rc = apply_dispatch(P, r, z2, nrhs, precision, dflag, s, ep))) { cleanup(); return rc; }
     hipLaunchKernelGGL(pcg_end_iter_kernel, vgrid, vblock, 0, s, z2, p, n2, pc, kVecGrid, pa, pb, nab, P->sc, par,
                        P->done, k, maxit, rtol, P->sc_host_dev + slot * P->max_nrhs);
     STFD_HIP(hipGetLastError());
@@ -1365,6 +1420,15 @@ int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64
   }
   return status;
 }
+
+#ifdef STFD_PHASE_TIMING
+int stfd_debug_phase_times(unsigned long long* out) {
+  STFD_HIP(hipDeviceSynchronize());
+  STFD_HIP(hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase), sizeof(g_phase)));
+  STFD_HIP(hipMemcpyFromSymbol(out + 4096 * 8, HIP_SYMBOL(g_cycles), sizeof(g_cycles)));
+  return STFD_OK;
+}
+#endif
 
 int stfd_debug_mfma_layout(double* out64, float* out32, float* outbf) {
   if (!out64 || !out32 || !outbf) return STFD_EINVAL;

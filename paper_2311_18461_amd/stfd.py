@@ -67,6 +67,12 @@ SIGNATURES = {
 def _lib():
     global _LIB
     if _LIB is None:
+        # Load torch first so that the library binds to the HIP runtime torch already
+        # loaded; two runtimes in one process do not see the same devices.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_18461_amd.build`")
         lib = ctypes.CDLL(LIB_PATH)
