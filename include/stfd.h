@@ -119,6 +119,40 @@ int stfd_setup(const stfd_setup_desc *desc, stfd_problem **out);
 /* Sizes: n_t, n_s[0..2] (unused directions = 1), N = n_t * prod n_s. */
 int stfd_sizes(const stfd_problem *P, int64_t *n_t, int64_t n_s[3], int64_t *n_dof);
 
+/* Right-hand side of the free system with lifting (Section 2.2: u = u_bar +
+ * u_bar_0, f_bar = f - S u_bar_0; Section 4.3: load vector f_i = (f, S B_i);
+ * here with S_V = S + V):
+ *   f_bar_I = integral over (0,T) x Omega of (f - S_V u_bar) conj(S_V B_I),
+ * evaluated with the element Gauss rule of the setup (n_quad points per element
+ * and direction) by sum factorisation on the device.  u_bar is the joint L2
+ * projection of the data onto the B-splines that do not vanish on
+ * Gamma = {t = 0} x Omega U (0,T) x boundary(Omega), i.e. the initial face and the
+ * lateral faces together (the paper leaves the lifting open); its normal
+ * equations are solved on the device by CG, preconditioned face by face with
+ * the inverse Kronecker mass matrices, to a relative residual of 1e-14.
+ * Grids are the element-wise Gauss points of stfd_quad_points per direction
+ * (Q_t points in time, Q_l in x_l).  All samples are complex FP64, interleaved,
+ * in device memory, nrhs stacked:
+ *   f_q_dev          f on the space-time grid, index q_t + Q_t (q_1 + Q_1 (q_2 + Q_2 q_3));
+ *                    NULL: f = 0.
+ *   u0_q_dev         u(0, x) on the spatial grid (x_1 fastest); NULL: u0 = 0.
+ *   dirichlet_q_dev  host array of 2d device pointers, face x_l = 0 at [2l] and
+ *                    x_l = 1 at [2l+1], each the Dirichlet data on the face grid
+ *                    (time fastest, then x_k for k != l ascending).  NULL array or
+ *                    NULL entry: zero data.
+ *   fbar_dev         nrhs free vectors of N complex (output).
+ *   lift             host or NULL: nrhs full coefficient tensors of u_bar,
+ *                    m_t m_1 ... m_d complex (m_t = n_t + 1, m_l = n_l + 2, time
+ *                    fastest), zero at free positions (output).
+ * The call allocates and frees device scratch (about 16 (prod_a Q_a + 4 m_t
+ * prod_l max(m_l, Q_l)) bytes) and returns after the device work has finished;
+ * the lifting solve synchronises the stream every few iterations.
+ * Errors: STFD_EINVAL (NULL handle or output, nrhs < 1), STFD_ENOTSPD (breakdown
+ * of the lifting solve), STFD_ENOMEM, STFD_EHIP. */
+int stfd_load_vector(const stfd_problem *P, const void *f_q_dev, const void *u0_q_dev,
+                     const void *const *dirichlet_q_dev, void *fbar_dev, double *lift, int64_t nrhs,
+                     void *stream);
+
 /* s = P-hat^{-1} r by fast diagonalisation (Algorithm 1 steps 2-4,
  * eq. preconditioner_str2): mode products with U_l^T, N_s independent banded
  * time solves with H_i, mode products with U_l.  r_dev, s_dev: nrhs stacked

@@ -361,6 +361,7 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
   // time (Section 3.2: drop the first function; eq. time_mat)
   Gram1D gt;
   gram_1d(hp.dir_t, gt);
+  hp.Mfull_t = gt.M;
   const int mt = gt.m, nt = mt - 1;
   hp.n_t = nt;
   hp.Mt.assign(size_t(nt) * nt, 0.0);
@@ -378,6 +379,7 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
   for (int l = 0; l < v.d; ++l) {
     Gram1D g;
     gram_1d(hp.dir_s[l], g);
+    hp.Mfull_s[l] = g.M;
     const int m = g.m, n = m - 2;
     if (n < 1) return -1;
     hp.n_s[l] = n;
@@ -513,6 +515,9 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
     }
   }
   if (v.V_quad) {
+    size_t nqv = 1;
+    for (int l = 0; l < v.d; ++l) nqv *= hp.dir_s[l].x.size();
+    hp.Vq.assign(v.V_quad, v.V_quad + nqv);
     const size_t ns = size_t(hp.N_s) * stencil;
     std::vector<double> MV(ns, 0.0), MV2(ns, 0.0), KV(ns, 0.0);
     size_t nq = 1;

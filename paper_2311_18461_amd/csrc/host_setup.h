@@ -50,6 +50,10 @@ struct HostProblem {
   // spatial stencils S_k[i][s], s = sum_l (o_l + p_s) (2p_s+1)^l, k = 0..2
   int stencil = 0;  // (2 p_s + 1)^d
   std::vector<double> Sc;  // 3 * N_s * stencil
+  // potential at the spatial Gauss grid (x_1 fastest), empty for V = 0
+  std::vector<double> Vq;
+  // full (unreduced) 1D mass matrices, for the lifting of initial and boundary data
+  std::vector<double> Mfull_t, Mfull_s[3];
 };
 
 // Returns 0 or a negative stfd_status.

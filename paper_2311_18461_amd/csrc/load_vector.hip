@@ -1,0 +1,844 @@
+// Lifting and load vector on the device (Sections 2.2 and 4.3).
+//
+// With u = u_free + u_bar (u_bar the lifting of the initial and Dirichlet
+// data), the free coefficients solve A u_free = f_bar with
+//   f_bar_I = integral over (0,T) x Omega of (f - S_V u_bar) conj(S_V B_I),
+// S_V = i d_t - nu Lap + V.  The B-splines are real, so
+//   conj(S_V B_I) = -i b_t' phi - nu b_t Lap phi + V b_t phi.
+// Everything is sum-factorised on the tensor Gauss grid:
+//   evaluation  A0 = (B_1^T (x) ... (x) B_d^T) G,  A2 = sum_l (... B_l''^T ...) G  (space first)
+//               R  = f - i B_t'^T A0 + B_t^T (nu A2 - V A0)                      (R = f - S_V u_bar)
+//   load        X0 = B_t^w R,  X1 = B_t'^w R                                      (time first)
+//               f_bar = (B_1^w (x) ... (x) B_d^w)(-i X1 + V X0) - nu sum_l (... B_l''^w ...) X0
+// where ^w marks the weighted free-row matrices.  V does not depend on t, so it
+// commutes with every time contraction.
+//
+// Lifting u_bar: the coefficients of the B-splines that do not vanish on Gamma
+// (initial face and lateral faces) minimise sum_F ||u_bar - data_F||^2_{L2(F)}.
+// On face F only the functions with index normal_index along the normal axis
+// are non-zero (b_0(0) = 1 in time, phi_0(0) = phi_{m-1}(1) = 1 in space), so
+// the normal equations are (sum_F P_F^T M_F P_F) g = sum_F P_F^T b_F with M_F the
+// Kronecker product of the full 1D mass matrices tangent to F.  They are solved
+// by CG preconditioned with the overlapping additive Schwarz operator
+// sum_F P_F^T M_F^{-1} P_F (dense 1D inverses applied axis by axis).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "load_vector.h"
+
+namespace stfd {
+
+// out[o][i][r] = alpha * sum_{k in [lo_i, hi_i)} M[i * ld + k] in[o][k][r]  (+ out if accumulate)
+__global__ void __launch_bounds__(256) axis_contract_kernel(const double2* __restrict__ in, double2* __restrict__ out,
+                                                            const double* __restrict__ M, const int* __restrict__ lo,
+                                                            const int* __restrict__ hi, int ld, int n_out, int n_in,
+                                                            int64_t inner, int64_t total, double ar, double ai,
+                                                            int accumulate) {
+  for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = g % inner;
+    const int64_t t = g / inner;
+    const int i = int(t % n_out);
+    const int64_t o = t / n_out;
+    const double2* src = in + o * n_in * inner + r;
+    const double* row = M + int64_t(i) * ld;
+    double sr = 0.0, si = 0.0;
+    for (int k = lo[i]; k < hi[i]; ++k) {
+      const double c = row[k];
+      const double2 v = src[int64_t(k) * inner];
+      sr = fma(c, v.x, sr);
+      si = fma(c, v.y, si);
+    }
+    double2 res;
+    res.x = ar * sr - ai * si;
+    res.y = ar * si + ai * sr;
+    if (accumulate) {
+      const double2 prev = out[g];
+      res.x += prev.x;
+      res.y += prev.y;
+    }
+    out[g] = res;
+  }
+}
+
+// out[x][t] = alpha * A[x][t] + beta * V[x] * B[x][t]   (t fastest, n_time entries per x)
+__global__ void __launch_bounds__(256) combine_v_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
+                                                        const double* __restrict__ V, double2* __restrict__ out,
+                                                        int64_t n_time, int64_t total, double ar, double ai,
+                                                        double beta) {
+  for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += int64_t(gridDim.x) * blockDim.x) {
+    const double2 a = A[g];
+    double2 res;
+    res.x = ar * a.x - ai * a.y;
+    res.y = ar * a.y + ai * a.x;
+    if (V) {
+      const double s = beta * V[g / n_time];
+      const double2 b = B[g];
+      res.x = fma(s, b.x, res.x);
+      res.y = fma(s, b.y, res.y);
+    }
+    out[g] = res;
+  }
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(double* __restrict__ x, int64_t n) {
+  for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < n; g += int64_t(gridDim.x) * blockDim.x)
+    x[g] = 0.0;
+}
+
+namespace {
+
+int grid_for(int64_t total) { return int(std::min<int64_t>((total + 255) / 256, 8192)); }
+
+template <typename T>
+int plan_upload(LoadPlan& plan, T** dst, const std::vector<T>& src) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, std::max<size_t>(src.size(), 1) * sizeof(T));
+  if (e != hipSuccess) return int(e);
+  plan.allocs.push_back(p);
+  e = hipMemcpy(p, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return int(e);
+  *dst = static_cast<T*>(p);
+  return 0;
+}
+
+// A tensor whose axes are (time, x_1, ..., x_d) with current extents dims[].
+struct Shape {
+  int na;
+  int64_t dims[4];
+};
+
+// Contract axis a of `in` (extent dims[a]) into extent n_out with matrix M (n_out x ld).
+int contract(const double* in, double* out, Shape& sh, int a, const double* M, const int* lo, const int* hi, int ld,
+             int n_out, double ar, double ai, bool accumulate, hipStream_t s) {
+  int64_t inner = 1;
+  for (int b = 0; b < a; ++b) inner *= sh.dims[b];
+  int64_t outer = 1;
+  for (int b = a + 1; b < sh.na; ++b) outer *= sh.dims[b];
+  const int n_in = int(sh.dims[a]);
+  const int64_t total = outer * n_out * inner;
+  sh.dims[a] = n_out;
+  if (total == 0) return 0;
+  hipLaunchKernelGGL(axis_contract_kernel, dim3(grid_for(total)), dim3(256), 0, s, (const double2*)in,
+                     (double2*)out, M, lo, hi, ld, n_out, n_in, inner, total, ar, ai, accumulate ? 1 : 0);
+  return int(hipGetLastError());
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// lifting kernels (fixed set of size n_fixed, faces packed in LiftFaces)
+// ---------------------------------------------------------------------------
+struct LiftState {
+  double bn, rz, alpha, beta, rn;
+  int done;  // 0 running, 1 converged, 2 breakdown, 3 iteration limit
+  int iters;
+};
+
+struct LiftArgs {
+  LiftFaces fc;
+  const int64_t* fixed;
+  const int* pos;
+  int64_t n_fixed;
+  const double* Mband[4];
+  const double* Minv[4];
+};
+
+constexpr int kLiftMaxIter = 200;
+constexpr double kLiftTol2 = 1e-28;  // (relative residual 1e-14)^2
+
+// Sum of one double over a 256-thread block (wave reductions, then LDS).
+__device__ __forceinline__ double block_sum256(double v, double* lds) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ void decode_index(int64_t g, const LiftFaces& fc, int* idx) {
+  for (int a = 0; a < fc.na; ++a) idx[a] = int((g / fc.stride[a]) % fc.m[a]);
+}
+
+// y = (sum_F P_F^T M_F P_F) x on the fixed set, and per-block partials of Re <x, y>.
+__global__ void __launch_bounds__(256) lift_matvec_kernel(LiftArgs A, const double2* __restrict__ x,
+                                                          double2* __restrict__ y, double* __restrict__ part,
+                                                          const LiftState* __restrict__ st) {
+  __shared__ double lds[4];
+  if (st->done) return;
+  double acc_xy = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < A.n_fixed; i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t g = A.fixed[i];
+    int idx[4];
+    decode_index(g, A.fc, idx);
+    double yr = 0.0, yi = 0.0;
+    for (int f = 0; f < A.fc.count; ++f) {
+      const LiftFace& F = A.fc.f[f];
+      if (idx[F.normal_axis] != F.normal_index) continue;
+      int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, ax[3] = {0, 0, 0};
+      for (int k = 0; k < F.n_tan; ++k) {
+        ax[k] = F.tan_axis[k];
+        const int pa = A.fc.p[ax[k]];
+        lo[k] = max(0, idx[ax[k]] - pa);
+        hi[k] = min(A.fc.m[ax[k]] - 1, idx[ax[k]] + pa);
+      }
+      for (int j0 = lo[0]; j0 <= hi[0]; ++j0) {
+        const double c0 = F.n_tan > 0 ? A.Mband[ax[0]][idx[ax[0]] * (2 * A.fc.p[ax[0]] + 1) + j0 - idx[ax[0]] +
+                                                       A.fc.p[ax[0]]]
+                                      : 1.0;
+        const int64_t g0 = g + int64_t(j0 - idx[ax[0]]) * A.fc.stride[ax[0]];
+        for (int j1 = lo[1]; j1 <= hi[1]; ++j1) {
+          const double c1 = F.n_tan > 1 ? c0 * A.Mband[ax[1]][idx[ax[1]] * (2 * A.fc.p[ax[1]] + 1) + j1 -
+                                                              idx[ax[1]] + A.fc.p[ax[1]]]
+                                        : c0;
+          const int64_t g1 = g0 + (F.n_tan > 1 ? int64_t(j1 - idx[ax[1]]) * A.fc.stride[ax[1]] : 0);
+          for (int j2 = lo[2]; j2 <= hi[2]; ++j2) {
+            const double c2 = F.n_tan > 2 ? c1 * A.Mband[ax[2]][idx[ax[2]] * (2 * A.fc.p[ax[2]] + 1) + j2 -
+                                                                idx[ax[2]] + A.fc.p[ax[2]]]
+                                          : c1;
+            const int64_t g2 = g1 + (F.n_tan > 2 ? int64_t(j2 - idx[ax[2]]) * A.fc.stride[ax[2]] : 0);
+            const double2 v = x[A.pos[g2]];
+            yr = fma(c2, v.x, yr);
+            yi = fma(c2, v.y, yi);
+          }
+        }
+      }
+    }
+    y[i] = make_double2(yr, yi);
+    const double2 xv = x[i];
+    acc_xy += xv.x * yr + xv.y * yi;
+  }
+  const double t = block_sum256(acc_xy, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// One axis of the face-wise inverse: out[F][loc] = sum_j Minv[ax][i_s][j] in_F(loc with i_s := j),
+// in_F read from the fixed-set vector r (step 0) or from the packed buffer `in` (later steps).
+__global__ void __launch_bounds__(256) lift_prec_axis_kernel(LiftArgs A, int step, const double2* __restrict__ r,
+                                                             const double2* __restrict__ in,
+                                                             double2* __restrict__ out,
+                                                             const LiftState* __restrict__ st) {
+  if (st->done) return;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < A.fc.total; e += int64_t(gridDim.x) * blockDim.x) {
+    int f = 0;
+    while (f + 1 < A.fc.count && e >= A.fc.f[f + 1].offset) ++f;
+    const LiftFace& F = A.fc.f[f];
+    const int64_t loc = e - F.offset;
+    int li[3] = {0, 0, 0};
+    int64_t lstride[3] = {1, 1, 1};
+    {
+      int64_t rr = loc, ls = 1;
+      for (int k = 0; k < F.n_tan; ++k) {
+        li[k] = int(rr % F.dims[k]);
+        rr /= F.dims[k];
+        lstride[k] = ls;
+        ls *= F.dims[k];
+      }
+    }
+    const int ax = F.tan_axis[step];
+    const int mm = F.dims[step];
+    const double* row = A.Minv[ax] + int64_t(li[step]) * mm;
+    double sr = 0.0, si = 0.0;
+    if (step == 0) {
+      int64_t g = int64_t(F.normal_index) * A.fc.stride[F.normal_axis];
+      for (int k = 0; k < F.n_tan; ++k)
+        if (k != step) g += int64_t(li[k]) * A.fc.stride[F.tan_axis[k]];
+      const int64_t sg = A.fc.stride[ax];
+      for (int j = 0; j < mm; ++j) {
+        const double2 v = r[A.pos[g + j * sg]];
+        sr = fma(row[j], v.x, sr);
+        si = fma(row[j], v.y, si);
+      }
+    } else {
+      const double2* src = in + F.offset + (loc - int64_t(li[step]) * lstride[step]);
+      for (int j = 0; j < mm; ++j) {
+        const double2 v = src[j * lstride[step]];
+        sr = fma(row[j], v.x, sr);
+        si = fma(row[j], v.y, si);
+      }
+    }
+    out[e] = make_double2(sr, si);
+  }
+}
+
+// z[i] = sum over the faces containing i of the packed face result; partials of <r,r> and <r,z>.
+__global__ void __launch_bounds__(256) lift_prec_sum_kernel(LiftArgs A, const double2* __restrict__ W,
+                                                            const double2* __restrict__ r, double2* __restrict__ z,
+                                                            double* __restrict__ part_rr,
+                                                            double* __restrict__ part_rz,
+                                                            const LiftState* __restrict__ st) {
+  __shared__ double lds[4];
+  if (st->done) return;
+  double arr = 0.0, arz = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < A.n_fixed; i += int64_t(gridDim.x) * blockDim.x) {
+    int idx[4];
+    decode_index(A.fixed[i], A.fc, idx);
+    double zr = 0.0, zi = 0.0;
+    for (int f = 0; f < A.fc.count; ++f) {
+      const LiftFace& F = A.fc.f[f];
+      if (idx[F.normal_axis] != F.normal_index) continue;
+      int64_t loc = 0, ls = 1;
+      for (int k = 0; k < F.n_tan; ++k) {
+        loc += int64_t(idx[F.tan_axis[k]]) * ls;
+        ls *= F.dims[k];
+      }
+      const double2 v = W[F.offset + loc];
+      zr += v.x;
+      zi += v.y;
+    }
+    z[i] = make_double2(zr, zi);
+    const double2 rv = r[i];
+    arr += rv.x * rv.x + rv.y * rv.y;
+    arz += rv.x * zr + rv.y * zi;
+  }
+  const double t1 = block_sum256(arr, lds);
+  const double t2 = block_sum256(arz, lds);
+  if (threadIdx.x == 0) {
+    part_rr[blockIdx.x] = t1;
+    part_rz[blockIdx.x] = t2;
+  }
+}
+
+__global__ void __launch_bounds__(256) lift_update_kernel(double2* __restrict__ g, double2* __restrict__ r,
+                                                          const double2* __restrict__ p,
+                                                          const double2* __restrict__ q, int64_t n,
+                                                          const LiftState* __restrict__ st) {
+  if (st->done) return;
+  const double al = st->alpha;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 pv = p[i], qv = q[i];
+    double2 gv = g[i], rv = r[i];
+    gv.x = fma(al, pv.x, gv.x);
+    gv.y = fma(al, pv.y, gv.y);
+    rv.x = fma(-al, qv.x, rv.x);
+    rv.y = fma(-al, qv.y, rv.y);
+    g[i] = gv;
+    r[i] = rv;
+  }
+}
+
+// p = z + beta p (first: p = z).
+__global__ void __launch_bounds__(256) lift_p_kernel(double2* __restrict__ p, const double2* __restrict__ z, int64_t n,
+                                                     const LiftState* __restrict__ st, int first) {
+  if (!first && st->done) return;
+  const double be = first ? 0.0 : st->beta;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double2 zv = z[i];
+    if (first) {
+      p[i] = zv;
+    } else {
+      const double2 pv = p[i];
+      p[i] = make_double2(fma(be, pv.x, zv.x), fma(be, pv.y, zv.y));
+    }
+  }
+}
+
+enum { LIFT_RESET = 0, LIFT_INIT = 1, LIFT_ALPHA = 2, LIFT_BETA = 3 };
+
+// Scalar step of the lifting CG (one thread): partials are summed in block order.
+__global__ void lift_scalar_kernel(int mode, const double* __restrict__ pa, const double* __restrict__ pb, int nparts,
+                                   LiftState* __restrict__ st, int* __restrict__ status_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  if (pa)
+    for (int k = 0; k < nparts; ++k) a += pa[k];
+  if (pb)
+    for (int k = 0; k < nparts; ++k) b += pb[k];
+  LiftState s = *st;
+  if (mode == LIFT_RESET) {
+    s.bn = s.rz = s.alpha = s.beta = s.rn = 0.0;
+    s.done = 0;
+    s.iters = 0;
+  } else if (mode == LIFT_INIT) {
+    s.bn = a;
+    s.rz = b;
+    s.rn = a;
+    s.iters = 0;
+    s.done = (a == 0.0) ? 1 : 0;
+    if (!(b > 0.0) && a != 0.0) s.done = 2;
+  } else if (mode == LIFT_ALPHA) {
+    if (s.done) return;
+    if (!(a > 0.0) || !isfinite(a)) {
+      s.done = 2;
+    } else {
+      s.alpha = s.rz / a;
+    }
+  } else {
+    if (s.done) return;
+    s.iters += 1;
+    s.rn = a;
+    if (!isfinite(a) || !isfinite(b)) {
+      s.done = 2;
+    } else if (a <= kLiftTol2 * s.bn) {
+      s.done = 1;
+    } else if (!(b > 0.0)) {
+      s.done = 2;
+    } else if (s.iters >= kLiftMaxIter) {
+      s.done = 3;
+    } else {
+      s.beta = b / s.rz;
+      s.rz = b;
+    }
+  }
+  *st = s;
+  if (status_out) status_out[0] = s.done;
+}
+
+// b[pos[g(F, loc)]] += loc_vals[loc] for the entries of one face (entries of a face are distinct).
+__global__ void __launch_bounds__(256) lift_face_scatter_kernel(LiftArgs A, int f, const double2* __restrict__ vals,
+                                                                double2* __restrict__ b) {
+  const LiftFace& F = A.fc.f[f];
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < F.size; e += int64_t(gridDim.x) * blockDim.x) {
+    int64_t rr = e, g = int64_t(F.normal_index) * A.fc.stride[F.normal_axis];
+    for (int k = 0; k < F.n_tan; ++k) {
+      g += (rr % F.dims[k]) * A.fc.stride[F.tan_axis[k]];
+      rr /= F.dims[k];
+    }
+    const int64_t i = A.pos[g];
+    double2 v = b[i];
+    const double2 w = vals[e];
+    v.x += w.x;
+    v.y += w.y;
+    b[i] = v;
+  }
+}
+
+// G (full tensor) = 0 except G[fixed[i]] = g[i].
+__global__ void __launch_bounds__(256) lift_expand_kernel(const double2* __restrict__ gv, const int* __restrict__ pos,
+                                                          double2* __restrict__ G, int64_t n_full) {
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n_full; k += int64_t(gridDim.x) * blockDim.x) {
+    const int i = pos[k];
+    G[k] = (i >= 0) ? gv[i] : make_double2(0.0, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+
+// Dense inverse of a symmetric positive definite m x m matrix (Cholesky, then C^{-T} C^{-1}).
+bool spd_inverse(const std::vector<double>& M, int m, std::vector<double>& inv) {
+  std::vector<double> C(size_t(m) * m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    double s = M[size_t(j) * m + j];
+    for (int k = 0; k < j; ++k) s -= C[size_t(j) * m + k] * C[size_t(j) * m + k];
+    if (!(s > 0.0)) return false;
+    const double cjj = std::sqrt(s);
+    C[size_t(j) * m + j] = cjj;
+    for (int i = j + 1; i < m; ++i) {
+      double t = M[size_t(i) * m + j];
+      for (int k = 0; k < j; ++k) t -= C[size_t(i) * m + k] * C[size_t(j) * m + k];
+      C[size_t(i) * m + j] = t / cjj;
+    }
+  }
+  // X = C^{-1} (lower triangular), inv = X^T X
+  std::vector<double> X(size_t(m) * m, 0.0);
+  for (int c = 0; c < m; ++c)
+    for (int i = c; i < m; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) t -= C[size_t(i) * m + k] * X[size_t(k) * m + c];
+      X[size_t(i) * m + c] = t / C[size_t(i) * m + i];
+    }
+  inv.assign(size_t(m) * m, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      double t = 0.0;
+      for (int k = std::max(i, j); k < m; ++k) t += X[size_t(k) * m + i] * X[size_t(k) * m + j];
+      inv[size_t(i) * m + j] = t;
+    }
+  return true;
+}
+
+LiftArgs lift_args(const LoadPlan& plan) {
+  LiftArgs A;
+  A.fc = plan.faces;
+  A.fixed = plan.fixed;
+  A.pos = plan.pos;
+  A.n_fixed = plan.n_fixed;
+  for (int a = 0; a < 4; ++a) {
+    A.Mband[a] = plan.Mband[a];
+    A.Minv[a] = plan.Minv[a];
+  }
+  return A;
+}
+
+struct RhsWork {
+  double *R, *A0, *A2, *T0, *T1, *F0, *F1, *g, *r, *z, *p, *q, *W0, *W1, *part;
+  LiftState* st;
+};
+
+size_t work_layout(const LoadPlan& plan, RhsWork* w, double* base) {
+  size_t grid = 1, mid = size_t(plan.m[0]), fmax = 1;
+  for (int a = 0; a < plan.na; ++a) grid *= size_t(plan.Q[a]);
+  for (int a = 1; a < plan.na; ++a) mid *= size_t(std::max(plan.m[a], plan.Q[a]));
+  for (int f = 0; f < plan.faces.count; ++f) {
+    size_t s = 1;
+    for (int k = 0; k < plan.faces.f[f].n_tan; ++k) {
+      const int ax = plan.faces.f[f].tan_axis[k];
+      s *= size_t(std::max(plan.m[ax], plan.Q[ax]));
+    }
+    fmax = std::max(fmax, s);
+  }
+  const size_t nf = size_t(plan.n_fixed), tot = size_t(plan.faces.total);
+  const size_t nparts = 2 * size_t(std::max(plan.lift_blocks, 1));
+  size_t off = 0;
+  auto take = [&](double** dst, size_t n) {
+    if (w) *dst = base + off;
+    off += (n + 31) & ~size_t(31);  // 256-byte aligned sub-buffers
+  };
+  RhsWork dummy;
+  RhsWork* ww = w ? w : &dummy;
+  take(&ww->R, 2 * grid);
+  take(&ww->A0, 2 * mid);
+  take(&ww->A2, 2 * mid);
+  take(&ww->T0, 2 * mid);
+  take(&ww->T1, 2 * mid);
+  take(&ww->F0, 2 * fmax);
+  take(&ww->F1, 2 * fmax);
+  take(&ww->g, 2 * nf);
+  take(&ww->r, 2 * nf);
+  take(&ww->z, 2 * nf);
+  take(&ww->p, 2 * nf);
+  take(&ww->q, 2 * nf);
+  take(&ww->W0, 2 * tot);
+  take(&ww->W1, 2 * tot);
+  take(&ww->part, nparts);
+  double* stp = nullptr;
+  take(&stp, 8);
+  if (w) w->st = reinterpret_cast<LiftState*>(stp);
+  return off;
+}
+
+}  // namespace
+
+int load_plan_build(const HostProblem& hp, LoadPlan& plan) {
+  plan.na = hp.d + 1;
+  const Direction* dirs[4] = {&hp.dir_t, &hp.dir_s[0], &hp.dir_s[1], &hp.dir_s[2]};
+  const std::vector<double>* mfull[4] = {&hp.Mfull_t, &hp.Mfull_s[0], &hp.Mfull_s[1], &hp.Mfull_s[2]};
+  LiftFaces& fc = plan.faces;
+  fc.na = plan.na;
+  int64_t stride = 1;
+  for (int a = 0; a < plan.na; ++a) {
+    const Direction& D = *dirs[a];
+    const int Q = int(D.x.size()), m = D.m, p = D.p;
+    const int n = (a == 0) ? m - 1 : m - 2;
+    plan.Q[a] = Q;
+    plan.m[a] = m;
+    plan.n[a] = n;
+    fc.m[a] = m;
+    fc.p[a] = p;
+    fc.stride[a] = stride;
+    stride *= m;
+    std::vector<int> elo(Q), ehi(Q), llo(n, Q), lhi(n, 0), wlo(m, Q), whi(m, 0);
+    std::vector<double> ev[3], ld[3], wf(size_t(m) * Q, 0.0);
+    for (int r = 0; r < 3; ++r) {
+      ev[r].assign(size_t(Q) * m, 0.0);
+      ld[r].assign(size_t(n) * Q, 0.0);
+    }
+    for (int e = 0; e < D.n_el; ++e)
+      for (int g = 0; g < D.q; ++g) {
+        const int q = e * D.q + g;
+        elo[q] = D.first[e];
+        ehi[q] = D.first[e] + p + 1;
+        for (int k = 0; k <= p; ++k) {
+          const int i = D.first[e] + k;
+          for (int r = 0; r < 3; ++r) ev[r][size_t(q) * m + i] = D.b(e, g, r, k);
+          wf[size_t(i) * Q + q] = D.w[q] * D.b(e, g, 0, k);
+          wlo[i] = std::min(wlo[i], q);
+          whi[i] = std::max(whi[i], q + 1);
+          const int fi = i - 1;  // free index (first function dropped)
+          if (fi < 0 || fi >= n) continue;
+          for (int r = 0; r < 3; ++r) ld[r][size_t(fi) * Q + q] = D.w[q] * D.b(e, g, r, k);
+          llo[fi] = std::min(llo[fi], q);
+          lhi[fi] = std::max(lhi[fi], q + 1);
+        }
+      }
+    for (int r = 0; r < 3; ++r) {
+      if (int rc = plan_upload(plan, &plan.eval[a][r], ev[r])) return rc;
+      if (int rc = plan_upload(plan, &plan.load[a][r], ld[r])) return rc;
+    }
+    if (int rc = plan_upload(plan, &plan.eval_lo[a], elo)) return rc;
+    if (int rc = plan_upload(plan, &plan.eval_hi[a], ehi)) return rc;
+    if (int rc = plan_upload(plan, &plan.load_lo[a], llo)) return rc;
+    if (int rc = plan_upload(plan, &plan.load_hi[a], lhi)) return rc;
+    if (int rc = plan_upload(plan, &plan.wfull[a], wf)) return rc;
+    if (int rc = plan_upload(plan, &plan.wfull_lo[a], wlo)) return rc;
+    if (int rc = plan_upload(plan, &plan.wfull_hi[a], whi)) return rc;
+    // banded and inverse full mass matrices
+    const std::vector<double>& M = *mfull[a];
+    std::vector<double> band(size_t(m) * (2 * p + 1), 0.0), inv;
+    for (int i = 0; i < m; ++i)
+      for (int j = std::max(0, i - p); j <= std::min(m - 1, i + p); ++j)
+        band[size_t(i) * (2 * p + 1) + (j - i + p)] = M[size_t(i) * m + j];
+    if (!spd_inverse(M, m, inv)) return -2;
+    if (int rc = plan_upload(plan, &plan.Mband[a], band)) return rc;
+    if (int rc = plan_upload(plan, &plan.Minv[a], inv)) return rc;
+  }
+  plan.n_full = stride;
+  // faces: initial (time index 0), then x_l = 0 and x_l = 1
+  fc.count = 0;
+  auto add_face = [&](int axis, int index) {
+    LiftFace& F = fc.f[fc.count++];
+    F.normal_axis = axis;
+    F.normal_index = index;
+    F.n_tan = 0;
+    F.size = 1;
+    for (int a = 0; a < plan.na; ++a)
+      if (a != axis) {
+        F.tan_axis[F.n_tan] = a;
+        F.dims[F.n_tan] = fc.m[a];
+        F.size *= fc.m[a];
+        ++F.n_tan;
+      }
+  };
+  add_face(0, 0);
+  for (int l = 1; l < plan.na; ++l) {
+    add_face(l, 0);
+    add_face(l, fc.m[l] - 1);
+  }
+  fc.total = 0;
+  for (int f = 0; f < fc.count; ++f) {
+    fc.f[f].offset = fc.total;
+    fc.total += fc.f[f].size;
+  }
+  std::vector<int> pos(size_t(plan.n_full), -1);
+  std::vector<int64_t> fixed;
+  for (int f = 0; f < fc.count; ++f) {
+    const LiftFace& F = fc.f[f];
+    for (int64_t e = 0; e < F.size; ++e) {
+      int64_t rr = e, g = int64_t(F.normal_index) * fc.stride[F.normal_axis];
+      for (int k = 0; k < F.n_tan; ++k) {
+        g += (rr % F.dims[k]) * fc.stride[F.tan_axis[k]];
+        rr /= F.dims[k];
+      }
+      if (pos[size_t(g)] < 0) {
+        pos[size_t(g)] = int(fixed.size());
+        fixed.push_back(g);
+      }
+    }
+  }
+  plan.n_fixed = int64_t(fixed.size());
+  plan.lift_blocks = int(std::min<int64_t>((plan.n_fixed + 255) / 256, 1024));
+  if (int rc = plan_upload(plan, &plan.fixed, fixed)) return rc;
+  if (int rc = plan_upload(plan, &plan.pos, pos)) return rc;
+  if (!hp.Vq.empty())
+    if (int rc = plan_upload(plan, &plan.Vq, hp.Vq)) return rc;
+  return 0;
+}
+
+void load_plan_free(LoadPlan& plan) {
+  for (void* p : plan.allocs) (void)hipFree(p);
+  plan.allocs.clear();
+}
+
+size_t rhs_work_reals(const LoadPlan& plan) { return work_layout(plan, nullptr, nullptr); }
+
+namespace {
+
+// u_bar: b from the face data, then preconditioned CG on the fixed set, then G.
+int lifting_device(const LoadPlan& plan, const double* u0_q, const double* const* faces, double* G,
+                   const RhsWork& w, int* status_dev, volatile int* status_host, hipStream_t s) {
+  const LiftArgs A = lift_args(plan);
+  const int64_t nf = plan.n_fixed;
+  const int nb = plan.lift_blocks;
+  int rc;
+  auto scalar = [&](int mode, const double* pa, const double* pb) -> int {
+    hipLaunchKernelGGL(lift_scalar_kernel, dim3(1), dim3(64), 0, s, mode, pa, pb, nb, w.st, status_dev);
+    return int(hipGetLastError());
+  };
+  if ((rc = scalar(LIFT_RESET, nullptr, nullptr))) return rc;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(2 * nf)), dim3(256), 0, s, w.r, 2 * nf);
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for(2 * nf)), dim3(256), 0, s, w.g, 2 * nf);
+  if ((rc = int(hipGetLastError()))) return rc;
+  // b_F = face data contracted with the weighted full basis along the tangent axes
+  for (int f = 0; f < plan.faces.count; ++f) {
+    const double* data = (f == 0) ? u0_q : (faces ? faces[f - 1] : nullptr);
+    if (!data) continue;
+    const LiftFace& F = plan.faces.f[f];
+    Shape sh;
+    sh.na = F.n_tan;
+    for (int k = 0; k < F.n_tan; ++k) sh.dims[k] = plan.Q[F.tan_axis[k]];
+    const double* src = data;
+    double* buf[2] = {w.F0, w.F1};
+    for (int k = 0; k < F.n_tan; ++k) {
+      const int ax = F.tan_axis[k];
+      double* o = buf[k & 1];
+      if ((rc = contract(src, o, sh, k, plan.wfull[ax], plan.wfull_lo[ax], plan.wfull_hi[ax], plan.Q[ax], plan.m[ax],
+                         1.0, 0.0, false, s)))
+        return rc;
+      src = o;
+    }
+    hipLaunchKernelGGL(lift_face_scatter_kernel, dim3(grid_for(F.size)), dim3(256), 0, s, A, f,
+                       (const double2*)src, (double2*)w.r);
+    if ((rc = int(hipGetLastError()))) return rc;
+  }
+  // z = sum_F P_F^T M_F^{-1} P_F r with partials of <r,r> and <r,z>
+  auto precondition = [&]() -> int {
+    const double* in = nullptr;
+    double* bufs[2] = {w.W0, w.W1};
+    const int nt = plan.faces.f[0].n_tan;
+    for (int k = 0; k < nt; ++k) {
+      hipLaunchKernelGGL(lift_prec_axis_kernel, dim3(grid_for(plan.faces.total)), dim3(256), 0, s, A, k,
+                         (const double2*)w.r, (const double2*)in, (double2*)bufs[k & 1], (const LiftState*)w.st);
+      in = bufs[k & 1];
+    }
+    hipLaunchKernelGGL(lift_prec_sum_kernel, dim3(nb), dim3(256), 0, s, A, (const double2*)in, (const double2*)w.r,
+                       (double2*)w.z, w.part, w.part + nb, (const LiftState*)w.st);
+    return int(hipGetLastError());
+  };
+  if ((rc = precondition())) return rc;
+  if ((rc = scalar(LIFT_INIT, w.part, w.part + nb))) return rc;
+  hipLaunchKernelGGL(lift_p_kernel, dim3(grid_for(nf)), dim3(256), 0, s, (double2*)w.p, (const double2*)w.z, nf,
+                     (const LiftState*)w.st, 1);
+  if ((rc = int(hipGetLastError()))) return rc;
+  // iterations in chunks; the host checks the device's status after each chunk
+  constexpr int kChunk = 4;
+  for (int it = 0; it < kLiftMaxIter; it += kChunk) {
+    for (int c = 0; c < kChunk; ++c) {
+      hipLaunchKernelGGL(lift_matvec_kernel, dim3(nb), dim3(256), 0, s, A, (const double2*)w.p, (double2*)w.q, w.part,
+                         (const LiftState*)w.st);
+      if ((rc = int(hipGetLastError()))) return rc;
+      if ((rc = scalar(LIFT_ALPHA, w.part, nullptr))) return rc;
+      hipLaunchKernelGGL(lift_update_kernel, dim3(grid_for(nf)), dim3(256), 0, s, (double2*)w.g, (double2*)w.r,
+                         (const double2*)w.p, (const double2*)w.q, nf, (const LiftState*)w.st);
+      if ((rc = int(hipGetLastError()))) return rc;
+      if ((rc = precondition())) return rc;
+      if ((rc = scalar(LIFT_BETA, w.part, w.part + nb))) return rc;
+      hipLaunchKernelGGL(lift_p_kernel, dim3(grid_for(nf)), dim3(256), 0, s, (double2*)w.p, (const double2*)w.z, nf,
+                         (const LiftState*)w.st, 0);
+      if ((rc = int(hipGetLastError()))) return rc;
+    }
+    if ((rc = int(hipStreamSynchronize(s)))) return rc;
+    if (*status_host != 0) break;
+  }
+  hipLaunchKernelGGL(lift_expand_kernel, dim3(grid_for(plan.n_full)), dim3(256), 0, s, (const double2*)w.g, plan.pos,
+                     (double2*)G, plan.n_full);
+  return int(hipGetLastError());
+}
+
+// f_bar = (f - S_V u_bar, S_V B_I) by sum factorisation (see the top of this file).
+int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, const double* G, double* fbar,
+                       const RhsWork& w, hipStream_t s) {
+  const int na = plan.na, d = na - 1;
+  const double nu = hp.nu;
+  size_t grid = 1;
+  for (int a = 0; a < na; ++a) grid *= size_t(plan.Q[a]);
+  double* R = w.R;
+  double* A0 = w.A0;
+  double* A2 = w.A2;
+  double* T[2] = {w.T0, w.T1};
+  int rc;
+
+  // evaluation of u_bar and S_V u_bar on the grid: chains over the spatial axes,
+  // deriv_axis = -1 -> values, else the second derivative along that axis
+  auto eval_chain = [&](int deriv_axis, double* dst, bool accumulate, double ar) -> int {
+    Shape sh;
+    sh.na = na;
+    for (int a = 0; a < na; ++a) sh.dims[a] = plan.m[a];
+    const double* src = G;
+    for (int a = 1; a < na; ++a) {
+      const bool last = (a == na - 1);
+      double* o = last ? dst : T[a & 1];
+      const int r = (a == deriv_axis) ? 2 : 0;
+      int e = contract(src, o, sh, a, plan.eval[a][r], plan.eval_lo[a], plan.eval_hi[a], plan.m[a], plan.Q[a],
+                       last ? ar : 1.0, 0.0, last && accumulate, s);
+      if (e) return e;
+      src = o;
+    }
+    return 0;
+  };
+  if ((rc = eval_chain(-1, A0, false, 1.0))) return rc;
+  for (int l = 1; l <= d; ++l)
+    if ((rc = eval_chain(l, A2, l > 1, nu))) return rc;  // A2 = nu Lap u_bar (spatial part)
+  // C = nu Lap u_bar - V u_bar (in place in A2), per spatial point, time fastest
+  const int64_t mid_t = int64_t(plan.m[0]);
+  int64_t msz = mid_t;
+  for (int a = 1; a < na; ++a) msz *= plan.Q[a];
+  if (plan.Vq) {
+    hipLaunchKernelGGL(combine_v_kernel, dim3(grid_for(msz)), dim3(256), 0, s, (const double2*)A2,
+                       (const double2*)A0, plan.Vq, (double2*)A2, mid_t, msz, 1.0, 0.0, -1.0);
+    if ((rc = int(hipGetLastError()))) return rc;
+  }
+  // R = f - i B_t'^T A0 + B_t^T C
+  if (f_q) {
+    if ((rc = int(hipMemcpyAsync(R, f_q, grid * 2 * sizeof(double), hipMemcpyDeviceToDevice, s)))) return rc;
+  } else {
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(2 * int64_t(grid))), dim3(256), 0, s, R, int64_t(2 * grid));
+    if ((rc = int(hipGetLastError()))) return rc;
+  }
+  {
+    Shape sh;
+    sh.na = na;
+    sh.dims[0] = plan.m[0];
+    for (int a = 1; a < na; ++a) sh.dims[a] = plan.Q[a];
+    Shape sh2 = sh;
+    if ((rc = contract(A0, R, sh, 0, plan.eval[0][1], plan.eval_lo[0], plan.eval_hi[0], plan.m[0], plan.Q[0], 0.0,
+                       -1.0, true, s)))
+      return rc;
+    if ((rc = contract(A2, R, sh2, 0, plan.eval[0][0], plan.eval_lo[0], plan.eval_hi[0], plan.m[0], plan.Q[0], 1.0,
+                       0.0, true, s)))
+      return rc;
+  }
+
+  // load vector: X0 = B_t^w R, X1 = B_t'^w R (free time rows)
+  double* X0 = A0;
+  double* X1 = A2;
+  {
+    Shape sh;
+    sh.na = na;
+    for (int a = 0; a < na; ++a) sh.dims[a] = plan.Q[a];
+    Shape sh2 = sh;
+    if ((rc = contract(R, X0, sh, 0, plan.load[0][0], plan.load_lo[0], plan.load_hi[0], plan.Q[0], plan.n[0], 1.0,
+                       0.0, false, s)))
+      return rc;
+    if ((rc = contract(R, X1, sh2, 0, plan.load[0][1], plan.load_lo[0], plan.load_hi[0], plan.Q[0], plan.n[0], 1.0,
+                       0.0, false, s)))
+      return rc;
+  }
+  // Y = -i X1 + V X0 (in place in X1)
+  int64_t xs = plan.n[0];
+  for (int a = 1; a < na; ++a) xs *= plan.Q[a];
+  hipLaunchKernelGGL(combine_v_kernel, dim3(grid_for(xs)), dim3(256), 0, s, (const double2*)X1, (const double2*)X0,
+                     plan.Vq, (double2*)X1, int64_t(plan.n[0]), xs, 0.0, -1.0, 1.0);
+  if ((rc = int(hipGetLastError()))) return rc;
+  auto load_chain = [&](const double* src0, int deriv_axis, double ar, bool accumulate) -> int {
+    Shape sh;
+    sh.na = na;
+    sh.dims[0] = plan.n[0];
+    for (int a = 1; a < na; ++a) sh.dims[a] = plan.Q[a];
+    const double* src = src0;
+    for (int a = 1; a < na; ++a) {
+      const bool last = (a == na - 1);
+      double* o = last ? fbar : T[a & 1];
+      const int r = (a == deriv_axis) ? 2 : 0;
+      int e = contract(src, o, sh, a, plan.load[a][r], plan.load_lo[a], plan.load_hi[a], plan.Q[a], plan.n[a],
+                       last ? ar : 1.0, 0.0, last && accumulate, s);
+      if (e) return e;
+      src = o;
+    }
+    return 0;
+  };
+  if ((rc = load_chain(X1, -1, 1.0, false))) return rc;
+  for (int l = 1; l <= d; ++l)
+    if ((rc = load_chain(X0, l, -nu, true))) return rc;
+  return 0;
+}
+
+}  // namespace
+
+int rhs_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, const double* u0_q,
+               const double* const* faces, double* G, double* fbar, double* work, int* status_dev,
+               volatile int* status_host, hipStream_t stream) {
+  RhsWork w;
+  work_layout(plan, &w, work);
+  int rc = lifting_device(plan, u0_q, faces, G, w, status_dev, status_host, stream);
+  if (rc) return rc;
+  return load_vector_device(hp, plan, f_q, G, fbar, w, stream);
+}
+
+}  // namespace stfd

@@ -21,6 +21,7 @@
 #include "../../include/stfd.h"
 #include "host_setup.h"
 #include "kernels.h"
+#include "load_vector.h"
 
 namespace stfd {
 
@@ -906,6 +907,9 @@ struct stfd_problem {
   int64_t mp_last_blocks = 0;            // blocks per rhs of the last mode product (dot partials)
   int64_t mv_blocks = 0;
   size_t max_lds = 65536;  // per-block LDS limit of the device used at setup
+  stfd::LoadPlan load;     // basis matrices on the Gauss grids (right-hand side assembly)
+  int* lift_status_host = nullptr;  // pinned: status of the last lifting CG, written by the device
+  int* lift_status_dev = nullptr;   // device address of lift_status_host
   std::vector<void*> allocs;
 };
 
@@ -1146,7 +1150,9 @@ int stfd_quad_points(const double* knots, int n_knots, int degree, int n_quad, d
 void stfd_destroy(stfd_problem* P) {
   if (!P) return;
   for (void* p : P->allocs) (void)hipFree(p);
+  stfd::load_plan_free(P->load);
   if (P->sc_host) (void)hipHostFree(P->sc_host);
+  if (P->lift_status_host) (void)hipHostFree(P->lift_status_host);
   delete P;
 }
 
@@ -1282,8 +1288,91 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     stfd_destroy(P);
     return STFD_EHIP;
   }
+  if (int he = load_plan_build(hp, P->load)) {
+    stfd_destroy(P);
+    if (he == -2) return STFD_ENOTSPD;
+    g_last_hip_error = he;
+    return STFD_EHIP;
+  }
+  e = hipHostMalloc(reinterpret_cast<void**>(&P->lift_status_host), sizeof(int));
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    P->lift_status_host = nullptr;
+    stfd_destroy(P);
+    return STFD_ENOMEM;
+  }
+  e = hipHostGetDevicePointer(reinterpret_cast<void**>(&P->lift_status_dev), P->lift_status_host, 0);
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    stfd_destroy(P);
+    return STFD_EHIP;
+  }
   *out = P;
   return STFD_OK;
+}
+
+int stfd_load_vector(const stfd_problem* P, const void* f_q_dev, const void* u0_q_dev,
+                     const void* const* dirichlet_q_dev, void* fbar_dev, double* lift, int64_t nrhs, void* stream) {
+  if (!P || !fbar_dev || nrhs < 1) return STFD_EINVAL;
+  const HostProblem& hp = P->hp;
+  const LoadPlan& plan = P->load;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  size_t grid = 1, nq_s = 1;
+  for (int a = 0; a < plan.na; ++a) grid *= size_t(plan.Q[a]);
+  for (int a = 1; a < plan.na; ++a) nq_s *= size_t(plan.Q[a]);
+  // face grids: time fastest, then the tangent spatial directions
+  size_t nq_face[6];
+  for (int l = 0; l < hp.d; ++l) {
+    size_t c = size_t(plan.Q[0]);
+    for (int k = 0; k < hp.d; ++k)
+      if (k != l) c *= size_t(plan.Q[k + 1]);
+    nq_face[2 * l] = nq_face[2 * l + 1] = c;
+  }
+  const size_t nfull = size_t(plan.n_full);
+  double* work = nullptr;
+  double* Gd = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&work), rhs_work_reals(plan) * sizeof(double));
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    return STFD_ENOMEM;
+  }
+  e = hipMalloc(reinterpret_cast<void**>(&Gd), nfull * 2 * sizeof(double) * size_t(lift ? nrhs : 1));
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    (void)hipFree(work);
+    return STFD_ENOMEM;
+  }
+  int rc = STFD_OK;
+  const double* faces[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  for (int64_t r = 0; r < nrhs && rc == STFD_OK; ++r) {
+    for (int k = 0; k < 2 * hp.d; ++k)
+      faces[k] = (dirichlet_q_dev && dirichlet_q_dev[k])
+                     ? static_cast<const double*>(dirichlet_q_dev[k]) + size_t(r) * 2 * nq_face[k]
+                     : nullptr;
+    const double* u0 = u0_q_dev ? static_cast<const double*>(u0_q_dev) + size_t(r) * 2 * nq_s : nullptr;
+    const double* fq = f_q_dev ? static_cast<const double*>(f_q_dev) + size_t(r) * 2 * grid : nullptr;
+    double* out = static_cast<double*>(fbar_dev) + size_t(r) * P->n2;
+    double* G = Gd + (lift ? size_t(r) * 2 * nfull : 0);
+    *P->lift_status_host = 0;
+    int he = rhs_device(hp, plan, fq, u0, faces, G, out, work, P->lift_status_dev, P->lift_status_host, s);
+    if (he == 0) he = int(hipStreamSynchronize(s));
+    if (he != 0) {
+      g_last_hip_error = he;
+      rc = STFD_EHIP;
+    } else if (*P->lift_status_host == 2) {
+      rc = STFD_ENOTSPD;
+    }
+  }
+  if (rc == STFD_OK && lift) {
+    e = hipMemcpy(lift, Gd, nfull * 2 * sizeof(double) * size_t(nrhs), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      g_last_hip_error = int(e);
+      rc = STFD_EHIP;
+    }
+  }
+  (void)hipFree(Gd);
+  (void)hipFree(work);
+  return rc;
 }
 
 int stfd_sizes(const stfd_problem* P, int64_t* n_t, int64_t n_s[3], int64_t* n_dof) {

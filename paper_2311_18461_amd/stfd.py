@@ -57,6 +57,7 @@ SIGNATURES = {
     "stfd_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _I64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.POINTER(PcgInfo), _VP]),
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
+    "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
     "stfd_destroy": (None, [_VP]),
     "stfd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stfd_last_hip_error": (ctypes.c_int, []),
@@ -163,6 +164,9 @@ class Problem:
         self.d, self.n_t, self.n_s, self.N = d, nt.value, [ns[i] for i in range(d)], nd.value
         self.N_s = self.N // self.n_t
         self.max_nrhs = max_nrhs
+        # Gauss grids of the load vector: time (scaled by T), then x_1 .. x_d
+        self.quad = [quad_points(knots_t, p_t, n_quad, T)] + [quad_points(k, p_s, n_quad) for k in knots_s]
+        self.m_full = [self.n_t + 1] + [n + 2 for n in self.n_s]
 
     def close(self):
         if self._h is not None and _LIB is not None:
@@ -180,6 +184,73 @@ class Problem:
         U, lam = np.empty((n, n)), np.empty(n)
         _check(_lib().stfd_get_pencil(self._h, l, _dptr(U), _dptr(lam)), "stfd_get_pencil")
         return U, lam
+
+    def grid_shape(self, axes):
+        """Sample counts of the Gauss grid over the listed axes (0 = time, l + 1 = x_l), fastest first."""
+        return [len(self.quad[a][0]) for a in axes]
+
+    def face_axes(self, l: int):
+        """Axes of the face x_l = const, fastest first: time, then x_k for k != l."""
+        return [0] + [k + 1 for k in range(self.d) if k != l]
+
+    def _grid(self, axes):
+        """Coordinate arrays of the Gauss grid over `axes` (fastest first), in C order (slowest first)."""
+        pts = [self.quad[a][0] for a in axes]
+        return list(reversed(np.meshgrid(*reversed(pts), indexing="ij")))
+
+    def sample_spacetime(self, fn):
+        """fn(t, x_1, ..., x_d) on the space-time grid, flattened time fastest (complex128)."""
+        g = self._grid(range(self.d + 1))
+        return np.array(np.broadcast_to(fn(*g), g[0].shape), dtype=np.complex128).ravel()
+
+    def sample_space(self, fn):
+        """fn(x_1, ..., x_d) on the spatial grid, flattened x_1 fastest (complex128)."""
+        g = self._grid(range(1, self.d + 1))
+        return np.array(np.broadcast_to(fn(*g), g[0].shape), dtype=np.complex128).ravel()
+
+    def sample_faces(self, fn):
+        """fn(t, x_1, ..., x_d) on the 2d lateral faces (x_l = 0, then x_l = 1, for each l)."""
+        out = []
+        for l in range(self.d):
+            g = self._grid(self.face_axes(l))
+            for side in (0.0, 1.0):
+                coords, j = [g[0]], 1
+                for k in range(self.d):
+                    if k == l:
+                        coords.append(np.full_like(g[0], side))
+                    else:
+                        coords.append(g[j])
+                        j += 1
+                out.append(np.array(np.broadcast_to(fn(*coords), g[0].shape), dtype=np.complex128).ravel())
+        return out
+
+    def load_vector(self, fbar, f_q=None, u0_q=None, dirichlet_q=None, nrhs: int = 1, stream=None,
+                    return_lift: bool = False):
+        """stfd_load_vector: fbar (device, N * nrhs complex128) <- right-hand side with lifting.
+
+        f_q: space-time samples (time fastest), u0_q: spatial samples (x_1 fastest),
+        dirichlet_q: None or 2 d face samples (x_l = 0, x_l = 1 for each l; entries may be None);
+        all contiguous complex128 device tensors with nrhs samples stacked.
+        Returns the lifting tensors (host, nrhs x prod m_full, time fastest) if return_lift.
+        """
+        n_grid = int(np.prod(self.grid_shape(range(self.d + 1))))
+        n_sp = int(np.prod(self.grid_shape(range(1, self.d + 1))))
+        fq = _dev_ptr(f_q, n_grid * nrhs, "f_q") if f_q is not None else None
+        u0 = _dev_ptr(u0_q, n_sp * nrhs, "u0_q") if u0_q is not None else None
+        faces = None
+        if dirichlet_q is not None:
+            if len(dirichlet_q) != 2 * self.d:
+                raise ValueError("dirichlet_q needs 2 d face arrays")
+            faces = (_VP * (2 * self.d))()
+            for k, a in enumerate(dirichlet_q):
+                if a is not None:
+                    n_face = int(np.prod(self.grid_shape(self.face_axes(k // 2))))
+                    faces[k] = _dev_ptr(a, n_face * nrhs, f"dirichlet_q[{k}]").value
+        lift = np.zeros(int(np.prod(self.m_full)) * nrhs, dtype=np.complex128) if return_lift else None
+        _check(_lib().stfd_load_vector(self._h, fq, u0, faces, _dev_ptr(fbar, self.N * nrhs, "fbar"),
+                                       lift.ctypes.data_as(_DP) if lift is not None else None, nrhs,
+                                       _stream_ptr(stream)), "stfd_load_vector")
+        return lift
 
     def apply_preconditioner(self, r, s, nrhs: int = 1, precision=FP64, stream=None):
         precision = PRECISIONS.get(precision, precision)

@@ -100,3 +100,13 @@ def test_setup_rejects_direction_above_mode_product_limit():
     with pytest.raises(stfd.StfdError) as ei:
         stfd.Problem(inputs.uniform_open_knots(4, 2), [kn], 2, 2)
     assert ei.value.code == stfd.EINVAL
+
+
+def test_handle_entry_points_reject_null_handle():
+    """Every entry point that takes a handle validates it before touching the device."""
+    stfd = _lib()
+    lib = stfd._lib()
+    assert lib.stfd_load_vector(None, None, None, None, None, None, 1, None) == stfd.EINVAL
+    assert lib.stfd_matvec(None, None, None, 1, None) == stfd.EINVAL
+    assert lib.stfd_apply_preconditioner(None, None, None, 1, 0, None) == stfd.EINVAL
+    assert lib.stfd_pcg_solve(None, None, None, 1, 1e-8, 10, 0, 0, None, None) == stfd.EINVAL
