@@ -53,6 +53,53 @@ def time_events(fn, reps, stream):
     return start.elapsed_time(end) / reps  # ms
 
 
+def batched_section(dev, stream, reps=3):
+    """64 wave-packet systems (V = 0, p = 3) dealt over the grids 16^3 .. 64^3: one batched call
+    (graph per iteration, one stream per grid) vs the same systems solved grid by grid and one by one."""
+    import torch
+    from paper_2311_18461_amd import inputs, stfd
+    work = inputs.batched_2d_workload()
+    probs, fs, us, nr = [], [], [], []
+    for n_el, packets in work.items():
+        kt, ks = inputs.uniform_open_knots(n_el, 3), [inputs.uniform_open_knots(n_el, 3)] * 2
+        pr = stfd.Problem(kt, ks, 3, 3, 1.0, 1.0, max_nrhs=len(packets))
+        u0 = torch.from_numpy(np.concatenate([pr.sample_space(w) for w in packets])).to(dev)
+        f = torch.empty(pr.N * len(packets), dtype=torch.complex128, device=dev)
+        pr.load_vector(f, u0_q=u0, nrhs=len(packets), stream=stream)
+        probs.append(pr)
+        fs.append(f)
+        us.append(torch.empty_like(f))
+        nr.append(len(packets))
+    total = sum(pr.N * n for pr, n in zip(probs, nr))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3, out
+
+    t_batch, (rc, info) = timed(lambda: stfd.pcg_solve_batched(probs, fs, us, nr, rtol=1e-8, maxit=1000,
+                                                                stream=stream))
+    t_grid, _ = timed(lambda: [pr.pcg_solve(f, u, nrhs=n, rtol=1e-8, maxit=1000, stream=stream)
+                               for pr, f, u, n in zip(probs, fs, us, nr)])
+
+    def one_by_one():
+        for pr, f, u, n in zip(probs, fs, us, nr):
+            for j in range(n):
+                pr.pcg_solve(f[j * pr.N:(j + 1) * pr.N], u[j * pr.N:(j + 1) * pr.N], rtol=1e-8, maxit=1000,
+                             stream=stream)
+    t_one, _ = timed(one_by_one)
+    its = [i["iters"] for i in info]
+    return {"systems": len(its), "grids": list(work.keys()), "systems_per_grid": nr, "total_dofs": total,
+            "batched_ms": round(t_batch, 3), "batched_mdofs": round(total / (t_batch * 1e-3) / 1e6, 2),
+            "grid_by_grid_ms": round(t_grid, 3), "one_by_one_ms": round(t_one, 3),
+            "iterations_min_max": [min(its), max(its)],
+            "max_true_rel_res": float(f"{max(i['true_rel_res'] for i in info):.3e}")}
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The oracle (FP64 NumPy/SciPy, all host cores): right-hand side with lifting, then PCG to 1e-8,
     on the same workload (setup excluded)."""
@@ -170,6 +217,15 @@ def main():
         pcg_iters[prec] = info[0]["iters"]
         pcg_true[prec] = info[0]["true_rel_res"]
 
+    # the same solve with every iteration replayed from a captured graph
+    prob.pcg_solve(f, u, rtol=1e-8, maxit=1000, stream=stream, graph=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(5):
+        rc, info = prob.pcg_solve(f, u, rtol=1e-8, maxit=1000, stream=stream, graph=True)
+    torch.cuda.synchronize()
+    pcg_graph_ms = (time.perf_counter() - t1) / 5 * 1e3
+
     # apply and matvec throughput with HIP events on the launch stream
     r = torch.from_numpy(inputs.random_complex(N, 2998)).to(dev)
     s = torch.empty_like(r)
@@ -214,11 +270,13 @@ def main():
         "pcg_ms_to_1e-8": {k: round(v, 4) for k, v in pcg_ms.items()},
         "pcg_iterations": pcg_iters,
         "pcg_true_rel_res": {k: float(f"{v:.3e}") for k, v in pcg_true.items()},
+        "pcg_graph_ms_to_1e-8": round(pcg_graph_ms, 4),
         "fd_apply_mdofs": {k: round(N / (v * 1e-3) / 1e6, 1) for k, v in apply_ms.items()},
         "fd_apply_us": {k: round(v * 1e3, 2) for k, v in apply_ms.items()},
         "matvec_us": round(matvec_ms * 1e3, 2),
         "roofline": roofline,
     }
+    out["batched"] = batched_section(dev, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

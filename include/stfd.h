@@ -59,7 +59,9 @@ typedef enum {
   STFD_BF16 = 2  /* BF16 MFMA mode products with FP32 accumulation, FP32 time solves */
 } stfd_precision;
 
-enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1 };
+/* pcg flags: the initial guess (one of the first two), optionally or-ed with
+ * STFD_PCG_GRAPH to replay each iteration from a captured HIP graph. */
+enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1, STFD_PCG_GRAPH = 2 };
 
 /* Problem description (Sections 2, 3.1-3.2, 4.3).
  * knots_t / knots_s[l]: open knot vectors on [0,1] (first and last p+1 knots
@@ -172,13 +174,28 @@ int stfd_matvec(const stfd_problem *P, const void *x_dev, void *y_dev, int64_t n
  * ||f - A u_k||_2 <= rtol ||f||_2 (recursive residual) or after maxit
  * iterations; beta uses the Polak-Ribiere form <r_k+1, z_k+1 - z_k>/<r_k, z_k>.
  * flags: STFD_X0_ZERO (u_dev is overwritten) or STFD_X0_GIVEN (u_dev holds
- * the initial guess).  Each right-hand side converges independently (a
+ * the initial guess), optionally | STFD_PCG_GRAPH (each iteration replayed
+ * from a captured HIP graph; same results).  Each right-hand side converges independently (a
  * converged system is frozen).  info: host array of nrhs entries (may be NULL).
  * precision: arithmetic of the preconditioner (stfd_precision); everything
  * else is FP64.  Returns STFD_OK if all systems converged, STFD_NOT_CONVERGED
  * if some hit maxit, STFD_EBREAKDOWN on breakdown, STFD_EINVAL, STFD_EHIP. */
 int stfd_pcg_solve(const stfd_problem *P, const void *f_dev, void *u_dev, int64_t nrhs, double rtol,
                    int maxit, int flags, int precision, stfd_pcg_info *info, void *stream);
+
+/* Batched PCG over several problems (uneven grids), each with its own stack of
+ * right-hand sides: job k solves A_k u = f on handle probs[k] for nrhs[k]
+ * systems stored at f_dev[k] / u_dev[k] (device, layout as stfd_pcg_solve).
+ * Same algorithm and stopping rule as stfd_pcg_solve, per system.  Each PCG
+ * iteration of the whole batch is one captured HIP graph (one per iteration
+ * parity) in which every job runs on its own stream, so the small grids
+ * overlap the large ones on the device; converged systems are masked by
+ * their done flags.  The handles must be distinct (each owns one set of work
+ * buffers).  info: host array of sum_k nrhs[k] entries in job order (may be
+ * NULL).  count <= 64.  Returns as stfd_pcg_solve. */
+int stfd_pcg_solve_batched(const stfd_problem *const *probs, int count, const void *const *f_dev,
+                           void *const *u_dev, const int64_t *nrhs, double rtol, int maxit, int flags,
+                           int precision, stfd_pcg_info *info, void *stream);
 
 /* Host copies of setup data for inspection: U_l (n_l x n_l, row-major,
  * U[j*n_l + k] = entry (j,k), column k = k-th eigenvector) and Lambda_l.

@@ -43,6 +43,8 @@ __device__ unsigned long long g_cycles[4096][8];
 
 static thread_local int g_last_hip_error = 0;
 
+constexpr int kLag = 3;  // iterations the host lets the device run ahead of its convergence check
+
 #define STFD_HIP(expr)                          \
   do {                                          \
     hipError_t e_ = (expr);                     \
@@ -647,7 +649,7 @@ struct PcgScalars {
   int iters;
   int status;
   int done;
-  int pad;
+  int kcur;  // iteration index of the iteration in flight (set by pcg_update_xr)
 };
 
 // partial sums of Re<a, b> (and optionally Re<a, c>) over this block's range
@@ -700,15 +702,17 @@ __global__ __launch_bounds__(kVecBlock) void pcg_init_kernel(const double* f, co
 
 // scalar bookkeeping after the initial residual: ||f||^2, ||r_0||, convergence at k = 0
 __global__ __launch_bounds__(kVecBlock) void pcg_start_kernel(const double* pf, const double* prr, int nparts,
-                                                               PcgScalars* sc, int* done, double tol) {
+                                                               PcgScalars* sc, int* done, double tol, int* ctr) {
   __shared__ double sh[kVecBlock / 64];
   const int rhs = blockIdx.x;
+  if (rhs == 0 && threadIdx.x == 0) ctr[0] = 0;
   const double nf2 = sum_partials<kVecBlock>(pf + rhs * nparts, nparts, sh);
   const double rr = prr ? sum_partials<kVecBlock>(prr + rhs * nparts, nparts, sh) : nf2;
   if (threadIdx.x == 0) {
     PcgScalars& s = sc[rhs];
     s.nf2 = nf2;
     s.iters = 0;
+    s.kcur = 0;
     s.status = STFD_OK;
     s.done = 0;
     s.rz[0] = s.rz[1] = 0.0;
@@ -752,11 +756,14 @@ __global__ __launch_bounds__(kVecBlock) void pcg_first_p_kernel(const double* z,
 // alpha = rz / <p, q>; x += alpha p; r -= alpha q; partial ||r||^2
 __global__ __launch_bounds__(kVecBlock) void pcg_update_xr_kernel(const double* p, const double* q, double* x,
                                                                    double* r, int64_t n2, const double* ppq,
-                                                                   int npq, const PcgScalars* sc, int parity,
-                                                                   double* prr, const int* done) {
+                                                                   int npq, PcgScalars* sc, int parity,
+                                                                   double* prr, const int* done, int* ctr) {
   __shared__ double sh[kVecBlock / 64];
   const int rhs = blockIdx.y;
+  // launch counter of this solve (read by pcg_end_iter to pick its host ring slot)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) ctr[0] += 1;
   if (done[rhs]) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[rhs].kcur = sc[rhs].iters;
   const double pq = sum_partials<kVecBlock>(ppq + rhs * npq, npq, sh);
   const double rz = sc[rhs].rz[parity];
   const bool ok = (pq > 0.0) && std::isfinite(pq);
@@ -786,11 +793,18 @@ __global__ __launch_bounds__(kVecBlock) void pcg_update_xr_kernel(const double* 
 __global__ __launch_bounds__(kVecBlock) void pcg_end_iter_kernel(const double* znew, double* p, int64_t n2,
                                                                   const double* prr, int nrr, const double* pa,
                                                                   const double* pb, int nab, PcgScalars* sc,
-                                                                  int parity, int* done, int k, int maxit, double tol,
-                                                                  PcgScalars* host_slot) {
+                                                                  int parity, int* done, int maxit, double tol,
+                                                                  PcgScalars* host_ring, int ring_stride,
+                                                                  const int* ctr) {
   __shared__ double sh[kVecBlock / 64];
   const int rhs = blockIdx.y;
-  if (done[rhs]) return;
+  // host ring slot of this iteration (the host reads slot k % kLag after iteration k)
+  PcgScalars* host_slot = host_ring ? host_ring + ((ctr[0] - 1) % kLag) * ring_stride : nullptr;
+  if (done[rhs]) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && host_slot) host_slot[rhs] = sc[rhs];
+    return;
+  }
+  const int k = sc[rhs].kcur;
   const double rr = sum_partials<kVecBlock>(prr + rhs * nrr, nrr, sh);
   const double nf2 = sc[rhs].nf2;
   const double res = sqrt(rr / nf2);
@@ -902,6 +916,7 @@ struct stfd_problem {
   int64_t max_parts = 0;
   stfd::PcgScalars* sc = nullptr;
   int* done = nullptr;
+  int* ctr = nullptr;  // iterations launched in the current solve (device)
   stfd::PcgScalars* sc_host = nullptr;  // pinned host ring [kLag][max_nrhs], written by kernels
   stfd::PcgScalars* sc_host_dev = nullptr;  // device address of sc_host
   int64_t mp_last_blocks = 0;            // blocks per rhs of the last mode product (dot partials)
@@ -914,8 +929,6 @@ struct stfd_problem {
 };
 
 namespace stfd {
-
-constexpr int kLag = 3;  // iterations the host lets the device run ahead of its convergence check
 
 template <typename T>
 static int dev_alloc(stfd_problem* P, T** ptr, size_t count) {
@@ -1271,7 +1284,8 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   }
   P->max_parts = std::max<int64_t>(std::max<int64_t>(P->mv_blocks, P->mp_last_blocks), kVecGrid);
   if ((rc = dev_alloc(P, &P->parts, size_t(6) * P->max_parts * P->max_nrhs)) ||
-      (rc = dev_alloc(P, &P->sc, size_t(P->max_nrhs))) || (rc = dev_alloc(P, &P->done, size_t(P->max_nrhs)))) {
+      (rc = dev_alloc(P, &P->sc, size_t(P->max_nrhs))) || (rc = dev_alloc(P, &P->done, size_t(P->max_nrhs))) ||
+      (rc = dev_alloc(P, &P->ctr, size_t(1)))) {
     stfd_destroy(P);
     return rc;
   }
@@ -1407,94 +1421,102 @@ int stfd_matvec(const stfd_problem* Pc, const void* x_dev, void* y_dev, int64_t 
                          static_cast<hipStream_t>(stream));
 }
 
-int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64_t nrhs, double rtol, int maxit,
-                   int flags, int precision, stfd_pcg_info* info, void* stream) {
-  stfd_problem* P = const_cast<stfd_problem*>(Pc);
-  if (!P || !f_dev || !u_dev || nrhs < 1 || nrhs > P->max_nrhs || maxit < 0 || !(rtol >= 0.0)) return STFD_EINVAL;
-  if (flags != STFD_X0_ZERO && flags != STFD_X0_GIVEN) return STFD_EINVAL;
-  if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const double* f = static_cast<const double*>(f_dev);
-  double* x = static_cast<double*>(u_dev);
+namespace stfd {
+
+// One solve of a batch: a problem handle with its own right-hand sides and work buffers.
+struct PcgJob {
+  stfd_problem* P;
+  const double* f;
+  double* x;
+  int64_t nrhs;
+};
+
+// r_0 = f - A x_0, ||f||, z_0 = P^{-1} r_0, p_0 = z_0, <r_0, z_0>.
+static int pcg_init(const PcgJob& J, int flags, int precision, double rtol, hipStream_t s) {
+  stfd_problem* P = J.P;
   double* r = P->vec[0];
   double* z = P->vec[1];
-  double* z2 = P->vec[2];
+  double* p = P->vec[3];
+  double* q = P->vec[4];
+  const int64_t n2 = P->n2;
+  double* pa = P->parts;
+  double* pb = pa + P->max_parts * P->max_nrhs;
+  const dim3 vgrid(kVecGrid, unsigned(J.nrhs)), vblock(kVecBlock);
+  int rc;
+  if (flags == STFD_X0_GIVEN) {
+    if ((rc = matvec_dispatch(P, J.x, q, J.nrhs, nullptr, nullptr, s))) return rc;
+    hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, J.f, q, r, J.x, n2, pa);
+    hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, r, r, nullptr, n2, pb, nullptr, nullptr);
+    hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(J.nrhs)), vblock, 0, s, pa, pb, kVecGrid, P->sc, P->done, rtol,
+                       P->ctr);
+  } else {
+    hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, J.f, nullptr, r, J.x, n2, pa);
+    hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(J.nrhs)), vblock, 0, s, pa, nullptr, kVecGrid, P->sc, P->done,
+                       rtol, P->ctr);
+  }
+  STFD_HIP(hipGetLastError());
+  if ((rc = apply_dispatch(P, r, z, J.nrhs, precision, P->done, s))) return rc;
+  hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, r, z, nullptr, n2, pa, nullptr, P->done);
+  hipLaunchKernelGGL(pcg_first_p_kernel, vgrid, vblock, 0, s, z, p, n2, pa, kVecGrid, P->sc, P->done);
+  STFD_HIP(hipGetLastError());
+  return STFD_OK;
+}
+
+// Iteration k (parity = k & 1): q = A p (+<p,q>), x/r update (+||r||^2),
+// z_new = P^{-1} r (+<r,z_new>, <r,z_old>), end-of-iteration test and p update.  The
+// iteration index, the ring slot and every scalar live on the device, so the same launch
+// sequence serves every iteration of a parity (and can be captured into a graph).
+static int pcg_iteration(const PcgJob& J, int parity, int precision, int maxit, double rtol, hipStream_t s) {
+  stfd_problem* P = J.P;
+  double* r = P->vec[0];
+  double* zold = P->vec[1 + parity];
+  double* znew = P->vec[2 - parity];
   double* p = P->vec[3];
   double* q = P->vec[4];
   const int64_t n2 = P->n2;
   const int64_t mp = P->max_parts;
-  double* pa = P->parts;                 // <r, z_new> partials (last mode product) / scratch
-  double* pb = pa + mp * P->max_nrhs;    // <r, z_old> partials / scratch
-  double* pc = pb + mp * P->max_nrhs;    // ||r||^2 partials (pcg_update_xr)
-  double* pd = pc + mp * P->max_nrhs;    // <p, A p> partials (matvec)
-  const dim3 vgrid(kVecGrid, unsigned(nrhs)), vblock(kVecBlock);
-  const int nab = int(P->mp_last_blocks);
+  double* pa = P->parts;               // <r, z_new> partials (last mode product)
+  double* pb = pa + mp * P->max_nrhs;  // <r, z_old> partials
+  double* pc = pb + mp * P->max_nrhs;  // ||r||^2 partials (pcg_update_xr)
+  double* pd = pc + mp * P->max_nrhs;  // <p, A p> partials (matvec)
+  const dim3 vgrid(kVecGrid, unsigned(J.nrhs)), vblock(kVecBlock);
+  // With one right-hand side the matvec and apply kernels skip the done-flag test: the few
+  // iterations launched after convergence only overwrite q and z_new, while x, r and p are
+  // guarded by the flag in pcg_update_xr / pcg_end_iter.
+  const int* dflag = J.nrhs > 1 ? P->done : nullptr;
   int rc;
-  // r_0 = f - A x_0 and ||f||
-  if (flags == STFD_X0_GIVEN) {
-    if ((rc = matvec_dispatch(P, x, q, nrhs, nullptr, nullptr, s))) return rc;
-    hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, f, q, r, x, n2, pa);
-    hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, r, r, nullptr, n2, pb, nullptr, nullptr);
-    hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(nrhs)), vblock, 0, s, pa, pb, kVecGrid, P->sc, P->done, rtol);
-  } else {
-    hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, f, nullptr, r, x, n2, pa);
-    hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(nrhs)), vblock, 0, s, pa, nullptr, kVecGrid, P->sc, P->done,
-                       rtol);
-  }
+  if ((rc = matvec_dispatch(P, p, q, J.nrhs, pd, dflag, s))) return rc;
+  hipLaunchKernelGGL(pcg_update_xr_kernel, vgrid, vblock, 0, s, p, q, J.x, r, n2, pd, int(P->mv_blocks), P->sc,
+                     parity, pc, P->done, P->ctr);
+  DotEpilogue ep;
+  ep.r = r;
+  ep.zold = zold;
+  ep.part_a = pa;
+  ep.part_b = pb;
+  if ((rc = apply_dispatch(P, r, znew, J.nrhs, precision, dflag, s, ep))) return rc;
+  hipLaunchKernelGGL(pcg_end_iter_kernel, vgrid, vblock, 0, s, znew, p, n2, pc, kVecGrid, pa, pb,
+                     int(P->mp_last_blocks), P->sc, parity, P->done, maxit, rtol, P->sc_host_dev, P->max_nrhs,
+                     (const int*)P->ctr);
   STFD_HIP(hipGetLastError());
-  // z_0 = P^{-1} r_0, p_0 = z_0, rz_0 = <r_0, z_0>
-  if ((rc = apply_dispatch(P, r, z, nrhs, precision, P->done, s))) return rc;
-  hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, r, z, nullptr, n2, pa, nullptr, P->done);
-  hipLaunchKernelGGL(pcg_first_p_kernel, vgrid, vblock, 0, s, z, p, n2, pa, kVecGrid, P->sc, P->done);
+  return STFD_OK;
+}
+
+// true residual ||f - A x|| / ||f|| and the per-system results
+static int pcg_finish(const PcgJob& J, stfd_pcg_info* info, hipStream_t s) {
+  stfd_problem* P = J.P;
+  double* q = P->vec[4];
+  double* pa = P->parts;
+  const dim3 vgrid(kVecGrid, unsigned(J.nrhs)), vblock(kVecBlock);
+  int rc;
+  if ((rc = matvec_dispatch(P, J.x, q, J.nrhs, nullptr, nullptr, s))) return rc;
+  hipLaunchKernelGGL(resid_norm_kernel, vgrid, vblock, 0, s, J.f, q, P->n2, pa);
+  hipLaunchKernelGGL(pcg_finish_kernel, dim3(unsigned(J.nrhs)), vblock, 0, s, pa, kVecGrid, P->sc);
   STFD_HIP(hipGetLastError());
-  std::vector<hipEvent_t> ev(kLag);
-  for (int k = 0; k < kLag; ++k) STFD_HIP(hipEventCreateWithFlags(&ev[k], hipEventDisableTiming));
-  auto cleanup = [&]() {
-    for (auto e : ev) (void)hipEventDestroy(e);
-  };
-  // Iteration k: q = A p (+<p,q>), x/r update (+||r||^2), z_new = P^{-1} r (+<r,z_new>, <r,z_old>),
-  // end-of-iteration test and p update.  The host runs up to kLag iterations ahead of the
-  // device-side test; iterations launched after convergence see done[rhs] and return at once.
-  for (int k = 0; k < maxit; ++k) {
-    if (k >= kLag) {
-      const int slot = (k - kLag) % kLag;
-      if (hipEventSynchronize(ev[slot]) != hipSuccess) { cleanup(); return STFD_EHIP; }
-      bool all = true;
-      for (int64_t rr = 0; rr < nrhs; ++rr) all = all && P->sc_host[slot * P->max_nrhs + rr].done;
-      if (all) break;
-    }
-    const int par = k & 1;
-    const int slot = k % kLag;
-    // With one right-hand side the matvec and apply kernels skip the done-flag test: the few
-    // iterations launched after convergence only overwrite q and z2, while x, r and p are
-    // guarded by the flag in pcg_update_xr / pcg_end_iter.
-    const int* dflag = nrhs > 1 ? P->done : nullptr;
-    if ((rc = matvec_dispatch(P, p, q, nrhs, pd, dflag, s))) { cleanup(); return rc; }
-    hipLaunchKernelGGL(pcg_update_xr_kernel, vgrid, vblock, 0, s, p, q, x, r, n2, pd, int(P->mv_blocks), P->sc, par,
-                       pc, P->done);
-    DotEpilogue ep;
-    ep.r = r;
-    ep.zold = z;
-    ep.part_a = pa;
-    ep.part_b = pb;
-    if ((rc = apply_dispatch(P, r, z2, nrhs, precision, dflag, s, ep))) { cleanup(); return rc; }
-    hipLaunchKernelGGL(pcg_end_iter_kernel, vgrid, vblock, 0, s, z2, p, n2, pc, kVecGrid, pa, pb, nab, P->sc, par,
-                       P->done, k, maxit, rtol, P->sc_host_dev + slot * P->max_nrhs);
-    STFD_HIP(hipGetLastError());
-    std::swap(z, z2);
-    if (hipEventRecord(ev[slot], s) != hipSuccess) { cleanup(); return STFD_EHIP; }
-  }
-  cleanup();
-  // true residual ||f - A x|| / ||f||
-  if ((rc = matvec_dispatch(P, x, q, nrhs, nullptr, nullptr, s))) return rc;
-  hipLaunchKernelGGL(resid_norm_kernel, vgrid, vblock, 0, s, f, q, n2, pa);
-  hipLaunchKernelGGL(pcg_finish_kernel, dim3(unsigned(nrhs)), vblock, 0, s, pa, kVecGrid, P->sc);
-  STFD_HIP(hipGetLastError());
-  std::vector<PcgScalars> fin(nrhs);
-  STFD_HIP(hipMemcpyAsync(fin.data(), P->sc, sizeof(PcgScalars) * nrhs, hipMemcpyDeviceToHost, s));
+  std::vector<PcgScalars> fin(J.nrhs);
+  STFD_HIP(hipMemcpyAsync(fin.data(), P->sc, sizeof(PcgScalars) * J.nrhs, hipMemcpyDeviceToHost, s));
   STFD_HIP(hipStreamSynchronize(s));
   int status = STFD_OK;
-  for (int64_t rr = 0; rr < nrhs; ++rr) {
+  for (int64_t rr = 0; rr < J.nrhs; ++rr) {
     const PcgScalars& sc = fin[rr];
     int st = sc.status;
     if (!sc.done && st == STFD_OK) st = STFD_NOT_CONVERGED;  // maxit == 0 with a non-converged start
@@ -1508,6 +1530,184 @@ int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64
     else if (st == STFD_NOT_CONVERGED && status == STFD_OK) status = STFD_NOT_CONVERGED;
   }
   return status;
+}
+
+// Captured iteration graphs (one per parity) of a batch of solves: every job runs on its own
+// stream forked from `s`, so the independent systems overlap on the device.
+// The graphs are recorded on a private capture stream (the caller's stream may be the null
+// stream, which cannot capture) and launched on the caller's stream.
+struct IterationGraphs {
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipStream_t cap = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+  ~IterationGraphs() {
+    for (auto& e : exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    if (cap) (void)hipStreamDestroy(cap);
+    for (auto st : streams)
+      if (st) (void)hipStreamDestroy(st);
+    for (auto ev : events)
+      if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+static int capture_iterations(const std::vector<PcgJob>& jobs, int precision, int maxit, double rtol,
+                              IterationGraphs& G) {
+  const size_t nj = jobs.size();
+  STFD_HIP(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+  hipStream_t s = G.cap;
+  if (nj > 1) {
+    G.streams.resize(nj, nullptr);
+    G.events.resize(nj + 1, nullptr);
+    for (size_t k = 0; k < nj; ++k) STFD_HIP(hipStreamCreateWithFlags(&G.streams[k], hipStreamNonBlocking));
+    for (size_t k = 0; k <= nj; ++k) STFD_HIP(hipEventCreateWithFlags(&G.events[k], hipEventDisableTiming));
+  }
+  for (int par = 0; par < 2; ++par) {
+    hipGraph_t graph = nullptr;
+    STFD_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = STFD_OK;
+    if (nj == 1) {
+      rc = pcg_iteration(jobs[0], par, precision, maxit, rtol, s);
+    } else {
+      hipError_t e = hipEventRecord(G.events[nj], s);
+      for (size_t k = 0; k < nj && rc == STFD_OK && e == hipSuccess; ++k) {
+        e = hipStreamWaitEvent(G.streams[k], G.events[nj], 0);
+        if (e == hipSuccess) rc = pcg_iteration(jobs[k], par, precision, maxit, rtol, G.streams[k]);
+        if (rc == STFD_OK && e == hipSuccess) e = hipEventRecord(G.events[k], G.streams[k]);
+        if (rc == STFD_OK && e == hipSuccess) e = hipStreamWaitEvent(s, G.events[k], 0);
+      }
+      if (e != hipSuccess && rc == STFD_OK) {
+        g_last_hip_error = int(e);
+        rc = STFD_EHIP;
+      }
+    }
+    hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (rc != STFD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (ec != hipSuccess) {
+      g_last_hip_error = int(ec);
+      return STFD_EHIP;
+    }
+    hipError_t ei = hipGraphInstantiateWithFlags(&G.exec[par], graph, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g_last_hip_error = int(ei);
+      return STFD_EHIP;
+    }
+  }
+  return STFD_OK;
+}
+
+// Shared driver of stfd_pcg_solve and stfd_pcg_solve_batched.  The host launches iteration k
+// (directly or as a graph), records an event, and before iteration k reads the pinned ring
+// slot that iteration k - kLag wrote; the loop ends when every system of every job is done.
+static int pcg_run(std::vector<PcgJob>& jobs, double rtol, int maxit, int flags, int precision, bool use_graph,
+                   stfd_pcg_info* info, hipStream_t s) {
+  int rc;
+  for (const PcgJob& J : jobs)
+    if ((rc = pcg_init(J, flags, precision, rtol, s))) return rc;
+  IterationGraphs G;
+  if (use_graph && maxit > 0)
+    if ((rc = capture_iterations(jobs, precision, maxit, rtol, G))) return rc;
+  std::vector<hipEvent_t> ev(kLag, nullptr);
+  auto cleanup = [&]() {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  };
+  for (int k = 0; k < kLag; ++k)
+    if (hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return STFD_EHIP;
+    }
+  for (int k = 0; k < maxit; ++k) {
+    if (k >= kLag) {
+      const int slot = (k - kLag) % kLag;
+      if (hipEventSynchronize(ev[slot]) != hipSuccess) {
+        cleanup();
+        return STFD_EHIP;
+      }
+      bool all = true;
+      for (const PcgJob& J : jobs)
+        for (int64_t rr = 0; rr < J.nrhs; ++rr) all = all && J.P->sc_host[slot * J.P->max_nrhs + rr].done;
+      if (all) break;
+    }
+    const int par = k & 1;
+    if (use_graph) {
+      if (hipGraphLaunch(G.exec[par], s) != hipSuccess) {
+        cleanup();
+        return STFD_EHIP;
+      }
+    } else {
+      for (const PcgJob& J : jobs)
+        if ((rc = pcg_iteration(J, par, precision, maxit, rtol, s))) {
+          cleanup();
+          return rc;
+        }
+    }
+    if (hipEventRecord(ev[k % kLag], s) != hipSuccess) {
+      cleanup();
+      return STFD_EHIP;
+    }
+  }
+  cleanup();
+  int status = STFD_OK;
+  int64_t off = 0;
+  for (const PcgJob& J : jobs) {
+    const int st = pcg_finish(J, info ? info + off : nullptr, s);
+    off += J.nrhs;
+    if (st < 0) return st;
+    if (st == STFD_NOT_CONVERGED && status == STFD_OK) status = st;
+  }
+  for (int64_t k = 0; k < off && info; ++k)
+    if (info[k].status == STFD_EBREAKDOWN) return STFD_EBREAKDOWN;
+  return status;
+}
+
+}  // namespace stfd
+
+int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64_t nrhs, double rtol, int maxit,
+                   int flags, int precision, stfd_pcg_info* info, void* stream) {
+  stfd_problem* P = const_cast<stfd_problem*>(Pc);
+  if (!P || !f_dev || !u_dev || nrhs < 1 || nrhs > P->max_nrhs || maxit < 0 || !(rtol >= 0.0)) return STFD_EINVAL;
+  const int x0 = flags & ~STFD_PCG_GRAPH;
+  if (x0 != STFD_X0_ZERO && x0 != STFD_X0_GIVEN) return STFD_EINVAL;
+  if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
+  std::vector<PcgJob> jobs(1);
+  jobs[0].P = P;
+  jobs[0].f = static_cast<const double*>(f_dev);
+  jobs[0].x = static_cast<double*>(u_dev);
+  jobs[0].nrhs = nrhs;
+  std::vector<stfd_pcg_info> tmp(info ? 0 : size_t(nrhs));
+  return pcg_run(jobs, rtol, maxit, x0, precision, (flags & STFD_PCG_GRAPH) != 0, info ? info : tmp.data(),
+                 static_cast<hipStream_t>(stream));
+}
+
+int stfd_pcg_solve_batched(const stfd_problem* const* probs, int count, const void* const* f_dev,
+                           void* const* u_dev, const int64_t* nrhs, double rtol, int maxit, int flags,
+                           int precision, stfd_pcg_info* info, void* stream) {
+  if (!probs || !f_dev || !u_dev || !nrhs || count < 1 || count > 64 || maxit < 0 || !(rtol >= 0.0))
+    return STFD_EINVAL;
+  const int x0 = flags & ~STFD_PCG_GRAPH;
+  if (x0 != STFD_X0_ZERO && x0 != STFD_X0_GIVEN) return STFD_EINVAL;
+  if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
+  std::vector<PcgJob> jobs(static_cast<size_t>(count));
+  int64_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    stfd_problem* P = const_cast<stfd_problem*>(probs[k]);
+    if (!P || !f_dev[k] || !u_dev[k] || nrhs[k] < 1 || nrhs[k] > P->max_nrhs) return STFD_EINVAL;
+    for (int j = 0; j < k; ++j)
+      if (jobs[size_t(j)].P == P) return STFD_EINVAL;  // one job per handle: it owns one set of work buffers
+    jobs[size_t(k)].P = P;
+    jobs[size_t(k)].f = static_cast<const double*>(f_dev[k]);
+    jobs[size_t(k)].x = static_cast<double*>(u_dev[k]);
+    jobs[size_t(k)].nrhs = nrhs[k];
+    total += nrhs[k];
+  }
+  std::vector<stfd_pcg_info> tmp(info ? 0 : size_t(total));
+  return pcg_run(jobs, rtol, maxit, x0, precision, true, info ? info : tmp.data(), static_cast<hipStream_t>(stream));
 }
 
 #ifdef STFD_PHASE_TIMING

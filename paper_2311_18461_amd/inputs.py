@@ -272,3 +272,16 @@ def traveling_wave_workload(n_el: int, p: int) -> Workload:
     return Workload("travel2d", d=2, p=p, n_el=n_el, f=tw.f,
                     u0=lambda x1, x2: tw.u(0.0, x1, x2), dirichlet=tw.u,
                     extra={"exact": tw.u})
+
+
+BATCH_GRIDS = (16, 24, 32, 48, 64)
+
+
+def batched_2d_workload(count: int = 64, grids=BATCH_GRIDS, p: int = 3, seed0: int = 4000):
+    """Batched 2D + time, p = 3, V = 0: `count` systems dealt round-robin over the uneven grids
+    (64 -> 13, 13, 13, 13, 12), each with a seeded wave-packet initial datum (|k| <= 30).
+    Returns {n_el: [WavePacket, ...]} in grid order."""
+    out = {n: [] for n in grids}
+    for k in range(count):
+        out[grids[k % len(grids)]].append(wave_packet(2, seed0 + k, kmax=30.0))
+    return out

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libstfd.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EHIP = 0, 1, -1, -2, -3, -4, -5
 FP64, FP32, BF16 = 0, 1, 2
-X0_ZERO, X0_GIVEN = 0, 1
+X0_ZERO, X0_GIVEN, PCG_GRAPH = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
 
@@ -58,6 +58,10 @@ SIGNATURES = {
                                       ctypes.c_int, ctypes.POINTER(PcgInfo), _VP]),
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
     "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
+    "stfd_pcg_solve_batched": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP),
+                                              ctypes.POINTER(_VP), ctypes.POINTER(_I64), ctypes.c_double,
+                                              ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(PcgInfo),
+                                              _VP]),
     "stfd_destroy": (None, [_VP]),
     "stfd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "stfd_last_hip_error": (ctypes.c_int, []),
@@ -263,16 +267,37 @@ class Problem:
                                          nrhs, _stream_ptr(stream)), "stfd_matvec")
 
     def pcg_solve(self, f, u, nrhs: int = 1, rtol: float = 1e-8, maxit: int = 200, x0_given: bool = False,
-                  precision=FP64, stream=None, check=True):
+                  precision=FP64, stream=None, check=True, graph: bool = False):
         precision = PRECISIONS.get(precision, precision)
         info = (PcgInfo * nrhs)()
+        flags = (X0_GIVEN if x0_given else X0_ZERO) | (PCG_GRAPH if graph else 0)
         rc = _lib().stfd_pcg_solve(self._h, _dev_ptr(f, self.N * nrhs, "f"), _dev_ptr(u, self.N * nrhs, "u"),
-                                   nrhs, rtol, maxit, X0_GIVEN if x0_given else X0_ZERO, precision, info,
-                                   _stream_ptr(stream))
+                                   nrhs, rtol, maxit, flags, precision, info, _stream_ptr(stream))
         if check:
             _check(rc, "stfd_pcg_solve", allow=(OK, NOT_CONVERGED))
-        return rc, [dict(iters=i.iters, status=i.status, rel_res=i.rel_res, true_rel_res=i.true_rel_res)
-                    for i in info]
+        return rc, _infos(info)
+
+
+def _infos(info):
+    return [dict(iters=i.iters, status=i.status, rel_res=i.rel_res, true_rel_res=i.true_rel_res) for i in info]
+
+
+def pcg_solve_batched(problems, fs, us, nrhs=None, rtol: float = 1e-8, maxit: int = 200, x0_given: bool = False,
+                      precision=FP64, stream=None, check=True):
+    """stfd_pcg_solve_batched: job k solves problems[k] for nrhs[k] stacked systems fs[k] -> us[k]."""
+    count = len(problems)
+    nrhs = list(nrhs) if nrhs is not None else [1] * count
+    precision = PRECISIONS.get(precision, precision)
+    handles = (_VP * count)(*[pr._h.value for pr in problems])
+    fp = (_VP * count)(*[_dev_ptr(f, pr.N * n, "f").value for pr, f, n in zip(problems, fs, nrhs)])
+    up = (_VP * count)(*[_dev_ptr(u, pr.N * n, "u").value for pr, u, n in zip(problems, us, nrhs)])
+    nr = (_I64 * count)(*nrhs)
+    info = (PcgInfo * sum(nrhs))()
+    rc = _lib().stfd_pcg_solve_batched(handles, count, fp, up, nr, rtol, maxit,
+                                       X0_GIVEN if x0_given else X0_ZERO, precision, info, _stream_ptr(stream))
+    if check:
+        _check(rc, "stfd_pcg_solve_batched", allow=(OK, NOT_CONVERGED))
+    return rc, _infos(info)
 
 
 def debug_mfma_layout():
