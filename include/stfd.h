@@ -63,6 +63,15 @@ typedef enum {
  * STFD_PCG_GRAPH to replay each iteration from a captured HIP graph. */
 enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1, STFD_PCG_GRAPH = 2 };
 
+/* Physical domain.  STFD_GEOM_UNIT_CUBE: Omega = (0,1)^d, x = xi.
+ * STFD_GEOM_QUARTER_ANNULUS (d = 2): x = (r0 + (r1 - r0) xi_1) c(xi_2) with c the
+ * quarter circle written as a rational quadratic arc (control points (1,0), (1,1),
+ * (0,1), weights 1, sqrt(2)/2, 1), an exact parametrisation of the domain
+ * (Section 3.1 allows a mapped domain Omega = F(Omega_hat); the paper's tests use
+ * the unit cube).  The system operator uses the physical Laplacian and measure; the
+ * preconditioner stays the parametric-domain P-hat (Section 5). */
+enum { STFD_GEOM_UNIT_CUBE = 0, STFD_GEOM_QUARTER_ANNULUS = 1 };
+
 /* Problem description (Sections 2, 3.1-3.2, 4.3).
  * knots_t / knots_s[l]: open knot vectors on [0,1] (first and last p+1 knots
  *   repeated, non-decreasing), length m + p + 1.  The time basis is
@@ -71,7 +80,8 @@ enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1, STFD_PCG_GRAPH = 2 };
  * p_t >= 1, p_s >= 2 (Assumption 2).  T > 0, nu > 0.
  * V_quad: NULL (V = 0) or the potential sampled at the spatial tensor Gauss
  *   grid returned by stfd_quad_points for each direction (n_quad points per
- *   element), stored x_1 fastest: V_quad[q_1 + Q_1 (q_2 + Q_2 q_3)].  The
+ *   element; on a mapped domain at the mapped points, see stfd_map_points),
+ *   stored x_1 fastest: V_quad[q_1 + Q_1 (q_2 + Q_2 q_3)].  The
  *   system operator uses S_V = i d_t - nu Lap + V; the preconditioner always
  *   uses V = 0 (it is defined for the parametric domain, Section 5).
  * n_quad: Gauss points per element and direction; 0 means p + 1.
@@ -88,6 +98,8 @@ typedef struct {
   const double *V_quad;
   int n_quad;
   int max_nrhs;
+  int geometry;   /* STFD_GEOM_UNIT_CUBE or STFD_GEOM_QUARTER_ANNULUS */
+  double geom[2]; /* quarter annulus: inner and outer radius (0 < geom[0] < geom[1]) */
 } stfd_setup_desc;
 
 typedef struct {
@@ -117,6 +129,17 @@ int stfd_quad_points(const double *knots, int n_knots, int degree, int n_quad, d
  * Errors: STFD_EINVAL (see stfd_setup_desc), STFD_ENOTSPD, STFD_ENOMEM, STFD_EHIP.
  * On success *out owns all host and device data of the problem. */
 int stfd_setup(const stfd_setup_desc *desc, stfd_problem **out);
+
+/* Replace the potential of a set-up problem (same conventions as V_quad in
+ * stfd_setup_desc; NULL: V = 0).  The spatial factors S_1..S_3 are rebuilt on
+ * the device (one thread per stencil entry, d <= 2; host quadrature for d = 3);
+ * the preconditioner does not depend on V and is kept.  Synchronises `stream`.
+ * Errors: STFD_EINVAL (NULL handle, non-finite V), STFD_EHIP. */
+int stfd_update_potential(stfd_problem *P, const double *V_quad, void *stream);
+
+/* Physical coordinates x = F(xi) of n parametric points (host arrays of n * d
+ * doubles, point-major: xi[k * d + l]).  Errors: STFD_EINVAL. */
+int stfd_map_points(const stfd_problem *P, const double *xi, int64_t n, double *x);
 
 /* Sizes: n_t, n_s[0..2] (unused directions = 1), N = n_t * prod n_s. */
 int stfd_sizes(const stfd_problem *P, int64_t *n_t, int64_t n_s[3], int64_t *n_dof);

@@ -13,6 +13,7 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
 
+from .geometry import mapped_spatial_factors
 from .matrices import space_1d, time_1d
 from .spatial import kron_operators, kron_seq, system_spatial_factors
 
@@ -26,7 +27,7 @@ class Problem:
     """
 
     def __init__(self, knots_t, knots_s: list, p_t: int, p_s: int, nu: float = 1.0,
-                 V=None, q: int | None = None):
+                 V=None, q: int | None = None, geometry=None):
         self.d = len(knots_s)
         self.nu = float(nu)
         self.p_t, self.p_s = p_t, p_s
@@ -38,7 +39,10 @@ class Problem:
         self.n_s = [s["M"].shape[0] for s in self.space1d]
         self.N_s = int(np.prod(self.n_s))
         self.N = self.n_t * self.N_s
-        self.S = system_spatial_factors(self.knots_s, p_s, self.nu, V, q, sparse=True)
+        if geometry is None:
+            self.S = system_spatial_factors(self.knots_s, p_s, self.nu, V, q, sparse=True)
+        else:  # mapped domain (V in physical coordinates); P-hat stays the parametric one
+            self.S = mapped_spatial_factors(self.knots_s, p_s, self.nu, geometry, V, q)
         self.T = [self.time["L"], self.time["M"], self.time["T3"]]
 
     # -- eq. syst_mat ---------------------------------------------------------

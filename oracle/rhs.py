@@ -40,7 +40,8 @@ def apply_axes(X, mats):
 class SpaceTimeBasis:
     """Basis values at the tensor Gauss grid (q points per element and direction)."""
 
-    def __init__(self, knots_t, knots_s, p_t, p_s, q=None):
+    def __init__(self, knots_t, knots_s, p_t, p_s, q=None, geometry=None):
+        self.geometry = geometry
         self.d = len(knots_s)
         self.knots = [np.asarray(k, dtype=np.float64) for k in knots_s] + [np.asarray(knots_t, dtype=np.float64)]
         self.deg = [p_s] * self.d + [p_t]
@@ -79,6 +80,33 @@ class SpaceTimeBasis:
             out.append(np.broadcast_to(self.pts[l].reshape(s), shape))
         return out
 
+    def physical_space_grid(self):
+        """Physical coordinates of the spatial grid (the parametric ones when F = Id)."""
+        xs = self.space_grid()
+        if self.geometry is None:
+            return xs
+        Fx = self.geometry.F(xs[0], xs[1])
+        return [Fx[..., 0], Fx[..., 1]]
+
+    def jacobian(self):
+        """|det DF| on the spatial grid, shape (Q_d, ..., Q_1, 1) (1 when F = Id)."""
+        if self.geometry is None:
+            return 1.0
+        from .geometry import laplacian_coefficients
+        xs = self.space_grid()
+        return laplacian_coefficients(self.geometry, xs[0], xs[1])["J"][..., None]
+
+    def laplacian_terms(self):
+        """[(coefficient on the grid (broadcast over time), {direction: order})] with
+        Lap_x = sum coefficient * derivative (parametric Laplacian when F = Id)."""
+        if self.geometry is None:
+            return [(1.0, {l: 2}) for l in range(self.d)]
+        from .geometry import laplacian_coefficients
+        xs = self.space_grid()
+        cf = laplacian_coefficients(self.geometry, xs[0], xs[1])
+        return [(cf["a11"][..., None], {0: 2}), (cf["a12"][..., None], {0: 1, 1: 1}),
+                (cf["a22"][..., None], {1: 2}), (cf["b1"][..., None], {0: 1}), (cf["b2"][..., None], {1: 1})]
+
     def weights(self):
         W = np.ones([1] * (self.d + 1))
         for direction in ["t"] + list(range(self.d)):
@@ -114,11 +142,11 @@ def load_vector(stb: SpaceTimeBasis, Fq, nu, Vq=None):
     Fq: samples at the tensor grid, shape (Q_d, ..., Q_1, Q_t).  Vq: (Q_d, ..., Q_1) or None.
     Returns an array of shape (n_d, ..., n_1, n_t).
     """
-    Fw = Fq * stb.weights()
+    Fw = Fq * stb.weights() * stb.jacobian()
     rows = stb.free_rows()
     out = -1j * apply_axes(Fw, stb.mats({"t": 1}, rows))
-    for l in range(stb.d):
-        out = out - nu * apply_axes(Fw, stb.mats({l: 2}, rows))
+    for coef, orders in stb.laplacian_terms():
+        out = out - nu * apply_axes(coef * Fw, stb.mats(orders, rows))
     if Vq is not None:
         out = out + apply_axes(Fw * Vq[..., None], stb.mats({}, rows))
     return out
@@ -128,8 +156,8 @@ def evaluate(stb: SpaceTimeBasis, C, nu, Vq=None):
     """Values of u = sum C_I B_I and of S_V u at the grid (C over the full basis)."""
     u = apply_axes(C, stb.mats({}, transpose=True))
     Su = 1j * apply_axes(C, stb.mats({"t": 1}, transpose=True))
-    for l in range(stb.d):
-        Su = Su - nu * apply_axes(C, stb.mats({l: 2}, transpose=True))
+    for coef, orders in stb.laplacian_terms():
+        Su = Su - nu * coef * apply_axes(C, stb.mats(orders, transpose=True))
     if Vq is not None:
         Su = Su + Vq[..., None] * u
     return u, Su
@@ -165,7 +193,7 @@ def lifting(stb: SpaceTimeBasis, u0=None, dirichlet=None):
     rhs = np.zeros(tuple(reversed(m_s)) + (m_t,), dtype=np.complex128)
     # initial face t = 0: traces phi_I for i_t = 0
     if u0 is not None:
-        xs = stb.space_grid()
+        xs = stb.physical_space_grid()
         ws = np.ones([1] * d)
         for l in range(d):
             s = [1] * d
@@ -216,8 +244,10 @@ def assemble_rhs(stb: SpaceTimeBasis, nu, f=None, u0=None, dirichlet=None, V=Non
     Returns (f_bar flattened time-fastest, lifting tensor G).
     """
     tg = stb.grid()
+    if stb.geometry is not None and (f is not None or dirichlet is not None):
+        raise NotImplementedError("mapped domains: f = 0 and homogeneous Dirichlet data only")
     Fq = f(*tg) if f is not None else np.zeros(tg[0].shape, dtype=np.complex128)
-    Vq = V(*stb.space_grid()) if V is not None else None
+    Vq = V(*stb.physical_space_grid()) if V is not None else None
     G = lifting(stb, u0, dirichlet)
     _, SG = evaluate(stb, G, nu, Vq)
     fbar = load_vector(stb, Fq - SG, nu, Vq)

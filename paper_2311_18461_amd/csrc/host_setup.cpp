@@ -268,7 +268,7 @@ int gen_eig(int n, const double* Lm, const double* Mm, double* U, double* lam) {
 // quadrature, contracted one direction at a time, scattered into stencil rows.
 // ders[l] = {order on phi_I, order on phi_J} in direction l.
 // ---------------------------------------------------------------------------
-static void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2], double* out_stencil) {
+void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2], double* out_stencil) {
   const int d = hp.d, p = hp.p_s, nl = p + 1, w2 = 2 * p + 1;
   int Q[3] = {1, 1, 1};
   int nel[3] = {1, 1, 1};
@@ -458,7 +458,8 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
       hp.Tband[(size_t(1) * nt + t) * wt + dt + pt] = hp.Mt[ix];
       hp.Tband[(size_t(2) * nt + t) * wt + dt + pt] = hp.Kt[ix];
     }
-  // spatial factors as stencils.  V = 0 part from the 1D matrices:
+  // spatial factors as stencils.  V = 0 part on the unit cube from the 1D matrices
+  // (on a mapped domain every part comes from weighted terms, added later):
   //   S_1 = (x) M_l, S_3 = nu sum_l (L_l in slot l, M elsewhere),
   //   S_2 = nu^2 B_s, B_s = sum_l (J_l in slot l) + sum_{l != k} (L_l, L_k in slots l, k)
   //   (integration by parts on the Dirichlet-reduced basis).
@@ -470,7 +471,7 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
   double* S1 = hp.Sc.data();
   double* S2 = S1 + size_t(hp.N_s) * stencil;
   double* S3 = S2 + size_t(hp.N_s) * stencil;
-  for (int64_t i = 0; i < hp.N_s; ++i) {
+  for (int64_t i = 0; i < (v.kronecker_base ? hp.N_s : 0); ++i) {
     int il[3] = {0, 0, 0};
     int64_t r = i;
     for (int l = 0; l < v.d; ++l) { il[l] = int(r % hp.n_s[l]); r /= hp.n_s[l]; }
@@ -512,54 +513,6 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
       S1[ix] = m_all;
       S2[ix] = nu * nu * bsum;
       S3[ix] = nu * lsum;
-    }
-  }
-  if (v.V_quad) {
-    size_t nqv = 1;
-    for (int l = 0; l < v.d; ++l) nqv *= hp.dir_s[l].x.size();
-    hp.Vq.assign(v.V_quad, v.V_quad + nqv);
-    const size_t ns = size_t(hp.N_s) * stencil;
-    std::vector<double> MV(ns, 0.0), MV2(ns, 0.0), KV(ns, 0.0);
-    size_t nq = 1;
-    for (int l = 0; l < v.d; ++l) nq *= hp.dir_s[l].x.size();
-    std::vector<double> V2(nq);
-    for (size_t k = 0; k < nq; ++k) {
-      if (!std::isfinite(v.V_quad[k])) return -1;
-      V2[k] = v.V_quad[k] * v.V_quad[k];
-    }
-    int dm[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-    weighted_form(hp, v.V_quad, dm, MV.data());
-    weighted_form(hp, V2.data(), dm, MV2.data());
-    for (int l = 0; l < v.d; ++l) {  // K_V = int V phi_I Lap phi_J = sum_l int V phi_I d_l^2 phi_J
-      int dl[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-      dl[l][1] = 2;
-      weighted_form(hp, v.V_quad, dl, KV.data());
-    }
-    for (int64_t i = 0; i < hp.N_s; ++i) {
-      int il[3] = {0, 0, 0};
-      int64_t r = i;
-      for (int l = 0; l < v.d; ++l) { il[l] = int(r % hp.n_s[l]); r /= hp.n_s[l]; }
-      for (int s = 0; s < stencil; ++s) {
-        // transpose entry K_V[J][I]: row J = I + o, offset -o
-        int rs = s, sT = 0, sst = 1;
-        int64_t J = 0, st = 1;
-        bool ok = true;
-        for (int l = 0; l < v.d; ++l) {
-          int o = rs % w2 - ps;
-          rs /= w2;
-          int j = il[l] + o;
-          if (j < 0 || j >= hp.n_s[l]) ok = false;
-          J += int64_t(j) * st;
-          st *= hp.n_s[l];
-          sT += (-o + ps) * sst;
-          sst *= w2;
-        }
-        if (!ok) continue;
-        size_t ix = size_t(i) * stencil + s;
-        double kt = KV[size_t(J) * stencil + sT];
-        S2[ix] += -nu * (KV[ix] + kt) + MV2[ix];
-        S3[ix] += MV[ix];
-      }
     }
   }
   return 0;

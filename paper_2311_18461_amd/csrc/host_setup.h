@@ -50,8 +50,6 @@ struct HostProblem {
   // spatial stencils S_k[i][s], s = sum_l (o_l + p_s) (2p_s+1)^l, k = 0..2
   int stencil = 0;  // (2 p_s + 1)^d
   std::vector<double> Sc;  // 3 * N_s * stencil
-  // potential at the spatial Gauss grid (x_1 fastest), empty for V = 0
-  std::vector<double> Vq;
   // full (unreduced) 1D mass matrices, for the lifting of initial and boundary data
   std::vector<double> Mfull_t, Mfull_s[3];
 };
@@ -63,6 +61,9 @@ void gram_1d(const Direction& dir, Gram1D& g);
 int gauss_legendre(int q, double* x, double* w);  // on (-1,1)
 int gen_eig(int n, const double* L, const double* M, double* U, double* lam);  // 0 or -2
 int host_setup(const struct stfd_setup_desc_view& v, HostProblem& hp);
+// out_stencil[I][s] += int cq D^{ders[l][0]} phi_I D^{ders[l][1]} phi_J (element Gauss rule, cq on
+// the spatial grid or nullptr for 1), for the Dirichlet-reduced spatial basis.
+void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2], double* out_stencil);
 
 // Flat view of the public descriptor (keeps this header free of the C ABI).
 struct stfd_setup_desc_view {
@@ -72,8 +73,8 @@ struct stfd_setup_desc_view {
   const double* knots_s[3];
   int n_knots_s[3];
   double T, nu;
-  const double* V_quad;
   int n_quad;
+  bool kronecker_base;  // assemble the V-free unit-cube stencils from 1D matrices
 };
 
 }  // namespace stfd

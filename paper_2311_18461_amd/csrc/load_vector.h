@@ -50,7 +50,13 @@ struct LoadPlan {
   double* wfull[4] = {};
   int* wfull_lo[4] = {};
   int* wfull_hi[4] = {};
-  double* Vq = nullptr;  // potential on the spatial grid (x_1 fastest) or nullptr
+  // spatial coefficients on the spatial Gauss grid (x_1 fastest), owned elsewhere:
+  const double* Vq = nullptr;  // potential or nullptr
+  const double* Jq = nullptr;  // Jacobian determinant or nullptr (1)
+  int n_lap = 0;               // physical Laplacian = sum_k lap_c[k] D^{lap_ord[k]}
+  int lap_ord[4][3] = {};
+  const double* lap_c[4] = {};   // nullptr: 1
+  const double* lap_cJ[4] = {};  // lap_c * J, nullptr: 1
   // lifting
   LiftFaces faces;
   int64_t n_fixed = 0, n_full = 0;

@@ -62,11 +62,12 @@ __global__ void __launch_bounds__(256) axis_contract_kernel(const double2* __res
   }
 }
 
-// out[x][t] = alpha * A[x][t] + beta * V[x] * B[x][t]   (t fastest, n_time entries per x)
+// out[x][t] = J[x] (alpha A[x][t] + beta V[x] B[x][t])  (t fastest, n_time entries per x;
+// V == nullptr drops the second term, J == nullptr means J = 1)
 __global__ void __launch_bounds__(256) combine_v_kernel(const double2* __restrict__ A, const double2* __restrict__ B,
-                                                        const double* __restrict__ V, double2* __restrict__ out,
-                                                        int64_t n_time, int64_t total, double ar, double ai,
-                                                        double beta) {
+                                                        const double* __restrict__ V, const double* __restrict__ J,
+                                                        double2* __restrict__ out, int64_t n_time, int64_t total,
+                                                        double ar, double ai, double beta) {
   for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += int64_t(gridDim.x) * blockDim.x) {
     const double2 a = A[g];
     double2 res;
@@ -77,6 +78,28 @@ __global__ void __launch_bounds__(256) combine_v_kernel(const double2* __restric
       const double2 b = B[g];
       res.x = fma(s, b.x, res.x);
       res.y = fma(s, b.y, res.y);
+    }
+    if (J) {
+      const double j = J[g / n_time];
+      res.x *= j;
+      res.y *= j;
+    }
+    out[g] = res;
+  }
+}
+
+// out[x][t] += c[x] A[x][t]
+__global__ void __launch_bounds__(256) scale_add_kernel(const double2* __restrict__ A, const double* __restrict__ c,
+                                                        double2* __restrict__ out, int64_t n_time, int64_t total,
+                                                        double scale, int accumulate) {
+  for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < total; g += int64_t(gridDim.x) * blockDim.x) {
+    const double f = scale * c[g / n_time];
+    const double2 a = A[g];
+    double2 res = make_double2(f * a.x, f * a.y);
+    if (accumulate) {
+      const double2 o = out[g];
+      res.x += o.x;
+      res.y += o.y;
     }
     out[g] = res;
   }
@@ -626,8 +649,6 @@ int load_plan_build(const HostProblem& hp, LoadPlan& plan) {
   plan.lift_blocks = int(std::min<int64_t>((plan.n_fixed + 255) / 256, 1024));
   if (int rc = plan_upload(plan, &plan.fixed, fixed)) return rc;
   if (int rc = plan_upload(plan, &plan.pos, pos)) return rc;
-  if (!hp.Vq.empty())
-    if (int rc = plan_upload(plan, &plan.Vq, hp.Vq)) return rc;
   return 0;
 }
 
@@ -721,10 +742,11 @@ int lifting_device(const LoadPlan& plan, const double* u0_q, const double* const
   return int(hipGetLastError());
 }
 
-// f_bar = (f - S_V u_bar, S_V B_I) by sum factorisation (see the top of this file).
+// f_bar = (f - S_V u_bar, S_V B_I) by sum factorisation (see the top of this file).  On a
+// mapped domain the Laplacian is sum_k c_k D^k and every spatial integral carries J.
 int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, const double* G, double* fbar,
                        const RhsWork& w, hipStream_t s) {
-  const int na = plan.na, d = na - 1;
+  const int na = plan.na;
   const double nu = hp.nu;
   size_t grid = 1;
   for (int a = 0; a < na; ++a) grid *= size_t(plan.Q[a]);
@@ -734,9 +756,8 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
   double* T[2] = {w.T0, w.T1};
   int rc;
 
-  // evaluation of u_bar and S_V u_bar on the grid: chains over the spatial axes,
-  // deriv_axis = -1 -> values, else the second derivative along that axis
-  auto eval_chain = [&](int deriv_axis, double* dst, bool accumulate, double ar) -> int {
+  // evaluation on the grid: chain over the spatial axes with derivative order ord[l] on x_l
+  auto eval_chain = [&](const int* ord, double* dst, bool accumulate, double ar) -> int {
     Shape sh;
     sh.na = na;
     for (int a = 0; a < na; ++a) sh.dims[a] = plan.m[a];
@@ -744,7 +765,7 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
     for (int a = 1; a < na; ++a) {
       const bool last = (a == na - 1);
       double* o = last ? dst : T[a & 1];
-      const int r = (a == deriv_axis) ? 2 : 0;
+      const int r = ord ? ord[a - 1] : 0;
       int e = contract(src, o, sh, a, plan.eval[a][r], plan.eval_lo[a], plan.eval_hi[a], plan.m[a], plan.Q[a],
                        last ? ar : 1.0, 0.0, last && accumulate, s);
       if (e) return e;
@@ -752,16 +773,26 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
     }
     return 0;
   };
-  if ((rc = eval_chain(-1, A0, false, 1.0))) return rc;
-  for (int l = 1; l <= d; ++l)
-    if ((rc = eval_chain(l, A2, l > 1, nu))) return rc;  // A2 = nu Lap u_bar (spatial part)
-  // C = nu Lap u_bar - V u_bar (in place in A2), per spatial point, time fastest
   const int64_t mid_t = int64_t(plan.m[0]);
   int64_t msz = mid_t;
   for (int a = 1; a < na; ++a) msz *= plan.Q[a];
+  if ((rc = eval_chain(nullptr, A0, false, 1.0))) return rc;
+  // A2 = nu Lap u_bar
+  for (int k = 0; k < plan.n_lap; ++k) {
+    if (!plan.lap_c[k]) {
+      if ((rc = eval_chain(plan.lap_ord[k], A2, k > 0, nu))) return rc;
+    } else {
+      if ((rc = eval_chain(plan.lap_ord[k], R, false, 1.0))) return rc;
+      hipLaunchKernelGGL(scale_add_kernel, dim3(grid_for(msz)), dim3(256), 0, s, (const double2*)R, plan.lap_c[k],
+                         (double2*)A2, mid_t, msz, nu, k > 0 ? 1 : 0);
+      if ((rc = int(hipGetLastError()))) return rc;
+    }
+  }
+  // C = nu Lap u_bar - V u_bar (in place in A2), per spatial point, time fastest
   if (plan.Vq) {
     hipLaunchKernelGGL(combine_v_kernel, dim3(grid_for(msz)), dim3(256), 0, s, (const double2*)A2,
-                       (const double2*)A0, plan.Vq, (double2*)A2, mid_t, msz, 1.0, 0.0, -1.0);
+                       (const double2*)A0, plan.Vq, (const double*)nullptr, (double2*)A2, mid_t, msz, 1.0, 0.0,
+                       -1.0);
     if ((rc = int(hipGetLastError()))) return rc;
   }
   // R = f - i B_t'^T A0 + B_t^T C
@@ -800,13 +831,13 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
                        0.0, false, s)))
       return rc;
   }
-  // Y = -i X1 + V X0 (in place in X1)
+  // Y = J (-i X1 + V X0) (in place in X1)
   int64_t xs = plan.n[0];
   for (int a = 1; a < na; ++a) xs *= plan.Q[a];
   hipLaunchKernelGGL(combine_v_kernel, dim3(grid_for(xs)), dim3(256), 0, s, (const double2*)X1, (const double2*)X0,
-                     plan.Vq, (double2*)X1, int64_t(plan.n[0]), xs, 0.0, -1.0, 1.0);
+                     plan.Vq, plan.Jq, (double2*)X1, int64_t(plan.n[0]), xs, 0.0, -1.0, 1.0);
   if ((rc = int(hipGetLastError()))) return rc;
-  auto load_chain = [&](const double* src0, int deriv_axis, double ar, bool accumulate) -> int {
+  auto load_chain = [&](const double* src0, const int* ord, double ar, bool accumulate) -> int {
     Shape sh;
     sh.na = na;
     sh.dims[0] = plan.n[0];
@@ -815,7 +846,7 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
     for (int a = 1; a < na; ++a) {
       const bool last = (a == na - 1);
       double* o = last ? fbar : T[a & 1];
-      const int r = (a == deriv_axis) ? 2 : 0;
+      const int r = ord ? ord[a - 1] : 0;
       int e = contract(src, o, sh, a, plan.load[a][r], plan.load_lo[a], plan.load_hi[a], plan.Q[a], plan.n[a],
                        last ? ar : 1.0, 0.0, last && accumulate, s);
       if (e) return e;
@@ -823,9 +854,18 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
     }
     return 0;
   };
-  if ((rc = load_chain(X1, -1, 1.0, false))) return rc;
-  for (int l = 1; l <= d; ++l)
-    if ((rc = load_chain(X0, l, -nu, true))) return rc;
+  if ((rc = load_chain(X1, nullptr, 1.0, false))) return rc;
+  // - nu sum_k (D^k phi_I, c_k J X0): R is free again and holds c_k J X0
+  for (int k = 0; k < plan.n_lap; ++k) {
+    const double* src = X0;
+    if (plan.lap_cJ[k]) {
+      hipLaunchKernelGGL(scale_add_kernel, dim3(grid_for(xs)), dim3(256), 0, s, (const double2*)X0, plan.lap_cJ[k],
+                         (double2*)R, int64_t(plan.n[0]), xs, 1.0, 0);
+      if ((rc = int(hipGetLastError()))) return rc;
+      src = R;
+    }
+    if ((rc = load_chain(src, plan.lap_ord[k], -nu, true))) return rc;
+  }
   return 0;
 }
 

@@ -22,6 +22,8 @@
 #include "host_setup.h"
 #include "kernels.h"
 #include "load_vector.h"
+#include "spatial.h"
+#include "spatial_dev.h"
 
 namespace stfd {
 
@@ -923,6 +925,9 @@ struct stfd_problem {
   int64_t mv_blocks = 0;
   size_t max_lds = 65536;  // per-block LDS limit of the device used at setup
   stfd::LoadPlan load;     // basis matrices on the Gauss grids (right-hand side assembly)
+  stfd::Geometry geom;
+  stfd::SpatialModel model;   // weighted terms of the spatial factors (potential, geometry)
+  stfd::SpatialDevice sdev;   // device basis tables, base stencils and model arrays
   int* lift_status_host = nullptr;  // pinned: status of the last lifting CG, written by the device
   int* lift_status_dev = nullptr;   // device address of lift_status_host
   std::vector<void*> allocs;
@@ -1160,10 +1165,52 @@ int stfd_quad_points(const double* knots, int n_knots, int degree, int n_quad, d
   return STFD_OK;
 }
 
+namespace stfd {
+
+// Point the load-vector plan at the device copies of the current model's arrays.
+static void set_plan_model(stfd_problem* P) {
+  const SpatialModel& m = P->model;
+  LoadPlan& L = P->load;
+  auto arr = [&](int k) -> const double* { return k >= 0 ? P->sdev.arrays[size_t(k)] : nullptr; };
+  L.Vq = arr(m.V);
+  L.Jq = arr(m.J);
+  L.n_lap = int(std::min<size_t>(m.lap.size(), 4));
+  for (int k = 0; k < L.n_lap; ++k) {
+    for (int l = 0; l < 3; ++l) L.lap_ord[k][l] = m.lap[size_t(k)].ord[l];
+    L.lap_c[k] = arr(m.lap[size_t(k)].coef);
+    L.lap_cJ[k] = arr(m.lap[size_t(k)].coefJ);
+  }
+}
+
+}  // namespace stfd
+
+int stfd_update_potential(stfd_problem* P, const double* V_quad, void* stream) {
+  if (!P) return STFD_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SpatialModel m;
+  if (build_spatial_model(P->hp, P->geom, V_quad, m)) return STFD_EINVAL;
+  P->model = std::move(m);
+  int he = spatial_device_apply(P->hp, P->model, P->sdev, P->Sc, s);
+  if (he == 0) he = int(hipStreamSynchronize(s));
+  stfd::set_plan_model(P);
+  if (he != 0) {
+    g_last_hip_error = he;
+    return STFD_EHIP;
+  }
+  return STFD_OK;
+}
+
+int stfd_map_points(const stfd_problem* P, const double* xi, int64_t n, double* x) {
+  if (!P || n < 0 || (n > 0 && (!xi || !x))) return STFD_EINVAL;
+  map_points(P->geom, P->hp.d, xi, n, x);
+  return STFD_OK;
+}
+
 void stfd_destroy(stfd_problem* P) {
   if (!P) return;
   for (void* p : P->allocs) (void)hipFree(p);
   stfd::load_plan_free(P->load);
+  stfd::spatial_device_free(P->sdev);
   if (P->sc_host) (void)hipHostFree(P->sc_host);
   if (P->lift_status_host) (void)hipHostFree(P->lift_status_host);
   delete P;
@@ -1185,8 +1232,15 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   }
   v.T = desc->T;
   v.nu = desc->nu;
-  v.V_quad = desc->V_quad;
   v.n_quad = desc->n_quad;
+  Geometry geom;
+  geom.kind = desc->geometry;
+  geom.r0 = desc->geom[0];
+  geom.r1 = desc->geom[1];
+  if (geom.kind != GEOM_UNIT && !(geom.kind == GEOM_QUARTER_ANNULUS && desc->d == 2 && geom.r0 > 0.0 &&
+                                   geom.r1 > geom.r0 && std::isfinite(geom.r1)))
+    return STFD_EINVAL;
+  v.kronecker_base = (geom.kind == GEOM_UNIT);
   stfd_problem* P = new (std::nothrow) stfd_problem;
   if (!P) return STFD_ENOMEM;
   int rc = host_setup(v, P->hp);
@@ -1204,6 +1258,11 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     return rc;
   }
   const HostProblem& hp = P->hp;
+  P->geom = geom;
+  if (build_spatial_model(hp, geom, desc->V_quad, P->model)) {
+    delete P;
+    return STFD_EINVAL;
+  }
   P->max_nrhs = desc->max_nrhs;
   P->n2 = 2 * hp.N;
   // pencils: forward operand U, backward operand U^T
@@ -1252,16 +1311,25 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
         }
       }
     }
-    // spatial coefficients interleaved per row and stencil offset: [N_s][stencil][3]
+    // spatial coefficients interleaved per row and stencil offset: [N_s][stencil][3];
+    // V-free unit-cube base from the host, weighted terms (potential, geometry) added on the device
     std::vector<double> ScI(hp.Sc.size());
     const size_t ns = size_t(hp.N_s) * hp.stencil;
     for (size_t is = 0; is < ns; ++is)
       for (int k = 0; k < 3; ++k) ScI[is * 3 + k] = hp.Sc[k * ns + is];
     if ((rc = upload(P, &P->Lb, Lb.data(), Lb.size())) || (rc = upload(P, &P->Db, Db.data(), Db.size())) ||
         (rc = upload(P, &P->Tband, hp.Tband.data(), hp.Tband.size())) ||
-        (rc = upload(P, &P->Sc, ScI.data(), ScI.size()))) {
+        (rc = dev_alloc(P, &P->Sc, ScI.size()))) {
       stfd_destroy(P);
       return rc;
+    }
+    int he = spatial_device_init(hp, P->model.kronecker_base ? ScI.data() : nullptr, P->sdev);
+    if (he == 0) he = spatial_device_apply(hp, P->model, P->sdev, P->Sc, nullptr);
+    if (he == 0) he = int(hipDeviceSynchronize());
+    if (he != 0) {
+      g_last_hip_error = he;
+      stfd_destroy(P);
+      return STFD_EHIP;
     }
   }
   const size_t nvec = size_t(P->n2) * P->max_nrhs;
@@ -1308,6 +1376,7 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     g_last_hip_error = he;
     return STFD_EHIP;
   }
+  stfd::set_plan_model(P);
   e = hipHostMalloc(reinterpret_cast<void**>(&P->lift_status_host), sizeof(int));
   if (e != hipSuccess) {
     g_last_hip_error = int(e);

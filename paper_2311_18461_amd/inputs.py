@@ -285,3 +285,47 @@ def batched_2d_workload(count: int = 64, grids=BATCH_GRIDS, p: int = 3, seed0: i
     for k in range(count):
         out[grids[k % len(grids)]].append(wave_packet(2, seed0 + k, kmax=30.0))
     return out
+
+
+# ----------------------------------------------------------------------------
+# quarter annulus r0 <= |x| <= r1, x_1, x_2 >= 0 (learned warm-start workload)
+# ----------------------------------------------------------------------------
+
+ANNULUS_RADII = (1.0, 2.0)
+
+
+def _annulus_point(g, r0, r1, margin=0.0):
+    """Area-uniform point of the quarter annulus at distance >= margin from its boundary."""
+    while True:
+        r = np.sqrt(g.uniform(r0 * r0, r1 * r1))
+        a = g.uniform(0.0, 0.5 * np.pi)
+        x = np.array([r * np.cos(a), r * np.sin(a)])
+        if margin <= 0.0 or (r - r0 >= margin and r1 - r >= margin and min(x) >= margin):
+            return x
+
+
+def annulus_gaussian_potential(seed: int, radii=ANNULUS_RADII, count_range=(4, 12), w_range=(0.05, 0.2),
+                               a_range=(0.0, 50.0)) -> GaussianSum:
+    """Seeded sum of 4-12 Gaussians with area-uniform centres in the quarter annulus."""
+    g = np.random.default_rng(seed)
+    count = int(g.integers(count_range[0], count_range[1] + 1))
+    centres = np.array([_annulus_point(g, *radii) for _ in range(count)])
+    return GaussianSum(centres=centres, widths=g.uniform(*w_range, size=count),
+                       amps=g.uniform(*a_range, size=count))
+
+
+def annulus_wave_packet(seed: int, radii=ANNULUS_RADII, kmax: float = 20.0,
+                        sigma_range=(0.05, 0.15)) -> WavePacket:
+    """Seeded packet with |k| <= kmax and a centre at least 3 sigma inside the quarter annulus."""
+    g = np.random.default_rng(seed)
+    sigma = float(g.uniform(*sigma_range))
+    c = _annulus_point(g, *radii, margin=3.0 * sigma)
+    direction = g.standard_normal(2)
+    direction /= np.linalg.norm(direction)
+    k = kmax * np.sqrt(g.uniform()) * direction
+    return WavePacket(centre=c, sigma=sigma, k=k)
+
+
+def annulus_sample(seed: int):
+    """(potential, initial datum) of one learned warm-start sample (train 5000-6999, held-out 7000-7199)."""
+    return annulus_gaussian_potential(seed), annulus_wave_packet(seed + 100000)

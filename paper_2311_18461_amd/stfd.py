@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libstfd.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EHIP = 0, 1, -1, -2, -3, -4, -5
 FP64, FP32, BF16 = 0, 1, 2
+GEOM_UNIT_CUBE, GEOM_QUARTER_ANNULUS = 0, 1
 X0_ZERO, X0_GIVEN, PCG_GRAPH = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
@@ -27,7 +28,7 @@ class SetupDesc(ctypes.Structure):
                 ("knots_s", ctypes.POINTER(ctypes.c_double) * 3), ("n_knots_s", ctypes.c_int * 3),
                 ("T", ctypes.c_double), ("nu", ctypes.c_double),
                 ("V_quad", ctypes.POINTER(ctypes.c_double)), ("n_quad", ctypes.c_int),
-                ("max_nrhs", ctypes.c_int)]
+                ("max_nrhs", ctypes.c_int), ("geometry", ctypes.c_int), ("geom", ctypes.c_double * 2)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -58,6 +59,8 @@ SIGNATURES = {
                                       ctypes.c_int, ctypes.POINTER(PcgInfo), _VP]),
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
     "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
+    "stfd_update_potential": (ctypes.c_int, [_VP, _DP, _VP]),
+    "stfd_map_points": (ctypes.c_int, [_VP, _DP, _I64, _DP]),
     "stfd_pcg_solve_batched": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP),
                                               ctypes.POINTER(_VP), ctypes.POINTER(_I64), ctypes.c_double,
                                               ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(PcgInfo),
@@ -138,7 +141,7 @@ class Problem:
     """Handle of one set-up problem (stfd_setup / stfd_destroy)."""
 
     def __init__(self, knots_t, knots_s, p_t: int, p_s: int, T: float = 1.0, nu: float = 1.0,
-                 V_quad=None, n_quad: int = 0, max_nrhs: int = 1):
+                 V_quad=None, n_quad: int = 0, max_nrhs: int = 1, geometry=GEOM_UNIT_CUBE, radii=(1.0, 2.0)):
         d = len(knots_s)
         self._keep = [np.ascontiguousarray(knots_t, dtype=np.float64)]
         desc = SetupDesc()
@@ -159,6 +162,8 @@ class Problem:
         else:
             desc.V_quad = None
         desc.n_quad, desc.max_nrhs = n_quad, max_nrhs
+        desc.geometry = geometry
+        desc.geom[0], desc.geom[1] = radii
         h = ctypes.c_void_p()
         self._h = None
         _check(_lib().stfd_setup(ctypes.byref(desc), ctypes.byref(h)), "stfd_setup")
@@ -196,6 +201,26 @@ class Problem:
     def face_axes(self, l: int):
         """Axes of the face x_l = const, fastest first: time, then x_k for k != l."""
         return [0] + [k + 1 for k in range(self.d) if k != l]
+
+    def map_points(self, xi):
+        """Physical coordinates of parametric points xi (n x d)."""
+        xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, self.d)
+        x = np.empty_like(xi)
+        _check(_lib().stfd_map_points(self._h, _dptr(xi), xi.shape[0], _dptr(x)), "stfd_map_points")
+        return x
+
+    def physical_grid(self):
+        """Physical coordinates (x_1, ..., x_d) of the spatial Gauss grid, each flattened x_1 fastest."""
+        g = self._grid(range(1, self.d + 1))
+        xi = np.stack([a.ravel() for a in g], axis=1)
+        x = self.map_points(xi)
+        return [x[:, l] for l in range(self.d)]
+
+    def update_potential(self, V_quad=None, stream=None):
+        """stfd_update_potential: replace V (samples on the spatial Gauss grid, x_1 fastest)."""
+        v = np.ascontiguousarray(V_quad, dtype=np.float64) if V_quad is not None else None
+        _check(_lib().stfd_update_potential(self._h, _dptr(v) if v is not None else None, _stream_ptr(stream)),
+               "stfd_update_potential")
 
     def _grid(self, axes):
         """Coordinate arrays of the Gauss grid over `axes` (fastest first), in C order (slowest first)."""
