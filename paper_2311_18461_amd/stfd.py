@@ -36,6 +36,12 @@ class PcgInfo(ctypes.Structure):
                 ("true_rel_res", ctypes.c_double)]
 
 
+class FnoDesc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("c_in", ctypes.c_int), ("width", ctypes.c_int),
+                ("modes1", ctypes.c_int), ("modes2", ctypes.c_int), ("layers", ctypes.c_int), ("proj", ctypes.c_int),
+                ("c_out", ctypes.c_int), ("max_batch", ctypes.c_int), ("seed", ctypes.c_uint64)]
+
+
 class StfdError(RuntimeError):
     def __init__(self, code, where):
         self.code = code
@@ -49,6 +55,7 @@ _LIB = None
 
 # exported symbols and their signatures (mirrors include/stfd.h)
 _VP, _DP, _IP, _I64 = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_int64
+_FP = ctypes.POINTER(ctypes.c_float)
 SIGNATURES = {
     "stfd_quad_points": (ctypes.c_int, [_DP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, _DP, _DP, _IP]),
     "stfd_setup": (ctypes.c_int, [ctypes.POINTER(SetupDesc), ctypes.POINTER(_VP)]),
@@ -60,6 +67,17 @@ SIGNATURES = {
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
     "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
     "stfd_update_potential": (ctypes.c_int, [_VP, _DP, _VP]),
+    "stfd_fno_create": (ctypes.c_int, [ctypes.POINTER(FnoDesc), ctypes.POINTER(_VP)]),
+    "stfd_fno_num_params": (ctypes.c_int, [_VP, ctypes.POINTER(_I64)]),
+    "stfd_fno_get_params": (ctypes.c_int, [_VP, _FP]),
+    "stfd_fno_set_params": (ctypes.c_int, [_VP, _FP]),
+    "stfd_fno_get_grads": (ctypes.c_int, [_VP, _FP]),
+    "stfd_fno_forward": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
+    "stfd_fno_backward": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
+    "stfd_fno_rel_l2": (ctypes.c_int, [_VP, _VP, _I64, ctypes.c_int, _VP, _FP, _VP]),
+    "stfd_fno_adam_step": (ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP]),
+    "stfd_fno_to_f64": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
+    "stfd_fno_destroy": (None, [_VP]),
     "stfd_map_points": (ctypes.c_int, [_VP, _DP, _I64, _DP]),
     "stfd_pcg_solve_batched": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP),
                                               ctypes.POINTER(_VP), ctypes.POINTER(_I64), ctypes.c_double,
@@ -333,3 +351,84 @@ def debug_mfma_layout():
                                          obf.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
            "stfd_debug_mfma_layout")
     return o64, o32, obf
+
+
+def _dev_ptr_f32(t, n_expected, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if t.numel() != n_expected:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n_expected}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Fno:
+    """Handle of the spectral-convolution network (include/stfd_fno.h)."""
+
+    def __init__(self, H, W, c_in, width=32, modes1=16, modes2=16, layers=4, proj=128, c_out=1, max_batch=1,
+                 seed=0):
+        self.desc = FnoDesc(H, W, c_in, width, modes1, modes2, layers, proj, c_out, max_batch, seed)
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(_lib().stfd_fno_create(ctypes.byref(self.desc), ctypes.byref(h)), "stfd_fno_create")
+        self._h = h
+        n = ctypes.c_int64()
+        _check(_lib().stfd_fno_num_params(self._h, ctypes.byref(n)), "stfd_fno_num_params")
+        self.n_params = n.value
+        self.n_in = H * W * c_in
+        self.n_out = H * W * c_out
+
+    def close(self):
+        if self._h is not None and _LIB is not None:
+            _LIB.stfd_fno_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(_lib().stfd_fno_get_params(self._h, out.ctypes.data_as(_FP)), "stfd_fno_get_params")
+        return out
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.size != self.n_params:
+            raise ValueError("wrong parameter count")
+        _check(_lib().stfd_fno_set_params(self._h, th.ctypes.data_as(_FP)), "stfd_fno_set_params")
+
+    def get_grads(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(_lib().stfd_fno_get_grads(self._h, out.ctypes.data_as(_FP)), "stfd_fno_get_grads")
+        return out
+
+    def forward(self, x, y, batch, stream=None):
+        _check(_lib().stfd_fno_forward(self._h, _dev_ptr_f32(x, self.n_in * batch, "x"),
+                                       _dev_ptr_f32(y, self.n_out * batch, "y"), batch, _stream_ptr(stream)),
+               "stfd_fno_forward")
+
+    def backward(self, dy, batch, dx=None, stream=None):
+        _check(_lib().stfd_fno_backward(self._h, _dev_ptr_f32(dy, self.n_out * batch, "dy"),
+                                        _dev_ptr_f32(dx, self.n_in * batch, "dx") if dx is not None else None,
+                                        batch, _stream_ptr(stream)), "stfd_fno_backward")
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_lib().stfd_fno_adam_step(self._h, lr, beta1, beta2, eps, _stream_ptr(stream)), "stfd_fno_adam_step")
+
+
+def fno_rel_l2(y, t, n, batch, dy=None, stream=None):
+    """stfd_fno_rel_l2: mean relative l2 error over `batch` samples of n values; fills dy if given."""
+    loss = ctypes.c_float()
+    _check(_lib().stfd_fno_rel_l2(_dev_ptr_f32(y, n * batch, "y"), _dev_ptr_f32(t, n * batch, "t"), n, batch,
+                                  _dev_ptr_f32(dy, n * batch, "dy") if dy is not None else None,
+                                  ctypes.byref(loss), _stream_ptr(stream)), "stfd_fno_rel_l2")
+    return loss.value
+
+
+def fno_to_f64(y, x, n, stream=None):
+    """stfd_fno_to_f64: FP32 network output -> FP64 (complex128 tensor x of n / 2 entries)."""
+    _check(_lib().stfd_fno_to_f64(_dev_ptr_f32(y, n, "y"), _dev_ptr(x, n // 2, "x"), n, _stream_ptr(stream)),
+           "stfd_fno_to_f64")

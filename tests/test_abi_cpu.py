@@ -20,16 +20,20 @@ def _lib():
 
 
 def _declared_functions():
-    txt = open(os.path.join(ROOT, "include", "stfd.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(stfd_[a-z0-9_]+)\s*\(", txt)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(stfd_[a-z0-9_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     stfd = _lib()
     lib = stfd._lib()
     names = _declared_functions()
-    assert len(names) >= 10
+    assert len(names) >= 25 and "stfd_fno_forward" in names
     for name in names:
         assert hasattr(lib, name), name
         assert name in stfd.SIGNATURES, name
@@ -110,3 +114,14 @@ def test_handle_entry_points_reject_null_handle():
     assert lib.stfd_matvec(None, None, None, 1, None) == stfd.EINVAL
     assert lib.stfd_apply_preconditioner(None, None, None, 1, 0, None) == stfd.EINVAL
     assert lib.stfd_pcg_solve(None, None, None, 1, 1e-8, 10, 0, 0, None, None) == stfd.EINVAL
+
+
+def test_fno_rejects_invalid_descriptors():
+    """The network's shape checks run before any device work."""
+    stfd = _lib()
+    for kw in [dict(modes1=40), dict(modes2=7), dict(modes2=80), dict(width=0), dict(max_batch=0)]:
+        args = dict(H=66, W=66, c_in=5, width=8, modes1=16, modes2=16, layers=2, proj=8, c_out=4, max_batch=1)
+        args.update(kw)
+        with pytest.raises(stfd.StfdError) as ei:
+            stfd.Fno(**args)
+        assert ei.value.code == stfd.EINVAL
