@@ -69,8 +69,17 @@ enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1, STFD_PCG_GRAPH = 2 };
  * (0,1), weights 1, sqrt(2)/2, 1), an exact parametrisation of the domain
  * (Section 3.1 allows a mapped domain Omega = F(Omega_hat); the paper's tests use
  * the unit cube).  The system operator uses the physical Laplacian and measure; the
- * preconditioner stays the parametric-domain P-hat (Section 5). */
+ * preconditioner is chosen by the precond field (below). */
 enum { STFD_GEOM_UNIT_CUBE = 0, STFD_GEOM_QUARTER_ANNULUS = 1 };
+
+/* Preconditioner on a mapped domain.  The paper defines P-hat for the unit cube only
+ * (Section 5, eq. prec_definition).  STFD_PRECOND_PARAMETRIC applies that P-hat unchanged on
+ * the parametric square.  STFD_PRECOND_AUTO (default) applies the same formula with the
+ * physical mass and stiffness matrices M, L of the quarter annulus: its metric is separable,
+ * so U^T M U = I, U^T L U = Lambda holds with U = [W_j (x) v_j] from a pencil in theta and one
+ * pencil in rho per theta mode, and Algorithm 1 runs with a per-mode matrix along x_1.  On the
+ * unit cube both choices are the paper's P-hat. */
+enum { STFD_PRECOND_AUTO = 0, STFD_PRECOND_PARAMETRIC = 1 };
 
 /* Problem description (Sections 2, 3.1-3.2, 4.3).
  * knots_t / knots_s[l]: open knot vectors on [0,1] (first and last p+1 knots
@@ -100,6 +109,7 @@ typedef struct {
   int max_nrhs;
   int geometry;   /* STFD_GEOM_UNIT_CUBE or STFD_GEOM_QUARTER_ANNULUS */
   double geom[2]; /* quarter annulus: inner and outer radius (0 < geom[0] < geom[1]) */
+  int precond;    /* STFD_PRECOND_AUTO or STFD_PRECOND_PARAMETRIC */
 } stfd_setup_desc;
 
 typedef struct {

@@ -28,6 +28,7 @@ class Problem:
 
     def __init__(self, knots_t, knots_s: list, p_t: int, p_s: int, nu: float = 1.0,
                  V=None, q: int | None = None, geometry=None):
+        self.geometry, self.q = geometry, q
         self.d = len(knots_s)
         self.nu = float(nu)
         self.p_t, self.p_s = p_t, p_s
@@ -67,6 +68,42 @@ class Problem:
         t = self.time
         return (np.kron(Ms, t["L"]) + self.nu ** 2 * np.kron(LML, t["M"])
                 + self.nu * np.kron(Ls, t["T3"]))
+
+
+def mapped_pencil(prob: Problem):
+    """Physical mass and stiffness matrices (M, L) of a mapped domain: S_1 and S_3 / nu of the
+    V-free mapped system (dense)."""
+    S1, _, S3 = mapped_spatial_factors(prob.knots_s, prob.p_s, prob.nu, prob.geometry, None, prob.q)
+    return S1.toarray(), S3.toarray() / prob.nu
+
+
+def dense_P_mapped(prob: Problem) -> np.ndarray:
+    """eq. prec_definition with the physical M and L of a mapped domain (tiny grids only)."""
+    M, L = mapped_pencil(prob)
+    t = prob.time
+    return (np.kron(M, t["L"]) + prob.nu ** 2 * np.kron(L @ np.linalg.solve(M, L), t["M"])
+            + prob.nu * np.kron(L, t["T3"]))
+
+
+class MappedFastDiagonalization:
+    """P-hat^{-1} with the physical M and L of a mapped domain, by fast diagonalisation with one
+    dense generalised eigenproblem L U = M U Lambda of the whole spatial pencil (scipy eigh),
+    then the same time solves as Algorithm 1.  Independent of any separable structure."""
+
+    def __init__(self, prob: Problem):
+        self.prob = prob
+        M, L = mapped_pencil(prob)
+        self.lam, self.U = sla.eigh(L, M)
+        t = prob.time
+        self.Lt, self.Mt, self.T3 = t["L"], t["M"], t["T3"]
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        prob = self.prob
+        Y = self.U.T @ np.asarray(r, dtype=np.complex128).reshape(prob.N_s, prob.n_t)
+        mu = prob.nu * self.lam
+        H = self.Lt[None] + (mu ** 2)[:, None, None] * self.Mt[None] + mu[:, None, None] * self.T3[None]
+        Z = np.linalg.solve(H, Y[..., None])[..., 0]
+        return (self.U @ Z).reshape(-1)
 
 
 class FastDiagonalization:

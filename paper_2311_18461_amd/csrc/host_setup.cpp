@@ -339,6 +339,48 @@ void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2]
       }
 }
 
+// LDL^H factors of H_i = L_t + mu^2 M_t + i mu K_t, mu = nu lambda_i (Section 5.2), for the
+// current eigenvalues hp.lam.  0 or -2 (a block is not positive definite).
+int time_factors(HostProblem& hp) {
+  const int pt = hp.p_t, nt = hp.n_t;
+  const double nu = hp.nu;
+  hp.Lfac.assign(size_t(nt) * pt * hp.N_s, cplx(0.0, 0.0));
+  hp.Dinv.assign(size_t(nt) * hp.N_s, 0.0);
+  {
+    std::vector<cplx> Lrow(size_t(nt) * (pt + 1));  // Lrow[t*(pt+1) + k] = L[t][t-k]
+    std::vector<double> D(nt);
+    for (int64_t i = 0; i < hp.N_s; ++i) {
+      const double mu = nu * hp.lam[i];
+      auto H = [&](int r, int c) -> cplx {
+        size_t ix = size_t(r) * nt + c;
+        return cplx(hp.Lt[ix] + mu * mu * hp.Mt[ix], mu * hp.Kt[ix]);
+      };
+      for (int t = 0; t < nt; ++t) {
+        for (int k = std::min(pt, t); k >= 1; --k) {
+          int j = t - k;
+          cplx s = H(t, j);
+          for (int kk = k + 1; kk <= std::min(pt, t); ++kk) {  // columns m = t-kk < j
+            int mcol = t - kk;
+            if (j - mcol > pt) continue;
+            s -= Lrow[size_t(t) * (pt + 1) + kk] * D[mcol] * std::conj(Lrow[size_t(j) * (pt + 1) + (j - mcol)]);
+          }
+          Lrow[size_t(t) * (pt + 1) + k] = s / D[j];
+        }
+        double dt = H(t, t).real();
+        for (int k = 1; k <= std::min(pt, t); ++k) dt -= std::norm(Lrow[size_t(t) * (pt + 1) + k]) * D[t - k];
+        if (!(dt > 0.0) || !std::isfinite(dt)) return -2;
+        D[t] = dt;
+      }
+      for (int t = 0; t < nt; ++t) {
+        hp.Dinv[size_t(t) * hp.N_s + i] = 1.0 / D[t];
+        for (int k = 1; k <= pt; ++k)
+          hp.Lfac[(size_t(t) * pt + (k - 1)) * hp.N_s + i] = (t - k >= 0) ? Lrow[size_t(t) * (pt + 1) + k] : cplx(0, 0);
+      }
+    }
+  }
+  return 0;
+}
+
 int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
   if (v.d < 1 || v.d > 3 || v.p_t < 1 || v.p_s < 2 || v.p_t > kMaxDeg || v.p_s > kMaxDeg) return -1;
   if (!(v.T > 0.0) || !(v.nu > 0.0) || !std::isfinite(v.T) || !std::isfinite(v.nu)) return -1;
@@ -410,42 +452,8 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
     }
     hp.lam[i] = s;
   }
-  // LDL^H factors of H_i = L_t + mu^2 M_t + i mu K_t, mu = nu lambda_i (Section 5.2)
+  if (int rc = time_factors(hp)) return rc;
   const int pt = v.p_t;
-  hp.Lfac.assign(size_t(nt) * pt * hp.N_s, cplx(0.0, 0.0));
-  hp.Dinv.assign(size_t(nt) * hp.N_s, 0.0);
-  {
-    std::vector<cplx> Lrow(size_t(nt) * (pt + 1));  // Lrow[t*(pt+1) + k] = L[t][t-k]
-    std::vector<double> D(nt);
-    for (int64_t i = 0; i < hp.N_s; ++i) {
-      const double mu = nu * hp.lam[i];
-      auto H = [&](int r, int c) -> cplx {
-        size_t ix = size_t(r) * nt + c;
-        return cplx(hp.Lt[ix] + mu * mu * hp.Mt[ix], mu * hp.Kt[ix]);
-      };
-      for (int t = 0; t < nt; ++t) {
-        for (int k = std::min(pt, t); k >= 1; --k) {
-          int j = t - k;
-          cplx s = H(t, j);
-          for (int kk = k + 1; kk <= std::min(pt, t); ++kk) {  // columns m = t-kk < j
-            int mcol = t - kk;
-            if (j - mcol > pt) continue;
-            s -= Lrow[size_t(t) * (pt + 1) + kk] * D[mcol] * std::conj(Lrow[size_t(j) * (pt + 1) + (j - mcol)]);
-          }
-          Lrow[size_t(t) * (pt + 1) + k] = s / D[j];
-        }
-        double dt = H(t, t).real();
-        for (int k = 1; k <= std::min(pt, t); ++k) dt -= std::norm(Lrow[size_t(t) * (pt + 1) + k]) * D[t - k];
-        if (!(dt > 0.0) || !std::isfinite(dt)) return -2;
-        D[t] = dt;
-      }
-      for (int t = 0; t < nt; ++t) {
-        hp.Dinv[size_t(t) * hp.N_s + i] = 1.0 / D[t];
-        for (int k = 1; k <= pt; ++k)
-          hp.Lfac[(size_t(t) * pt + (k - 1)) * hp.N_s + i] = (t - k >= 0) ? Lrow[size_t(t) * (pt + 1) + k] : cplx(0, 0);
-      }
-    }
-  }
   // time bands of the system factors T_1 = L_t, T_2 = M_t, T_3 = i K_t
   const int wt = 2 * pt + 1;
   hp.Tband.assign(size_t(3) * nt * wt, 0.0);

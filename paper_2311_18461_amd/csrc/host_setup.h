@@ -41,7 +41,10 @@ struct HostProblem {
   std::vector<double> Ms1[3], Ls1[3], Js1[3];
   // generalised eigendecomposition per direction: U[j*n + k], lambda[k]
   std::vector<double> U[3], lam1[3];
-  std::vector<double> lam;  // Kronecker sum, N_s
+  std::vector<double> lam;  // eigenvalues of the spatial pencil, N_s (x_1 fastest)
+  // Two-level pencils of a mapped domain: direction 0 has one n_0 x n_0 eigenvector
+  // matrix per mode of direction 1, Uslice[(j n_0 + r) n_0 + c] (empty: U[0] for all)
+  std::vector<double> Uslice;
   // LDL^H factors of H_i, layout [t][k-1][mode] (complex) and [t][mode] (real)
   std::vector<cplx> Lfac;
   std::vector<double> Dinv;
@@ -61,6 +64,7 @@ void gram_1d(const Direction& dir, Gram1D& g);
 int gauss_legendre(int q, double* x, double* w);  // on (-1,1)
 int gen_eig(int n, const double* L, const double* M, double* U, double* lam);  // 0 or -2
 int host_setup(const struct stfd_setup_desc_view& v, HostProblem& hp);
+int time_factors(HostProblem& hp);
 // out_stencil[I][s] += int cq D^{ders[l][0]} phi_I D^{ders[l][1]} phi_J (element Gauss rule, cq on
 // the spatial grid or nullptr for 1), for the Dirichlet-reduced spatial basis.
 void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2], double* out_stencil);

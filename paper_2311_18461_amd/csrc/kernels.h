@@ -29,6 +29,7 @@ struct ModeProductArgs {
   const void* in;
   void* out;
   const double* U;     // n x n operand, U'[j][a] = Uop[j*n + a] (FP64 master copy)
+  int64_t u_slice_stride;  // 0: one operand; else one per outer slice (o mod outer_per_rhs)
   int n;               // size of the contracted direction
   int64_t inner;       // contiguous reals below the direction
   int64_t outer;       // number of outer slices (directions above, times nrhs)

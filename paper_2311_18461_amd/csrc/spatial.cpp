@@ -168,6 +168,67 @@ int build_spatial_model(const HostProblem& hp, const Geometry& g, const double* 
   return 0;
 }
 
+namespace {
+
+// Dirichlet-reduced weighted 1D Gram matrix out[i][j] = int w b_i^(r) b_j^(r) (element Gauss rule).
+template <typename Wf>
+void weighted_gram_1d(const Direction& D, int r, Wf w, std::vector<double>& out) {
+  const int n = D.m - 2;
+  out.assign(size_t(n) * n, 0.0);
+  for (int e = 0; e < D.n_el; ++e)
+    for (int g = 0; g < D.q; ++g) {
+      const size_t q = size_t(e) * D.q + g;
+      const double wq = D.w[q] * w(D.x[q]);
+      for (int a = 0; a <= D.p; ++a) {
+        const int i = D.first[e] + a - 1;
+        if (i < 0 || i >= n) continue;
+        for (int b = 0; b <= D.p; ++b) {
+          const int j = D.first[e] + b - 1;
+          if (j < 0 || j >= n) continue;
+          out[size_t(i) * n + j] += wq * D.b(e, g, r, a) * D.b(e, g, r, b);
+        }
+      }
+    }
+}
+
+}  // namespace
+
+int geometry_pencils(HostProblem& hp, const Geometry& g) {
+  if (g.kind != GEOM_QUARTER_ANNULUS || hp.d != 2) return -1;
+  const double r0 = g.r0, dr = g.r1 - g.r0;
+  const Direction& Dr = hp.dir_s[0];
+  const Direction& Dt = hp.dir_s[1];
+  const int nr = hp.n_s[0], nth = hp.n_s[1];
+  auto s_of = [](double t) {
+    double c[2], c1[2], c2[2];
+    arc(t, c, c1, c2);
+    return c[0] * c1[1] - c[1] * c1[0];
+  };
+  // theta pencil: stiffness weight 1/s, mass weight s
+  std::vector<double> Kt, Mt;
+  weighted_gram_1d(Dt, 1, [&](double t) { return 1.0 / s_of(t); }, Kt);
+  weighted_gram_1d(Dt, 0, [&](double t) { return s_of(t); }, Mt);
+  std::vector<double> V(static_cast<size_t>(nth) * nth), mu(static_cast<size_t>(nth));
+  if (gen_eig(nth, Kt.data(), Mt.data(), V.data(), mu.data())) return -2;
+  // rho pencils: stiffness weight r/dr, cross weight dr/r, mass weight dr r
+  std::vector<double> Kr, Xr, Mr;
+  weighted_gram_1d(Dr, 1, [&](double x) { return (r0 + dr * x) / dr; }, Kr);
+  weighted_gram_1d(Dr, 0, [&](double x) { return dr / (r0 + dr * x); }, Xr);
+  weighted_gram_1d(Dr, 0, [&](double x) { return dr * (r0 + dr * x); }, Mr);
+  hp.Uslice.assign(size_t(nth) * nr * nr, 0.0);
+  hp.lam.assign(size_t(nr) * nth, 0.0);
+  std::vector<double> A(static_cast<size_t>(nr) * nr), W(static_cast<size_t>(nr) * nr), lam(static_cast<size_t>(nr));
+  for (int j = 0; j < nth; ++j) {
+    for (size_t k = 0; k < A.size(); ++k) A[k] = Kr[k] + mu[size_t(j)] * Xr[k];
+    if (gen_eig(nr, A.data(), Mr.data(), W.data(), lam.data())) return -2;
+    std::copy(W.begin(), W.end(), hp.Uslice.begin() + size_t(j) * nr * nr);
+    for (int i = 0; i < nr; ++i) hp.lam[size_t(j) * nr + i] = lam[size_t(i)];
+  }
+  hp.U[1] = V;
+  hp.lam1[1] = mu;
+  return time_factors(hp);
+}
+
 void apply_terms_host(const HostProblem& hp, const SpatialModel& m, double* Sc) {
   const size_t ns = size_t(hp.N_s) * hp.stencil;
   for (const WeightedTerm& t : m.terms) {

@@ -60,6 +60,16 @@ int build_spatial_model(const HostProblem& hp, const Geometry& g, const double* 
 // Physical coordinates of n parametric points (d values each, xi_1 fastest).
 void map_points(const Geometry& g, int d, const double* xi, int64_t n, double* x);
 
+// Preconditioner pencils of the quarter annulus.  Its metric is separable: the physical mass
+// and stiffness matrices are M = M_r^{dr r} (x) M_t^{s} and
+// L = K_r^{r/dr} (x) M_t^{s} + M_r^{dr/r} (x) K_t^{1/s} (superscript: 1D weight).  The theta
+// pencil (K_t^{1/s}, M_t^{s}) -> V, mu; then per theta mode j the rho pencil
+// (K_r^{r/dr} + mu_j M_r^{dr/r}, M_r^{dr r}) -> W_j, lambda_j: U = [W_j (x) v_j] diagonalises
+// both (U^T M U = I, U^T L U = diag(lambda)), so P-hat with these M and L is applied by the
+// same fast diagonalisation with a per-mode matrix in the rho direction.  Sets hp.U[1],
+// hp.Uslice, hp.lam and the time factors.  0, -1 (not an annulus) or -2.
+int geometry_pencils(HostProblem& hp, const Geometry& g);
+
 // Host evaluation of the weighted terms (any d): Sc (layout [k][N_s][stencil]) += terms.
 void apply_terms_host(const HostProblem& hp, const SpatialModel& m, double* Sc);
 

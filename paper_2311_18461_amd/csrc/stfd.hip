@@ -168,6 +168,7 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int a0 = wave * 16;
   const int col = lane & 15, grp = lane >> 4;
+  const double* Uo = a.U + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0);
   // this wave's operand fragments of U'^T: element (m = col, k = K/4*grp + e) of each K step
   op_t ua[KSTEPS_MAX][K / 4];
 #pragma unroll
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
     for (int e = 0; e < K / 4; ++e) {
       const int j = ks * K + (K / 4) * grp + e;
       const int aa = a0 + col;
-      const double v = a.U[min(j, n - 1) * n + min(aa, n - 1)];
+      const double v = Uo[min(j, n - 1) * n + min(aa, n - 1)];
       ua[ks][e] = to_op<PREC>((ks < nks && j < n && aa < n) ? v : 0.0);
     }
   // stage the input tile tile[j*RT + r] = In[o][j][row0 + r]: batches of loads from clamped
@@ -922,6 +923,7 @@ struct stfd_problem {
   stfd::PcgScalars* sc_host = nullptr;  // pinned host ring [kLag][max_nrhs], written by kernels
   stfd::PcgScalars* sc_host_dev = nullptr;  // device address of sc_host
   int64_t mp_last_blocks = 0;            // blocks per rhs of the last mode product (dot partials)
+  int64_t u_slice0 = 0;                  // per-mode pencils along x_1 (mapped domain): n_1^2, else 0
   int64_t mv_blocks = 0;
   size_t max_lds = 65536;  // per-block LDS limit of the device used at setup
   stfd::LoadPlan load;     // basis matrices on the Gauss grids (right-hand side assembly)
@@ -982,11 +984,12 @@ struct DotEpilogue {
 template <int PREC, typename Tin, typename Tout>
 static int launch_mode_product(const void* in, void* out, const double* U, int n, int64_t inner, int64_t outer,
                                int64_t outer_per_rhs, const int* done, hipStream_t s,
-                               const DotEpilogue& ep = DotEpilogue()) {
+                               const DotEpilogue& ep = DotEpilogue(), int64_t u_slice_stride = 0) {
   ModeProductArgs a;
   a.in = in;
   a.out = out;
   a.U = U;
+  a.u_slice_stride = u_slice_stride;
   a.n = n;
   a.inner = inner;
   a.outer = outer;
@@ -1054,31 +1057,44 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
     outer[l] = above * nrhs;
     below *= hp.n_s[l];
   }
+  // forward order of the directions (the backward products run in reverse): x_1 first on
+  // the unit cube; on a mapped domain the per-mode direction x_1 must act on the modes of x_2,
+  // so x_2 goes first
+  int order[3] = {0, 1, 2};
+  if (P->u_slice0)
+    for (int k = 0; k < d; ++k) order[k] = d - 1 - k;
+  auto slice = [&](int l) -> int64_t { return l == 0 ? P->u_slice0 : 0; };
   int rc;
-  // step 2: y = (U_s^T (x) I) r, directions 1..d; r (FP64) -> w0 -> w1 -> ...
+  // step 2: y = (U_s^T (x) I) r; r (FP64) -> w0 -> w1 -> ...
   TW* bufs[2] = {w0, w1};
   int cur = 0;
-  rc = launch_mode_product<PREC, double, TW>(r, bufs[cur], P->U_fwd[0], hp.n_s[0], inner[0], outer[0], outer_rhs[0],
-                                             done, s);
-  if (rc) return rc;
-  for (int l = 1; l < d; ++l) {
+  {
+    const int l = order[0];
+    rc = launch_mode_product<PREC, double, TW>(r, bufs[cur], P->U_fwd[l], hp.n_s[l], inner[l], outer[l], outer_rhs[l],
+                                               done, s, DotEpilogue(), slice(l));
+    if (rc) return rc;
+  }
+  for (int k = 1; k < d; ++k) {
+    const int l = order[k];
     rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], P->U_fwd[l], hp.n_s[l], inner[l], outer[l],
-                                           outer_rhs[l], done, s);
+                                           outer_rhs[l], done, s, DotEpilogue(), slice(l));
     if (rc) return rc;
     cur ^= 1;
   }
   // step 3: N_s independent banded time solves, in place
   rc = launch_time_solve<TW>(P, bufs[cur], nrhs, done, s);
   if (rc) return rc;
-  // step 4: s = (U_s (x) I) x, directions d..1, last product writes FP64 output
-  for (int l = d - 1; l >= 1; --l) {
+  // step 4: s = (U_s (x) I) x in reverse order, the last product writes FP64 output
+  for (int k = d - 1; k >= 1; --k) {
+    const int l = order[k];
     rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], P->U_bwd[l], hp.n_s[l], inner[l], outer[l],
-                                           outer_rhs[l], done, s);
+                                           outer_rhs[l], done, s, DotEpilogue(), slice(l));
     if (rc) return rc;
     cur ^= 1;
   }
-  return launch_mode_product<PREC, TW, double>(bufs[cur], s_out, P->U_bwd[0], hp.n_s[0], inner[0], outer[0],
-                                               outer_rhs[0], done, s, ep);
+  const int l = order[0];
+  return launch_mode_product<PREC, TW, double>(bufs[cur], s_out, P->U_bwd[l], hp.n_s[l], inner[l], outer[l],
+                                               outer_rhs[l], done, s, ep, slice(l));
 }
 
 static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64_t nrhs, int precision,
@@ -1265,17 +1281,32 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   }
   P->max_nrhs = desc->max_nrhs;
   P->n2 = 2 * hp.N;
-  // pencils: forward operand U, backward operand U^T
+  // on the quarter annulus P-hat uses the physical mass and stiffness matrices (two-level
+  // pencils) unless the parametric one is requested
+  if (geom.kind == GEOM_QUARTER_ANNULUS && desc->precond == STFD_PRECOND_AUTO) {
+    const int gp = geometry_pencils(P->hp, geom);
+    if (gp) {
+      delete P;
+      return gp == -2 ? STFD_ENOTSPD : STFD_EINVAL;
+    }
+  }
+  // pencils: forward operand U, backward operand U^T (direction 0 of a mapped domain: one
+  // matrix per mode of direction 1)
   for (int l = 0; l < hp.d; ++l) {
     const int n = hp.n_s[l];
-    std::vector<double> Ut(size_t(n) * n);
-    for (int j = 0; j < n; ++j)
-      for (int a = 0; a < n; ++a) Ut[size_t(j) * n + a] = hp.U[l][size_t(a) * n + j];
-    if ((rc = upload(P, &P->U_fwd[l], hp.U[l].data(), hp.U[l].size())) ||
-        (rc = upload(P, &P->U_bwd[l], Ut.data(), Ut.size()))) {
+    const bool sliced = (l == 0 && !hp.Uslice.empty());
+    const std::vector<double>& Uf = sliced ? hp.Uslice : hp.U[l];
+    const int nsl = sliced ? hp.n_s[1] : 1;
+    std::vector<double> Ut(Uf.size());
+    for (int k = 0; k < nsl; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int a = 0; a < n; ++a)
+          Ut[(size_t(k) * n + j) * n + a] = Uf[(size_t(k) * n + a) * n + j];
+    if ((rc = upload(P, &P->U_fwd[l], Uf.data(), Uf.size())) || (rc = upload(P, &P->U_bwd[l], Ut.data(), Ut.size()))) {
       stfd_destroy(P);
       return rc;
     }
+    if (sliced) P->u_slice0 = int64_t(n) * n;
   }
   {
     int dev = 0, lds = 0;
@@ -1346,9 +1377,13 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   // matvec launch shape: one wave per spatial point, kMvWaves points per block
   P->mv_blocks = (hp.N_s + kMvWaves - 1) / kMvWaves;
   {
+    // the last backward product runs along x_1 (unit cube) or along x_d (mapped domain)
     int64_t outer0 = 1;
     for (int l = 1; l < hp.d; ++l) outer0 *= hp.n_s[l];
-    P->mp_last_blocks = mode_product_blocks_per_rhs(2 * int64_t(hp.n_t), outer0);
+    if (P->u_slice0)
+      P->mp_last_blocks = mode_product_blocks_per_rhs(2 * int64_t(hp.n_t) * (hp.N_s / hp.n_s[hp.d - 1]), 1);
+    else
+      P->mp_last_blocks = mode_product_blocks_per_rhs(2 * int64_t(hp.n_t), outer0);
   }
   P->max_parts = std::max<int64_t>(std::max<int64_t>(P->mv_blocks, P->mp_last_blocks), kVecGrid);
   if ((rc = dev_alloc(P, &P->parts, size_t(6) * P->max_parts * P->max_nrhs)) ||

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libstfd.so")
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EHIP = 0, 1, -1, -2, -3, -4, -5
 FP64, FP32, BF16 = 0, 1, 2
 GEOM_UNIT_CUBE, GEOM_QUARTER_ANNULUS = 0, 1
+PRECOND_AUTO, PRECOND_PARAMETRIC = 0, 1
 X0_ZERO, X0_GIVEN, PCG_GRAPH = 0, 1, 2
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
@@ -28,7 +29,8 @@ class SetupDesc(ctypes.Structure):
                 ("knots_s", ctypes.POINTER(ctypes.c_double) * 3), ("n_knots_s", ctypes.c_int * 3),
                 ("T", ctypes.c_double), ("nu", ctypes.c_double),
                 ("V_quad", ctypes.POINTER(ctypes.c_double)), ("n_quad", ctypes.c_int),
-                ("max_nrhs", ctypes.c_int), ("geometry", ctypes.c_int), ("geom", ctypes.c_double * 2)]
+                ("max_nrhs", ctypes.c_int), ("geometry", ctypes.c_int), ("geom", ctypes.c_double * 2),
+                ("precond", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -159,7 +161,8 @@ class Problem:
     """Handle of one set-up problem (stfd_setup / stfd_destroy)."""
 
     def __init__(self, knots_t, knots_s, p_t: int, p_s: int, T: float = 1.0, nu: float = 1.0,
-                 V_quad=None, n_quad: int = 0, max_nrhs: int = 1, geometry=GEOM_UNIT_CUBE, radii=(1.0, 2.0)):
+                 V_quad=None, n_quad: int = 0, max_nrhs: int = 1, geometry=GEOM_UNIT_CUBE, radii=(1.0, 2.0),
+                 precond=PRECOND_AUTO):
         d = len(knots_s)
         self._keep = [np.ascontiguousarray(knots_t, dtype=np.float64)]
         desc = SetupDesc()
@@ -182,6 +185,7 @@ class Problem:
         desc.n_quad, desc.max_nrhs = n_quad, max_nrhs
         desc.geometry = geometry
         desc.geom[0], desc.geom[1] = radii
+        desc.precond = precond
         h = ctypes.c_void_p()
         self._h = None
         _check(_lib().stfd_setup(ctypes.byref(desc), ctypes.byref(h)), "stfd_setup")

@@ -1,0 +1,232 @@
+"""Learned warm start for PCG on the quarter-annulus workload (driver; every computation runs
+in the library's kernels through the C ABI).
+
+Workload: quarter annulus r in [1, 2] (exact rational quadratic map), 2D space + time, p = 4,
+64^3 elements (n_s = 66, n_t = 67, N = 291,852), T = 1, nu = 1, f = 0, homogeneous Dirichlet
+data; per sample a seeded sum of 4-12 Gaussians V and a seeded wave-packet initial datum.
+The network sees, on the 66 x 66 Greville grid of the free spatial basis, the channels
+(V / 50, Re u0, Im u0, rho, theta) and predicts the 2 n_t = 134 real channels of the free
+solution coefficients at each spatial function, i.e. the PCG unknown itself.  Training data
+are FP64 PCG solutions (tol 1e-8) of the training seeds stored as FP32; the loss is the mean
+relative l2 error; Adam with a cosine learning-rate decay.  At solve time the prediction is
+an initial guess; if its residual exceeds that of x_0 = 0 the solver falls back to the cold
+start.
+
+    python -m paper_2311_18461_amd.warmstart train --out W.npz [--n-train 2000 --epochs 60]
+    python -m paper_2311_18461_amd.warmstart evaluate --weights W.npz [--n-test 200]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import inputs, stfd
+
+N_EL, P = 64, 4
+TRAIN_SEED0, N_TRAIN = 5000, 2000
+TEST_SEED0, N_TEST = 7000, 200
+V_SCALE = 1.0 / 50.0
+NET = dict(width=32, modes1=16, modes2=16, layers=4, proj=128)
+
+
+def greville(knots, p):
+    """Greville abscissae (averages of p consecutive interior knots) of every B-spline."""
+    kn = np.asarray(knots, dtype=np.float64)
+    m = len(kn) - p - 1
+    return np.array([kn[i + 1:i + p + 1].mean() for i in range(m)])
+
+
+class AnnulusWorkload:
+    def __init__(self, n_el=N_EL, p=P, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.dev, self.stream = device, stream
+        kn = inputs.uniform_open_knots(n_el, p)
+        self.prob = stfd.Problem(kn, [kn, kn], p, p, 1.0, 1.0, max_nrhs=1, geometry=stfd.GEOM_QUARTER_ANNULUS,
+                                 radii=inputs.ANNULUS_RADII)
+        self.N = self.prob.N
+        self.n_t = self.prob.n_t
+        self.ns = self.prob.n_s[0]
+        self.quad_xy = self.prob.physical_grid()
+        g = greville(kn, p)[1:-1]  # free functions only
+        R, T = np.meshgrid(g, g, indexing="xy")  # (i2, i1) arrays, i1 (rho) fastest
+        self.rt = np.stack([R.ravel(), T.ravel()], axis=1)
+        xy = self.prob.map_points(self.rt)
+        self.feat_xy = (xy[:, 0], xy[:, 1])
+        self.c_out = 2 * self.n_t
+
+    def features(self, V, u0):
+        u = u0(*self.feat_xy)
+        f = np.stack([V(*self.feat_xy) * V_SCALE, u.real, u.imag, self.rt[:, 0], self.rt[:, 1]], axis=1)
+        return f.astype(np.float32).reshape(self.ns, self.ns, 5)
+
+    def rhs(self, V, u0, fbar):
+        self.prob.update_potential(V(*self.quad_xy), stream=self.stream)
+        u0q = self.torch.from_numpy(np.ascontiguousarray(u0(*self.quad_xy))).to(self.dev)
+        self.prob.load_vector(fbar, u0_q=u0q, stream=self.stream)
+
+    def solve(self, f, u, x0_given=False, maxit=5000):
+        return self.prob.pcg_solve(f, u, rtol=1e-8, maxit=maxit, x0_given=x0_given, stream=self.stream)
+
+
+def make_net(wl, max_batch, seed=0):
+    return stfd.Fno(H=wl.ns, W=wl.ns, c_in=5, c_out=wl.c_out, max_batch=max_batch, seed=seed, **NET)
+
+
+def generate(wl, seed0, count, log=None):
+    """Features (host) and FP32 targets (device) of `count` consecutive seeds, solved cold."""
+    torch = wl.torch
+    feats = np.empty((count, wl.ns, wl.ns, 5), dtype=np.float32)
+    targets = torch.empty((count, 2 * wl.N), dtype=torch.float32, device=wl.dev)
+    f = torch.empty(wl.N, dtype=torch.complex128, device=wl.dev)
+    u = torch.empty_like(f)
+    iters = []
+    t0 = time.perf_counter()
+    for k in range(count):
+        V, u0 = inputs.annulus_sample(seed0 + k)
+        feats[k] = wl.features(V, u0)
+        wl.rhs(V, u0, f)
+        rc, info = wl.solve(f, u)
+        if info[0]["status"] != 0:
+            raise RuntimeError(f"seed {seed0 + k}: PCG status {info[0]['status']}")
+        iters.append(info[0]["iters"])
+        targets[k] = torch.view_as_real(u).reshape(-1).float()
+        if log and (k + 1) % 50 == 0:
+            log({"phase": "data", "done": k + 1, "of": count, "s": round(time.perf_counter() - t0, 1),
+                 "mean_iters": float(np.mean(iters))})
+    return feats, targets, iters
+
+
+def train(wl, feats, targets, epochs=60, batch=16, lr=1e-3, seed=0, log=None):
+    torch = wl.torch
+    n = feats.shape[0]
+    net = make_net(wl, batch, seed)
+    X = torch.from_numpy(feats).to(wl.dev)
+    y = torch.empty((batch, wl.ns * wl.ns * wl.c_out), dtype=torch.float32, device=wl.dev)
+    dy = torch.empty_like(y)
+    rng = np.random.default_rng(seed)
+    steps = epochs * (n // batch)
+    step = 0
+    t0 = time.perf_counter()
+    hist = []
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        losses = []
+        for b0 in range(0, n - batch + 1, batch):
+            idx = torch.from_numpy(perm[b0:b0 + batch]).to(wl.dev)
+            xb = X[idx].contiguous().view(-1)
+            tb = targets[idx].contiguous().view(-1)
+            net.forward(xb, y.view(-1), batch, stream=wl.stream)
+            losses.append(stfd.fno_rel_l2(y.view(-1), tb, y.shape[1], batch, dy=dy.view(-1), stream=wl.stream))
+            net.backward(dy.view(-1), batch, stream=wl.stream)
+            cur = 0.5 * lr * (1.0 + math.cos(math.pi * step / max(steps, 1)))
+            net.adam_step(cur, stream=wl.stream)
+            step += 1
+        hist.append(float(np.mean(losses)))
+        if log:
+            log({"phase": "train", "epoch": ep + 1, "loss": round(hist[-1], 5), "s": round(time.perf_counter() - t0, 1)})
+    return net, hist
+
+
+def evaluate(wl, net, seed0=TEST_SEED0, count=N_TEST, log=None):
+    """Cold vs warm PCG on held-out seeds; warm time includes inference and the fallback test."""
+    torch = wl.torch
+    f = torch.empty(wl.N, dtype=torch.complex128, device=wl.dev)
+    u = torch.empty_like(f)
+    x0 = torch.empty_like(f)
+    y = torch.empty(wl.ns * wl.ns * wl.c_out, dtype=torch.float32, device=wl.dev)
+    rows = []
+    for k in range(count):
+        V, u0 = inputs.annulus_sample(seed0 + k)
+        xf = torch.from_numpy(wl.features(V, u0)).to(wl.dev).view(-1)
+        wl.rhs(V, u0, f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, ic = wl.solve(f, u)
+        torch.cuda.synchronize()
+        t_cold = time.perf_counter() - t0
+        ref = u.clone()
+        t0 = time.perf_counter()
+        net.forward(xf, y, 1, stream=wl.stream)
+        stfd.fno_to_f64(y, x0, y.numel(), stream=wl.stream)
+        u.copy_(x0)
+        _, i0 = wl.prob.pcg_solve(f, u, rtol=1e-8, maxit=0, x0_given=True, stream=wl.stream, check=False)
+        fallback = not (i0[0]["true_rel_res"] < 1.0)
+        if fallback:
+            _, iw = wl.solve(f, u)
+        else:
+            u.copy_(x0)
+            _, iw = wl.solve(f, u, x0_given=True)
+        torch.cuda.synchronize()
+        t_warm = time.perf_counter() - t0
+        diff = (torch.linalg.norm(u - ref) / torch.linalg.norm(ref)).item()
+        rows.append(dict(seed=seed0 + k, cold_iters=ic[0]["iters"], warm_iters=iw[0]["iters"],
+                         cold_ms=t_cold * 1e3, warm_ms=t_warm * 1e3, x0_rel_res=i0[0]["true_rel_res"],
+                         fallback=fallback, warm_true_rel_res=iw[0]["true_rel_res"], solution_diff=diff))
+        if log and (k + 1) % 20 == 0:
+            log({"phase": "eval", "done": k + 1, "of": count})
+    return rows
+
+
+def summarize(rows):
+    a = lambda key: np.array([r[key] for r in rows], dtype=np.float64)  # noqa: E731
+    return {"samples": len(rows), "cold_iters_mean": float(a("cold_iters").mean()),
+            "warm_iters_mean": float(a("warm_iters").mean()), "cold_ms_mean": float(a("cold_ms").mean()),
+            "warm_ms_mean": float(a("warm_ms").mean()),
+            "speedup_time": float(a("cold_ms").mean() / a("warm_ms").mean()),
+            "x0_rel_res_median": float(np.median(a("x0_rel_res"))),
+            "fallbacks": int(a("fallback").sum()),
+            "max_warm_true_rel_res": float(a("warm_true_rel_res").max()),
+            "max_solution_diff": float(a("solution_diff").max())}
+
+
+def load_net(wl, path, max_batch=1):
+    theta = np.load(path)["theta"]
+    net = make_net(wl, max_batch)
+    net.set_params(theta)
+    return net
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train", "evaluate"])
+    ap.add_argument("--out", default="warmstart_weights.npz")
+    ap.add_argument("--weights", default="warmstart_weights.npz")
+    ap.add_argument("--n-train", type=int, default=N_TRAIN)
+    ap.add_argument("--n-test", type=int, default=N_TEST)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--n-el", type=int, default=N_EL)
+    ap.add_argument("--results", default=None, help="write per-seed evaluation rows (JSON) here")
+    args = ap.parse_args(argv)
+    import torch
+    torch.cuda.init()
+
+    def log(d):
+        print(json.dumps(d), flush=True)
+    wl = AnnulusWorkload(n_el=args.n_el)
+    if args.cmd == "train":
+        feats, targets, iters = generate(wl, TRAIN_SEED0, args.n_train, log)
+        log({"phase": "data_done", "mean_iters": float(np.mean(iters)), "max_iters": int(np.max(iters))})
+        net, hist = train(wl, feats, targets, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+        np.savez_compressed(args.out, theta=net.get_params(), loss=np.array(hist))
+        del targets
+        rows = evaluate(wl, net, TEST_SEED0, args.n_test, log)
+    else:
+        net = load_net(wl, args.weights)
+        rows = evaluate(wl, net, TEST_SEED0, args.n_test, log)
+    if args.results:
+        with open(args.results, "w") as fh:
+            json.dump(rows, fh)
+    log({"phase": "summary", **summarize(rows)})
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

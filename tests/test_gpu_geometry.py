@@ -11,7 +11,8 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle.geometry import QuarterAnnulus  # noqa: E402
-from oracle.operators import FastDiagonalization, Problem as OProblem  # noqa: E402
+from oracle.operators import (FastDiagonalization, MappedFastDiagonalization, Problem as OProblem,  # noqa: E402
+                              dense_P_mapped)
 from oracle.pcg import pcg  # noqa: E402
 from oracle.rhs import SpaceTimeBasis, assemble_rhs  # noqa: E402
 from paper_2311_18461_amd import inputs  # noqa: E402
@@ -26,11 +27,12 @@ def _stfd():
     return stfd
 
 
-def annulus_problem(n_el, p, V=None, max_nrhs=1):
+def annulus_problem(n_el, p, V=None, max_nrhs=1, parametric=False):
     stfd = _stfd()
     kt, ks = inputs.uniform_open_knots(n_el, p), [inputs.uniform_open_knots(n_el, p)] * 2
     pr = stfd.Problem(kt, ks, p, p, 1.0, 1.0, max_nrhs=max_nrhs, geometry=stfd.GEOM_QUARTER_ANNULUS,
-                      radii=inputs.ANNULUS_RADII)
+                      radii=inputs.ANNULUS_RADII,
+                      precond=stfd.PRECOND_PARAMETRIC if parametric else stfd.PRECOND_AUTO)
     if V is not None:
         x, y = pr.physical_grid()
         pr.update_potential(V(x, y))
@@ -81,7 +83,7 @@ def test_annulus_pcg_and_load_vector_vs_oracle():
     err_f = np.linalg.norm(fb.cpu().numpy() - fb_ref) / np.linalg.norm(fb_ref)
     u = torch.empty_like(fb)
     rc, info = pr.pcg_solve(fb, u, rtol=1e-8, maxit=1000)
-    x_ref, oinfo = pcg(ref.matvec, FastDiagonalization(ref).apply, fb_ref, tol=1e-8, maxit=1000)
+    x_ref, oinfo = pcg(ref.matvec, MappedFastDiagonalization(ref).apply, fb_ref, tol=1e-8, maxit=1000)
     err_x = np.linalg.norm(u.cpu().numpy() - x_ref) / np.linalg.norm(x_ref)
     print(f"annulus load vector err {err_f:.2e}; pcg iters {info[0]['iters']} (oracle {oinfo['iters']}), "
           f"solution diff {err_x:.2e}")
@@ -121,3 +123,47 @@ def test_update_potential_equals_fresh_setup(geom):
     a.load_vector(fa, u0_q=u0q)
     b.load_vector(fb, u0_q=u0q)
     assert torch.equal(fa, fb)
+
+
+def test_annulus_preconditioner_vs_dense_inverse():
+    """The two-level FD apply inverts eq. prec_definition written with the physical M and L."""
+    pr, ref = annulus_problem(3, 3)
+    P = dense_P_mapped(ref)
+    r = inputs.random_complex(pr.N, 21)
+    s = torch.empty(pr.N, dtype=torch.complex128, device=DEV)
+    pr.apply_preconditioner(to_dev(r), s)
+    sv = s.cpu().numpy()
+    back = np.linalg.norm(P @ sv - r) / (np.linalg.norm(P, 2) * np.linalg.norm(sv))
+    assert back < 1e-15
+
+
+@pytest.mark.parametrize("n_el,p", [(12, 3), (24, 4)])
+def test_annulus_preconditioner_vs_oracle_fd(n_el, p):
+    pr, ref = annulus_problem(n_el, p)
+    r = inputs.random_complex(pr.N, 22)
+    s = torch.empty(pr.N, dtype=torch.complex128, device=DEV)
+    pr.apply_preconditioner(to_dev(r), s)
+    want = MappedFastDiagonalization(ref).apply(r)
+    err = np.linalg.norm(s.cpu().numpy() - want) / np.linalg.norm(want)
+    print(f"annulus FD apply n_el={n_el} p={p}: {err:.2e}")
+    assert err < 1e-10
+
+
+def test_annulus_physical_preconditioner_is_h_robust():
+    """V = 0 on the annulus: the parametric P-hat loses h-robustness (the dispersion of the mapped
+    operator differs), the physical-pencil P-hat does not."""
+    u0 = inputs.annulus_wave_packet(3)
+    its = {}
+    for param in (False, True):
+        for n_el in (8, 16):
+            pr, _ = annulus_problem(n_el, 4, parametric=param)
+            x, y = pr.physical_grid()
+            fb = torch.empty(pr.N, dtype=torch.complex128, device=DEV)
+            pr.load_vector(fb, u0_q=to_dev(u0(x, y)))
+            u = torch.empty_like(fb)
+            rc, info = pr.pcg_solve(fb, u, rtol=1e-8, maxit=3000)
+            assert rc == 0
+            its[(param, n_el)] = info[0]["iters"]
+    print("annulus iterations (parametric, n_el):", its)
+    assert its[(False, 16)] <= 20 and its[(False, 16)] <= its[(False, 8)] + 3
+    assert its[(True, 16)] > 5 * its[(False, 16)]

@@ -130,3 +130,17 @@ def test_annulus_system_is_hermitian_positive_definite():
     for S in pr.S:
         Sd = S.toarray()
         assert np.max(np.abs(Sd - Sd.T)) < 1e-12 * np.max(np.abs(Sd))
+
+
+def test_mapped_fd_inverts_the_dense_mapped_preconditioner():
+    """The oracle's mapped FD (one dense 2D eigenproblem) equals the inverse of eq. prec_definition
+    written with the physical M and L."""
+    from oracle.operators import MappedFastDiagonalization, dense_P_mapped
+    g = QuarterAnnulus(1.0, 2.0)
+    kn = inputs.uniform_open_knots(3, 3)
+    pr = Problem(kn, [kn, kn], 3, 3, 1.0, None, geometry=g)
+    P = dense_P_mapped(pr)
+    r = inputs.random_complex(pr.N, 4)
+    s = MappedFastDiagonalization(pr).apply(r)
+    assert np.linalg.norm(P @ s - r) < 1e-11 * np.linalg.norm(r)
+    assert np.max(np.abs(P - P.conj().T)) < 1e-12 * np.max(np.abs(P))
