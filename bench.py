@@ -100,6 +100,24 @@ def batched_section(dev, stream, reps=3):
             "max_true_rel_res": float(f"{max(i['true_rel_res'] for i in info):.3e}")}
 
 
+WARMSTART_WEIGHTS = os.path.join(ROOT, "paper_2311_18461_amd", "data", "warmstart_annulus_p4_n64.npz")
+
+
+def warmstart_section(stream, n_eval=20):
+    """Learned warm start on the quarter-annulus workload (p = 4, 64^3): cold vs warm PCG on the
+    first n_eval held-out seeds with the trained network (training: warmstart.py train)."""
+    from paper_2311_18461_amd import warmstart
+    if not os.path.exists(WARMSTART_WEIGHTS):
+        return {"skipped": "no trained weights in paper_2311_18461_amd/data"}
+    wl = warmstart.AnnulusWorkload(stream=stream)
+    net = warmstart.load_net(wl, WARMSTART_WEIGHTS)
+    rows = warmstart.evaluate(wl, net, warmstart.TEST_SEED0, n_eval)
+    out = warmstart.summarize(rows)
+    out["held_out_seeds"] = [warmstart.TEST_SEED0, warmstart.TEST_SEED0 + n_eval - 1]
+    out["n_dof_free"] = wl.N
+    return out
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The oracle (FP64 NumPy/SciPy, all host cores): right-hand side with lifting, then PCG to 1e-8,
     on the same workload (setup excluded)."""
@@ -277,6 +295,7 @@ def main():
         "roofline": roofline,
     }
     out["batched"] = batched_section(dev, stream)
+    out["warm_start"] = warmstart_section(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

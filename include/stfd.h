@@ -59,9 +59,13 @@ typedef enum {
   STFD_BF16 = 2  /* BF16 MFMA mode products with FP32 accumulation, FP32 time solves */
 } stfd_precision;
 
-/* pcg flags: the initial guess (one of the first two), optionally or-ed with
- * STFD_PCG_GRAPH to replay each iteration from a captured HIP graph. */
-enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1, STFD_PCG_GRAPH = 2 };
+/* pcg flags: the initial guess (STFD_X0_ZERO, STFD_X0_GIVEN, or STFD_X0_GIVEN |
+ * STFD_X0_SCALED), optionally or-ed with STFD_PCG_GRAPH to replay each iteration from a
+ * captured HIP graph.  STFD_X0_SCALED replaces the given x0 by alpha x0 with
+ * alpha = Re<x0, f> / <x0, A x0>, the multiple closest to the solution in the A-norm (the
+ * norm CG minimises); alpha = 0 (a cold start) when Re<x0, f> <= 0, so a poor guess (for
+ * instance a learned prediction) can never start CG farther from the solution than x0 = 0. */
+enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1, STFD_PCG_GRAPH = 2, STFD_X0_SCALED = 4 };
 
 /* Physical domain.  STFD_GEOM_UNIT_CUBE: Omega = (0,1)^d, x = xi.
  * STFD_GEOM_QUARTER_ANNULUS (d = 2): x = (r0 + (r1 - r0) xi_1) c(xi_2) with c the
@@ -117,6 +121,7 @@ typedef struct {
   int status;          /* stfd_status of this right-hand side */
   double rel_res;      /* ||r_k||_2 / ||f||_2 of the recursively updated residual */
   double true_rel_res; /* ||f - A u||_2 / ||f||_2 recomputed with the FP64 matvec */
+  double x0_scale;     /* factor applied to the initial guess (0: cold start, 1: as given) */
 } stfd_pcg_info;
 
 /* Element-wise Gauss-Legendre rule on the non-empty knot spans of an open

@@ -653,6 +653,7 @@ struct PcgScalars {
   int status;
   int done;
   int kcur;  // iteration index of the iteration in flight (set by pcg_update_xr)
+  double x0_scale;  // factor applied to a given initial guess (0: cold start)
 };
 
 // partial sums of Re<a, b> (and optionally Re<a, c>) over this block's range
@@ -704,8 +705,39 @@ __global__ __launch_bounds__(kVecBlock) void pcg_init_kernel(const double* f, co
 }
 
 // scalar bookkeeping after the initial residual: ||f||^2, ||r_0||, convergence at k = 0
+// Energy-optimal scaling of a given initial guess: with q = A x0, alpha = Re<x0, f> / <x0, q>
+// minimises ||u - alpha x0||_A (u = A^{-1} f); alpha <= 0 (or a non-finite value) means x0 does
+// not help and the start becomes x0 = 0.  x <- alpha x, r = f - alpha q, partials of ||f||^2.
+__global__ __launch_bounds__(kVecBlock) void pcg_x0_scale_kernel(const double* f, const double* q, double* r,
+                                                                  double* x, int64_t n2, const double* pxf,
+                                                                  const double* pxq, int nparts, double* pf,
+                                                                  PcgScalars* sc) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.y;
+  const double xf = sum_partials<kVecBlock>(pxf + rhs * nparts, nparts, sh);
+  const double xq = sum_partials<kVecBlock>(pxq + rhs * nparts, nparts, sh);
+  double alpha = xf / xq;
+  if (!(xq > 0.0) || !(xf > 0.0) || !std::isfinite(alpha)) alpha = 0.0;
+  const double* F = f + rhs * n2;
+  const double* Q = q + rhs * n2;
+  double* R = r + rhs * n2;
+  double* X = x + rhs * n2;
+  double s = 0.0;
+  for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
+    const double fr = F[k], fi = F[k + 1];
+    s += fr * fr + fi * fi;
+    R[k] = fr - alpha * Q[k];
+    R[k + 1] = fi - alpha * Q[k + 1];
+    X[k] *= alpha;
+    X[k + 1] *= alpha;
+  }
+  s = block_sum<kVecBlock>(s, sh);
+  if (threadIdx.x == 0) pf[rhs * gridDim.x + blockIdx.x] = s;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[rhs].x0_scale = alpha;
+}
 __global__ __launch_bounds__(kVecBlock) void pcg_start_kernel(const double* pf, const double* prr, int nparts,
-                                                               PcgScalars* sc, int* done, double tol, int* ctr) {
+                                                               PcgScalars* sc, int* done, double tol, int* ctr,
+                                                               int x0_mode) {
   __shared__ double sh[kVecBlock / 64];
   const int rhs = blockIdx.x;
   if (rhs == 0 && threadIdx.x == 0) ctr[0] = 0;
@@ -716,6 +748,7 @@ __global__ __launch_bounds__(kVecBlock) void pcg_start_kernel(const double* pf, 
     s.nf2 = nf2;
     s.iters = 0;
     s.kcur = 0;
+    if (x0_mode != 2) s.x0_scale = (x0_mode == 1) ? 1.0 : 0.0;
     s.status = STFD_OK;
     s.done = 0;
     s.rz[0] = s.rz[1] = 0.0;
@@ -1547,16 +1580,24 @@ static int pcg_init(const PcgJob& J, int flags, int precision, double rtol, hipS
   double* pb = pa + P->max_parts * P->max_nrhs;
   const dim3 vgrid(kVecGrid, unsigned(J.nrhs)), vblock(kVecBlock);
   int rc;
-  if (flags == STFD_X0_GIVEN) {
+  if (flags & STFD_X0_GIVEN) {
     if ((rc = matvec_dispatch(P, J.x, q, J.nrhs, nullptr, nullptr, s))) return rc;
-    hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, J.f, q, r, J.x, n2, pa);
+    int mode = 1;
+    if (flags & STFD_X0_SCALED) {
+      double* pc = pb + P->max_parts * P->max_nrhs;
+      hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, J.x, J.f, q, n2, pb, pc, nullptr);
+      hipLaunchKernelGGL(pcg_x0_scale_kernel, vgrid, vblock, 0, s, J.f, q, r, J.x, n2, pb, pc, kVecGrid, pa, P->sc);
+      mode = 2;
+    } else {
+      hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, J.f, q, r, J.x, n2, pa);
+    }
     hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, r, r, nullptr, n2, pb, nullptr, nullptr);
     hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(J.nrhs)), vblock, 0, s, pa, pb, kVecGrid, P->sc, P->done, rtol,
-                       P->ctr);
+                       P->ctr, mode);
   } else {
     hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, J.f, nullptr, r, J.x, n2, pa);
     hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(J.nrhs)), vblock, 0, s, pa, nullptr, kVecGrid, P->sc, P->done,
-                       rtol, P->ctr);
+                       rtol, P->ctr, 0);
   }
   STFD_HIP(hipGetLastError());
   if ((rc = apply_dispatch(P, r, z, J.nrhs, precision, P->done, s))) return rc;
@@ -1629,6 +1670,7 @@ static int pcg_finish(const PcgJob& J, stfd_pcg_info* info, hipStream_t s) {
       info[rr].status = st;
       info[rr].rel_res = sc.res;
       info[rr].true_rel_res = sc.true_res;
+      info[rr].x0_scale = sc.x0_scale;
     }
     if (st == STFD_EBREAKDOWN) status = STFD_EBREAKDOWN;
     else if (st == STFD_NOT_CONVERGED && status == STFD_OK) status = STFD_NOT_CONVERGED;
@@ -1777,7 +1819,7 @@ int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64
   stfd_problem* P = const_cast<stfd_problem*>(Pc);
   if (!P || !f_dev || !u_dev || nrhs < 1 || nrhs > P->max_nrhs || maxit < 0 || !(rtol >= 0.0)) return STFD_EINVAL;
   const int x0 = flags & ~STFD_PCG_GRAPH;
-  if (x0 != STFD_X0_ZERO && x0 != STFD_X0_GIVEN) return STFD_EINVAL;
+  if (x0 != STFD_X0_ZERO && x0 != STFD_X0_GIVEN && x0 != (STFD_X0_GIVEN | STFD_X0_SCALED)) return STFD_EINVAL;
   if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
   std::vector<PcgJob> jobs(1);
   jobs[0].P = P;
@@ -1795,7 +1837,7 @@ int stfd_pcg_solve_batched(const stfd_problem* const* probs, int count, const vo
   if (!probs || !f_dev || !u_dev || !nrhs || count < 1 || count > 64 || maxit < 0 || !(rtol >= 0.0))
     return STFD_EINVAL;
   const int x0 = flags & ~STFD_PCG_GRAPH;
-  if (x0 != STFD_X0_ZERO && x0 != STFD_X0_GIVEN) return STFD_EINVAL;
+  if (x0 != STFD_X0_ZERO && x0 != STFD_X0_GIVEN && x0 != (STFD_X0_GIVEN | STFD_X0_SCALED)) return STFD_EINVAL;
   if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
   std::vector<PcgJob> jobs(static_cast<size_t>(count));
   int64_t total = 0;

@@ -19,7 +19,7 @@ OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, ENOMEM, EHIP = 0, 1, -1, -2, -3,
 FP64, FP32, BF16 = 0, 1, 2
 GEOM_UNIT_CUBE, GEOM_QUARTER_ANNULUS = 0, 1
 PRECOND_AUTO, PRECOND_PARAMETRIC = 0, 1
-X0_ZERO, X0_GIVEN, PCG_GRAPH = 0, 1, 2
+X0_ZERO, X0_GIVEN, PCG_GRAPH, X0_SCALED = 0, 1, 2, 4
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
 
@@ -35,7 +35,7 @@ class SetupDesc(ctypes.Structure):
 
 class PcgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int), ("rel_res", ctypes.c_double),
-                ("true_rel_res", ctypes.c_double)]
+                ("true_rel_res", ctypes.c_double), ("x0_scale", ctypes.c_double)]
 
 
 class FnoDesc(ctypes.Structure):
@@ -314,10 +314,12 @@ class Problem:
                                          nrhs, _stream_ptr(stream)), "stfd_matvec")
 
     def pcg_solve(self, f, u, nrhs: int = 1, rtol: float = 1e-8, maxit: int = 200, x0_given: bool = False,
-                  precision=FP64, stream=None, check=True, graph: bool = False):
+                  precision=FP64, stream=None, check=True, graph: bool = False, x0_scaled: bool = False):
         precision = PRECISIONS.get(precision, precision)
         info = (PcgInfo * nrhs)()
         flags = (X0_GIVEN if x0_given else X0_ZERO) | (PCG_GRAPH if graph else 0)
+        if x0_scaled:
+            flags |= X0_GIVEN | X0_SCALED
         rc = _lib().stfd_pcg_solve(self._h, _dev_ptr(f, self.N * nrhs, "f"), _dev_ptr(u, self.N * nrhs, "u"),
                                    nrhs, rtol, maxit, flags, precision, info, _stream_ptr(stream))
         if check:
@@ -326,7 +328,8 @@ class Problem:
 
 
 def _infos(info):
-    return [dict(iters=i.iters, status=i.status, rel_res=i.rel_res, true_rel_res=i.true_rel_res) for i in info]
+    return [dict(iters=i.iters, status=i.status, rel_res=i.rel_res, true_rel_res=i.true_rel_res,
+                 x0_scale=i.x0_scale) for i in info]
 
 
 def pcg_solve_batched(problems, fs, us, nrhs=None, rtol: float = 1e-8, maxit: int = 200, x0_given: bool = False,
