@@ -63,8 +63,9 @@ typedef enum {
  * STFD_X0_SCALED), optionally or-ed with STFD_PCG_GRAPH to replay each iteration from a
  * captured HIP graph.  STFD_X0_SCALED replaces the given x0 by alpha x0 with
  * alpha = Re<x0, f> / <x0, A x0>, the multiple closest to the solution in the A-norm (the
- * norm CG minimises); alpha = 0 (a cold start) when Re<x0, f> <= 0, so a poor guess (for
- * instance a learned prediction) can never start CG farther from the solution than x0 = 0. */
+ * norm CG minimises); alpha = 0 (a cold start) when Re<x0, f> <= 0 or when the residual of
+ * alpha x0 exceeds ||f||, so a poor guess (for instance a learned prediction) never starts CG
+ * farther from the solution, or with a larger residual, than x0 = 0. */
 enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1, STFD_PCG_GRAPH = 2, STFD_X0_SCALED = 4 };
 
 /* Physical domain.  STFD_GEOM_UNIT_CUBE: Omega = (0,1)^d, x = xi.

@@ -75,6 +75,17 @@ int stfd_fno_rel_l2(const float *y_dev, const float *t_dev, int64_t n, int batch
 /* One Adam step (Kingma & Ba) on all parameters with the current gradients; step counter
  * kept in the handle (bias correction). */
 int stfd_fno_adam_step(stfd_fno *net, float lr, float beta1, float beta2, float eps, void *stream);
+/* e = y - t in FP64 (t may be NULL: e = y), n values. */
+int stfd_fno_diff_f64(const float *y_dev, const float *t_dev, double *e_dev, int64_t n, void *stream);
+/* Energy-norm loss of a prediction error, given e (FP64, [batch][n], n reals = interleaved complex
+ * coefficients) and Ae = A e from stfd_matvec of a Hermitian positive definite operator A:
+ * E_b = e_b^H A e_b, loss = (1/batch) sum_b sqrt(E_b / T_b) with T_b = t_energy_dev[b] (device; NULL:
+ * 1), and dy_b = A e_b / (batch sqrt(E_b T_b)) (FP32, may be NULL), the gradient of the loss with
+ * respect to the prediction.  energy_host (may be NULL) receives E_b; *loss is written after the
+ * stream synchronises.  Relative errors in the energy norm are what CG minimises, so a warm start
+ * trained this way is measured in the norm that decides its value. */
+int stfd_fno_energy_loss(const double *e_dev, const double *Ae_dev, const double *t_energy_dev, int64_t n,
+                         int batch, float *dy_dev, double *energy_host, float *loss, void *stream);
 /* y (FP32, [batch][n]) -> x (FP64, [batch][n]) on the device: the network's complex output
  * channels (re, im pairs) become an initial guess for stfd_pcg_solve. */
 int stfd_fno_to_f64(const float *y_dev, double *x_dev, int64_t n, void *stream);

@@ -287,6 +287,54 @@ __global__ void __launch_bounds__(256) to_f64_kernel(const float* y, double* x, 
     x[i] = double(y[i]);
 }
 
+// e = y - t (t may be nullptr) in FP64
+__global__ void __launch_bounds__(256) diff_f64_kernel(const float* y, const float* t, double* e, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    e[i] = double(y[i]) - (t ? double(t[i]) : 0.0);
+}
+
+// per-sample partial sums of e . Ae (FP64)
+__global__ void __launch_bounds__(256) energy_part_kernel(const double* e, const double* Ae, int64_t n,
+                                                          double* parts) {
+  const int b = blockIdx.y;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    s = fma(e[int64_t(b) * n + i], Ae[int64_t(b) * n + i], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) parts[int64_t(b) * gridDim.x + blockIdx.x] = red[0];
+}
+
+// per-sample energies, loss (1/B) sum_b sqrt(E_b / T_b) and gradient scales (one thread)
+__global__ void energy_final_kernel(const double* parts, int nparts, int batch, const double* t_energy,
+                                    double* scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double loss = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    double E = 0.0;
+    for (int k = 0; k < nparts; ++k) E += parts[int64_t(b) * nparts + k];
+    scal[2 + batch + b] = E;
+    const double T = t_energy ? t_energy[b] : 1.0;
+    const double rel = (E > 0.0 && T > 0.0) ? sqrt(E / T) : 0.0;
+    loss += rel;
+    // d sqrt(e^H A e / T) / de = A e / sqrt(E T)
+    scal[2 + b] = (E > 0.0 && T > 0.0) ? 1.0 / (double(batch) * sqrt(E * T)) : 0.0;
+  }
+  scal[0] = loss / double(batch);
+}
+
+__global__ void __launch_bounds__(256) energy_grad_kernel(const double* Ae, const double* scal, int64_t n, float* dy) {
+  const int b = blockIdx.y;
+  const double s = scal[2 + b];
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    dy[int64_t(b) * n + i] = float(s * Ae[int64_t(b) * n + i]);
+}
+
 inline int grid_for(int64_t n) { return int(std::min<int64_t>((n + 255) / 256, 16384)); }
 
 }  // namespace fno
@@ -744,5 +792,43 @@ int stfd_fno_to_f64(const float* y_dev, double* x_dev, int64_t n, void* stream) 
   hipLaunchKernelGGL(to_f64_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), y_dev, x_dev,
                      n);
   FNO_HIP(hipGetLastError());
+  return STFD_OK;
+}
+
+int stfd_fno_diff_f64(const float* y_dev, const float* t_dev, double* e_dev, int64_t n, void* stream) {
+  if (!y_dev || !e_dev || n < 0) return STFD_EINVAL;
+  if (n == 0) return STFD_OK;
+  hipLaunchKernelGGL(diff_f64_kernel, dim3(grid_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), y_dev, t_dev,
+                     e_dev, n);
+  FNO_HIP(hipGetLastError());
+  return STFD_OK;
+}
+
+int stfd_fno_energy_loss(const double* e_dev, const double* Ae_dev, const double* t_energy_dev, int64_t n, int batch,
+                         float* dy_dev, double* energy_host, float* loss, void* stream) {
+  if (!e_dev || !Ae_dev || n < 1 || batch < 1 || batch > 65535) return STFD_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nparts = 64;
+  double* scratch = nullptr;
+  FNO_HIP(hipMalloc(reinterpret_cast<void**>(&scratch), (size_t(batch) * nparts + 2 + 2 * size_t(batch)) * sizeof(double)));
+  double* scal = scratch + size_t(batch) * nparts;
+  hipLaunchKernelGGL(energy_part_kernel, dim3(nparts, unsigned(batch)), dim3(256), 0, s, e_dev, Ae_dev, n, scratch);
+  hipLaunchKernelGGL(energy_final_kernel, dim3(1), dim3(64), 0, s, (const double*)scratch, nparts, batch, t_energy_dev,
+                     scal);
+  if (dy_dev)
+    hipLaunchKernelGGL(energy_grad_kernel, dim3(unsigned(std::min(grid_for(n), 1024)), unsigned(batch)), dim3(256), 0,
+                       s, Ae_dev, (const double*)scal, n, dy_dev);
+  hipError_t e = hipGetLastError();
+  std::vector<double> host(2 + 2 * size_t(batch));
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), scal, host.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(scratch);
+  if (e != hipSuccess) {
+    g_hip_err = int(e);
+    return STFD_EHIP;
+  }
+  if (loss) *loss = float(host[0]);
+  if (energy_host)
+    for (int b = 0; b < batch; ++b) energy_host[b] = host[2 + size_t(batch) + b];
   return STFD_OK;
 }

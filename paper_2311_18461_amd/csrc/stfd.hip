@@ -735,6 +735,29 @@ __global__ __launch_bounds__(kVecBlock) void pcg_x0_scale_kernel(const double* f
   if (threadIdx.x == 0) pf[rhs * gridDim.x + blockIdx.x] = s;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[rhs].x0_scale = alpha;
 }
+// A scaled initial guess whose residual exceeds ||f|| is dropped: x = 0, r = f (the cold start),
+// so the residual-based stopping test never starts behind the cold start either.
+__global__ __launch_bounds__(kVecBlock) void pcg_x0_revert_kernel(const double* f, double* r, double* x, int64_t n2,
+                                                                   const PcgScalars* sc) {
+  const int rhs = blockIdx.y;
+  const PcgScalars st = sc[rhs];
+  if (st.x0_scale == 0.0 || !(st.res > 1.0)) return;
+  for (int64_t k = int64_t(blockIdx.x) * kVecBlock + threadIdx.x; k < n2; k += int64_t(gridDim.x) * kVecBlock) {
+    r[rhs * n2 + k] = f[rhs * n2 + k];
+    x[rhs * n2 + k] = 0.0;
+  }
+}
+// second half of the revert (a separate launch: the kernel above reads the flags it clears here)
+__global__ void pcg_x0_revert_finish_kernel(PcgScalars* sc, int* done, int nrhs, double tol) {
+  const int rhs = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rhs >= nrhs) return;
+  PcgScalars& st = sc[rhs];
+  if (st.x0_scale == 0.0 || !(st.res > 1.0)) return;
+  st.x0_scale = 0.0;
+  st.res = 1.0;
+  st.done = (1.0 <= tol) ? 1 : 0;
+  done[rhs] = st.done;
+}
 __global__ __launch_bounds__(kVecBlock) void pcg_start_kernel(const double* pf, const double* prr, int nparts,
                                                                PcgScalars* sc, int* done, double tol, int* ctr,
                                                                int x0_mode) {
@@ -1594,6 +1617,11 @@ static int pcg_init(const PcgJob& J, int flags, int precision, double rtol, hipS
     hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, r, r, nullptr, n2, pb, nullptr, nullptr);
     hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(J.nrhs)), vblock, 0, s, pa, pb, kVecGrid, P->sc, P->done, rtol,
                        P->ctr, mode);
+    if (mode == 2) {
+      hipLaunchKernelGGL(pcg_x0_revert_kernel, vgrid, vblock, 0, s, J.f, r, J.x, n2, (const PcgScalars*)P->sc);
+      hipLaunchKernelGGL(pcg_x0_revert_finish_kernel, dim3(unsigned((J.nrhs + 63) / 64)), dim3(64), 0, s, P->sc,
+                         P->done, int(J.nrhs), rtol);
+    }
   } else {
     hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, J.f, nullptr, r, J.x, n2, pa);
     hipLaunchKernelGGL(pcg_start_kernel, dim3(unsigned(J.nrhs)), vblock, 0, s, pa, nullptr, kVecGrid, P->sc, P->done,

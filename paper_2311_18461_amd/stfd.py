@@ -79,6 +79,8 @@ SIGNATURES = {
     "stfd_fno_rel_l2": (ctypes.c_int, [_VP, _VP, _I64, ctypes.c_int, _VP, _FP, _VP]),
     "stfd_fno_adam_step": (ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _VP]),
     "stfd_fno_to_f64": (ctypes.c_int, [_VP, _VP, _I64, _VP]),
+    "stfd_fno_diff_f64": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP]),
+    "stfd_fno_energy_loss": (ctypes.c_int, [_VP, _VP, _VP, _I64, ctypes.c_int, _VP, _DP, _FP, _VP]),
     "stfd_fno_destroy": (None, [_VP]),
     "stfd_map_points": (ctypes.c_int, [_VP, _DP, _I64, _DP]),
     "stfd_pcg_solve_batched": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int, ctypes.POINTER(_VP),
@@ -439,3 +441,25 @@ def fno_to_f64(y, x, n, stream=None):
     """stfd_fno_to_f64: FP32 network output -> FP64 (complex128 tensor x of n / 2 entries)."""
     _check(_lib().stfd_fno_to_f64(_dev_ptr_f32(y, n, "y"), _dev_ptr(x, n // 2, "x"), n, _stream_ptr(stream)),
            "stfd_fno_to_f64")
+
+
+def fno_diff_f64(y, t, e, stream=None):
+    """stfd_fno_diff_f64: e (complex128 tensor) = y - t (float32 tensors of 2 e.numel() values; t may be None)."""
+    n = 2 * e.numel()
+    _check(_lib().stfd_fno_diff_f64(_dev_ptr_f32(y, n, "y"), _dev_ptr_f32(t, n, "t") if t is not None else None,
+                                    _dev_ptr(e, n // 2, "e"), n, _stream_ptr(stream)), "stfd_fno_diff_f64")
+
+
+def fno_energy_loss(e, Ae, n, batch, t_energy=None, dy=None, stream=None):
+    """stfd_fno_energy_loss: returns (loss, per-sample energies e^H A e); fills dy if given."""
+    import torch
+    loss = ctypes.c_float()
+    en = np.empty(batch, dtype=np.float64)
+    if t_energy is not None and not (t_energy.is_cuda and t_energy.dtype == torch.float64 and t_energy.numel() == batch):
+        raise ValueError("t_energy must be a float64 CUDA tensor with one entry per sample")
+    _check(_lib().stfd_fno_energy_loss(_dev_ptr(e, n // 2 * batch, "e"), _dev_ptr(Ae, n // 2 * batch, "Ae"),
+                                       ctypes.c_void_p(t_energy.data_ptr()) if t_energy is not None else None, n,
+                                       batch, _dev_ptr_f32(dy, n * batch, "dy") if dy is not None else None,
+                                       en.ctypes.data_as(_DP), ctypes.byref(loss), _stream_ptr(stream)),
+           "stfd_fno_energy_loss")
+    return loss.value, en

@@ -12,7 +12,7 @@ relative l2 error; Adam with a cosine learning-rate decay.  At solve time the pr
 an initial guess, scaled by the library to the multiple closest to the solution in the A-norm
 (STFD_X0_SCALED); a useless guess gets the factor 0, i.e. the cold start (the fallback).
 
-    python -m paper_2311_18461_amd.warmstart train --out W.npz [--n-train 2000 --epochs 60]
+    python -m paper_2311_18461_amd.warmstart train --out W.npz [--n-train 2000 --epochs 150 --lr 2e-3]
     python -m paper_2311_18461_amd.warmstart evaluate --weights W.npz [--n-test 200]
 """
 from __future__ import annotations
@@ -47,6 +47,7 @@ class AnnulusWorkload:
         self.torch = torch
         self.dev, self.stream = device, stream
         kn = inputs.uniform_open_knots(n_el, p)
+        self.kn, self.p = kn, p
         self.prob = stfd.Problem(kn, [kn, kn], p, p, 1.0, 1.0, max_nrhs=1, geometry=stfd.GEOM_QUARTER_ANNULUS,
                                  radii=inputs.ANNULUS_RADII)
         self.N = self.prob.N
@@ -69,6 +70,13 @@ class AnnulusWorkload:
         self.prob.update_potential(V(*self.quad_xy), stream=self.stream)
         u0q = self.torch.from_numpy(np.ascontiguousarray(u0(*self.quad_xy))).to(self.dev)
         self.prob.load_vector(fbar, u0_q=u0q, stream=self.stream)
+
+    def energy_operator(self, max_nrhs):
+        """The potential-free system operator of the same grid and geometry (energy-norm loss)."""
+        if getattr(self, "_energy", None) is None or self._energy.max_nrhs < max_nrhs:
+            self._energy = stfd.Problem(self.kn, [self.kn, self.kn], self.p, self.p, 1.0, 1.0, max_nrhs=max_nrhs,
+                                        geometry=stfd.GEOM_QUARTER_ANNULUS, radii=inputs.ANNULUS_RADII)
+        return self._energy
 
     def solve(self, f, u, x0_given=False, maxit=5000):
         return self.prob.pcg_solve(f, u, rtol=1e-8, maxit=maxit, x0_given=x0_given, stream=self.stream)
@@ -105,13 +113,37 @@ def generate(wl, seed0, count, log=None):
     return feats, targets, iters
 
 
-def train(wl, feats, targets, epochs=60, batch=16, lr=1e-3, seed=0, log=None):
+def target_energies(wl, targets, batch):
+    """t_b^H A_0 t_b of every target (device float64)."""
+    torch = wl.torch
+    A0 = wl.energy_operator(batch)
+    n = targets.shape[1]
+    out = torch.empty(targets.shape[0], dtype=torch.float64, device=wl.dev)
+    e = torch.empty(batch * wl.N, dtype=torch.complex128, device=wl.dev)
+    Ae = torch.empty_like(e)
+    for b0 in range(0, targets.shape[0], batch):
+        nb = min(batch, targets.shape[0] - b0)
+        tb = targets[b0:b0 + nb].contiguous().view(-1)
+        stfd.fno_diff_f64(tb, None, e[:nb * wl.N], stream=wl.stream)
+        A0.matvec(e[:nb * wl.N], Ae[:nb * wl.N], nrhs=nb, stream=wl.stream)
+        _, en = stfd.fno_energy_loss(e[:nb * wl.N], Ae[:nb * wl.N], n, nb, stream=wl.stream)
+        out[b0:b0 + nb] = torch.from_numpy(en).to(wl.dev)
+    return out
+
+
+def train(wl, feats, targets, epochs=60, batch=16, lr=1e-3, seed=0, loss="energy", log=None):
     torch = wl.torch
     n = feats.shape[0]
     net = make_net(wl, batch, seed)
     X = torch.from_numpy(feats).to(wl.dev)
     y = torch.empty((batch, wl.ns * wl.ns * wl.c_out), dtype=torch.float32, device=wl.dev)
     dy = torch.empty_like(y)
+    nval = y.shape[1]
+    if loss == "energy":
+        A0 = wl.energy_operator(batch)
+        tE = target_energies(wl, targets, batch)
+        e = torch.empty(batch * wl.N, dtype=torch.complex128, device=wl.dev)
+        Ae = torch.empty_like(e)
     rng = np.random.default_rng(seed)
     steps = epochs * (n // batch)
     step = 0
@@ -125,7 +157,14 @@ def train(wl, feats, targets, epochs=60, batch=16, lr=1e-3, seed=0, log=None):
             xb = X[idx].contiguous().view(-1)
             tb = targets[idx].contiguous().view(-1)
             net.forward(xb, y.view(-1), batch, stream=wl.stream)
-            losses.append(stfd.fno_rel_l2(y.view(-1), tb, y.shape[1], batch, dy=dy.view(-1), stream=wl.stream))
+            if loss == "energy":
+                stfd.fno_diff_f64(y.view(-1), tb, e, stream=wl.stream)
+                A0.matvec(e, Ae, nrhs=batch, stream=wl.stream)
+                lv, _ = stfd.fno_energy_loss(e, Ae, nval, batch, t_energy=tE[idx].contiguous(), dy=dy.view(-1),
+                                             stream=wl.stream)
+            else:
+                lv = stfd.fno_rel_l2(y.view(-1), tb, nval, batch, dy=dy.view(-1), stream=wl.stream)
+            losses.append(lv)
             net.backward(dy.view(-1), batch, stream=wl.stream)
             cur = 0.5 * lr * (1.0 + math.cos(math.pi * step / max(steps, 1)))
             net.adam_step(cur, stream=wl.stream)
@@ -195,10 +234,11 @@ def main(argv=None):
     ap.add_argument("--weights", default="warmstart_weights.npz")
     ap.add_argument("--n-train", type=int, default=N_TRAIN)
     ap.add_argument("--n-test", type=int, default=N_TEST)
-    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--epochs", type=int, default=150)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--n-el", type=int, default=N_EL)
+    ap.add_argument("--loss", default="energy", choices=["energy", "l2"])
     ap.add_argument("--results", default=None, help="write per-seed evaluation rows (JSON) here")
     args = ap.parse_args(argv)
     import torch
@@ -210,7 +250,8 @@ def main(argv=None):
     if args.cmd == "train":
         feats, targets, iters = generate(wl, TRAIN_SEED0, args.n_train, log)
         log({"phase": "data_done", "mean_iters": float(np.mean(iters)), "max_iters": int(np.max(iters))})
-        net, hist = train(wl, feats, targets, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+        net, hist = train(wl, feats, targets, epochs=args.epochs, batch=args.batch, lr=args.lr, loss=args.loss,
+                          log=log)
         np.savez_compressed(args.out, theta=net.get_params(), loss=np.array(hist))
         del targets
         rows = evaluate(wl, net, TEST_SEED0, args.n_test, log)

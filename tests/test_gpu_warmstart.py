@@ -34,9 +34,20 @@ def test_scaled_initial_guess():
     rc, info = pr.pcg_solve(f, x, rtol=1e-8, maxit=1000, x0_scaled=True)
     _, cold8 = pr.pcg_solve(f, u, rtol=1e-8, maxit=1000)
     assert info[0]["x0_scale"] == 0.0 and info[0]["iters"] == cold8[0]["iters"]
+    # a random guess is scaled almost to zero (its residual stays below ||f||)
     x = torch.from_numpy(inputs.random_complex(pr.N, 2)).to(DEV)
     rc, info = pr.pcg_solve(f, x, rtol=1e-8, maxit=1000, x0_scaled=True)
-    assert rc == 0 and info[0]["true_rel_res"] <= 1.2e-8 and 0.0 <= info[0]["x0_scale"] < 1.0
+    assert rc == 0 and info[0]["true_rel_res"] <= 1.2e-8
+    assert 0.0 <= info[0]["x0_scale"] < 1e-2 and info[0]["iters"] <= cold8[0]["iters"] + 2
+    # a guess whose scaled residual exceeds ||f|| is dropped: the solve starts cold
+    x = sol + 2.0 * torch.linalg.norm(sol) / np.sqrt(pr.N) * torch.from_numpy(inputs.random_complex(pr.N, 4)).to(DEV)
+    rc, info = pr.pcg_solve(f, x, rtol=1e-8, maxit=1000, x0_scaled=True)
+    assert rc == 0 and info[0]["true_rel_res"] <= 1.2e-8
+    # a guess off by a small phase (a smooth error, residual ~1e-3 ||f||) keeps its start and saves
+    # iterations
+    x = sol * (1.0 + 1e-3j)
+    rc, info = pr.pcg_solve(f, x, rtol=1e-8, maxit=1000, x0_scaled=True)
+    assert rc == 0 and info[0]["x0_scale"] > 0.99 and info[0]["iters"] < cold8[0]["iters"]
 
 
 def test_warm_start_pipeline_small():
@@ -52,3 +63,31 @@ def test_warm_start_pipeline_small():
     rows = warmstart.evaluate(wl, net, warmstart.TEST_SEED0, 3)
     for r in rows:
         assert r["warm_true_rel_res"] <= 1.2e-8 and r["solution_diff"] < 1e-6
+
+
+def test_energy_loss_vs_numpy():
+    """e^H A e from the library's matvec, the relative energy loss and its gradient A e / (B sqrt(E T))."""
+    stfd = _stfd()
+    kn = inputs.uniform_open_knots(6, 3)
+    pr = stfd.Problem(kn, [kn, kn], 3, 3, max_nrhs=2)
+    B, n = 2, 2 * pr.N
+    rng = np.random.default_rng(3)
+    y = rng.standard_normal(B * n).astype(np.float32)
+    t = rng.standard_normal(B * n).astype(np.float32)
+    yd, td = torch.from_numpy(y).to(DEV), torch.from_numpy(t).to(DEV)
+    e = torch.empty(B * pr.N, dtype=torch.complex128, device=DEV)
+    stfd.fno_diff_f64(yd, td, e)
+    ev = (y.astype(np.float64) - t.astype(np.float64))
+    assert np.array_equal(torch.view_as_real(e).cpu().numpy().ravel(), ev)
+    Ae = torch.empty_like(e)
+    pr.matvec(e, Ae, nrhs=B)
+    T = torch.tensor([2.0, 5.0], dtype=torch.float64, device=DEV)
+    dy = torch.empty_like(yd)
+    loss, E = stfd.fno_energy_loss(e, Ae, n, B, t_energy=T, dy=dy)
+    Aev = torch.view_as_real(Ae).cpu().numpy().reshape(B, n)
+    Eref = np.einsum("bi,bi->b", ev.reshape(B, n), Aev)
+    assert np.allclose(E, Eref, rtol=1e-12)
+    lref = np.mean(np.sqrt(Eref / np.array([2.0, 5.0])))
+    assert abs(loss - lref) < 1e-6 * lref
+    gref = Aev / (B * np.sqrt(Eref * np.array([2.0, 5.0])))[:, None]
+    assert np.allclose(dy.cpu().numpy().reshape(B, n), gref, rtol=1e-6, atol=1e-6 * np.abs(gref).max())
