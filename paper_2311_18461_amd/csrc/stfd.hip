@@ -181,8 +181,9 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
       ua[ks][e] = to_op<PREC>((ks < nks && j < n && aa < n) ? v : 0.0);
     }
   // stage the input tile tile[j*RT + r] = In[o][j][row0 + r]: batches of loads from clamped
-  // (always in-bounds) addresses are issued before any is consumed; padding is zeroed after
-  constexpr int kBatch = 8;
+  // (always in-bounds) addresses are issued before any is consumed (one batch covers a 64-row
+  // tile of n <= 65 with 5 waves); padding is zeroed after
+  constexpr int kBatch = 16;
   const int ntile = kpad * RT;
   for (int b0 = 0; b0 < ntile; b0 += int(blockDim.x) * kBatch) {
     Tin v[kBatch];
@@ -205,21 +206,24 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
   double dot_a = 0.0, dot_b = 0.0;
   for (int r0 = 0; r0 < RT; r0 += 16) {
     typename Tr::acc_t acc = {0, 0, 0, 0};
+    // (reading every B operand of the row group before the MFMA chain was measured slower: the
+    // extra registers cost more than the LDS waits it saves)
 #pragma unroll
     for (int ks = 0; ks < KSTEPS_MAX; ++ks) {
       if (ks < nks) {
+        op_t bk[1][K / 4];
+#pragma unroll
+        for (int e = 0; e < K / 4; ++e) bk[0][e] = tile[(ks * K + (K / 4) * grp + e) * RT + r0 + col];
         if constexpr (PREC == MP_F64) {
-          const double b = tile[(ks * K + grp) * RT + r0 + col];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], b, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], bk[0][0], acc, 0, 0, 0);
         } else if constexpr (PREC == MP_F32) {
-          const float b = tile[(ks * K + grp) * RT + r0 + col];
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[ks][0], b, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[ks][0], bk[0][0], acc, 0, 0, 0);
         } else {
           s4_t av, bv;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             av[e] = ua[ks][e];
-            bv[e] = tile[(ks * K + 4 * grp + e) * RT + r0 + col];
+            bv[e] = bk[0][e];
           }
           acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
         }
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
 // LDS y layout: ys[t][m] complex (lane-contiguous).
 // ---------------------------------------------------------------------------
 constexpr int kTsThreads = 256;
-constexpr int kTsBatch = 8;
+constexpr int kTsBatch = 24;
 
 template <typename T, int P>
 __global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const double* Lb, const double* Db, int n_t,
@@ -1014,14 +1018,15 @@ static int upload(stfd_problem* P, T** ptr, const T* src, size_t count) {
   return STFD_OK;
 }
 
-// Row tile for a mode product: at most 64 rows, balanced so that the last
-// tile is not mostly padding; smaller tiles when one right-hand side alone
-// would not give the launch enough blocks.  Depends only on per-rhs sizes so
-// that the number of blocks per right-hand side is fixed for a problem.
+// Row tile for a mode product: at most 64 rows, balanced so that the last tile is not
+// mostly padding.  Measured on MI355X (2D, p = 3, 64^3): tiles of up to 64 rows beat both
+// smaller tiles with more blocks (16-row tiles: +25% apply time, the launch is bound by
+// workgroup dispatch, not by the work per block) and 128/256-row tiles (too few blocks).
+// Depends only on per-rhs sizes, so the number of blocks per right-hand side is fixed.
 static int pick_row_tile(int64_t inner, int64_t outer_per_rhs) {
-  int64_t ntile = (inner + 63) / 64;
-  int rt = int(16 * ((inner + 16 * ntile - 1) / (16 * ntile)));
-  while (rt > 16 && outer_per_rhs * ((inner + rt - 1) / rt) < 512) rt -= 16;
+  (void)outer_per_rhs;
+  const int64_t ntile = (inner + 63) / 64;
+  const int rt = int(16 * ((inner + 16 * ntile - 1) / (16 * ntile)));
   return std::max(rt, 16);
 }
 
@@ -1379,9 +1384,9 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   {
     const int nt = hp.n_t, pt = hp.p_t;
     const size_t per_mode = size_t(nt) * (2 * pt + 1 + 2) * sizeof(double);
+    // 64 modes (one full wave of sweeping lanes) per block when the LDS allows: measured faster
+    // than 16 modes per block with four times the blocks
     int mpb = int(std::min<size_t>(64, P->max_lds / per_mode));
-    // the sweep is a latency-bound recurrence: spread small problems over more blocks
-    while (mpb > 16 && (hp.N_s + mpb - 1) / mpb < 512) mpb /= 2;
     P->ts_mpb = mpb;
     const int64_t nblk = (hp.N_s + mpb - 1) / mpb;
     std::vector<double> Lb(size_t(nblk) * nt * pt * mpb * 2, 0.0), Db(size_t(nblk) * nt * mpb, 1.0);
