@@ -381,6 +381,104 @@ int time_factors(HostProblem& hp) {
   return 0;
 }
 
+int time_segment_length(int n_t, int p_t) {
+  // segment lengths compiled per half-bandwidth P (one lane keeps len rows of y, L and 1/D
+  // plus two P x P transfers in registers); cost = dependent FP64 work per lane: four sweeps of
+  // len rows (4P fused multiply-adds each) and two reduced recurrences of S-1 steps (4P^2 + 4P)
+  static const int cand[7][3] = {{0, 0, 0}, {8, 16, 0}, {8, 12, 16}, {8, 12, 16}, {6, 8, 12}, {6, 8, 0}, {6, 0, 0}};
+  if (p_t < 1 || p_t > 6 || n_t < 1) return 0;
+  int best = 0;
+  double best_cost = 0.0;
+  for (int len : cand[p_t]) {
+    if (len == 0) continue;
+    const int segs = (n_t + len - 1) / len;
+    if (segs > 64) continue;
+    const double cost = 16.0 * len * p_t + 2.0 * (segs - 1) * (4.0 * p_t * p_t + 4.0 * p_t);
+    if (best == 0 || cost < best_cost) {
+      best = len;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
+int time_solve_plan(const HostProblem& hp, int len, TimeSolvePlan& out) {
+  const int nt = hp.n_t, P = hp.p_t;
+  if (len < P || len < 1) return -1;
+  const int segs = (nt + len - 1) / len;
+  if (segs > 64) return -1;
+  const int mpb = 64 / segs;
+  const int64_t nblk = (hp.N_s + mpb - 1) / mpb;
+  out.len = len;
+  out.segs = segs;
+  out.mpb = mpb;
+  out.blocks = nblk;
+  out.Lf.assign(size_t(nblk) * len * P * 64 * 2, 0.0);
+  out.Df.assign(size_t(nblk) * len * 64, 0.0);
+  out.Tf.assign(size_t(nblk) * P * P * 64 * 2, 0.0);
+  out.Tb.assign(size_t(nblk) * P * P * 64 * 2, 0.0);
+  // L[t][t-k] of mode i (zero outside the band and for padded rows t >= n_t)
+  auto Lv = [&](int64_t i, int t, int k) -> cplx {
+    if (t >= nt || t - k < 0) return cplx(0.0, 0.0);
+    return hp.Lfac[(size_t(t) * P + (k - 1)) * hp.N_s + i];
+  };
+  std::vector<cplx> h(P), g(P);
+  for (int64_t i = 0; i < hp.N_s; ++i) {
+    const int64_t b = i / mpb;
+    const int m = int(i - b * mpb);
+    for (int s = 0; s < segs; ++s) {
+      const int lane = m * segs + s, t0 = s * len;
+      for (int j = 0; j < len; ++j) {
+        const int t = t0 + j;
+        if (t < nt) out.Df[(size_t(b) * len + j) * 64 + lane] = hp.Dinv[size_t(t) * hp.N_s + i];
+        for (int k = 1; k <= P; ++k) {
+          const cplx v = Lv(i, t, k);
+          const size_t o = ((((size_t(b) * len + j) * P + (k - 1)) * 64) + lane) * 2;
+          out.Lf[o] = v.real();
+          out.Lf[o + 1] = v.imag();
+        }
+      }
+      // forward transfer: last P values z_{t0+len-1-a} of the homogeneous forward recurrence
+      // over the segment, started from the history z_{t0-1-c} = delta(c, col)
+      for (int col = 0; col < P; ++col) {
+        std::fill(h.begin(), h.end(), cplx(0.0, 0.0));
+        h[col] = 1.0;
+        for (int j = 0; j < len; ++j) {
+          const int t = t0 + j;
+          cplx z(0.0, 0.0);
+          for (int k = 1; k <= P; ++k) z -= Lv(i, t, k) * h[k - 1];
+          for (int k = P - 1; k >= 1; --k) h[k] = h[k - 1];
+          h[0] = z;
+        }
+        for (int a = 0; a < P; ++a) {
+          const size_t o = ((((size_t(b) * P + a) * P + col) * 64) + lane) * 2;
+          out.Tf[o] = h[a].real();
+          out.Tf[o + 1] = h[a].imag();
+        }
+      }
+      // backward transfer: first P values x_{t0+a} of the homogeneous backward recurrence
+      // x_t = -sum_k conj(L[t+k][t]) x_{t+k} over the segment, started from x_{t0+len+c} = delta(c, col)
+      for (int col = 0; col < P; ++col) {
+        std::fill(g.begin(), g.end(), cplx(0.0, 0.0));
+        g[col] = 1.0;
+        for (int j = len - 1; j >= 0; --j) {
+          const int t = t0 + j;
+          cplx x(0.0, 0.0);
+          for (int k = 1; k <= P; ++k) x -= std::conj(Lv(i, t + k, k)) * g[k - 1];
+          for (int k = P - 1; k >= 1; --k) g[k] = g[k - 1];
+          g[0] = x;
+        }
+        for (int a = 0; a < P; ++a) {
+          const size_t o = ((((size_t(b) * P + a) * P + col) * 64) + lane) * 2;
+          out.Tb[o] = g[a].real();
+          out.Tb[o + 1] = g[a].imag();
+        }
+      }
+    }
+  }
+  return 0;
+}
+
 int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
   if (v.d < 1 || v.d > 3 || v.p_t < 1 || v.p_s < 2 || v.p_t > kMaxDeg || v.p_s > kMaxDeg) return -1;
   if (!(v.T > 0.0) || !(v.nu > 0.0) || !std::isfinite(v.T) || !std::isfinite(v.nu)) return -1;

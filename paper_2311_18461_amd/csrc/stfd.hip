@@ -274,209 +274,248 @@ __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
 // Banded time solves (Algorithm 1 step 3): for every spatial mode i solve
 // H_i x_i = y_i, H_i = L_t + mu_i^2 M_t + i mu_i K_t (Section 5.2), Hermitian
 // positive definite with half-bandwidth P, factorised at setup as L D L^H
-// (unit lower band L, real D > 0).  The recurrence over t is latency-bound,
-// so a block of `mpb` modes first copies everything it needs into LDS with
-// batched loads (no load waits inside the copy loops), then one lane per
-// mode sweeps forward (z_t = y_t - sum_k L[t][t-k] z_{t-k}, w_t = z_t / D_t)
-// and backward (x_t = w_t - sum_k conj(L[t+k][t]) x_{t+k}) reading LDS only,
-// four steps of operands at a time.  Arithmetic is FP64 for every precision
-// of the surrounding mode products (T is the storage type of y).
-// Factor layout (global and LDS, per block of mpb modes):
-//   Lb[blk][t][k-1][m] complex = L[t][t-k] of mode blk*mpb + m,  Db[blk][t][m] = 1 / D[t].
-// LDS y layout: ys[t][m] complex (lane-contiguous).
+// (unit lower band L, real D > 0).
+// A single sweep over n_t rows is a chain of 2 n_t dependent steps, and with one
+// lane per mode the grid holds only N_s lanes.  Here each mode's rows are cut
+// into S segments of LEN rows (the last padded with zero rows) and lane
+// m*S + s of a 64-lane block keeps segment s of mode m in registers (rows of y,
+// L and 1/D).  The forward substitution z = L^{-1} y is exact in three steps:
+//  (1) sweep the segment from a zero history; its last P values are the local
+//      tail;
+//  (2) reduced recurrence tail_s = tail~_s + Tf_s tail_{s-1} over the segments,
+//      S-1 rounds of neighbour-lane shuffles (Tf_s = P x P response of the
+//      segment's last P values to its history, from setup);
+//  (3) sweep again from the true history tail_{s-1}; w = z / D.
+// The backward substitution x = L^{-H} w takes the same three steps from the
+// other end (future = first P values of the next segment, transfer Tb_s).
+// Dependent chain per lane: 4 LEN sweep steps + 2 (S-1) reduced steps.
+// Arithmetic is FP64 for every precision of the surrounding mode products (T is
+// the storage type of y).  Table layouts: time_solve_plan in host_setup.h.
 // ---------------------------------------------------------------------------
-constexpr int kTsThreads = 256;
-constexpr int kTsBatch = 24;
+constexpr int kTsLanes = 64;
+// compiled (P, LEN) pairs; the segment lengths offered per P by time_segment_length
+#define STFD_TS_INSTANCES                                                                                    \
+  STFD_TS(1, 8) STFD_TS(1, 16) STFD_TS(2, 8) STFD_TS(2, 12) STFD_TS(2, 16) STFD_TS(3, 8) STFD_TS(3, 12)      \
+  STFD_TS(3, 16) STFD_TS(4, 6) STFD_TS(4, 8) STFD_TS(4, 12) STFD_TS(5, 6) STFD_TS(5, 8) STFD_TS(6, 6)
 
-template <typename T, int P>
-__global__ __launch_bounds__(kTsThreads) void time_solve_kernel(T* y, const double* Lb, const double* Db, int n_t,
-                                                              int64_t N_s, int64_t blocks_per_rhs, int mpb,
-                                                              const int* done) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* Ls = reinterpret_cast<double*>(smem_raw);        // [n_t][P][mpb][2]
-  double* Ds = Ls + size_t(n_t) * P * mpb * 2;             // [n_t][mpb]
-  double* ys = Ds + size_t(n_t) * mpb;                     // [n_t][mpb][2]
+__device__ inline void ts_load(const double* p, int t, double& re, double& im) {
+  const double2 v = reinterpret_cast<const double2*>(p)[t];
+  re = v.x;
+  im = v.y;
+}
+__device__ inline void ts_load(const float* p, int t, double& re, double& im) {
+  const float2 v = reinterpret_cast<const float2*>(p)[t];
+  re = double(v.x);
+  im = double(v.y);
+}
+__device__ inline void ts_store(double* p, int t, double re, double im) {
+  reinterpret_cast<double2*>(p)[t] = make_double2(re, im);
+}
+__device__ inline void ts_store(float* p, int t, double re, double im) {
+  reinterpret_cast<float2*>(p)[t] = make_float2(float(re), float(im));
+}
+
+template <typename T, int P, int LEN>
+__global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double* Lf, const double* Df,
+                                                            const double* Tf, const double* Tb, int n_t, int segs,
+                                                            int mpb, int64_t N_s, int64_t blocks_per_rhs,
+                                                            const int* done) {
   const int64_t rhs = blockIdx.x / blocks_per_rhs;
   if (done && done[rhs]) return;
   const int64_t blk = blockIdx.x - rhs * blocks_per_rhs;
-  const int64_t i0 = blk * mpb;
-  const int nm = int(min<int64_t>(mpb, N_s - i0));
-  T* base = y + (rhs * N_s + i0) * int64_t(2 * n_t);
-  const int tid = threadIdx.x;
-  STFD_STAMP(0, 4);
-  // factors of this block: one contiguous chunk
+  const int lane = threadIdx.x;
+  const int m = lane / segs, s = lane - m * segs;
+  const int64_t mode = blk * mpb + m;
+  const bool live = m < mpb && mode < N_s;
+  const int t0 = s * LEN;
+  T* yb = y + (rhs * N_s + (live ? mode : 0)) * int64_t(2 * n_t);
+  const double2* Lb = reinterpret_cast<const double2*>(Lf) + blk * int64_t(LEN * P * kTsLanes);
+  const double* Db = Df + blk * int64_t(LEN * kTsLanes);
+  const double2* Tfb = reinterpret_cast<const double2*>(Tf) + blk * int64_t(P * P * kTsLanes);
+  const double2* Tbb = reinterpret_cast<const double2*>(Tb) + blk * int64_t(P * P * kTsLanes);
+
+  double yr[LEN], yi[LEN], lr[LEN][P], li[LEN][P];
+#pragma unroll
+  for (int j = 0; j < LEN; ++j) {
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const double2 v = Lb[(j * P + k) * kTsLanes + lane];
+      lr[j][k] = v.x;
+      li[j][k] = v.y;
+    }
+    const int t = t0 + j;
+    yr[j] = yi[j] = 0.0;
+    if (live && t < n_t) ts_load(yb, t, yr[j], yi[j]);
+  }
+  // L[t+k][t] for rows t+k of the next segment (rows jj < P of the neighbour lane)
+  const bool has_next = s + 1 < segs;
+  const int nxt = min(lane + 1, kTsLanes - 1);
+  double nlr[P][P], nli[P][P];
+#pragma unroll
+  for (int jj = 0; jj < P; ++jj)
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      nlr[jj][k] = nli[jj][k] = 0.0;
+      if (k >= jj) {
+        const double2 v = Lb[(jj * P + k) * kTsLanes + nxt];
+        nlr[jj][k] = has_next ? v.x : 0.0;
+        nli[jj][k] = has_next ? v.y : 0.0;
+      }
+    }
+  double hr[P], hi[P];
+
+  // z_t = y_t - sum_k L[t][t-k] z_{t-k}; h[k-1] = z_{t-k} (the z_{t-1} term last)
+#define STFD_TS_FWD_ROW(j)                                   \
+  double zr = yr[j], zi = yi[j];                             \
+  _Pragma("unroll") for (int k = P; k >= 1; --k) {           \
+    zr = fma(-lr[j][k - 1], hr[k - 1], zr);                  \
+    zr = fma(li[j][k - 1], hi[k - 1], zr);                   \
+    zi = fma(-lr[j][k - 1], hi[k - 1], zi);                  \
+    zi = fma(-li[j][k - 1], hr[k - 1], zi);                  \
+  }                                                          \
+  _Pragma("unroll") for (int k = P - 1; k >= 1; --k) {       \
+    hr[k] = hr[k - 1];                                       \
+    hi[k] = hi[k - 1];                                       \
+  }                                                          \
+  hr[0] = zr;                                                \
+  hi[0] = zi;
+
+  // x_t = w_t - sum_k conj(L[t+k][t]) x_{t+k}; h[k-1] = x_{t+k} (the x_{t+1} term last)
+#define STFD_TS_BWD_ROW(j)                                                      \
+  double xr = yr[j], xi = yi[j];                                                \
+  _Pragma("unroll") for (int k = P; k >= 1; --k) {                              \
+    const int q = j + k;                                                        \
+    const double cr = q < LEN ? lr[q < LEN ? q : 0][k - 1] : nlr[q < LEN ? 0 : q - LEN][k - 1]; \
+    const double ci = q < LEN ? li[q < LEN ? q : 0][k - 1] : nli[q < LEN ? 0 : q - LEN][k - 1]; \
+    xr = fma(-cr, hr[k - 1], xr);                                               \
+    xr = fma(-ci, hi[k - 1], xr);                                               \
+    xi = fma(-cr, hi[k - 1], xi);                                               \
+    xi = fma(ci, hr[k - 1], xi);                                                \
+  }                                                                             \
+  _Pragma("unroll") for (int k = P - 1; k >= 1; --k) {                          \
+    hr[k] = hr[k - 1];                                                          \
+    hi[k] = hi[k - 1];                                                          \
+  }                                                                             \
+  hr[0] = xr;                                                                   \
+  hi[0] = xi;
+
+  // (1) forward sweep from a zero history -> local tail
+#pragma unroll
+  for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
+#pragma unroll
+  for (int j = 0; j < LEN; ++j) {
+    STFD_TS_FWD_ROW(j)
+  }
+  // (2) reduced forward recurrence over the segments, then history = true tail of segment s-1
   {
-    const int nl = n_t * P * mpb * 2, nd = n_t * mpb;
-    const double* gl = Lb + blk * int64_t(nl);
-    const double* gd = Db + blk * int64_t(nd);
-    for (int b0 = 0; b0 < nl; b0 += kTsThreads * kTsBatch) {
-      double v[kTsBatch];
+    double tr[P][P], ti[P][P], cr0[P], ci0[P];
 #pragma unroll
-      for (int u = 0; u < kTsBatch; ++u) v[u] = gl[min(b0 + u * kTsThreads + tid, nl - 1)];
+    for (int a = 0; a < P; ++a) {
+      cr0[a] = hr[a];
+      ci0[a] = hi[a];
 #pragma unroll
-      for (int u = 0; u < kTsBatch; ++u)
-        if (b0 + u * kTsThreads + tid < nl) Ls[b0 + u * kTsThreads + tid] = v[u];
+      for (int c = 0; c < P; ++c) {
+        const double2 v = Tfb[(a * P + c) * kTsLanes + lane];
+        tr[a][c] = v.x;
+        ti[a][c] = v.y;
+      }
     }
-    for (int b0 = 0; b0 < nd; b0 += kTsThreads * kTsBatch) {
-      double v[kTsBatch];
+    for (int r = 1; r < segs; ++r) {
+      double pr[P], pi[P];
 #pragma unroll
-      for (int u = 0; u < kTsBatch; ++u) v[u] = gd[min(b0 + u * kTsThreads + tid, nd - 1)];
+      for (int c = 0; c < P; ++c) {
+        const double vr = __shfl_up(hr[c], 1), vi = __shfl_up(hi[c], 1);
+        pr[c] = s > 0 ? vr : 0.0;
+        pi[c] = s > 0 ? vi : 0.0;
+      }
 #pragma unroll
-      for (int u = 0; u < kTsBatch; ++u)
-        if (b0 + u * kTsThreads + tid < nd) Ds[b0 + u * kTsThreads + tid] = v[u];
+      for (int a = 0; a < P; ++a) {
+        double ar = cr0[a], ai = ci0[a];
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+          ar = fma(tr[a][c], pr[c], ar);
+          ar = fma(-ti[a][c], pi[c], ar);
+          ai = fma(tr[a][c], pi[c], ai);
+          ai = fma(ti[a][c], pr[c], ai);
+        }
+        hr[a] = ar;
+        hi[a] = ai;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      const double vr = __shfl_up(hr[c], 1), vi = __shfl_up(hi[c], 1);
+      hr[c] = s > 0 ? vr : 0.0;
+      hi[c] = s > 0 ? vi : 0.0;
     }
   }
-  // right-hand sides: global [m][t] (complex) -> LDS [t][m]
-  const int two_nt = 2 * n_t;
-  const int ny = nm * two_nt;
-  for (int b0 = 0; b0 < ny; b0 += kTsThreads * kTsBatch) {
-    T v[kTsBatch];
+  // (3) forward sweep from the true history; w = z / D in place of y
 #pragma unroll
-    for (int u = 0; u < kTsBatch; ++u) v[u] = base[min(b0 + u * kTsThreads + tid, ny - 1)];
+  for (int j = 0; j < LEN; ++j) {
+    STFD_TS_FWD_ROW(j)
+    const double d = Db[j * kTsLanes + lane];
+    yr[j] = zr * d;
+    yi[j] = zi * d;
+  }
+  // (4) backward sweep from a zero future -> local head
 #pragma unroll
-    for (int u = 0; u < kTsBatch; ++u) {
-      const int idx = b0 + u * kTsThreads + tid;
-      if (idx < ny) {
-        const int m = idx / two_nt, rem = idx - m * two_nt;
-        ys[((rem >> 1) * mpb + m) * 2 + (rem & 1)] = double(v[u]);
+  for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
+#pragma unroll
+  for (int j = LEN - 1; j >= 0; --j) {
+    STFD_TS_BWD_ROW(j)
+  }
+  // (5) reduced backward recurrence, then future = true head of segment s+1
+  {
+    double tr[P][P], ti[P][P], cr0[P], ci0[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      cr0[a] = hr[a];
+      ci0[a] = hi[a];
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const double2 v = Tbb[(a * P + c) * kTsLanes + lane];
+        tr[a][c] = v.x;
+        ti[a][c] = v.y;
       }
+    }
+    for (int r = 1; r < segs; ++r) {
+      double pr[P], pi[P];
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const double vr = __shfl_down(hr[c], 1), vi = __shfl_down(hi[c], 1);
+        pr[c] = has_next ? vr : 0.0;
+        pi[c] = has_next ? vi : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        double ar = cr0[a], ai = ci0[a];
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+          ar = fma(tr[a][c], pr[c], ar);
+          ar = fma(-ti[a][c], pi[c], ar);
+          ai = fma(tr[a][c], pi[c], ai);
+          ai = fma(ti[a][c], pr[c], ai);
+        }
+        hr[a] = ar;
+        hi[a] = ai;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      const double vr = __shfl_down(hr[c], 1), vi = __shfl_down(hi[c], 1);
+      hr[c] = has_next ? vr : 0.0;
+      hi[c] = has_next ? vi : 0.0;
     }
   }
-  __syncthreads();
-  STFD_STAMP(0, 5);
-  if (tid < nm) {
-    const int m = tid;
-    auto Lre = [&](int t, int k) { return Ls[((t * P + k - 1) * mpb + m) * 2]; };
-    auto Lim = [&](int t, int k) { return Ls[((t * P + k - 1) * mpb + m) * 2 + 1]; };
-    double hr[P], hi[P];
+  // (6) backward sweep from the true future; write x
 #pragma unroll
-    for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
-    // forward: z_t = y_t - sum_k L[t][t-k] z_{t-k} (z_{t-1} term last), w_t = z_t / D_t,
-    // four steps of operands read from LDS at a time
-    int t = 0;
-    for (; t + 4 <= n_t; t += 4) {
-      double yr4[4], yi4[4], d4[4], l4[4][P][2];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        yr4[u] = ys[((t + u) * mpb + m) * 2];
-        yi4[u] = ys[((t + u) * mpb + m) * 2 + 1];
-        d4[u] = Ds[(t + u) * mpb + m];
-#pragma unroll
-        for (int k = 1; k <= P; ++k) {
-          l4[u][k - 1][0] = Lre(t + u, k);
-          l4[u][k - 1][1] = Lim(t + u, k);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        double zr = yr4[u], zi = yi4[u];
-#pragma unroll
-        for (int k = P; k >= 2; --k) {
-          zr = fma(-l4[u][k - 1][0], hr[k - 1], zr);
-          zr = fma(l4[u][k - 1][1], hi[k - 1], zr);
-          zi = fma(-l4[u][k - 1][0], hi[k - 1], zi);
-          zi = fma(-l4[u][k - 1][1], hr[k - 1], zi);
-        }
-        zr = fma(-l4[u][0][0], hr[0], zr);
-        zi = fma(-l4[u][0][0], hi[0], zi);
-        zr = fma(l4[u][0][1], hi[0], zr);
-        zi = fma(-l4[u][0][1], hr[0], zi);
-#pragma unroll
-        for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
-        hr[0] = zr;
-        hi[0] = zi;
-        ys[((t + u) * mpb + m) * 2] = zr * d4[u];
-        ys[((t + u) * mpb + m) * 2 + 1] = zi * d4[u];
-      }
-    }
-    for (; t < n_t; ++t) {
-      double zr = ys[(t * mpb + m) * 2], zi = ys[(t * mpb + m) * 2 + 1];
-#pragma unroll
-      for (int k = P; k >= 1; --k) {
-        zr = fma(-Lre(t, k), hr[k - 1], zr);
-        zr = fma(Lim(t, k), hi[k - 1], zr);
-        zi = fma(-Lre(t, k), hi[k - 1], zi);
-        zi = fma(-Lim(t, k), hr[k - 1], zi);
-      }
-#pragma unroll
-      for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
-      hr[0] = zr;
-      hi[0] = zi;
-      const double dv = Ds[t * mpb + m];
-      ys[(t * mpb + m) * 2] = zr * dv;
-      ys[(t * mpb + m) * 2 + 1] = zi * dv;
-    }
-    // backward: x_t = w_t - sum_k conj(L[t+k][t]) x_{t+k} (x_{t+1} term last)
-#pragma unroll
-    for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
-    t = n_t - 1;
-    for (; t - 3 >= 0; t -= 4) {
-      double wr4[4], wi4[4], l4[4][P][2];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int tt = t - u;
-        wr4[u] = ys[(tt * mpb + m) * 2];
-        wi4[u] = ys[(tt * mpb + m) * 2 + 1];
-#pragma unroll
-        for (int k = 1; k <= P; ++k) {
-          const int row = min(tt + k, n_t - 1);
-          const bool ok = tt + k < n_t;
-          l4[u][k - 1][0] = ok ? Lre(row, k) : 0.0;
-          l4[u][k - 1][1] = ok ? Lim(row, k) : 0.0;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        double xr = wr4[u], xi = wi4[u];
-#pragma unroll
-        for (int k = P; k >= 2; --k) {
-          xr = fma(-l4[u][k - 1][0], hr[k - 1], xr);
-          xr = fma(-l4[u][k - 1][1], hi[k - 1], xr);
-          xi = fma(-l4[u][k - 1][0], hi[k - 1], xi);
-          xi = fma(l4[u][k - 1][1], hr[k - 1], xi);
-        }
-        xr = fma(-l4[u][0][0], hr[0], xr);
-        xi = fma(-l4[u][0][0], hi[0], xi);
-        xr = fma(-l4[u][0][1], hi[0], xr);
-        xi = fma(l4[u][0][1], hr[0], xi);
-#pragma unroll
-        for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
-        hr[0] = xr;
-        hi[0] = xi;
-        ys[((t - u) * mpb + m) * 2] = xr;
-        ys[((t - u) * mpb + m) * 2 + 1] = xi;
-      }
-    }
-    for (; t >= 0; --t) {
-      double xr = ys[(t * mpb + m) * 2], xi = ys[(t * mpb + m) * 2 + 1];
-#pragma unroll
-      for (int k = P; k >= 1; --k) {
-        if (t + k < n_t) {
-          xr = fma(-Lre(t + k, k), hr[k - 1], xr);
-          xr = fma(-Lim(t + k, k), hi[k - 1], xr);
-          xi = fma(-Lre(t + k, k), hi[k - 1], xi);
-          xi = fma(Lim(t + k, k), hr[k - 1], xi);
-        }
-      }
-#pragma unroll
-      for (int k = P - 1; k >= 1; --k) { hr[k] = hr[k - 1]; hi[k] = hi[k - 1]; }
-      hr[0] = xr;
-      hi[0] = xi;
-      ys[(t * mpb + m) * 2] = xr;
-      ys[(t * mpb + m) * 2 + 1] = xi;
-    }
+  for (int j = LEN - 1; j >= 0; --j) {
+    STFD_TS_BWD_ROW(j)
+    const int t = t0 + j;
+    if (live && t < n_t) ts_store(yb, t, xr, xi);
   }
-  __syncthreads();
-  STFD_STAMP(0, 6);
-  // write back [t][m] -> global [m][t]
-  for (int b0 = 0; b0 < ny; b0 += kTsThreads) {
-    const int idx = b0 + tid;
-    if (idx < ny) {
-      const int m = idx / two_nt, rem = idx - m * two_nt;
-      base[idx] = T(ys[((rem >> 1) * mpb + m) * 2 + (rem & 1)]);
-    }
-  }
-  STFD_STAMP(0, 7);
+#undef STFD_TS_FWD_ROW
+#undef STFD_TS_BWD_ROW
 }
 
 // ---------------------------------------------------------------------------
@@ -967,9 +1006,13 @@ struct stfd_problem {
   // device data
   double* U_fwd[3] = {nullptr, nullptr, nullptr};  // U'[j][a] = U[j][a]  (apply U^T)
   double* U_bwd[3] = {nullptr, nullptr, nullptr};  // U'[j][a] = U[a][j]  (apply U)
-  double* Lb = nullptr;     // time-block factors [blk][t][k][m] (complex), see time_solve_kernel
-  double* Db = nullptr;     // inverse pivots [blk][t][m]
-  int ts_mpb = 16;          // modes per time-solve block
+  // segmented time-solve tables (layout: TimeSolvePlan in host_setup.h)
+  double* TsL = nullptr;
+  double* TsD = nullptr;
+  double* TsTf = nullptr;
+  double* TsTb = nullptr;
+  int ts_len = 0, ts_segs = 0, ts_mpb = 0;
+  int64_t ts_blocks = 0;
   double* Tband = nullptr;  // [3][n_t][2 p_t + 1]: L_t, M_t, K_t bands
   double* Sc = nullptr;
   double* work64[2] = {nullptr, nullptr};
@@ -1076,28 +1119,18 @@ static int launch_mode_product(const void* in, void* out, const double* U, int n
 template <typename T>
 static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* done, hipStream_t s) {
   const HostProblem& hp = P->hp;
-  const int mpb = P->ts_mpb;
-  const int64_t bpr = (hp.N_s + mpb - 1) / mpb;
-  const size_t lds = size_t(mpb) * hp.n_t * (2 * hp.p_t + 1 + 2) * sizeof(double);
-  const dim3 grid(unsigned(bpr * nrhs)), block(kTsThreads);
-#define STFD_TS(PV)                                                                                          \
-  case PV:                                                                                                   \
-    hipLaunchKernelGGL((time_solve_kernel<T, PV>), grid, block, lds, s, y, P->Lb, P->Db, hp.n_t, hp.N_s,    \
-                       bpr, mpb, done);                                                                      \
-    break;
-  switch (hp.p_t) {
-    STFD_TS(1)
-    STFD_TS(2)
-    STFD_TS(3)
-    STFD_TS(4)
-    STFD_TS(5)
-    STFD_TS(6)
-    default:
-      return STFD_EINVAL;
+  const int64_t bpr = P->ts_blocks;
+  const dim3 grid(unsigned(bpr * nrhs)), block(kTsLanes);
+#define STFD_TS(PV, LV)                                                                                        \
+  if (hp.p_t == PV && P->ts_len == LV) {                                                                       \
+    hipLaunchKernelGGL((time_solve_kernel<T, PV, LV>), grid, block, 0, s, y, P->TsL, P->TsD, P->TsTf, P->TsTb, \
+                       hp.n_t, P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                      \
+    STFD_HIP(hipGetLastError());                                                                               \
+    return STFD_OK;                                                                                            \
   }
+  STFD_TS_INSTANCES
 #undef STFD_TS
-  STFD_HIP(hipGetLastError());
-  return STFD_OK;
+  return STFD_EINVAL;
 }
 
 // Algorithm 1 steps 2-4 on nrhs stacked vectors.  TW = working precision of
@@ -1374,34 +1407,26 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
       P->max_lds = size_t(lds);
-    const size_t ts_bytes = size_t(hp.n_t) * (2 * hp.p_t + 1 + 2) * sizeof(double);
-    if (ts_bytes > P->max_lds || hp.n_t > 64 * kMvMaxChunks) {
+    P->ts_len = time_segment_length(hp.n_t, hp.p_t);
+    if (P->ts_len == 0 || hp.n_t > 64 * kMvMaxChunks) {
       stfd_destroy(P);
       return STFD_EINVAL;
     }
   }
-  // time-block factors in the per-block layout of time_solve_kernel, time bands, spatial coefficients
+  // segmented time-solve tables, time bands, spatial coefficients
   {
-    const int nt = hp.n_t, pt = hp.p_t;
-    const size_t per_mode = size_t(nt) * (2 * pt + 1 + 2) * sizeof(double);
-    // 64 modes (one full wave of sweeping lanes) per block when the LDS allows: measured faster
-    // than 16 modes per block with four times the blocks
-    int mpb = int(std::min<size_t>(64, P->max_lds / per_mode));
-    P->ts_mpb = mpb;
-    const int64_t nblk = (hp.N_s + mpb - 1) / mpb;
-    std::vector<double> Lb(size_t(nblk) * nt * pt * mpb * 2, 0.0), Db(size_t(nblk) * nt * mpb, 1.0);
-    for (int64_t i = 0; i < hp.N_s; ++i) {
-      const int64_t b = i / mpb;
-      const int m = int(i - b * mpb);
-      for (int t = 0; t < nt; ++t) {
-        Db[(size_t(b) * nt + t) * mpb + m] = hp.Dinv[size_t(t) * hp.N_s + i];
-        for (int k = 1; k <= pt; ++k) {
-          const std::complex<double> v = hp.Lfac[(size_t(t) * pt + (k - 1)) * hp.N_s + i];
-          const size_t o = (((size_t(b) * nt + t) * pt + (k - 1)) * mpb + m) * 2;
-          Lb[o] = v.real();
-          Lb[o + 1] = v.imag();
-        }
-      }
+    TimeSolvePlan tp;
+    if (time_solve_plan(hp, P->ts_len, tp) != 0) {
+      stfd_destroy(P);
+      return STFD_EINVAL;
+    }
+    P->ts_segs = tp.segs;
+    P->ts_mpb = tp.mpb;
+    P->ts_blocks = tp.blocks;
+    if ((rc = upload(P, &P->TsL, tp.Lf.data(), tp.Lf.size())) || (rc = upload(P, &P->TsD, tp.Df.data(), tp.Df.size())) ||
+        (rc = upload(P, &P->TsTf, tp.Tf.data(), tp.Tf.size())) || (rc = upload(P, &P->TsTb, tp.Tb.data(), tp.Tb.size()))) {
+      stfd_destroy(P);
+      return rc;
     }
     // spatial coefficients interleaved per row and stencil offset: [N_s][stencil][3];
     // V-free unit-cube base from the host, weighted terms (potential, geometry) added on the device
@@ -1409,8 +1434,7 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     const size_t ns = size_t(hp.N_s) * hp.stencil;
     for (size_t is = 0; is < ns; ++is)
       for (int k = 0; k < 3; ++k) ScI[is * 3 + k] = hp.Sc[k * ns + is];
-    if ((rc = upload(P, &P->Lb, Lb.data(), Lb.size())) || (rc = upload(P, &P->Db, Db.data(), Db.size())) ||
-        (rc = upload(P, &P->Tband, hp.Tband.data(), hp.Tband.size())) ||
+    if ((rc = upload(P, &P->Tband, hp.Tband.data(), hp.Tband.size())) ||
         (rc = dev_alloc(P, &P->Sc, ScI.size()))) {
       stfd_destroy(P);
       return rc;
