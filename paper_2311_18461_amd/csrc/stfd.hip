@@ -93,12 +93,16 @@ __device__ __forceinline__ double sum_partials(const double* parts, int nparts, 
 }
 
 // ---------------------------------------------------------------------------
-// Mode product (Algorithm 1 steps 2 and 4): one block = one outer slice o and
-// one tile of `row_tile` rows; wave w owns output columns a in [16w, 16w+16).
-// The block stages In[o][0..n)[tile rows] in LDS (operand precision, zero
-// padded to the MFMA K step); each wave keeps its 16 columns of U' in
-// registers.  MFMA computes C^T = U'^T A^T so that the 16 rows of a result
-// fragment are contiguous in memory (coalesced stores).
+// Mode product (Algorithm 1 steps 2 and 4): Out[o][a][r] = sum_j U'[j][a] In[o][j][r].
+// One block = one outer slice o and one group of 16 rows r; wave w owns output
+// columns a in [16w, 16w+16).  Every operand goes straight from global memory
+// into registers in one batch of loads (the wave's U' fragments and the row
+// group's In fragments for all K steps; KSM = K steps rounded up to the bucket
+// of the instantiation, padded steps carry zeros), then one MFMA chain and the
+// stores: no LDS staging, no barrier, and a grid of outer * inner / 16 blocks.
+// The row group's In fragments are read by every wave of the block (L1 hits
+// after the first).  MFMA computes C^T = U'^T A^T so that the 16 rows of a
+// result fragment are contiguous in memory (coalesced stores).
 //   FP64: v_mfma_f64_16x16x4f64, K step 4
 //   FP32: v_mfma_f32_16x16x4f32, K step 4
 //   BF16: v_mfma_f32_16x16x16bf16_1k, K step 16, FP32 accumulation
@@ -142,112 +146,89 @@ __device__ __forceinline__ typename MPTraits<PREC>::op_t to_op(float v) {
   else return f32_to_bf16(v);
 }
 
-template <int PREC, typename Tin, typename Tout>
+template <int PREC, typename Tin, typename Tout, int KSM>
 __global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
   using Tr = MPTraits<PREC>;
   using op_t = typename Tr::op_t;
   constexpr int K = Tr::K;
-  constexpr int KSTEPS_MAX = kMaxModeN / K;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  op_t* tile = reinterpret_cast<op_t*>(smem_raw);
-
-  STFD_STAMP(0, 0);
+  constexpr int E = K / 4;
   const int n = a.n;
-  const int kpad = (n + K - 1) / K * K;
-  const int nks = kpad / K;
-  const int RT = a.row_tile;
   const int64_t o = blockIdx.x / a.n_row_tiles;
   const int64_t rt = blockIdx.x - o * a.n_row_tiles;
   if (a.done && a.done[o / a.outer_per_rhs]) return;
-  const int64_t row0 = rt * RT;
-  const int rows_here = int(min<int64_t>(RT, a.inner - row0));
+  const int64_t row0 = rt * 16;
+  const int rows_here = int(min<int64_t>(16, a.inner - row0));
   const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
   Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
-
-  STFD_STAMP(0, 1);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int a0 = wave * 16;
   const int col = lane & 15, grp = lane >> 4;
   const double* Uo = a.U + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0);
-  // this wave's operand fragments of U'^T: element (m = col, k = K/4*grp + e) of each K step
-  op_t ua[KSTEPS_MAX][K / 4];
+  // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row col), k = j;
+  // addresses are clamped into the operands, values outside them are replaced by zeros
+  const bool col_ok = a0 + col < n;
+  const int ac = min(a0 + col, n - 1), rc = min(col, rows_here - 1);
+  double ur[KSM][E];
+  Tin xr[KSM][E];
 #pragma unroll
-  for (int ks = 0; ks < KSTEPS_MAX; ++ks)
+  for (int ks = 0; ks < KSM; ++ks)
 #pragma unroll
-    for (int e = 0; e < K / 4; ++e) {
-      const int j = ks * K + (K / 4) * grp + e;
-      const int aa = a0 + col;
-      const double v = Uo[min(j, n - 1) * n + min(aa, n - 1)];
-      ua[ks][e] = to_op<PREC>((ks < nks && j < n && aa < n) ? v : 0.0);
+    for (int e = 0; e < E; ++e) {
+      const int jc = min(ks * K + E * grp + e, n - 1);
+      ur[ks][e] = Uo[int64_t(jc) * n + ac];
+      xr[ks][e] = src[int64_t(jc) * a.inner + rc];
     }
-  // stage the input tile tile[j*RT + r] = In[o][j][row0 + r]: batches of loads from clamped
-  // (always in-bounds) addresses are issued before any is consumed (one batch covers a 64-row
-  // tile of n <= 65 with 5 waves); padding is zeroed after
-  constexpr int kBatch = 16;
-  const int ntile = kpad * RT;
-  for (int b0 = 0; b0 < ntile; b0 += int(blockDim.x) * kBatch) {
-    Tin v[kBatch];
+  // operands of the fused dot products (last backward product of a PCG iteration)
+  double rv[4] = {0.0, 0.0, 0.0, 0.0}, zv[4] = {0.0, 0.0, 0.0, 0.0};
+  if (a.part_a) {
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int idx = b0 + u * int(blockDim.x) + int(threadIdx.x);
-      const int j = idx / RT, r = idx - j * RT;
-      v[u] = src[int64_t(min(j, n - 1)) * a.inner + min(r, rows_here - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int idx = b0 + u * int(blockDim.x) + int(threadIdx.x);
-      const int j = idx / RT, r = idx - j * RT;
-      if (idx < ntile) tile[idx] = (j < n && r < rows_here) ? to_op<PREC>(v[u]) : op_t(0);
+    for (int v = 0; v < 4; ++v) {
+      const int aa = min(a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
+      const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(aa) * a.inner + rc;
+      rv[v] = a.dot_r[g];
+      zv[v] = a.dot_z[g];
     }
   }
-  __syncthreads();
-  STFD_STAMP(0, 2);
-
+  // keep every load above the MFMA chain (the scheduler would otherwise interleave them to save
+  // registers, turning one memory latency into several); masking and conversion happen below
+  __builtin_amdgcn_sched_barrier(0);
+  typename Tr::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+  for (int ks = 0; ks < KSM; ++ks) {
+    op_t ua[E], xb[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool in_k = ks * K + E * grp + e < n;
+      ua[e] = to_op<PREC>((in_k && col_ok) ? ur[ks][e] : 0.0);
+      xb[e] = to_op<PREC>(in_k ? xr[ks][e] : Tin(0));
+    }
+    if constexpr (PREC == MP_F64) {
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0], xb[0], acc, 0, 0, 0);
+    } else if constexpr (PREC == MP_F32) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[0], xb[0], acc, 0, 0, 0);
+    } else {
+      s4_t av, bv;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        av[e] = ua[e];
+        bv[e] = xb[e];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+  }
   double dot_a = 0.0, dot_b = 0.0;
-  for (int r0 = 0; r0 < RT; r0 += 16) {
-    typename Tr::acc_t acc = {0, 0, 0, 0};
-    // (reading every B operand of the row group before the MFMA chain was measured slower: the
-    // extra registers cost more than the LDS waits it saves)
+  if (col < rows_here) {
 #pragma unroll
-    for (int ks = 0; ks < KSTEPS_MAX; ++ks) {
-      if (ks < nks) {
-        op_t bk[1][K / 4];
-#pragma unroll
-        for (int e = 0; e < K / 4; ++e) bk[0][e] = tile[(ks * K + (K / 4) * grp + e) * RT + r0 + col];
-        if constexpr (PREC == MP_F64) {
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[ks][0], bk[0][0], acc, 0, 0, 0);
-        } else if constexpr (PREC == MP_F32) {
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[ks][0], bk[0][0], acc, 0, 0, 0);
-        } else {
-          s4_t av, bv;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            av[e] = ua[ks][e];
-            bv[e] = bk[0][e];
-          }
-          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-        }
-      }
-    }
-    const int r = r0 + col;
-    if (r < rows_here) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int aa = a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
-        if (aa < n) {
-          const int64_t off = int64_t(aa) * a.inner + r;
-          dst[off] = Tout(acc[v]);
-          if (a.part_a) {
-            const int64_t g = o * int64_t(n) * a.inner + row0 + off;
-            const double rv = a.dot_r[g];
-            dot_a += rv * double(Tout(acc[v]));
-            dot_b += rv * a.dot_z[g];
-          }
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int aa = a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
+      if (aa < n) {
+        const int64_t off = int64_t(aa) * a.inner + col;
+        dst[off] = Tout(acc[v]);
+        dot_a += rv[v] * double(Tout(acc[v]));
+        dot_b += rv[v] * zv[v];
       }
     }
   }
-  STFD_STAMP(0, 3);
   if (a.part_a) {
     __shared__ double red[2][8];
     dot_a = wave_sum(dot_a);
@@ -1066,16 +1047,9 @@ static int upload(stfd_problem* P, T** ptr, const T* src, size_t count) {
 // smaller tiles with more blocks (16-row tiles: +25% apply time, the launch is bound by
 // workgroup dispatch, not by the work per block) and 128/256-row tiles (too few blocks).
 // Depends only on per-rhs sizes, so the number of blocks per right-hand side is fixed.
-static int pick_row_tile(int64_t inner, int64_t outer_per_rhs) {
-  (void)outer_per_rhs;
-  const int64_t ntile = (inner + 63) / 64;
-  const int rt = int(16 * ((inner + 16 * ntile - 1) / (16 * ntile)));
-  return std::max(rt, 16);
-}
-
+// blocks of one right-hand side: 16-row groups of every outer slice
 static int64_t mode_product_blocks_per_rhs(int64_t inner, int64_t outer_per_rhs) {
-  const int rt = pick_row_tile(inner, outer_per_rhs);
-  return outer_per_rhs * ((inner + rt - 1) / rt);
+  return outer_per_rhs * ((inner + 15) / 16);
 }
 
 struct DotEpilogue {
@@ -1098,20 +1072,38 @@ static int launch_mode_product(const void* in, void* out, const double* U, int n
   a.inner = inner;
   a.outer = outer;
   a.outer_per_rhs = outer_per_rhs;
-  a.row_tile = pick_row_tile(inner, outer_per_rhs);
-  a.n_row_tiles = (inner + a.row_tile - 1) / a.row_tile;
+  a.row_tile = 16;
+  a.n_row_tiles = (inner + 15) / 16;
   a.done = done;
   a.dot_r = ep.r;
   a.dot_z = ep.zold;
   a.part_a = ep.part_a;
   a.part_b = ep.part_b;
-  const int K = MPTraits<PREC>::K;
-  const int kpad = (n + K - 1) / K * K;
-  const size_t lds = size_t(kpad) * a.row_tile * sizeof(typename MPTraits<PREC>::op_t);
+  constexpr int K = MPTraits<PREC>::K;
+  const int nks = (n + K - 1) / K;
   const int waves = (n + 15) / 16;
   const int64_t blocks = outer * a.n_row_tiles;
   if (blocks <= 0) return STFD_OK;
-  hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout>), dim3(unsigned(blocks)), dim3(64 * waves), lds, s, a);
+  if (n < 1 || n > kMaxModeN) return STFD_EINVAL;
+  const dim3 grid(static_cast<unsigned>(blocks)), block(static_cast<unsigned>(64 * waves));
+  // K-step buckets: multiples of 4 steps for K = 4 (n <= 128), every count for K = 16
+#define STFD_MP(B)                                                                     \
+  case B:                                                                              \
+    hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, (K == 4 ? 4 * B : B)>), grid, block, 0, s, a); \
+    break;
+  switch (K == 4 ? (nks + 3) / 4 : nks) {
+    STFD_MP(1)
+    STFD_MP(2)
+    STFD_MP(3)
+    STFD_MP(4)
+    STFD_MP(5)
+    STFD_MP(6)
+    STFD_MP(7)
+    STFD_MP(8)
+    default:
+      return STFD_EINVAL;
+  }
+#undef STFD_MP
   STFD_HIP(hipGetLastError());
   return STFD_OK;
 }
