@@ -20,7 +20,6 @@ typedef short s4_t __attribute__((ext_vector_type(4)));
 constexpr int kMaxModeN = 128;   // largest n_l handled by the MFMA mode product
 constexpr int kVecBlock = 256;   // threads of the BLAS-1 kernels
 constexpr int kVecGrid = 1024;   // blocks per right-hand side of the BLAS-1 kernels
-constexpr int kTsModes = 64;     // modes (lanes) per time-solve block
 
 // Precision of a mode product: operands and accumulator.
 enum { MP_F64 = 0, MP_F32 = 1, MP_BF16 = 2 };
@@ -34,8 +33,10 @@ struct ModeProductArgs {
   int64_t inner;       // contiguous reals below the direction
   int64_t outer;       // number of outer slices (directions above, times nrhs)
   int64_t outer_per_rhs;
-  int row_tile;        // rows per block (multiple of 16)
-  int64_t n_row_tiles; // ceil(inner / row_tile)
+  int64_t n_row_tiles;    // 16-row groups per outer slice, ceil(inner / 16)
+  int64_t tiles_per_rhs;  // outer_per_rhs * n_row_tiles
+  int64_t tiles_pad;      // tiles_per_rhs rounded up to a multiple of the XCD count
+  int groups;             // 16-column groups, ceil(n / 16)
   const int* done;     // per right-hand side "converged" flags or nullptr
   // optional epilogue (FP64 output only): per-block partials of <r, out> and <r, zold>
   const double* dot_r;

@@ -94,15 +94,18 @@ __device__ __forceinline__ double sum_partials(const double* parts, int nparts, 
 
 // ---------------------------------------------------------------------------
 // Mode product (Algorithm 1 steps 2 and 4): Out[o][a][r] = sum_j U'[j][a] In[o][j][r].
-// One block = one outer slice o and one group of 16 rows r; wave w owns output
-// columns a in [16w, 16w+16).  Every operand goes straight from global memory
-// into registers in one batch of loads (the wave's U' fragments and the row
-// group's In fragments for all K steps; KSM = K steps rounded up to the bucket
-// of the instantiation, padded steps carry zeros), then one MFMA chain and the
-// stores: no LDS staging, no barrier, and a grid of outer * inner / 16 blocks.
-// The row group's In fragments are read by every wave of the block (L1 hits
-// after the first).  MFMA computes C^T = U'^T A^T so that the 16 rows of a
-// result fragment are contiguous in memory (coalesced stores).
+// One block = one wave = one group of 16 rows r of one outer slice o and one
+// group of 16 output columns a.  Every operand goes straight from global memory
+// into registers in one batch of loads (the U' fragments of the column group and
+// the In fragments of the row group for all KS = ceil(n / K) K steps), then one
+// MFMA chain and the stores: no LDS staging, no barrier.  KS is exact per
+// instantiation for FP64 (padded K steps cost full MFMAs; a skipping branch
+// breaks the load batch).  Block order: right-hand side, then column group, then
+// row tile, with the tiles of a right-hand side padded to a multiple of the XCD
+// count so that the column groups of one row group run on the same XCD (shared
+// L2 for their In fragments); padding blocks only write zero dot partials.
+// MFMA computes C^T = U'^T A^T so that the 16 rows of a result fragment are
+// contiguous in memory (coalesced stores).
 //   FP64: v_mfma_f64_16x16x4f64, K step 4
 //   FP32: v_mfma_f32_16x16x4f32, K step 4
 //   BF16: v_mfma_f32_16x16x16bf16_1k, K step 16, FP32 accumulation
@@ -146,107 +149,101 @@ __device__ __forceinline__ typename MPTraits<PREC>::op_t to_op(float v) {
   else return f32_to_bf16(v);
 }
 
-template <int PREC, typename Tin, typename Tout, int KSM>
-__global__ __launch_bounds__(512) void mode_product_kernel(ModeProductArgs a) {
+template <int PREC, typename Tin, typename Tout, int KS>
+__global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
   using Tr = MPTraits<PREC>;
   using op_t = typename Tr::op_t;
   constexpr int K = Tr::K;
   constexpr int E = K / 4;
   const int n = a.n;
-  const int64_t o = blockIdx.x / a.n_row_tiles;
-  const int64_t rt = blockIdx.x - o * a.n_row_tiles;
-  if (a.done && a.done[o / a.outer_per_rhs]) return;
-  const int64_t row0 = rt * 16;
-  const int rows_here = int(min<int64_t>(16, a.inner - row0));
-  const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
-  Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int a0 = wave * 16;
-  const int col = lane & 15, grp = lane >> 4;
-  const double* Uo = a.U + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0);
-  // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row col), k = j;
-  // addresses are clamped into the operands, values outside them are replaced by zeros
-  const bool col_ok = a0 + col < n;
-  const int ac = min(a0 + col, n - 1), rc = min(col, rows_here - 1);
-  double ur[KSM][E];
-  Tin xr[KSM][E];
-#pragma unroll
-  for (int ks = 0; ks < KSM; ++ks)
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int jc = min(ks * K + E * grp + e, n - 1);
-      ur[ks][e] = Uo[int64_t(jc) * n + ac];
-      xr[ks][e] = src[int64_t(jc) * a.inner + rc];
-    }
-  // operands of the fused dot products (last backward product of a PCG iteration)
-  double rv[4] = {0.0, 0.0, 0.0, 0.0}, zv[4] = {0.0, 0.0, 0.0, 0.0};
-  if (a.part_a) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int aa = min(a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
-      const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(aa) * a.inner + rc;
-      rv[v] = a.dot_r[g];
-      zv[v] = a.dot_z[g];
-    }
-  }
-  // keep every load above the MFMA chain (the scheduler would otherwise interleave them to save
-  // registers, turning one memory latency into several); masking and conversion happen below
-  __builtin_amdgcn_sched_barrier(0);
-  typename Tr::acc_t acc = {0, 0, 0, 0};
-#pragma unroll
-  for (int ks = 0; ks < KSM; ++ks) {
-    op_t ua[E], xb[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const bool in_k = ks * K + E * grp + e < n;
-      ua[e] = to_op<PREC>((in_k && col_ok) ? ur[ks][e] : 0.0);
-      xb[e] = to_op<PREC>(in_k ? xr[ks][e] : Tin(0));
-    }
-    if constexpr (PREC == MP_F64) {
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0], xb[0], acc, 0, 0, 0);
-    } else if constexpr (PREC == MP_F32) {
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[0], xb[0], acc, 0, 0, 0);
-    } else {
-      s4_t av, bv;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        av[e] = ua[e];
-        bv[e] = xb[e];
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
-    }
-  }
+  const int64_t per_rhs = int64_t(a.groups) * a.tiles_pad;
+  const int64_t rhs = blockIdx.x / per_rhs;
+  if (a.done && a.done[rhs]) return;
+  const int64_t rem = blockIdx.x - rhs * per_rhs;
+  const int cg = int(rem / a.tiles_pad);
+  const int64_t tile = rem - int64_t(cg) * a.tiles_pad;
+  const int lane = threadIdx.x;
   double dot_a = 0.0, dot_b = 0.0;
-  if (col < rows_here) {
+  if (tile < a.tiles_per_rhs) {
+    const int64_t o = rhs * a.outer_per_rhs + tile / a.n_row_tiles;
+    const int64_t row0 = (tile % a.n_row_tiles) * 16;
+    const int rows_here = int(min<int64_t>(16, a.inner - row0));
+    const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
+    Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
+    const int a0 = cg * 16;
+    const int col = lane & 15, grp = lane >> 4;
+    const double* Uo = a.U + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0);
+    // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row col), k = j;
+    // addresses are clamped into the operands, values outside them are replaced by zeros
+    const bool col_ok = a0 + col < n;
+    const int ac = min(a0 + col, n - 1), rc = min(col, rows_here - 1);
+    double ur[KS][E];
+    Tin xr[KS][E];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int aa = a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
-      if (aa < n) {
-        const int64_t off = int64_t(aa) * a.inner + col;
-        dst[off] = Tout(acc[v]);
-        dot_a += rv[v] * double(Tout(acc[v]));
-        dot_b += rv[v] * zv[v];
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int jc = min(ks * K + E * grp + e, n - 1);
+        ur[ks][e] = Uo[int64_t(jc) * n + ac];
+        xr[ks][e] = src[int64_t(jc) * a.inner + rc];
+      }
+    // operands of the fused dot products (last backward product of a PCG iteration)
+    double rv[4] = {0.0, 0.0, 0.0, 0.0}, zv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a.part_a) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int aa = min(a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
+        const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(aa) * a.inner + rc;
+        rv[v] = a.dot_r[g];
+        zv[v] = a.dot_z[g];
+      }
+    }
+    // keep every load above the MFMA chain (the scheduler would otherwise interleave them to save
+    // registers, turning one memory latency into several); masking and conversion happen below
+    __builtin_amdgcn_sched_barrier(0);
+    typename Tr::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      op_t ua[E], xb[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const bool in_k = ks * K + E * grp + e < n;
+        ua[e] = to_op<PREC>((in_k && col_ok) ? ur[ks][e] : 0.0);
+        xb[e] = to_op<PREC>(in_k ? xr[ks][e] : Tin(0));
+      }
+      if constexpr (PREC == MP_F64) {
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0], xb[0], acc, 0, 0, 0);
+      } else if constexpr (PREC == MP_F32) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[0], xb[0], acc, 0, 0, 0);
+      } else {
+        s4_t av, bv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          av[e] = ua[e];
+          bv[e] = xb[e];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+    }
+    if (col < rows_here) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int aa = a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
+        if (aa < n) {
+          const int64_t off = int64_t(aa) * a.inner + col;
+          dst[off] = Tout(acc[v]);
+          dot_a += rv[v] * double(Tout(acc[v]));
+          dot_b += rv[v] * zv[v];
+        }
       }
     }
   }
   if (a.part_a) {
-    __shared__ double red[2][8];
     dot_a = wave_sum(dot_a);
     dot_b = wave_sum(dot_b);
     if (lane == 0) {
-      red[0][wave] = dot_a;
-      red[1][wave] = dot_b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double sa = 0.0, sb = 0.0;
-      const int nw = blockDim.x >> 6;
-      for (int w = 0; w < nw; ++w) {
-        sa += red[0][w];
-        sb += red[1][w];
-      }
-      a.part_a[blockIdx.x] = sa;
-      a.part_b[blockIdx.x] = sb;
+      a.part_a[blockIdx.x] = dot_a;
+      a.part_b[blockIdx.x] = dot_b;
     }
   }
 }
@@ -1047,9 +1044,11 @@ static int upload(stfd_problem* P, T** ptr, const T* src, size_t count) {
 // smaller tiles with more blocks (16-row tiles: +25% apply time, the launch is bound by
 // workgroup dispatch, not by the work per block) and 128/256-row tiles (too few blocks).
 // Depends only on per-rhs sizes, so the number of blocks per right-hand side is fixed.
-// blocks of one right-hand side: 16-row groups of every outer slice
-static int64_t mode_product_blocks_per_rhs(int64_t inner, int64_t outer_per_rhs) {
-  return outer_per_rhs * ((inner + 15) / 16);
+// blocks of one right-hand side: 16-column groups x (16-row groups of every outer slice, padded
+// to a multiple of the XCD count)
+static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_per_rhs) {
+  const int64_t tiles = outer_per_rhs * ((inner + 15) / 16);
+  return int64_t((n + 15) / 16) * ((tiles + kXcds - 1) / kXcds * kXcds);
 }
 
 struct DotEpilogue {
@@ -1063,6 +1062,7 @@ template <int PREC, typename Tin, typename Tout>
 static int launch_mode_product(const void* in, void* out, const double* U, int n, int64_t inner, int64_t outer,
                                int64_t outer_per_rhs, const int* done, hipStream_t s,
                                const DotEpilogue& ep = DotEpilogue(), int64_t u_slice_stride = 0) {
+  if (n < 1 || n > kMaxModeN || outer_per_rhs < 1) return STFD_EINVAL;
   ModeProductArgs a;
   a.in = in;
   a.out = out;
@@ -1072,8 +1072,10 @@ static int launch_mode_product(const void* in, void* out, const double* U, int n
   a.inner = inner;
   a.outer = outer;
   a.outer_per_rhs = outer_per_rhs;
-  a.row_tile = 16;
   a.n_row_tiles = (inner + 15) / 16;
+  a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
+  a.tiles_pad = (a.tiles_per_rhs + kXcds - 1) / kXcds * kXcds;
+  a.groups = (n + 15) / 16;
   a.done = done;
   a.dot_r = ep.r;
   a.dot_z = ep.zold;
@@ -1081,27 +1083,30 @@ static int launch_mode_product(const void* in, void* out, const double* U, int n
   a.part_b = ep.part_b;
   constexpr int K = MPTraits<PREC>::K;
   const int nks = (n + K - 1) / K;
-  const int waves = (n + 15) / 16;
-  const int64_t blocks = outer * a.n_row_tiles;
+  const int64_t blocks = (outer / outer_per_rhs) * a.groups * a.tiles_pad;
   if (blocks <= 0) return STFD_OK;
-  if (n < 1 || n > kMaxModeN) return STFD_EINVAL;
-  const dim3 grid(static_cast<unsigned>(blocks)), block(static_cast<unsigned>(64 * waves));
-  // K-step buckets: multiples of 4 steps for K = 4 (n <= 128), every count for K = 16
-#define STFD_MP(B)                                                                     \
-  case B:                                                                              \
-    hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, (K == 4 ? 4 * B : B)>), grid, block, 0, s, a); \
+  const dim3 grid(static_cast<unsigned>(blocks)), block(64);
+  // FP64: one instantiation per K-step count; FP32 (K = 4): buckets of 4 steps; BF16 (K = 16): exact
+#define STFD_MP(B)                                                                                      \
+  case B:                                                                                               \
+    hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, (PREC == MP_F32 ? 4 * B : B)>), grid, block, 0, s, a); \
     break;
-  switch (K == 4 ? (nks + 3) / 4 : nks) {
-    STFD_MP(1)
-    STFD_MP(2)
-    STFD_MP(3)
-    STFD_MP(4)
-    STFD_MP(5)
-    STFD_MP(6)
-    STFD_MP(7)
-    STFD_MP(8)
-    default:
-      return STFD_EINVAL;
+  const int sel = PREC == MP_F32 ? (nks + 3) / 4 : nks;
+  if constexpr (PREC == MP_F64) {
+    switch (sel) {
+      STFD_MP(1) STFD_MP(2) STFD_MP(3) STFD_MP(4) STFD_MP(5) STFD_MP(6) STFD_MP(7) STFD_MP(8)
+      STFD_MP(9) STFD_MP(10) STFD_MP(11) STFD_MP(12) STFD_MP(13) STFD_MP(14) STFD_MP(15) STFD_MP(16)
+      STFD_MP(17) STFD_MP(18) STFD_MP(19) STFD_MP(20) STFD_MP(21) STFD_MP(22) STFD_MP(23) STFD_MP(24)
+      STFD_MP(25) STFD_MP(26) STFD_MP(27) STFD_MP(28) STFD_MP(29) STFD_MP(30) STFD_MP(31) STFD_MP(32)
+      default:
+        return STFD_EINVAL;
+    }
+  } else {
+    switch (sel) {
+      STFD_MP(1) STFD_MP(2) STFD_MP(3) STFD_MP(4) STFD_MP(5) STFD_MP(6) STFD_MP(7) STFD_MP(8)
+      default:
+        return STFD_EINVAL;
+    }
   }
 #undef STFD_MP
   STFD_HIP(hipGetLastError());
@@ -1458,9 +1463,9 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     int64_t outer0 = 1;
     for (int l = 1; l < hp.d; ++l) outer0 *= hp.n_s[l];
     if (P->u_slice0)
-      P->mp_last_blocks = mode_product_blocks_per_rhs(2 * int64_t(hp.n_t) * (hp.N_s / hp.n_s[hp.d - 1]), 1);
+      P->mp_last_blocks = mode_product_blocks_per_rhs(hp.n_s[hp.d - 1], 2 * int64_t(hp.n_t) * (hp.N_s / hp.n_s[hp.d - 1]), 1);
     else
-      P->mp_last_blocks = mode_product_blocks_per_rhs(2 * int64_t(hp.n_t), outer0);
+      P->mp_last_blocks = mode_product_blocks_per_rhs(hp.n_s[0], 2 * int64_t(hp.n_t), outer0);
   }
   P->max_parts = std::max<int64_t>(std::max<int64_t>(P->mv_blocks, P->mp_last_blocks), kVecGrid);
   if ((rc = dev_alloc(P, &P->parts, size_t(6) * P->max_parts * P->max_nrhs)) ||
