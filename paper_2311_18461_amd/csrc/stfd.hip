@@ -499,17 +499,25 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
 // ---------------------------------------------------------------------------
 // Matrix-free system matvec (Section 5.3, eq. syst_mat with potential terms):
 //   Y = sum_k T_k X S_k^T, X viewed as n_t x N_s (time fastest).
-// One wave per spatial point i, lanes over time (up to 4 chunks of 64).
-// Phase 1: Z_k(t, i) = sum_s S_k[i][s] X(t, i + o(s)) for the (2p+1)^d
-//          neighbours; the coefficients are wave-uniform (scalar loads),
-//          each neighbour column X(:, j) is one coalesced vector load.
+// Lanes run over the flat (spatial point, t) index of X, so that no lane idles
+// whatever n_t is; a block covers K whole spatial points (K n_t lanes) so that
+// the time coupling of phase 2 stays inside the block.
+// Phase 1: Z_k(t, i) = sum_s S_k[i][s] X(t, i + o(s)).  The block's
+//          coefficients S_k[i][s] are staged in LDS (the lanes of one point
+//          read one address: broadcast); each neighbour value is one 16-byte
+//          bounds-checked buffer load at a per-lane byte offset summed from
+//          per-axis offsets computed once; a neighbour outside the grid gets an
+//          offset beyond the buffer, which the load returns as zero.
 // Phase 2: Y(t, i) = sum_k sum_dt T_k[t][dt] Z_k(t + dt, i) with T_3 = i K_t,
-//          reading Z from the wave's LDS slice.
+//          Z from LDS (in the space of the coefficients, after a barrier) and
+//          the bands from LDS, zero outside 0 <= t + dt < n_t.
 // Optionally writes one partial of Re <x, y> per block (PCG's <p, A p>).
 // ---------------------------------------------------------------------------
-constexpr int kMvWaves = 4;
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
-constexpr int kMvMaxChunks = 2;  // n_t <= 128
+constexpr int kMvMaxNt = 128;      // longest time axis accepted at setup
+constexpr int kMvLanes = 512;      // lanes per matvec block at most
+constexpr size_t kMvLds = 48 * 1024;  // LDS per block for coefficients / Z (several blocks per CU)
+constexpr uint32_t kMvBadOffset = 1u << 30;  // neighbour outside the grid (beyond any buffer)
 
 struct MatvecArgs {
   const double* x;
@@ -518,6 +526,7 @@ struct MatvecArgs {
   const double* Tband;  // [3][n_t][2 pt + 1]
   int n_t, pt;
   int n1, n2, n3;
+  int K;                // spatial points per block
   int64_t N_s;
   int64_t blocks_per_rhs;
   int64_t nrhs;
@@ -526,12 +535,23 @@ struct MatvecArgs {
   const int* done;
 };
 
-template <int D, int PS, int NCH>
-__global__ __launch_bounds__(64 * kMvWaves) void matvec_kernel(MatvecArgs a) {
+typedef unsigned int mv_u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 mv_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const mv_u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  double2 o;
+  o.x = __builtin_bit_cast(double, (unsigned long long)v.x | ((unsigned long long)v.y << 32));
+  o.y = __builtin_bit_cast(double, (unsigned long long)v.z | ((unsigned long long)v.w << 32));
+  return o;
+}
+
+template <int D, int PS>
+__global__ __launch_bounds__(kMvLanes) void matvec_kernel(MatvecArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ double red[kMvWaves];
-  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
+  __shared__ double red[kMvLanes / 64];
+  constexpr int W = 2 * PS + 1;
+  constexpr int ST = (D == 1 ? W : (D == 2 ? W * W : W * W * W));
+  const int tid = threadIdx.x;
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous range of spatial points so that its L2 holds one slab of X.
   const int64_t lb = int64_t(blockIdx.x % kXcds) * a.xcd_span + blockIdx.x / kXcds;
@@ -539,124 +559,108 @@ __global__ __launch_bounds__(64 * kMvWaves) void matvec_kernel(MatvecArgs a) {
   const int64_t rhs = lb / a.blocks_per_rhs;
   const int64_t blk = lb - rhs * a.blocks_per_rhs;
   if (a.done && a.done[rhs]) return;
-  const int n_t = a.n_t;
-  constexpr int nch = NCH;
-  const int64_t i = blk * kMvWaves + wv;
-  const bool active = i < a.N_s;
-  const int wt = 2 * a.pt + 1;
-  double* Tb = reinterpret_cast<double*>(smem_raw);                    // [3][n_t][wt]
-  double* Zw = Tb + size_t(3) * n_t * wt + size_t(wv) * 6 * n_t;        // [3][n_t][2] per wave
-  STFD_STAMP(0, 0);
-  for (int idx = threadIdx.x; idx < 3 * n_t * wt; idx += 64 * kMvWaves) Tb[idx] = a.Tband[idx];
-  const double* X = a.x + rhs * a.N_s * int64_t(2 * n_t);
-  constexpr int W = 2 * PS + 1;
-  if (active) {
-    double z[NCH][6];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c)
-#pragma unroll
-      for (int e = 0; e < 6; ++e) z[c][e] = 0.0;
-    const int i1 = int(i % a.n1);
-    const int64_t rr = i / a.n1;
-    const int i2 = (D >= 2) ? int(rr % a.n2) : 0;
-    const int i3 = (D >= 3) ? int(rr / a.n2) : 0;
-    constexpr int ST = (D == 1 ? W : (D == 2 ? W * W : W * W * W));
-    const double* C = a.Sc + i * (ST * 3);
-    // time index of each chunk, clamped so that every load is in bounds
-    int tl[NCH];
-    bool tv[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      tv[c] = c * 64 + lane < n_t;
-      tl[c] = min(c * 64 + lane, n_t - 1);
-    }
-    // Stencil rows r = (o3, o2) flattened (x_2 offset fastest).  Rows outside the grid are
-    // clamped (loads stay in bounds) and their coefficients zeroed.
-    constexpr int NROWS = (D == 1 ? 1 : (D == 2 ? W : W * W));
-    auto row_ptr = [&](int r, bool& ok) {
-      const int o2 = (D >= 2) ? r % W - PS : 0;
-      const int o3 = (D >= 3) ? r / W - PS : 0;
-      const int j2 = i2 + o2, j3 = i3 + o3;
-      ok = (D < 2 || (j2 >= 0 && j2 < a.n2)) && (D < 3 || (j3 >= 0 && j3 < a.n3));
-      const int c2 = (D >= 2) ? min(max(j2, 0), a.n2 - 1) : 0;
-      const int c3 = (D >= 3) ? min(max(j3, 0), a.n3 - 1) : 0;
-      return X + (int64_t(a.n1) * (c2 + int64_t(a.n2) * c3)) * (2 * n_t);
-    };
-    // one row of W neighbours at a time: all of its loads are issued before any is used
-#pragma unroll 1
-    for (int r = 0; r < NROWS; ++r) {
-      bool row_ok;
-      const double* Xrow = row_ptr(r, row_ok);
-      double xr[W][NCH], xi[W][NCH];
-#pragma unroll
-      for (int o1 = 0; o1 < W; ++o1) {
-        const int j1 = min(max(i1 + o1 - PS, 0), a.n1 - 1);
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const double* q = Xrow + (int64_t(j1) * n_t + tl[c]) * 2;
-          xr[o1][c] = q[0];
-          xi[o1][c] = q[1];
-        }
-      }
-#pragma unroll
-      for (int o1 = 0; o1 < W; ++o1) {
-        const bool ok = row_ok && (i1 + o1 - PS >= 0) && (i1 + o1 - PS < a.n1);
-        const int s = r * W + o1;
-        const double c0 = ok ? C[3 * s] : 0.0, c1 = ok ? C[3 * s + 1] : 0.0, c2 = ok ? C[3 * s + 2] : 0.0;
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          const double vr = ok ? xr[o1][c] : 0.0, vi = ok ? xi[o1][c] : 0.0;
-          z[c][0] = fma(c0, vr, z[c][0]); z[c][1] = fma(c0, vi, z[c][1]);
-          z[c][2] = fma(c1, vr, z[c][2]); z[c][3] = fma(c1, vi, z[c][3]);
-          z[c][4] = fma(c2, vr, z[c][4]); z[c][5] = fma(c2, vi, z[c][5]);
-        }
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      if (tv[c]) {
-        const int t = tl[c];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          Zw[(k * n_t + t) * 2] = z[c][2 * k];
-          Zw[(k * n_t + t) * 2 + 1] = z[c][2 * k + 1];
-        }
-      }
-    }
+  const int n_t = a.n_t, pt = a.pt, wt = 2 * pt + 1, K = a.K;
+  const int64_t i0 = blk * K;
+  const int kp = int(min<int64_t>(K, a.N_s - i0));
+  double* Cs = reinterpret_cast<double*>(smem_raw);  // [K][ST][4]; later Z: [K][n_t][3] complex
+  const size_t area = max(size_t(K) * ST * 4, size_t(K) * n_t * 6);
+  double* Tb = Cs + area;                            // [n_t][wt][4]: L_t, M_t, K_t band entries
+  for (int idx = tid; idx < kp * ST * 3; idx += blockDim.x) {
+    const int ps = idx / 3;
+    Cs[ps * 4 + (idx - ps * 3)] = a.Sc[i0 * (ST * 3) + idx];
+  }
+  for (int idx = tid; idx < n_t * wt * 3; idx += blockDim.x) {
+    const int k = idx / (n_t * wt), rem = idx - k * (n_t * wt);
+    const int t = rem / wt, dt = rem - t * wt;
+    const int tt = t + dt - pt;
+    Tb[(t * wt + dt) * 4 + k] = (tt >= 0 && tt < n_t) ? a.Tband[idx] : 0.0;
   }
   __syncthreads();
-  STFD_STAMP(0, 1);
-  double part = 0.0;
-  if (active) {
-    for (int c = 0; c < nch; ++c) {
-      const int t = c * 64 + lane;
-      if (t >= n_t) continue;
-      double yr = 0, yi = 0;
-      for (int dt = -a.pt; dt <= a.pt; ++dt) {
-        const int tt = t + dt;
-        if (tt < 0 || tt >= n_t) continue;
-        const double tl = Tb[(0 * n_t + t) * wt + dt + a.pt];
-        const double tm = Tb[(1 * n_t + t) * wt + dt + a.pt];
-        const double tk = Tb[(2 * n_t + t) * wt + dt + a.pt];
-        yr += tl * Zw[(0 * n_t + tt) * 2] + tm * Zw[(1 * n_t + tt) * 2] - tk * Zw[(2 * n_t + tt) * 2 + 1];
-        yi += tl * Zw[(0 * n_t + tt) * 2 + 1] + tm * Zw[(1 * n_t + tt) * 2 + 1] + tk * Zw[(2 * n_t + tt) * 2];
-      }
-      const int64_t g = (rhs * a.N_s + i) * n_t + t;
-      a.y[2 * g] = yr;
-      a.y[2 * g + 1] = yi;
-      if (a.partial) part += a.x[2 * g] * yr + a.x[2 * g + 1] * yi;  // Re(conj(x) y)
+  const int pl = tid / n_t;             // point of this lane within the block
+  const int t = tid - pl * n_t;
+  const bool active = pl < kp;
+  const int pc = min(pl, kp - 1);
+  const int64_t i = i0 + pc;
+  const double* X = a.x + rhs * a.N_s * int64_t(2 * n_t);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X), 0, int(a.N_s * n_t * 16), 0x00020000);
+  // per-axis byte offsets of the neighbours (kMvBadOffset outside the grid)
+  const int i1 = int(i % a.n1);
+  const int64_t q = i / a.n1;
+  const int i2 = (D >= 2) ? int(q % a.n2) : 0;
+  const int i3 = (D >= 3) ? int(q / a.n2) : 0;
+  uint32_t off1[W], off2[D >= 2 ? W : 1], off3[D >= 3 ? W : 1];
+#pragma unroll
+  for (int o = 0; o < W; ++o) {
+    const int j1 = i1 + o - PS;
+    off1[o] = (j1 >= 0 && j1 < a.n1) ? uint32_t((j1 * n_t + t) * 16) : kMvBadOffset;
+    if constexpr (D >= 2) {
+      const int j2 = i2 + o - PS;
+      off2[o] = (j2 >= 0 && j2 < a.n2) ? uint32_t(j2) * uint32_t(a.n1 * n_t * 16) : kMvBadOffset;
+    }
+    if constexpr (D >= 3) {
+      const int j3 = i3 + o - PS;
+      off3[o] = (j3 >= 0 && j3 < a.n3) ? uint32_t(j3) * uint32_t(a.n2 * a.n1 * n_t * 16) : kMvBadOffset;
     }
   }
-  STFD_STAMP(0, 2);
+  double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double2 xc = make_double2(0.0, 0.0);  // X(t, i): the centre neighbour
+  const double* C = Cs + size_t(pc) * ST * 4;
+  constexpr int NROWS = ST / W;
+#pragma unroll 1
+  for (int r = 0; r < NROWS; ++r) {
+    uint32_t orow = 0;
+    if constexpr (D == 2) orow = off2[r];
+    if constexpr (D == 3) {
+      const uint32_t a2 = off2[r % W], a3 = off3[r / W];
+      orow = (a2 == kMvBadOffset || a3 == kMvBadOffset) ? kMvBadOffset : a2 + a3;
+    }
+    double2 v[W];
+#pragma unroll
+    for (int o = 0; o < W; ++o) v[o] = mv_load(rs, orow + off1[o]);
+#pragma unroll
+    for (int o = 0; o < W; ++o) {
+      const int sidx = r * W + o;
+      const double2 c01 = *reinterpret_cast<const double2*>(C + sidx * 4);
+      const double c2 = C[sidx * 4 + 2];
+      z[0] = fma(c01.x, v[o].x, z[0]); z[1] = fma(c01.x, v[o].y, z[1]);
+      z[2] = fma(c01.y, v[o].x, z[2]); z[3] = fma(c01.y, v[o].y, z[3]);
+      z[4] = fma(c2, v[o].x, z[4]);    z[5] = fma(c2, v[o].y, z[5]);
+      if (sidx == ST / 2) xc = v[o];
+    }
+  }
+  __syncthreads();  // every lane is done with the coefficients: Z takes their space
+  double2* Zs = reinterpret_cast<double2*>(Cs);
+  if (active) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Zs[tid * 3 + k] = make_double2(z[2 * k], z[2 * k + 1]);
+  }
+  __syncthreads();
+  double part = 0.0;
+  if (active) {
+    double yr = 0.0, yi = 0.0;
+    const int base = pl * n_t;
+    for (int dt = 0; dt < wt; ++dt) {
+      const int tt = min(max(t + dt - pt, 0), n_t - 1);
+      const double2 tlm = *reinterpret_cast<const double2*>(Tb + (t * wt + dt) * 4);
+      const double tk = Tb[(t * wt + dt) * 4 + 2];
+      const double2 z0 = Zs[(base + tt) * 3], z1 = Zs[(base + tt) * 3 + 1], z2 = Zs[(base + tt) * 3 + 2];
+      yr += tlm.x * z0.x + tlm.y * z1.x - tk * z2.y;
+      yi += tlm.x * z0.y + tlm.y * z1.y + tk * z2.x;
+    }
+    const int64_t g = (rhs * a.N_s + i) * n_t + t;
+    reinterpret_cast<double2*>(a.y)[g] = make_double2(yr, yi);
+    part = xc.x * yr + xc.y * yi;  // Re(conj(x) y)
+  }
   if (a.partial) {
     part = wave_sum(part);
-    if (lane == 0) red[wv] = part;
+    const int w = tid >> 6, nw = int(blockDim.x) >> 6;
+    if ((tid & 63) == 0) red[w] = part;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k < kMvWaves; ++k) s += red[k];
-      a.partial[rhs * a.blocks_per_rhs + blk] = s;
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int k = 0; k < nw; ++k) sum += red[k];
+      a.partial[rhs * a.blocks_per_rhs + blk] = sum;
     }
   }
 }
@@ -1006,6 +1010,7 @@ struct stfd_problem {
   int64_t mp_last_blocks = 0;            // blocks per rhs of the last mode product (dot partials)
   int64_t u_slice0 = 0;                  // per-mode pencils along x_1 (mapped domain): n_1^2, else 0
   int64_t mv_blocks = 0;
+  int mv_points = 1;  // spatial points per matvec block
   size_t max_lds = 65536;  // per-block LDS limit of the device used at setup
   stfd::LoadPlan load;     // basis matrices on the Gauss grids (right-hand side assembly)
   stfd::Geometry geom;
@@ -1202,6 +1207,14 @@ static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64
   }
 }
 
+// spatial points per matvec block: whole points, at most kMvLanes lanes, coefficients (or Z) in kMvLds
+static int matvec_points_per_block(const HostProblem& hp) {
+  const int st = hp.stencil;
+  const size_t per_point = std::max<size_t>(size_t(st) * 4, size_t(hp.n_t) * 6) * sizeof(double);
+  int K = std::min<int>(kMvLanes / hp.n_t, int(kMvLds / per_point));
+  return std::max(K, 1);
+}
+
 static int matvec_dispatch(stfd_problem* P, const double* x, double* y, int64_t nrhs, double* partial,
                            const int* done, hipStream_t s) {
   const HostProblem& hp = P->hp;
@@ -1215,20 +1228,21 @@ static int matvec_dispatch(stfd_problem* P, const double* x, double* y, int64_t 
   a.n1 = hp.n_s[0];
   a.n2 = hp.n_s[1];
   a.n3 = hp.n_s[2];
+  a.K = P->mv_points;
   a.N_s = hp.N_s;
   a.blocks_per_rhs = P->mv_blocks;
   a.nrhs = nrhs;
   a.xcd_span = (P->mv_blocks * nrhs + kXcds - 1) / kXcds;
   a.partial = partial;
   a.done = done;
-  const size_t lds = (size_t(3) * hp.n_t * (2 * hp.p_t + 1) + size_t(kMvWaves) * 6 * hp.n_t) * sizeof(double);
-  const dim3 grid(unsigned(a.xcd_span * kXcds)), block(64 * kMvWaves);
+  const int st = hp.stencil, wt = 2 * hp.p_t + 1;
+  const size_t area = std::max<size_t>(size_t(a.K) * st * 4, size_t(a.K) * hp.n_t * 6);
+  const size_t lds = (area + size_t(hp.n_t) * wt * 4) * sizeof(double);
+  const int lanes = (a.K * hp.n_t + 63) / 64 * 64;
+  const dim3 grid(static_cast<unsigned>(a.xcd_span * kXcds)), block(static_cast<unsigned>(lanes));
 #define STFD_MV(DV, PV)                                                                    \
   if (hp.d == DV && hp.p_s == PV) {                                                       \
-    if (hp.n_t <= 64)                                                                     \
-      hipLaunchKernelGGL((matvec_kernel<DV, PV, 1>), grid, block, lds, s, a);             \
-    else                                                                                  \
-      hipLaunchKernelGGL((matvec_kernel<DV, PV, 2>), grid, block, lds, s, a);             \
+    hipLaunchKernelGGL((matvec_kernel<DV, PV>), grid, block, lds, s, a);                  \
     STFD_HIP(hipGetLastError());                                                          \
     return STFD_OK;                                                                       \
   }
@@ -1405,7 +1419,7 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lds > 0)
       P->max_lds = size_t(lds);
     P->ts_len = time_segment_length(hp.n_t, hp.p_t);
-    if (P->ts_len == 0 || hp.n_t > 64 * kMvMaxChunks) {
+    if (P->ts_len == 0 || hp.n_t > kMvMaxNt || hp.N_s * hp.n_t * 16 >= int64_t(kMvBadOffset)) {
       stfd_destroy(P);
       return STFD_EINVAL;
     }
@@ -1456,8 +1470,9 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       stfd_destroy(P);
       return rc;
     }
-  // matvec launch shape: one wave per spatial point, kMvWaves points per block
-  P->mv_blocks = (hp.N_s + kMvWaves - 1) / kMvWaves;
+  // matvec launch shape: whole spatial points per block
+  P->mv_points = matvec_points_per_block(hp);
+  P->mv_blocks = (hp.N_s + P->mv_points - 1) / P->mv_points;
   {
     // the last backward product runs along x_1 (unit cube) or along x_d (mapped domain)
     int64_t outer0 = 1;
