@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <type_traits>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -84,12 +85,51 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// Sum of nparts partials (fixed order per thread, then block tree); all threads get it.
+// Sum of nparts partials (fixed order per thread, then block tree); all threads get it.  The loads
+// of a thread are issued in batches of kSumBatch before any is added (one memory round trip per
+// batch instead of one per partial).
+constexpr int kSumBatch = 8;
 template <int NT>
 __device__ __forceinline__ double sum_partials(const double* parts, int nparts, double* sh) {
   double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += NT) s += parts[i];
+  for (int b0 = 0; b0 < nparts; b0 += NT * kSumBatch) {
+    double v[kSumBatch];
+#pragma unroll
+    for (int u = 0; u < kSumBatch; ++u) {
+      const int idx = b0 + u * NT + int(threadIdx.x);
+      v[u] = idx < nparts ? parts[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSumBatch; ++u) s += v[u];
+  }
   return block_sum<NT>(s, sh);
+}
+
+// Three sums of partials in one pass (a: na partials, b and c: nbc partials each).
+template <int NT>
+__device__ __forceinline__ void sum_partials3(const double* a, int na, const double* b, const double* c, int nbc,
+                                              double* sh, double& sa, double& sb, double& sc) {
+  double ta = 0.0, tb = 0.0, tc = 0.0;
+  const int n = max(na, nbc);
+  for (int b0 = 0; b0 < n; b0 += NT * kSumBatch) {
+    double va[kSumBatch], vb[kSumBatch], vc[kSumBatch];
+#pragma unroll
+    for (int u = 0; u < kSumBatch; ++u) {
+      const int idx = b0 + u * NT + int(threadIdx.x);
+      va[u] = idx < na ? a[idx] : 0.0;
+      vb[u] = idx < nbc ? b[idx] : 0.0;
+      vc[u] = idx < nbc ? c[idx] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kSumBatch; ++u) {
+      ta += va[u];
+      tb += vb[u];
+      tc += vc[u];
+    }
+  }
+  sa = block_sum<NT>(ta, sh);
+  sb = block_sum<NT>(tb, sh);
+  sc = block_sum<NT>(tc, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,7 +563,7 @@ struct MatvecArgs {
   const double* x;
   double* y;
   const double* Sc;     // [N_s][stencil][3] interleaved spatial coefficients
-  const double* Tband;  // [3][n_t][2 pt + 1]
+  const double* TbL;    // time bands in the kernel's LDS layout [n_t][2 pt + 1][4]: L_t, M_t, K_t, 0
   int n_t, pt;
   int n1, n2, n3;
   int K;                // spatial points per block
@@ -545,12 +585,13 @@ __device__ __forceinline__ double2 mv_load(__amdgpu_buffer_rsrc_t r, uint32_t of
   return o;
 }
 
-template <int D, int PS>
+template <int D, int PS, int PT, int RB>
 __global__ __launch_bounds__(kMvLanes) void matvec_kernel(MatvecArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double red[kMvLanes / 64];
   constexpr int W = 2 * PS + 1;
   constexpr int ST = (D == 1 ? W : (D == 2 ? W * W : W * W * W));
+  constexpr int WT = 2 * PT + 1;
   const int tid = threadIdx.x;
   // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
   // contiguous range of spatial points so that its L2 holds one slab of X.
@@ -559,23 +600,38 @@ __global__ __launch_bounds__(kMvLanes) void matvec_kernel(MatvecArgs a) {
   const int64_t rhs = lb / a.blocks_per_rhs;
   const int64_t blk = lb - rhs * a.blocks_per_rhs;
   if (a.done && a.done[rhs]) return;
-  const int n_t = a.n_t, pt = a.pt, wt = 2 * pt + 1, K = a.K;
+  STFD_STAMP(0, 0);
+  const int n_t = a.n_t, K = a.K;
   const int64_t i0 = blk * K;
   const int kp = int(min<int64_t>(K, a.N_s - i0));
-  double* Cs = reinterpret_cast<double*>(smem_raw);  // [K][ST][4]; later Z: [K][n_t][3] complex
-  const size_t area = max(size_t(K) * ST * 4, size_t(K) * n_t * 6);
-  double* Tb = Cs + area;                            // [n_t][wt][4]: L_t, M_t, K_t band entries
-  for (int idx = tid; idx < kp * ST * 3; idx += blockDim.x) {
-    const int ps = idx / 3;
-    Cs[ps * 4 + (idx - ps * 3)] = a.Sc[i0 * (ST * 3) + idx];
-  }
-  for (int idx = tid; idx < n_t * wt * 3; idx += blockDim.x) {
-    const int k = idx / (n_t * wt), rem = idx - k * (n_t * wt);
-    const int t = rem / wt, dt = rem - t * wt;
-    const int tt = t + dt - pt;
-    Tb[(t * wt + dt) * 4 + k] = (tt >= 0 && tt < n_t) ? a.Tband[idx] : 0.0;
+  double* Cs = reinterpret_cast<double*>(smem_raw);  // [K][ST][3]; later Z: [K][n_t][3] complex
+  const size_t area = (max(size_t(K) * ST * 3, size_t(K) * n_t * 6) + 1) / 2 * 2;
+  double2* Tb = reinterpret_cast<double2*>(Cs + area);  // [n_t][WT][2] double2: (L_t, M_t), (K_t, 0)
+  // staging: all loads of a thread are issued before its LDS stores (one memory round trip)
+  {
+    constexpr int kBatch = 4;
+    const int nc = kp * ST * 3, nb = n_t * WT * 2;
+    const double* src = a.Sc + i0 * (ST * 3);
+    const double2* tsrc = reinterpret_cast<const double2*>(a.TbL);
+    for (int b0 = 0; b0 < max(nc, nb); b0 += int(blockDim.x) * kBatch) {
+      double cv[kBatch];
+      double2 tv[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = b0 + u * int(blockDim.x) + tid;
+        cv[u] = src[min(idx, nc - 1)];
+        tv[u] = tsrc[min(idx, nb - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int idx = b0 + u * int(blockDim.x) + tid;
+        if (idx < nc) Cs[idx] = cv[u];
+        if (idx < nb) Tb[idx] = tv[u];
+      }
+    }
   }
   __syncthreads();
+  STFD_STAMP(0, 1);
   const int pl = tid / n_t;             // point of this lane within the block
   const int t = tid - pl * n_t;
   const bool active = pl < kp;
@@ -584,51 +640,60 @@ __global__ __launch_bounds__(kMvLanes) void matvec_kernel(MatvecArgs a) {
   const double* X = a.x + rhs * a.N_s * int64_t(2 * n_t);
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(X), 0, int(a.N_s * n_t * 16), 0x00020000);
-  // per-axis byte offsets of the neighbours (kMvBadOffset outside the grid)
+  // byte offsets of the neighbours along x_1 (kMvBadOffset outside the grid), per lane
   const int i1 = int(i % a.n1);
   const int64_t q = i / a.n1;
   const int i2 = (D >= 2) ? int(q % a.n2) : 0;
   const int i3 = (D >= 3) ? int(q / a.n2) : 0;
-  uint32_t off1[W], off2[D >= 2 ? W : 1], off3[D >= 3 ? W : 1];
+  uint32_t off1[W];
 #pragma unroll
   for (int o = 0; o < W; ++o) {
     const int j1 = i1 + o - PS;
     off1[o] = (j1 >= 0 && j1 < a.n1) ? uint32_t((j1 * n_t + t) * 16) : kMvBadOffset;
-    if constexpr (D >= 2) {
-      const int j2 = i2 + o - PS;
-      off2[o] = (j2 >= 0 && j2 < a.n2) ? uint32_t(j2) * uint32_t(a.n1 * n_t * 16) : kMvBadOffset;
-    }
-    if constexpr (D >= 3) {
-      const int j3 = i3 + o - PS;
-      off3[o] = (j3 >= 0 && j3 < a.n3) ? uint32_t(j3) * uint32_t(a.n2 * a.n1 * n_t * 16) : kMvBadOffset;
-    }
   }
+  const uint32_t s2 = uint32_t(a.n1 * n_t * 16), s3 = uint32_t(a.n2) * s2;
+  // byte offset of stencil row r = (o_3, o_2) (x_2 offset fastest)
+  auto row_off = [&](int r) -> uint32_t {
+    if constexpr (D == 1) {
+      return 0u;
+    } else if constexpr (D == 2) {
+      const int j2 = i2 + r - PS;
+      return (j2 >= 0 && j2 < a.n2) ? uint32_t(j2) * s2 : kMvBadOffset;
+    } else {
+      const int j2 = i2 + r % W - PS, j3 = i3 + r / W - PS;
+      return (j2 >= 0 && j2 < a.n2 && j3 >= 0 && j3 < a.n3) ? uint32_t(j2) * s2 + uint32_t(j3) * s3 : kMvBadOffset;
+    }
+  };
   double z[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  double2 xc = make_double2(0.0, 0.0);  // X(t, i): the centre neighbour
-  const double* C = Cs + size_t(pc) * ST * 4;
+  const double* C = Cs + size_t(pc) * ST * 3;
   constexpr int NROWS = ST / W;
+  // N stencil rows from r0: all N*W loads are issued together, then used
+  auto rows = [&](auto nrows, int r0) {
+    constexpr int N = decltype(nrows)::value;
+    double2 v[N][W];
+#pragma unroll
+    for (int rr = 0; rr < N; ++rr) {
+      const uint32_t ro = row_off(r0 + rr);
+#pragma unroll
+      for (int o = 0; o < W; ++o) v[rr][o] = mv_load(rs, ro + off1[o]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int rr = 0; rr < N; ++rr)
+#pragma unroll
+      for (int o = 0; o < W; ++o) {
+        const int sidx = (r0 + rr) * W + o;
+        const double c0 = C[sidx * 3], c1 = C[sidx * 3 + 1], c2 = C[sidx * 3 + 2];
+        z[0] = fma(c0, v[rr][o].x, z[0]); z[1] = fma(c0, v[rr][o].y, z[1]);
+        z[2] = fma(c1, v[rr][o].x, z[2]); z[3] = fma(c1, v[rr][o].y, z[3]);
+        z[4] = fma(c2, v[rr][o].x, z[4]); z[5] = fma(c2, v[rr][o].y, z[5]);
+      }
+  };
+  constexpr int NB = NROWS / RB, REM = NROWS % RB;
 #pragma unroll 1
-  for (int r = 0; r < NROWS; ++r) {
-    uint32_t orow = 0;
-    if constexpr (D == 2) orow = off2[r];
-    if constexpr (D == 3) {
-      const uint32_t a2 = off2[r % W], a3 = off3[r / W];
-      orow = (a2 == kMvBadOffset || a3 == kMvBadOffset) ? kMvBadOffset : a2 + a3;
-    }
-    double2 v[W];
-#pragma unroll
-    for (int o = 0; o < W; ++o) v[o] = mv_load(rs, orow + off1[o]);
-#pragma unroll
-    for (int o = 0; o < W; ++o) {
-      const int sidx = r * W + o;
-      const double2 c01 = *reinterpret_cast<const double2*>(C + sidx * 4);
-      const double c2 = C[sidx * 4 + 2];
-      z[0] = fma(c01.x, v[o].x, z[0]); z[1] = fma(c01.x, v[o].y, z[1]);
-      z[2] = fma(c01.y, v[o].x, z[2]); z[3] = fma(c01.y, v[o].y, z[3]);
-      z[4] = fma(c2, v[o].x, z[4]);    z[5] = fma(c2, v[o].y, z[5]);
-      if (sidx == ST / 2) xc = v[o];
-    }
-  }
+  for (int b = 0; b < NB; ++b) rows(std::integral_constant<int, RB>(), b * RB);
+  if constexpr (REM > 0) rows(std::integral_constant<int, (REM > 0 ? REM : 1)>(), NB * RB);
+  STFD_STAMP(0, 2);
   __syncthreads();  // every lane is done with the coefficients: Z takes their space
   double2* Zs = reinterpret_cast<double2*>(Cs);
   if (active) {
@@ -640,18 +705,22 @@ __global__ __launch_bounds__(kMvLanes) void matvec_kernel(MatvecArgs a) {
   if (active) {
     double yr = 0.0, yi = 0.0;
     const int base = pl * n_t;
-    for (int dt = 0; dt < wt; ++dt) {
-      const int tt = min(max(t + dt - pt, 0), n_t - 1);
-      const double2 tlm = *reinterpret_cast<const double2*>(Tb + (t * wt + dt) * 4);
-      const double tk = Tb[(t * wt + dt) * 4 + 2];
+#pragma unroll
+    for (int dt = 0; dt < WT; ++dt) {
+      const int tt = min(max(t + dt - PT, 0), n_t - 1);
+      const double2 tlm = Tb[(t * WT + dt) * 2], tk = Tb[(t * WT + dt) * 2 + 1];
       const double2 z0 = Zs[(base + tt) * 3], z1 = Zs[(base + tt) * 3 + 1], z2 = Zs[(base + tt) * 3 + 2];
-      yr += tlm.x * z0.x + tlm.y * z1.x - tk * z2.y;
-      yi += tlm.x * z0.y + tlm.y * z1.y + tk * z2.x;
+      yr += tlm.x * z0.x + tlm.y * z1.x - tk.x * z2.y;
+      yi += tlm.x * z0.y + tlm.y * z1.y + tk.x * z2.x;
     }
     const int64_t g = (rhs * a.N_s + i) * n_t + t;
     reinterpret_cast<double2*>(a.y)[g] = make_double2(yr, yi);
-    part = xc.x * yr + xc.y * yi;  // Re(conj(x) y)
+    if (a.partial) {
+      const double2 xc = reinterpret_cast<const double2*>(a.x)[g];
+      part = xc.x * yr + xc.y * yi;  // Re(conj(x) y)
+    }
   }
+  STFD_STAMP(0, 3);
   if (a.partial) {
     part = wave_sum(part);
     const int w = tid >> 6, nw = int(blockDim.x) >> 6;
@@ -853,14 +922,17 @@ __global__ __launch_bounds__(kVecBlock) void pcg_update_xr_kernel(const double* 
   const bool ok = (pq > 0.0) && std::isfinite(pq);
   const double alpha = ok ? rz / pq : 0.0;
   double s = 0.0;
-  for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
-    const int64_t g = rhs * n2 + k;
-    const double rr = r[g] - alpha * q[g], ri = r[g + 1] - alpha * q[g + 1];
+  const double2* pc = reinterpret_cast<const double2*>(p + rhs * n2);
+  const double2* qc = reinterpret_cast<const double2*>(q + rhs * n2);
+  double2* xc = reinterpret_cast<double2*>(x + rhs * n2);
+  double2* rc = reinterpret_cast<double2*>(r + rhs * n2);
+  for (int64_t k = int64_t(blockIdx.x) * kVecBlock + threadIdx.x; k < n2 / 2; k += int64_t(gridDim.x) * kVecBlock) {
+    const double2 rv = rc[k], qv = qc[k];
+    const double rr = rv.x - alpha * qv.x, ri = rv.y - alpha * qv.y;
     if (ok) {
-      x[g] += alpha * p[g];
-      x[g + 1] += alpha * p[g + 1];
-      r[g] = rr;
-      r[g + 1] = ri;
+      const double2 pv = pc[k], xv = xc[k];
+      xc[k] = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+      rc[k] = make_double2(rr, ri);
     }
     s += rr * rr + ri * ri;
   }
@@ -889,7 +961,9 @@ __global__ __launch_bounds__(kVecBlock) void pcg_end_iter_kernel(const double* z
     return;
   }
   const int k = sc[rhs].kcur;
-  const double rr = sum_partials<kVecBlock>(prr + rhs * nrr, nrr, sh);
+  // ||r||^2 and, for the direction update, <r, z_new> and <r, z_old>: one batched pass
+  double rr, rzn_all, rzm;
+  sum_partials3<kVecBlock>(prr + rhs * nrr, nrr, pa + rhs * nab, pb + rhs * nab, nab, sh, rr, rzn_all, rzm);
   const double nf2 = sc[rhs].nf2;
   const double res = sqrt(rr / nf2);
   int status = STFD_OK;
@@ -904,19 +978,18 @@ __global__ __launch_bounds__(kVecBlock) void pcg_end_iter_kernel(const double* z
     status = STFD_NOT_CONVERGED;
     finished = true;
   } else {
-    rzn = sum_partials<kVecBlock>(pa + rhs * nab, nab, sh);
-    const double rzm = sum_partials<kVecBlock>(pb + rhs * nab, nab, sh);
+    rzn = rzn_all;
     const double rz = sc[rhs].rz[parity];
     if (!(rzn > 0.0) || !std::isfinite(rzn) || !std::isfinite(rzm)) {
       status = STFD_EBREAKDOWN;
       finished = true;
     } else {
       const double beta = (rzn - rzm) / rz;
-      for (int64_t q = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; q < n2;
-           q += int64_t(gridDim.x) * kVecBlock * 2) {
-        const int64_t g = rhs * n2 + q;
-        p[g] = znew[g] + beta * p[g];
-        p[g + 1] = znew[g + 1] + beta * p[g + 1];
+      const double2* zc = reinterpret_cast<const double2*>(znew + rhs * n2);
+      double2* pc = reinterpret_cast<double2*>(p + rhs * n2);
+      for (int64_t q = int64_t(blockIdx.x) * kVecBlock + threadIdx.x; q < n2 / 2; q += int64_t(gridDim.x) * kVecBlock) {
+        const double2 zv = zc[q], pv = pc[q];
+        pc[q] = make_double2(zv.x + beta * pv.x, zv.y + beta * pv.y);
       }
     }
   }
@@ -995,8 +1068,8 @@ struct stfd_problem {
   double* TsTb = nullptr;
   int ts_len = 0, ts_segs = 0, ts_mpb = 0;
   int64_t ts_blocks = 0;
-  double* Tband = nullptr;  // [3][n_t][2 p_t + 1]: L_t, M_t, K_t bands
   double* Sc = nullptr;
+  double* TbL = nullptr;  // time bands in the matvec's LDS layout
   double* work64[2] = {nullptr, nullptr};
   float* work32[2] = {nullptr, nullptr};
   double* vec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // r, z, z2, p, q
@@ -1207,11 +1280,12 @@ static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64
   }
 }
 
+constexpr int kMvRowBatch = 1;  // stencil rows whose loads are issued together (measured best)
+
 // spatial points per matvec block: whole points, at most kMvLanes lanes, coefficients (or Z) in kMvLds
 static int matvec_points_per_block(const HostProblem& hp) {
-  const int st = hp.stencil;
-  const size_t per_point = std::max<size_t>(size_t(st) * 4, size_t(hp.n_t) * 6) * sizeof(double);
-  int K = std::min<int>(kMvLanes / hp.n_t, int(kMvLds / per_point));
+  const size_t per_point = std::max<size_t>(size_t(hp.stencil) * 3, size_t(hp.n_t) * 6) * sizeof(double);
+  const int K = std::min<int>(kMvLanes / hp.n_t, int(kMvLds / per_point));
   return std::max(K, 1);
 }
 
@@ -1222,7 +1296,7 @@ static int matvec_dispatch(stfd_problem* P, const double* x, double* y, int64_t 
   a.x = x;
   a.y = y;
   a.Sc = P->Sc;
-  a.Tband = P->Tband;
+  a.TbL = P->TbL;
   a.n_t = hp.n_t;
   a.pt = hp.p_t;
   a.n1 = hp.n_s[0];
@@ -1236,20 +1310,30 @@ static int matvec_dispatch(stfd_problem* P, const double* x, double* y, int64_t 
   a.partial = partial;
   a.done = done;
   const int st = hp.stencil, wt = 2 * hp.p_t + 1;
-  const size_t area = std::max<size_t>(size_t(a.K) * st * 4, size_t(a.K) * hp.n_t * 6);
+  const size_t area = (std::max<size_t>(size_t(a.K) * st * 3, size_t(a.K) * hp.n_t * 6) + 1) / 2 * 2;
   const size_t lds = (area + size_t(hp.n_t) * wt * 4) * sizeof(double);
   const int lanes = (a.K * hp.n_t + 63) / 64 * 64;
   const dim3 grid(static_cast<unsigned>(a.xcd_span * kXcds)), block(static_cast<unsigned>(lanes));
-#define STFD_MV(DV, PV)                                                                    \
-  if (hp.d == DV && hp.p_s == PV) {                                                       \
-    hipLaunchKernelGGL((matvec_kernel<DV, PV>), grid, block, lds, s, a);                  \
-    STFD_HIP(hipGetLastError());                                                          \
-    return STFD_OK;                                                                       \
+#define STFD_MV_T(DV, PV, TV)                                                                     \
+  case TV:                                                                                       \
+    hipLaunchKernelGGL((matvec_kernel<DV, PV, TV, kMvRowBatch>), grid, block, lds, s, a);         \
+    break;
+#define STFD_MV(DV, PV)                                                                           \
+  if (hp.d == DV && hp.p_s == PV) {                                                              \
+    switch (hp.p_t) {                                                                            \
+      STFD_MV_T(DV, PV, 1) STFD_MV_T(DV, PV, 2) STFD_MV_T(DV, PV, 3) STFD_MV_T(DV, PV, 4)         \
+      STFD_MV_T(DV, PV, 5) STFD_MV_T(DV, PV, 6)                                                  \
+      default:                                                                                   \
+        return STFD_EINVAL;                                                                      \
+    }                                                                                            \
+    STFD_HIP(hipGetLastError());                                                                 \
+    return STFD_OK;                                                                              \
   }
   STFD_MV(1, 2) STFD_MV(1, 3) STFD_MV(1, 4) STFD_MV(1, 5) STFD_MV(1, 6)
   STFD_MV(2, 2) STFD_MV(2, 3) STFD_MV(2, 4) STFD_MV(2, 5)
   STFD_MV(3, 2) STFD_MV(3, 3) STFD_MV(3, 4)
 #undef STFD_MV
+#undef STFD_MV_T
   return STFD_EINVAL;
 }
 
@@ -1445,7 +1529,18 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     const size_t ns = size_t(hp.N_s) * hp.stencil;
     for (size_t is = 0; is < ns; ++is)
       for (int k = 0; k < 3; ++k) ScI[is * 3 + k] = hp.Sc[k * ns + is];
-    if ((rc = upload(P, &P->Tband, hp.Tband.data(), hp.Tband.size())) ||
+    // time bands in the matvec's LDS layout [t][dt][4] = (L_t, M_t, K_t, 0), zero where t + dt - p_t
+    // falls outside the time axis
+    const int wtb = 2 * hp.p_t + 1;
+    std::vector<double> TbL(size_t(hp.n_t) * wtb * 4, 0.0);
+    for (int k = 0; k < 3; ++k)
+      for (int t = 0; t < hp.n_t; ++t)
+        for (int dt = 0; dt < wtb; ++dt) {
+          const int tt = t + dt - hp.p_t;
+          if (tt >= 0 && tt < hp.n_t)
+            TbL[(size_t(t) * wtb + dt) * 4 + k] = hp.Tband[(size_t(k) * hp.n_t + t) * wtb + dt];
+        }
+    if ((rc = upload(P, &P->TbL, TbL.data(), TbL.size())) ||
         (rc = dev_alloc(P, &P->Sc, ScI.size()))) {
       stfd_destroy(P);
       return rc;
