@@ -31,11 +31,12 @@ sys.path.insert(0, ROOT)
 METRIC = "FD precond apply Mdof/s + PCG time to 1e-8: FP64 vs mixed/batched/warm-start"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and matrix peak
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of matvec_kernel<2,3,2> on this workload: FETCH_SIZE and WRITE_SIZE passes of
-# rocprofv3 over `bench.py --profile`, each scaled by what the same counter reads for a 64 MiB
+# HBM bytes per launch of the 2D p=3 matvec kernel on this workload: FETCH_SIZE and WRITE_SIZE passes
+# of rocprofv3 over `bench.py --profile`, each scaled by what the same counter reads for a 64 MiB
 # device copy in that run (x 1.999 and x 1.000); profiles/pcg_2d_p3_n64_gauss_traffic.md.  Valid for
-# the matvec kernel as profiled (17.31 MB read + 4.47 MB written per launch).
-MATVEC_TRAFFIC_BYTES = 21.78e6
+# the matvec kernel as profiled (12.59 MB read + 4.47 MB written per launch).
+MATVEC_KERNEL = "matvec_kernel<2,3,3,1>"
+MATVEC_TRAFFIC_BYTES = 17.06e6
 
 
 def build_workload(sample=0, n_el=64, p=3):
@@ -265,7 +266,7 @@ def main():
     p, d = w.p, 2
     flops_per_dof = 12 * ((2 * p + 1) ** d + 2 * p + 1)
     achieved = flops_per_dof * N / (matvec_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "matvec_kernel<2,3,2>", "achieved": round(achieved, 3),
+    roofline = {"bound": "alu", "kernel": MATVEC_KERNEL, "achieved": round(achieved, 3),
                 "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                 "traffic": MATVEC_TRAFFIC_BYTES, "traffic_unit": "bytes per launch (rocprofv3 FETCH/WRITE_SIZE, "
                                                                "copy-calibrated)",
