@@ -124,6 +124,49 @@ def warmstart_section(stream, n_eval=20):
     return out
 
 
+def precision_3d_section(stream, cases=((48, 3), (32, 4)), bf16_maxit=300):
+    """3D space + time with the seeded harmonic potential (p = 3 at 48^4 elements, p = 4 at 32^4):
+    FD apply throughput and error of the FP32 and BF16 mode products against the FP64 apply on the
+    same input, and PCG to 1e-8 per preconditioner precision (FP64 outer loop; BF16 capped)."""
+    import torch
+    from paper_2311_18461_amd import inputs, stfd
+    dev = torch.device("cuda:0")
+    out = {}
+    for n_el, p in cases:
+        w = inputs.harmonic_3d_workload(0, n_el=n_el, p=p, with_potential=True)
+        ks = [w.knots_s()] * 3
+        t0 = time.perf_counter()
+        prob = stfd.Problem(w.knots_t(), ks, p, p, w.T, w.nu, V_quad=stfd.sample_on_quad_grid(w.potential, ks, p))
+        torch.cuda.synchronize()
+        row = {"n_dof_free": prob.N, "setup_s": round(time.perf_counter() - t0, 2)}
+        r = torch.from_numpy(inputs.random_complex(prob.N, 3999)).to(dev)
+        z = torch.empty_like(r)
+        z64 = torch.empty_like(r)
+        for prec in ("fp64", "fp32", "bf16"):
+            prob.apply_preconditioner(r, z, precision=prec, stream=stream)
+            ms = time_events(lambda: prob.apply_preconditioner(r, z, precision=prec, stream=stream), 10, stream)
+            if prec == "fp64":
+                z64.copy_(z)
+            err = float(torch.linalg.vector_norm(z - z64) / torch.linalg.vector_norm(z64))
+            row[prec] = {"apply_ms": round(ms, 4), "apply_mdofs": round(prob.N / (ms * 1e-3) / 1e6, 1),
+                         "apply_relerr_vs_fp64": float(f"{err:.3e}")}
+        row["matvec_ms"] = round(time_events(lambda: prob.matvec(r, z, stream=stream), 10, stream), 4)
+        f = torch.empty_like(r)
+        prob.load_vector(f, u0_q=torch.from_numpy(prob.sample_space(w.u0)).to(dev), stream=stream)
+        u = torch.empty_like(r)
+        for prec in ("fp64", "fp32", "bf16"):
+            maxit = bf16_maxit if prec == "bf16" else 1000
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rc, info = prob.pcg_solve(f, u, rtol=1e-8, maxit=maxit, precision=prec, stream=stream)
+            torch.cuda.synchronize()
+            row[prec].update({"pcg_ms": round((time.perf_counter() - t1) * 1e3, 2), "pcg_iterations": info[0]["iters"],
+                              "pcg_converged": rc == stfd.OK, "pcg_true_rel_res": float(f"{info[0]['true_rel_res']:.3e}")})
+        prob.close()
+        out[f"p{p}_n{n_el}_harmonic"] = row
+    return out
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The oracle (FP64 NumPy/SciPy, all host cores): right-hand side with lifting, then PCG to 1e-8,
     on the same workload (setup excluded)."""
@@ -160,6 +203,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D precision section")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3: one solve, 20 applies and matvecs, and a device copy of "
@@ -305,6 +349,8 @@ def main():
     }
     out["batched"] = batched_section(dev, stream)
     out["warm_start"] = warmstart_section(stream)
+    if not args.no_3d:
+        out["precision_3d"] = precision_3d_section(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out))

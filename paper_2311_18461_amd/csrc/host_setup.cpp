@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 namespace stfd {
 
@@ -279,64 +280,89 @@ void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2]
   const int q = hp.dir_s[0].q;
   int npts = 1;
   for (int l = 0; l < d; ++l) npts *= q;
-  std::vector<double> cur, nxt;
-  for (int e3 = 0; e3 < nel[2]; ++e3)
-    for (int e2 = 0; e2 < nel[1]; ++e2)
-      for (int e1 = 0; e1 < nel[0]; ++e1) {
-        int e[3] = {e1, e2, e3};
-        // cur[(g_1 q + g_2) q + g_3] = weight at the local points (direction 1 slowest, so
-        // that each contraction below removes the slowest remaining point index)
-        cur.assign(npts, 0.0);
-        for (int g = 0; g < npts; ++g) {
-          int gl[3] = {0, 0, 0};
-          int rg = g;
-          for (int l = d - 1; l >= 0; --l) { gl[l] = rg % q; rg /= q; }
-          size_t gi = 0, st = 1;
-          for (int l = 0; l < d; ++l) { gi += size_t(e[l] * q + gl[l]) * st; st *= Q[l]; }
-          cur[g] = cq ? cq[gi] : 1.0;
-        }
-        // contract direction l: pairs (a_l, b_l) replace g_l; layout [pairs so far][remaining g]
-        int npairs = 1, rem = npts;
-        for (int l = 0; l < d; ++l) {
-          rem /= q;
-          const Direction& D = hp.dir_s[l];
-          nxt.assign(size_t(npairs) * nl * nl * rem, 0.0);
-          for (int pr = 0; pr < npairs; ++pr)
-            for (int a = 0; a < nl; ++a)
-              for (int b = 0; b < nl; ++b)
-                for (int r = 0; r < rem; ++r) {
-                  double s = 0.0;
-                  for (int g = 0; g < q; ++g)
-                    s += D.w[size_t(e[l]) * q + g] * D.b(e[l], g, ders[l][0], a) * D.b(e[l], g, ders[l][1], b) *
-                         cur[(size_t(pr) * q + g) * rem + r];
-                  nxt[((size_t(pr) * nl + a) * nl + b) * rem + r] = s;
-                }
-          npairs *= nl * nl;
-          cur.swap(nxt);
-        }
-        // scatter: cur[pairs] with pair index ((a_1 b_1) (a_2 b_2) ...), direction 1 slowest
-        for (int pr = 0; pr < npairs; ++pr) {
-          int rest = pr;
-          int a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
-          for (int l = d - 1; l >= 0; --l) {
-            b[l] = rest % nl; rest /= nl;
-            a[l] = rest % nl; rest /= nl;
-          }
-          int64_t I = 0, st = 1;
-          int s = 0, sst = 1;
-          bool ok = true;
-          for (int l = 0; l < d; ++l) {
-            int ri = hp.dir_s[l].first[e[l]] + a[l] - 1;  // reduced index
-            int rj = hp.dir_s[l].first[e[l]] + b[l] - 1;
-            if (ri < 0 || ri >= hp.n_s[l] || rj < 0 || rj >= hp.n_s[l]) { ok = false; break; }
-            I += int64_t(ri) * st;
-            st *= hp.n_s[l];
-            s += (rj - ri + p) * sst;
-            sst *= w2;
-          }
-          if (ok) out_stencil[size_t(I) * hp.stencil + s] += cur[pr];
-        }
+  // one element: quadrature weights at its points, sum-factorised contraction, scatter into the
+  // stencil rows of its basis functions
+  auto element = [&](const int (&e)[3], std::vector<double>& cur, std::vector<double>& nxt) {
+    // cur[(g_1 q + g_2) q + g_3] = weight at the local points (direction 1 slowest, so
+    // that each contraction below removes the slowest remaining point index)
+    cur.assign(npts, 0.0);
+    for (int g = 0; g < npts; ++g) {
+      int gl[3] = {0, 0, 0};
+      int rg = g;
+      for (int l = d - 1; l >= 0; --l) { gl[l] = rg % q; rg /= q; }
+      size_t gi = 0, st = 1;
+      for (int l = 0; l < d; ++l) { gi += size_t(e[l] * q + gl[l]) * st; st *= Q[l]; }
+      cur[g] = cq ? cq[gi] : 1.0;
+    }
+    // contract direction l: pairs (a_l, b_l) replace g_l; layout [pairs so far][remaining g]
+    int npairs = 1, rem = npts;
+    for (int l = 0; l < d; ++l) {
+      rem /= q;
+      const Direction& D = hp.dir_s[l];
+      nxt.assign(size_t(npairs) * nl * nl * rem, 0.0);
+      for (int pr = 0; pr < npairs; ++pr)
+        for (int a = 0; a < nl; ++a)
+          for (int b = 0; b < nl; ++b)
+            for (int r = 0; r < rem; ++r) {
+              double s = 0.0;
+              for (int g = 0; g < q; ++g)
+                s += D.w[size_t(e[l]) * q + g] * D.b(e[l], g, ders[l][0], a) * D.b(e[l], g, ders[l][1], b) *
+                     cur[(size_t(pr) * q + g) * rem + r];
+              nxt[((size_t(pr) * nl + a) * nl + b) * rem + r] = s;
+            }
+      npairs *= nl * nl;
+      cur.swap(nxt);
+    }
+    // scatter: cur[pairs] with pair index ((a_1 b_1) (a_2 b_2) ...), direction 1 slowest
+    for (int pr = 0; pr < npairs; ++pr) {
+      int rest = pr;
+      int a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+      for (int l = d - 1; l >= 0; --l) {
+        b[l] = rest % nl; rest /= nl;
+        a[l] = rest % nl; rest /= nl;
       }
+      int64_t I = 0, st = 1;
+      int s = 0, sst = 1;
+      bool ok = true;
+      for (int l = 0; l < d; ++l) {
+        int ri = hp.dir_s[l].first[e[l]] + a[l] - 1;  // reduced index
+        int rj = hp.dir_s[l].first[e[l]] + b[l] - 1;
+        if (ri < 0 || ri >= hp.n_s[l] || rj < 0 || rj >= hp.n_s[l]) { ok = false; break; }
+        I += int64_t(ri) * st;
+        st *= hp.n_s[l];
+        s += (rj - ri + p) * sst;
+        sst *= w2;
+      }
+      if (ok) out_stencil[size_t(I) * hp.stencil + s] += cur[pr];
+    }
+  };
+  // threads over the elements of the slowest direction L, one colour e_L mod (p + 1) at a time:
+  // elements of one colour share no basis function along L, so their stencil rows are disjoint
+  const int L = d - 1, colours = p + 1;
+  int nth = int(std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 32u));
+  nth = std::min(nth, std::max(1, nel[L] / colours));
+  auto work = [&](int colour, int tid) {
+    std::vector<double> cur, nxt;
+    int e[3] = {0, 0, 0};
+    for (int eL = colour + tid * colours; eL < nel[L]; eL += nth * colours) {
+      e[L] = eL;
+      const int n_other = (L >= 1 ? nel[0] : 1) * (L >= 2 ? nel[1] : 1);
+      for (int o = 0; o < n_other; ++o) {
+        if (L >= 1) e[0] = o % nel[0];
+        if (L >= 2) e[1] = o / nel[0];
+        element(e, cur, nxt);
+      }
+    }
+  };
+  for (int colour = 0; colour < colours; ++colour) {
+    if (nth == 1) {
+      work(colour, 0);
+      continue;
+    }
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nth; ++t) pool.emplace_back(work, colour, t);
+    for (std::thread& th : pool) th.join();
+  }
 }
 
 // LDL^H factors of H_i = L_t + mu^2 M_t + i mu K_t, mu = nu lambda_i (Section 5.2), for the
