@@ -30,6 +30,8 @@
 
 namespace stfd {
 
+constexpr int kContractBatch = 8;
+
 // out[o][i][r] = alpha * sum_{k in [lo_i, hi_i)} M[i * ld + k] in[o][k][r]  (+ out if accumulate)
 __global__ void __launch_bounds__(256) axis_contract_kernel(const double2* __restrict__ in, double2* __restrict__ out,
                                                             const double* __restrict__ M, const int* __restrict__ lo,
@@ -44,11 +46,23 @@ __global__ void __launch_bounds__(256) axis_contract_kernel(const double2* __res
     const double2* src = in + o * n_in * inner + r;
     const double* row = M + int64_t(i) * ld;
     double sr = 0.0, si = 0.0;
-    for (int k = lo[i]; k < hi[i]; ++k) {
-      const double c = row[k];
-      const double2 v = src[int64_t(k) * inner];
-      sr = fma(c, v.x, sr);
-      si = fma(c, v.y, si);
+    // the band in batches whose loads are all issued before any is used (addresses clamped
+    // into the band, coefficients of the clamped slots zero)
+    const int k0 = lo[i], k1 = hi[i];
+    for (int kb = k0; kb < k1; kb += kContractBatch) {
+      double c[kContractBatch];
+      double2 v[kContractBatch];
+#pragma unroll
+      for (int u = 0; u < kContractBatch; ++u) {
+        const int k = min(kb + u, k1 - 1);
+        c[u] = kb + u < k1 ? row[k] : 0.0;
+        v[u] = src[int64_t(k) * inner];
+      }
+#pragma unroll
+      for (int u = 0; u < kContractBatch; ++u) {
+        sr = fma(c[u], v[u].x, sr);
+        si = fma(c[u], v[u].y, si);
+      }
     }
     double2 res;
     res.x = ar * sr - ai * si;
@@ -59,6 +73,69 @@ __global__ void __launch_bounds__(256) axis_contract_kernel(const double2* __res
       res.y += prev.y;
     }
     out[g] = res;
+  }
+}
+
+// Time axis (the fastest one) of the load vector, one block per spatial grid point o, the point's
+// time line staged in LDS:
+//   time_expand: R[o][q] = f[o][q] - i sum_k E1[q][k] A[o][k] + sum_k E0[q][k] C[o][k]
+//                (f == nullptr: 0), E0 / E1 the time basis and its derivative at the Gauss points;
+//   time_load:   X0[o][i] = sum_q L0[i][q] R[o][q],  X1[o][i] = sum_q L1[i][q] R[o][q],
+//                Y[o][i] = J[o] (-i X1 + V[o] X0)  (V == nullptr drops the term, J == nullptr: 1).
+__global__ void __launch_bounds__(256) time_expand_kernel(const double2* __restrict__ A, const double2* __restrict__ C,
+                                                          const double2* __restrict__ f, double2* __restrict__ R,
+                                                          const double* __restrict__ E0, const double* __restrict__ E1,
+                                                          const int* __restrict__ lo, const int* __restrict__ hi, int m,
+                                                          int Q) {
+  extern __shared__ double2 tl[];  // [2][m]: A and C of this point
+  const int64_t o = blockIdx.x;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) {
+    tl[k] = A[o * m + k];
+    tl[m + k] = C[o * m + k];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) {
+    double ar = 0.0, ai = 0.0, cr = 0.0, ci = 0.0;
+    for (int k = lo[q]; k < hi[q]; ++k) {
+      const double e0 = E0[int64_t(q) * m + k], e1 = E1[int64_t(q) * m + k];
+      const double2 a = tl[k], c = tl[m + k];
+      ar = fma(e1, a.x, ar);
+      ai = fma(e1, a.y, ai);
+      cr = fma(e0, c.x, cr);
+      ci = fma(e0, c.y, ci);
+    }
+    double2 res = make_double2(ai + cr, ci - ar);  // -i (ar + i ai) + (cr + i ci)
+    if (f) {
+      const double2 fv = f[o * Q + q];
+      res.x += fv.x;
+      res.y += fv.y;
+    }
+    R[o * Q + q] = res;
+  }
+}
+
+__global__ void __launch_bounds__(256) time_load_kernel(const double2* __restrict__ R, double2* __restrict__ X0,
+                                                        double2* __restrict__ Y, const double* __restrict__ L0,
+                                                        const double* __restrict__ L1, const int* __restrict__ lo,
+                                                        const int* __restrict__ hi, int Q, int n,
+                                                        const double* __restrict__ V, const double* __restrict__ J) {
+  extern __shared__ double2 tl[];  // [Q]: R of this point
+  const int64_t o = blockIdx.x;
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) tl[q] = R[o * Q + q];
+  __syncthreads();
+  const double v = V ? V[o] : 0.0, jac = J ? J[o] : 1.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double x0r = 0.0, x0i = 0.0, x1r = 0.0, x1i = 0.0;
+    for (int q = lo[i]; q < hi[i]; ++q) {
+      const double l0 = L0[int64_t(i) * Q + q], l1 = L1[int64_t(i) * Q + q];
+      const double2 r = tl[q];
+      x0r = fma(l0, r.x, x0r);
+      x0i = fma(l0, r.y, x0i);
+      x1r = fma(l1, r.x, x1r);
+      x1i = fma(l1, r.y, x1i);
+    }
+    X0[o * n + i] = make_double2(x0r, x0i);
+    Y[o * n + i] = make_double2(jac * (x1i + v * x0r), jac * (v * x0i - x1r));
   }
 }
 
@@ -266,22 +343,46 @@ __global__ void __launch_bounds__(256) lift_prec_axis_kernel(LiftArgs A, int ste
     const int mm = F.dims[step];
     const double* row = A.Minv[ax] + int64_t(li[step]) * mm;
     double sr = 0.0, si = 0.0;
+    // dense row of the 1D inverse in batches whose loads are issued before use
     if (step == 0) {
       int64_t g = int64_t(F.normal_index) * A.fc.stride[F.normal_axis];
       for (int k = 0; k < F.n_tan; ++k)
         if (k != step) g += int64_t(li[k]) * A.fc.stride[F.tan_axis[k]];
       const int64_t sg = A.fc.stride[ax];
-      for (int j = 0; j < mm; ++j) {
-        const double2 v = r[A.pos[g + j * sg]];
-        sr = fma(row[j], v.x, sr);
-        si = fma(row[j], v.y, si);
+      for (int jb = 0; jb < mm; jb += kContractBatch) {
+        int pj[kContractBatch];
+        double c[kContractBatch];
+#pragma unroll
+        for (int u = 0; u < kContractBatch; ++u) {
+          const int j = min(jb + u, mm - 1);
+          pj[u] = A.pos[g + j * sg];
+          c[u] = jb + u < mm ? row[j] : 0.0;
+        }
+        double2 v[kContractBatch];
+#pragma unroll
+        for (int u = 0; u < kContractBatch; ++u) v[u] = r[pj[u]];
+#pragma unroll
+        for (int u = 0; u < kContractBatch; ++u) {
+          sr = fma(c[u], v[u].x, sr);
+          si = fma(c[u], v[u].y, si);
+        }
       }
     } else {
       const double2* src = in + F.offset + (loc - int64_t(li[step]) * lstride[step]);
-      for (int j = 0; j < mm; ++j) {
-        const double2 v = src[j * lstride[step]];
-        sr = fma(row[j], v.x, sr);
-        si = fma(row[j], v.y, si);
+      for (int jb = 0; jb < mm; jb += kContractBatch) {
+        double c[kContractBatch];
+        double2 v[kContractBatch];
+#pragma unroll
+        for (int u = 0; u < kContractBatch; ++u) {
+          const int j = min(jb + u, mm - 1);
+          c[u] = jb + u < mm ? row[j] : 0.0;
+          v[u] = src[j * lstride[step]];
+        }
+#pragma unroll
+        for (int u = 0; u < kContractBatch; ++u) {
+          sr = fma(c[u], v[u].x, sr);
+          si = fma(c[u], v[u].y, si);
+        }
       }
     }
     out[e] = make_double2(sr, si);
@@ -795,48 +896,25 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
                        -1.0);
     if ((rc = int(hipGetLastError()))) return rc;
   }
-  // R = f - i B_t'^T A0 + B_t^T C
-  if (f_q) {
-    if ((rc = int(hipMemcpyAsync(R, f_q, grid * 2 * sizeof(double), hipMemcpyDeviceToDevice, s)))) return rc;
-  } else {
-    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(2 * int64_t(grid))), dim3(256), 0, s, R, int64_t(2 * grid));
-    if ((rc = int(hipGetLastError()))) return rc;
-  }
-  {
-    Shape sh;
-    sh.na = na;
-    sh.dims[0] = plan.m[0];
-    for (int a = 1; a < na; ++a) sh.dims[a] = plan.Q[a];
-    Shape sh2 = sh;
-    if ((rc = contract(A0, R, sh, 0, plan.eval[0][1], plan.eval_lo[0], plan.eval_hi[0], plan.m[0], plan.Q[0], 0.0,
-                       -1.0, true, s)))
-      return rc;
-    if ((rc = contract(A2, R, sh2, 0, plan.eval[0][0], plan.eval_lo[0], plan.eval_hi[0], plan.m[0], plan.Q[0], 1.0,
-                       0.0, true, s)))
-      return rc;
-  }
-
-  // load vector: X0 = B_t^w R, X1 = B_t'^w R (free time rows)
+  // R = f - i B_t'^T A0 + B_t^T C, then X0 = B_t^w R and Y = J (-i B_t'^w R + V X0) (in X1) for the
+  // free time rows: one pass each over the space-time grid, one block per spatial grid point
   double* X0 = A0;
   double* X1 = A2;
-  {
-    Shape sh;
-    sh.na = na;
-    for (int a = 0; a < na; ++a) sh.dims[a] = plan.Q[a];
-    Shape sh2 = sh;
-    if ((rc = contract(R, X0, sh, 0, plan.load[0][0], plan.load_lo[0], plan.load_hi[0], plan.Q[0], plan.n[0], 1.0,
-                       0.0, false, s)))
-      return rc;
-    if ((rc = contract(R, X1, sh2, 0, plan.load[0][1], plan.load_lo[0], plan.load_hi[0], plan.Q[0], plan.n[0], 1.0,
-                       0.0, false, s)))
-      return rc;
-  }
-  // Y = J (-i X1 + V X0) (in place in X1)
   int64_t xs = plan.n[0];
-  for (int a = 1; a < na; ++a) xs *= plan.Q[a];
-  hipLaunchKernelGGL(combine_v_kernel, dim3(grid_for(xs)), dim3(256), 0, s, (const double2*)X1, (const double2*)X0,
-                     plan.Vq, plan.Jq, (double2*)X1, int64_t(plan.n[0]), xs, 0.0, -1.0, 1.0);
-  if ((rc = int(hipGetLastError()))) return rc;
+  {
+    int64_t npts = 1;
+    for (int a = 1; a < na; ++a) npts *= plan.Q[a];
+    const int m0 = plan.m[0], Q0 = plan.Q[0], n0 = plan.n[0];
+    hipLaunchKernelGGL(time_expand_kernel, dim3(static_cast<unsigned>(npts)), dim3(256), 2 * m0 * sizeof(double2), s,
+                       (const double2*)A0, (const double2*)A2, (const double2*)f_q, (double2*)R, plan.eval[0][0],
+                       plan.eval[0][1], plan.eval_lo[0], plan.eval_hi[0], m0, Q0);
+    if ((rc = int(hipGetLastError()))) return rc;
+    hipLaunchKernelGGL(time_load_kernel, dim3(static_cast<unsigned>(npts)), dim3(128), Q0 * sizeof(double2), s,
+                       (const double2*)R, (double2*)X0, (double2*)X1, plan.load[0][0], plan.load[0][1],
+                       plan.load_lo[0], plan.load_hi[0], Q0, n0, plan.Vq, plan.Jq);
+    if ((rc = int(hipGetLastError()))) return rc;
+    xs *= npts;
+  }
   auto load_chain = [&](const double* src0, const int* ord, double ar, bool accumulate) -> int {
     Shape sh;
     sh.na = na;
