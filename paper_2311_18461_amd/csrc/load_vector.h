@@ -47,6 +47,10 @@ struct LoadPlan {
   double* load[4][3] = {};
   int* load_lo[4] = {};
   int* load_hi[4] = {};
+  // time axis: bands of eval[0][r] and load[0][r] (r = 0, 1) transposed, band[u][row]
+  double* tband_eval[2] = {};
+  double* tband_load[2] = {};
+  int tband_ew = 0, tband_lw = 0;
   double* wfull[4] = {};
   int* wfull_lo[4] = {};
   int* wfull_hi[4] = {};

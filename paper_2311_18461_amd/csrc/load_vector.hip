@@ -80,13 +80,13 @@ __global__ void __launch_bounds__(256) axis_contract_kernel(const double2* __res
 // time line staged in LDS:
 //   time_expand: R[o][q] = f[o][q] - i sum_k E1[q][k] A[o][k] + sum_k E0[q][k] C[o][k]
 //                (f == nullptr: 0), E0 / E1 the time basis and its derivative at the Gauss points;
+//   (both matrices as transposed bands band[u][row] = M[row][lo_row + u]);
 //   time_load:   X0[o][i] = sum_q L0[i][q] R[o][q],  X1[o][i] = sum_q L1[i][q] R[o][q],
 //                Y[o][i] = J[o] (-i X1 + V[o] X0)  (V == nullptr drops the term, J == nullptr: 1).
 __global__ void __launch_bounds__(256) time_expand_kernel(const double2* __restrict__ A, const double2* __restrict__ C,
                                                           const double2* __restrict__ f, double2* __restrict__ R,
-                                                          const double* __restrict__ E0, const double* __restrict__ E1,
-                                                          const int* __restrict__ lo, const int* __restrict__ hi, int m,
-                                                          int Q) {
+                                                          const double* __restrict__ E0b, const double* __restrict__ E1b,
+                                                          const int* __restrict__ lo, int ew, int m, int Q) {
   extern __shared__ double2 tl[];  // [2][m]: A and C of this point
   const int64_t o = blockIdx.x;
   for (int k = threadIdx.x; k < m; k += blockDim.x) {
@@ -96,8 +96,10 @@ __global__ void __launch_bounds__(256) time_expand_kernel(const double2* __restr
   __syncthreads();
   for (int q = threadIdx.x; q < Q; q += blockDim.x) {
     double ar = 0.0, ai = 0.0, cr = 0.0, ci = 0.0;
-    for (int k = lo[q]; k < hi[q]; ++k) {
-      const double e0 = E0[int64_t(q) * m + k], e1 = E1[int64_t(q) * m + k];
+    const int k0 = lo[q];
+    for (int u = 0; u < ew; ++u) {
+      const int k = min(k0 + u, m - 1);  // slots past the row's band carry zero weights
+      const double e0 = E0b[int64_t(u) * Q + q], e1 = E1b[int64_t(u) * Q + q];
       const double2 a = tl[k], c = tl[m + k];
       ar = fma(e1, a.x, ar);
       ai = fma(e1, a.y, ai);
@@ -115,10 +117,10 @@ __global__ void __launch_bounds__(256) time_expand_kernel(const double2* __restr
 }
 
 __global__ void __launch_bounds__(256) time_load_kernel(const double2* __restrict__ R, double2* __restrict__ X0,
-                                                        double2* __restrict__ Y, const double* __restrict__ L0,
-                                                        const double* __restrict__ L1, const int* __restrict__ lo,
-                                                        const int* __restrict__ hi, int Q, int n,
-                                                        const double* __restrict__ V, const double* __restrict__ J) {
+                                                        double2* __restrict__ Y, const double* __restrict__ L0b,
+                                                        const double* __restrict__ L1b, const int* __restrict__ lo,
+                                                        int lw, int Q, int n, const double* __restrict__ V,
+                                                        const double* __restrict__ J) {
   extern __shared__ double2 tl[];  // [Q]: R of this point
   const int64_t o = blockIdx.x;
   for (int q = threadIdx.x; q < Q; q += blockDim.x) tl[q] = R[o * Q + q];
@@ -126,8 +128,10 @@ __global__ void __launch_bounds__(256) time_load_kernel(const double2* __restric
   const double v = V ? V[o] : 0.0, jac = J ? J[o] : 1.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double x0r = 0.0, x0i = 0.0, x1r = 0.0, x1i = 0.0;
-    for (int q = lo[i]; q < hi[i]; ++q) {
-      const double l0 = L0[int64_t(i) * Q + q], l1 = L1[int64_t(i) * Q + q];
+    const int q0 = lo[i];
+    for (int u = 0; u < lw; ++u) {
+      const int q = min(q0 + u, Q - 1);  // slots past the row's band carry zero weights
+      const double l0 = L0b[int64_t(u) * n + i], l1 = L1b[int64_t(u) * n + i];
       const double2 r = tl[q];
       x0r = fma(l0, r.x, x0r);
       x0i = fma(l0, r.y, x0i);
@@ -688,6 +692,24 @@ int load_plan_build(const HostProblem& hp, LoadPlan& plan) {
     }
     if (int rc = plan_upload(plan, &plan.eval_lo[a], elo)) return rc;
     if (int rc = plan_upload(plan, &plan.eval_hi[a], ehi)) return rc;
+    if (a == 0) {
+      // time axis: the bands of the evaluation (rows q) and load (rows i) matrices transposed,
+      // band[u][row] = M[row][lo_row + u], so that the rows of consecutive threads are adjacent
+      int ew = 0, lw = 0;
+      for (int q = 0; q < Q; ++q) ew = std::max(ew, ehi[q] - elo[q]);
+      for (int i = 0; i < n; ++i) lw = std::max(lw, lhi[i] - llo[i]);
+      plan.tband_ew = ew;
+      plan.tband_lw = lw;
+      for (int r = 0; r < 2; ++r) {
+        std::vector<double> eb(size_t(ew) * Q, 0.0), lb(size_t(std::max(lw, 1)) * n, 0.0);
+        for (int q = 0; q < Q; ++q)
+          for (int u = 0; u < ehi[q] - elo[q]; ++u) eb[size_t(u) * Q + q] = ev[r][size_t(q) * m + elo[q] + u];
+        for (int i = 0; i < n; ++i)
+          for (int u = 0; u < lhi[i] - llo[i]; ++u) lb[size_t(u) * n + i] = ld[r][size_t(i) * Q + llo[i] + u];
+        if (int rc = plan_upload(plan, &plan.tband_eval[r], eb)) return rc;
+        if (int rc = plan_upload(plan, &plan.tband_load[r], lb)) return rc;
+      }
+    }
     if (int rc = plan_upload(plan, &plan.load_lo[a], llo)) return rc;
     if (int rc = plan_upload(plan, &plan.load_hi[a], lhi)) return rc;
     if (int rc = plan_upload(plan, &plan.wfull[a], wf)) return rc;
@@ -906,12 +928,12 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
     for (int a = 1; a < na; ++a) npts *= plan.Q[a];
     const int m0 = plan.m[0], Q0 = plan.Q[0], n0 = plan.n[0];
     hipLaunchKernelGGL(time_expand_kernel, dim3(static_cast<unsigned>(npts)), dim3(256), 2 * m0 * sizeof(double2), s,
-                       (const double2*)A0, (const double2*)A2, (const double2*)f_q, (double2*)R, plan.eval[0][0],
-                       plan.eval[0][1], plan.eval_lo[0], plan.eval_hi[0], m0, Q0);
+                       (const double2*)A0, (const double2*)A2, (const double2*)f_q, (double2*)R, plan.tband_eval[0],
+                       plan.tband_eval[1], plan.eval_lo[0], plan.tband_ew, m0, Q0);
     if ((rc = int(hipGetLastError()))) return rc;
     hipLaunchKernelGGL(time_load_kernel, dim3(static_cast<unsigned>(npts)), dim3(128), Q0 * sizeof(double2), s,
-                       (const double2*)R, (double2*)X0, (double2*)X1, plan.load[0][0], plan.load[0][1],
-                       plan.load_lo[0], plan.load_hi[0], Q0, n0, plan.Vq, plan.Jq);
+                       (const double2*)R, (double2*)X0, (double2*)X1, plan.tband_load[0], plan.tband_load[1],
+                       plan.load_lo[0], plan.tband_lw, Q0, n0, plan.Vq, plan.Jq);
     if ((rc = int(hipGetLastError()))) return rc;
     xs *= npts;
   }
