@@ -234,6 +234,11 @@ int contract(const double* in, double* out, Shape& sh, int a, const double* M, c
 // ---------------------------------------------------------------------------
 // lifting kernels (fixed set of size n_fixed, faces packed in LiftFaces)
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum64(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 struct LiftState {
   double bn, rz, alpha, beta, rn;
   int done;  // 0 running, 1 converged, 2 breakdown, 3 iteration limit
@@ -269,13 +274,20 @@ __device__ __forceinline__ void decode_index(int64_t g, const LiftFaces& fc, int
 }
 
 // y = (sum_F P_F^T M_F P_F) x on the fixed set, and per-block partials of Re <x, y>.
-__global__ void __launch_bounds__(256) lift_matvec_kernel(LiftArgs A, const double2* __restrict__ x,
-                                                          double2* __restrict__ y, double* __restrict__ part,
-                                                          const LiftState* __restrict__ st) {
-  __shared__ double lds[4];
+// y = (sum_F P_F^T M_F P_F) x on the fixed set, partials of <x, y> per block.  One wave per fixed
+// unknown, lanes over the (flattened) tangent window of each face that contains it, so that a
+// face costs one round of gathers and a wave reduction.
+constexpr int kLiftMvWaves = 4;
+__global__ void __launch_bounds__(64 * kLiftMvWaves) lift_matvec_kernel(LiftArgs A, const double2* __restrict__ x,
+                                                                       double2* __restrict__ y,
+                                                                       double* __restrict__ part,
+                                                                       const LiftState* __restrict__ st) {
+  __shared__ double red[kLiftMvWaves];
   if (st->done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i = int64_t(blockIdx.x) * kLiftMvWaves + wave;
   double acc_xy = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < A.n_fixed; i += int64_t(gridDim.x) * blockDim.x) {
+  if (i < A.n_fixed) {
     const int64_t g = A.fixed[i];
     int idx[4];
     decode_index(g, A.fc, idx);
@@ -283,41 +295,49 @@ __global__ void __launch_bounds__(256) lift_matvec_kernel(LiftArgs A, const doub
     for (int f = 0; f < A.fc.count; ++f) {
       const LiftFace& F = A.fc.f[f];
       if (idx[F.normal_axis] != F.normal_index) continue;
-      int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, ax[3] = {0, 0, 0};
+      int lo[3] = {0, 0, 0}, len[3] = {1, 1, 1}, ax[3] = {0, 0, 0};
+      int nwin = 1;
       for (int k = 0; k < F.n_tan; ++k) {
         ax[k] = F.tan_axis[k];
         const int pa = A.fc.p[ax[k]];
         lo[k] = max(0, idx[ax[k]] - pa);
-        hi[k] = min(A.fc.m[ax[k]] - 1, idx[ax[k]] + pa);
+        len[k] = min(A.fc.m[ax[k]] - 1, idx[ax[k]] + pa) - lo[k] + 1;
+        nwin *= len[k];
       }
-      for (int j0 = lo[0]; j0 <= hi[0]; ++j0) {
-        const double c0 = F.n_tan > 0 ? A.Mband[ax[0]][idx[ax[0]] * (2 * A.fc.p[ax[0]] + 1) + j0 - idx[ax[0]] +
-                                                       A.fc.p[ax[0]]]
-                                      : 1.0;
-        const int64_t g0 = g + int64_t(j0 - idx[ax[0]]) * A.fc.stride[ax[0]];
-        for (int j1 = lo[1]; j1 <= hi[1]; ++j1) {
-          const double c1 = F.n_tan > 1 ? c0 * A.Mband[ax[1]][idx[ax[1]] * (2 * A.fc.p[ax[1]] + 1) + j1 -
-                                                              idx[ax[1]] + A.fc.p[ax[1]]]
-                                        : c0;
-          const int64_t g1 = g0 + (F.n_tan > 1 ? int64_t(j1 - idx[ax[1]]) * A.fc.stride[ax[1]] : 0);
-          for (int j2 = lo[2]; j2 <= hi[2]; ++j2) {
-            const double c2 = F.n_tan > 2 ? c1 * A.Mband[ax[2]][idx[ax[2]] * (2 * A.fc.p[ax[2]] + 1) + j2 -
-                                                                idx[ax[2]] + A.fc.p[ax[2]]]
-                                          : c1;
-            const int64_t g2 = g1 + (F.n_tan > 2 ? int64_t(j2 - idx[ax[2]]) * A.fc.stride[ax[2]] : 0);
-            const double2 v = x[A.pos[g2]];
-            yr = fma(c2, v.x, yr);
-            yi = fma(c2, v.y, yi);
+      for (int w0 = 0; w0 < nwin; w0 += 64) {
+        const int wi = w0 + lane;
+        if (wi < nwin) {
+          int rest = wi;
+          double c = 1.0;
+          int64_t gu = g;
+          for (int k = 0; k < F.n_tan; ++k) {
+            const int j = lo[k] + rest % len[k];
+            rest /= len[k];
+            const int pa = A.fc.p[ax[k]];
+            c *= A.Mband[ax[k]][idx[ax[k]] * (2 * pa + 1) + j - idx[ax[k]] + pa];
+            gu += int64_t(j - idx[ax[k]]) * A.fc.stride[ax[k]];
           }
+          const double2 v = x[A.pos[gu]];
+          yr = fma(c, v.x, yr);
+          yi = fma(c, v.y, yi);
         }
       }
     }
-    y[i] = make_double2(yr, yi);
-    const double2 xv = x[i];
-    acc_xy += xv.x * yr + xv.y * yi;
+    yr = wave_sum64(yr);
+    yi = wave_sum64(yi);
+    if (lane == 0) {
+      y[i] = make_double2(yr, yi);
+      const double2 xv = x[i];
+      acc_xy = xv.x * yr + xv.y * yi;
+    }
   }
-  const double t = block_sum256(acc_xy, lds);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (lane == 0) red[wave] = acc_xy;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kLiftMvWaves; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
 }
 
 // One axis of the face-wise inverse: out[F][loc] = sum_j Minv[ax][i_s][j] in_F(loc with i_s := j),
@@ -470,12 +490,27 @@ enum { LIFT_RESET = 0, LIFT_INIT = 1, LIFT_ALPHA = 2, LIFT_BETA = 3 };
 // Scalar step of the lifting CG (one thread): partials are summed in block order.
 __global__ void lift_scalar_kernel(int mode, const double* __restrict__ pa, const double* __restrict__ pb, int nparts,
                                    LiftState* __restrict__ st, int* __restrict__ status_out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (blockIdx.x != 0) return;
+  // partial sums: lane l adds the partials l, l + 64, ... (in batches of loads), then a fixed-order
+  // wave reduction
   double a = 0.0, b = 0.0;
-  if (pa)
-    for (int k = 0; k < nparts; ++k) a += pa[k];
-  if (pb)
-    for (int k = 0; k < nparts; ++k) b += pb[k];
+  for (int k0 = 0; k0 < nparts; k0 += 64 * 8) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u * 64 + int(threadIdx.x);
+      va[u] = (pa && k < nparts) ? pa[k] : 0.0;
+      vb[u] = (pb && k < nparts) ? pb[k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      a += va[u];
+      b += vb[u];
+    }
+  }
+  a = wave_sum64(a);
+  b = wave_sum64(b);
+  if (threadIdx.x != 0) return;
   LiftState s = *st;
   if (mode == LIFT_RESET) {
     s.bn = s.rz = s.alpha = s.beta = s.rn = 0.0;
@@ -613,7 +648,9 @@ size_t work_layout(const LoadPlan& plan, RhsWork* w, double* base) {
     fmax = std::max(fmax, s);
   }
   const size_t nf = size_t(plan.n_fixed), tot = size_t(plan.faces.total);
-  const size_t nparts = 2 * size_t(std::max(plan.lift_blocks, 1));
+  // partial sums: two per fixed-set block (preconditioner), one per lifting-matvec block
+  const size_t nparts = std::max(2 * size_t(std::max(plan.lift_blocks, 1)),
+                                 size_t((plan.n_fixed + kLiftMvWaves - 1) / kLiftMvWaves) + 1);
   size_t off = 0;
   auto take = [&](double** dst, size_t n) {
     if (w) *dst = base + off;
@@ -791,8 +828,10 @@ int lifting_device(const LoadPlan& plan, const double* u0_q, const double* const
   const int64_t nf = plan.n_fixed;
   const int nb = plan.lift_blocks;
   int rc;
-  auto scalar = [&](int mode, const double* pa, const double* pb) -> int {
-    hipLaunchKernelGGL(lift_scalar_kernel, dim3(1), dim3(64), 0, s, mode, pa, pb, nb, w.st, status_dev);
+  const int64_t mvb = (nf + kLiftMvWaves - 1) / kLiftMvWaves;  // lifting-matvec blocks (one partial each)
+  auto scalar = [&](int mode, const double* pa, const double* pb, int nparts = 0) -> int {
+    hipLaunchKernelGGL(lift_scalar_kernel, dim3(1), dim3(64), 0, s, mode, pa, pb, nparts > 0 ? nparts : nb, w.st,
+                       status_dev);
     return int(hipGetLastError());
   };
   if ((rc = scalar(LIFT_RESET, nullptr, nullptr))) return rc;
@@ -844,10 +883,10 @@ int lifting_device(const LoadPlan& plan, const double* u0_q, const double* const
   constexpr int kChunk = 4;
   for (int it = 0; it < kLiftMaxIter; it += kChunk) {
     for (int c = 0; c < kChunk; ++c) {
-      hipLaunchKernelGGL(lift_matvec_kernel, dim3(nb), dim3(256), 0, s, A, (const double2*)w.p, (double2*)w.q, w.part,
-                         (const LiftState*)w.st);
+      hipLaunchKernelGGL(lift_matvec_kernel, dim3(static_cast<unsigned>(mvb)), dim3(64 * kLiftMvWaves), 0, s, A,
+                         (const double2*)w.p, (double2*)w.q, w.part, (const LiftState*)w.st);
       if ((rc = int(hipGetLastError()))) return rc;
-      if ((rc = scalar(LIFT_ALPHA, w.part, nullptr))) return rc;
+      if ((rc = scalar(LIFT_ALPHA, w.part, nullptr, int(mvb)))) return rc;
       hipLaunchKernelGGL(lift_update_kernel, dim3(grid_for(nf)), dim3(256), 0, s, (double2*)w.g, (double2*)w.r,
                          (const double2*)w.p, (const double2*)w.q, nf, (const LiftState*)w.st);
       if ((rc = int(hipGetLastError()))) return rc;
