@@ -57,6 +57,8 @@ constexpr int kLag = 3;  // iterations the host lets the device run ahead of its
     }                                           \
   } while (0)
 
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
+
 // ---------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------
@@ -148,10 +150,14 @@ __device__ __forceinline__ void sum_partials3(const double* a, int na, const dou
 // the In fragments of the row group for all KS = ceil(n / K) K steps), then one
 // MFMA chain and the stores: no LDS staging, no barrier.  KS is exact per
 // instantiation for FP64 (padded K steps cost full MFMAs; a skipping branch
-// breaks the load batch).  Block order: right-hand side, then column group, then
-// row tile, with the tiles of a right-hand side padded to a multiple of the XCD
-// count so that the column groups of one row group run on the same XCD (shared
-// L2 for their In fragments); padding blocks only write zero dot partials.
+// breaks the load batch).  Block order: workgroups are dealt out round-robin over
+// the XCDs, so logical block lb = (b % X)(grid / X) + b / X (the grid is a
+// multiple of X) gives each XCD a contiguous range of (right-hand side, row tile,
+// column group), column group fastest: the column groups of a tile, which read
+// the same In fragments, and neighbouring tiles, whose 16-row fragments straddle
+// the same cache lines when a row is not a multiple of 128 bytes, share one L2.
+// Tiles are padded to a multiple of X per right-hand side; padding blocks only
+// write zero dot partials.  Dot partials are stored at the logical index.
 // MFMA computes C^T = U'^T A^T so that the 16 rows of a result fragment are
 // contiguous in memory (coalesced stores).
 //   FP64: v_mfma_f64_16x16x4f64, K step 4
@@ -205,11 +211,13 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
   constexpr int E = K / 4;
   const int n = a.n;
   const int64_t per_rhs = int64_t(a.groups) * a.tiles_pad;
-  const int64_t rhs = blockIdx.x / per_rhs;
+  const int64_t lb = int64_t(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+  const int64_t rhs = lb / per_rhs;
   if (a.done && a.done[rhs]) return;
-  const int64_t rem = blockIdx.x - rhs * per_rhs;
-  const int cg = int(rem / a.tiles_pad);
-  const int64_t tile = rem - int64_t(cg) * a.tiles_pad;
+  STFD_STAMP(1, 4);
+  const int64_t rem = lb - rhs * per_rhs;
+  const int64_t tile = rem / a.groups;
+  const int cg = int(rem - tile * a.groups);
   const int lane = threadIdx.x;
   double dot_a = 0.0, dot_b = 0.0;
   if (tile < a.tiles_per_rhs) {
@@ -249,6 +257,7 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
     // keep every load above the MFMA chain (the scheduler would otherwise interleave them to save
     // registers, turning one memory latency into several); masking and conversion happen below
     __builtin_amdgcn_sched_barrier(0);
+    STFD_STAMP(1, 5);
     typename Tr::acc_t acc = {0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
@@ -273,6 +282,7 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
       }
     }
+    STFD_STAMP(1, 6);
     if (col < rows_here) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -290,10 +300,11 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
     dot_a = wave_sum(dot_a);
     dot_b = wave_sum(dot_b);
     if (lane == 0) {
-      a.part_a[blockIdx.x] = dot_a;
-      a.part_b[blockIdx.x] = dot_b;
+      a.part_a[lb] = dot_a;
+      a.part_b[lb] = dot_b;
     }
   }
+  STFD_STAMP(1, 7);
 }
 
 // ---------------------------------------------------------------------------
@@ -561,7 +572,6 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
 //          the bands from LDS, zero outside 0 <= t + dt < n_t.
 // Optionally writes one partial of Re <x, y> per block (PCG's <p, A p>).
 // ---------------------------------------------------------------------------
-constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kMvMaxNt = 128;      // longest time axis accepted at setup
 constexpr int kMvLanes = 512;      // lanes per matvec block at most
 constexpr size_t kMvLds = 48 * 1024;  // LDS per block for coefficients / Z (several blocks per CU)
@@ -1269,6 +1279,7 @@ static int launch_mode_product(const void* in, void* out, const double* U, int n
   const int nks = (n + K - 1) / K;
   const int64_t blocks = (outer / outer_per_rhs) * a.groups * a.tiles_pad;
   if (blocks <= 0) return STFD_OK;
+  if (blocks % kXcds != 0 || blocks > int64_t(UINT32_MAX)) return STFD_EINVAL;  // the kernel's XCD remap needs it
   const dim3 grid(static_cast<unsigned>(blocks)), block(64);
   // FP64: one instantiation per K-step count; FP32 (K = 4): buckets of 4 steps; BF16 (K = 16): exact
 #define STFD_MP(B)                                                                                      \
