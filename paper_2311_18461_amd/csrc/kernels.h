@@ -27,7 +27,7 @@ enum { MP_F64 = 0, MP_F32 = 1, MP_BF16 = 2 };
 struct ModeProductArgs {
   const void* in;
   void* out;
-  const double* U;     // n x n operand, U'[j][a] = Uop[j*n + a] (FP64 master copy)
+  const void* U;       // n x n operand, U'[j][a] = Uop[j*n + a]: FP64 for FP64 products, else FP32
   int64_t u_slice_stride;  // 0: one operand; else one per outer slice (o mod outer_per_rhs)
   int n;               // size of the contracted direction
   int64_t inner;       // contiguous reals below the direction

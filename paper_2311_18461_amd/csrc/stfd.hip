@@ -171,22 +171,27 @@ __device__ __forceinline__ void sum_partials3(const double* a, int na, const dou
 // ---------------------------------------------------------------------------
 template <int PREC>
 struct MPTraits;
+// u_t: storage type of the U' operand the kernel reads (an FP32 copy for the FP32 and BF16
+// products: the value converted at use is the same, half the bytes)
 template <>
 struct MPTraits<MP_F64> {
   using op_t = double;
   using acc_t = d4_t;
+  using u_t = double;
   static constexpr int K = 4;
 };
 template <>
 struct MPTraits<MP_F32> {
   using op_t = float;
   using acc_t = f4_t;
+  using u_t = float;
   static constexpr int K = 4;
 };
 template <>
 struct MPTraits<MP_BF16> {
   using op_t = short;  // bf16 bits
   using acc_t = f4_t;
+  using u_t = float;
   static constexpr int K = 16;
 };
 
@@ -228,12 +233,13 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
     Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
     const int a0 = cg * 16;
     const int col = lane & 15, grp = lane >> 4;
-    const double* Uo = a.U + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0);
+    using u_t = typename Tr::u_t;
+    const u_t* Uo = static_cast<const u_t*>(a.U) + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0);
     // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row col), k = j;
     // addresses are clamped into the operands, values outside them are replaced by zeros
     const bool col_ok = a0 + col < n;
     const int ac = min(a0 + col, n - 1), rc = min(col, rows_here - 1);
-    double ur[KS][E];
+    u_t ur[KS][E];
     Tin xr[KS][E];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
@@ -265,7 +271,7 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const bool in_k = ks * K + E * grp + e < n;
-        ua[e] = to_op<PREC>((in_k && col_ok) ? ur[ks][e] : 0.0);
+        ua[e] = to_op<PREC>((in_k && col_ok) ? ur[ks][e] : u_t(0));
         xb[e] = to_op<PREC>(in_k ? xr[ks][e] : Tin(0));
       }
       if constexpr (PREC == MP_F64) {
@@ -1176,6 +1182,8 @@ struct stfd_problem {
   // device data
   double* U_fwd[3] = {nullptr, nullptr, nullptr};  // U'[j][a] = U[j][a]  (apply U^T)
   double* U_bwd[3] = {nullptr, nullptr, nullptr};  // U'[j][a] = U[a][j]  (apply U)
+  float* U_fwd32[3] = {nullptr, nullptr, nullptr};  // FP32 copies for the FP32 / BF16 products
+  float* U_bwd32[3] = {nullptr, nullptr, nullptr};
   // segmented time-solve tables (layout: TimeSolvePlan in host_setup.h)
   double* TsL = nullptr;
   double* TsD = nullptr;
@@ -1233,13 +1241,9 @@ static int upload(stfd_problem* P, T** ptr, const T* src, size_t count) {
   return STFD_OK;
 }
 
-// Row tile for a mode product: at most 64 rows, balanced so that the last tile is not
-// mostly padding.  Measured on MI355X (2D, p = 3, 64^3): tiles of up to 64 rows beat both
-// smaller tiles with more blocks (16-row tiles: +25% apply time, the launch is bound by
-// workgroup dispatch, not by the work per block) and 128/256-row tiles (too few blocks).
-// Depends only on per-rhs sizes, so the number of blocks per right-hand side is fixed.
-// blocks of one right-hand side: 16-column groups x (16-row groups of every outer slice, padded
-// to a multiple of the XCD count)
+// Blocks (one wave each) of one right-hand side of a mode product: 16-column groups x (16-row
+// groups of every outer slice, padded to a multiple of the XCD count).  Depends only on per-rhs
+// sizes, so the number of dot partials per right-hand side is fixed.
 static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_per_rhs) {
   const int64_t tiles = outer_per_rhs * ((inner + 15) / 16);
   return int64_t((n + 15) / 16) * ((tiles + kXcds - 1) / kXcds * kXcds);
@@ -1253,7 +1257,7 @@ struct DotEpilogue {
 };
 
 template <int PREC, typename Tin, typename Tout>
-static int launch_mode_product(const void* in, void* out, const double* U, int n, int64_t inner, int64_t outer,
+static int launch_mode_product(const void* in, void* out, const void* U, int n, int64_t inner, int64_t outer,
                                int64_t outer_per_rhs, const int* done, hipStream_t s,
                                const DotEpilogue& ep = DotEpilogue(), int64_t u_slice_stride = 0) {
   if (n < 1 || n > kMaxModeN || outer_per_rhs < 1) return STFD_EINVAL;
@@ -1350,19 +1354,21 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
   if (P->u_slice0)
     for (int k = 0; k < d; ++k) order[k] = d - 1 - k;
   auto slice = [&](int l) -> int64_t { return l == 0 ? P->u_slice0 : 0; };
+  auto Ufwd = [&](int l) -> const void* { return PREC == MP_F64 ? (const void*)P->U_fwd[l] : (const void*)P->U_fwd32[l]; };
+  auto Ubwd = [&](int l) -> const void* { return PREC == MP_F64 ? (const void*)P->U_bwd[l] : (const void*)P->U_bwd32[l]; };
   int rc;
   // step 2: y = (U_s^T (x) I) r; r (FP64) -> w0 -> w1 -> ...
   TW* bufs[2] = {w0, w1};
   int cur = 0;
   {
     const int l = order[0];
-    rc = launch_mode_product<PREC, double, TW>(r, bufs[cur], P->U_fwd[l], hp.n_s[l], inner[l], outer[l], outer_rhs[l],
+    rc = launch_mode_product<PREC, double, TW>(r, bufs[cur], Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l],
                                                done, s, DotEpilogue(), slice(l));
     if (rc) return rc;
   }
   for (int k = 1; k < d; ++k) {
     const int l = order[k];
-    rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], P->U_fwd[l], hp.n_s[l], inner[l], outer[l],
+    rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], Ufwd(l), hp.n_s[l], inner[l], outer[l],
                                            outer_rhs[l], done, s, DotEpilogue(), slice(l));
     if (rc) return rc;
     cur ^= 1;
@@ -1373,13 +1379,13 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
   // step 4: s = (U_s (x) I) x in reverse order, the last product writes FP64 output
   for (int k = d - 1; k >= 1; --k) {
     const int l = order[k];
-    rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], P->U_bwd[l], hp.n_s[l], inner[l], outer[l],
+    rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], Ubwd(l), hp.n_s[l], inner[l], outer[l],
                                            outer_rhs[l], done, s, DotEpilogue(), slice(l));
     if (rc) return rc;
     cur ^= 1;
   }
   const int l = order[0];
-  return launch_mode_product<PREC, TW, double>(bufs[cur], s_out, P->U_bwd[l], hp.n_s[l], inner[l], outer[l],
+  return launch_mode_product<PREC, TW, double>(bufs[cur], s_out, Ubwd(l), hp.n_s[l], inner[l], outer[l],
                                                outer_rhs[l], done, s, ep, slice(l));
 }
 
@@ -1624,7 +1630,10 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       for (int j = 0; j < n; ++j)
         for (int a = 0; a < n; ++a)
           Ut[(size_t(k) * n + j) * n + a] = Uf[(size_t(k) * n + a) * n + j];
-    if ((rc = upload(P, &P->U_fwd[l], Uf.data(), Uf.size())) || (rc = upload(P, &P->U_bwd[l], Ut.data(), Ut.size()))) {
+    const std::vector<float> Uf32(Uf.begin(), Uf.end()), Ut32(Ut.begin(), Ut.end());
+    if ((rc = upload(P, &P->U_fwd[l], Uf.data(), Uf.size())) || (rc = upload(P, &P->U_bwd[l], Ut.data(), Ut.size())) ||
+        (rc = upload(P, &P->U_fwd32[l], Uf32.data(), Uf32.size())) ||
+        (rc = upload(P, &P->U_bwd32[l], Ut32.data(), Ut32.size()))) {
       stfd_destroy(P);
       return rc;
     }
