@@ -146,8 +146,9 @@ __device__ __forceinline__ void sum_partials3(const double* a, int na, const dou
 // Mode product (Algorithm 1 steps 2 and 4): Out[o][a][r] = sum_j U'[j][a] In[o][j][r].
 // One block = one wave = one group of 16 rows r of one outer slice o and one
 // group of 16 output columns a.  Every operand goes straight from global memory
-// into registers in one batch of loads (the U' fragments of the column group and
-// the In fragments of the row group for all KS = ceil(n / K) K steps), then one
+// into registers in one batch of loads (the U' fragments of the column group, packed
+// at setup in the order the lanes read them, and the In fragments of the row group
+// for all KS = ceil(n / K) K steps), then one
 // MFMA chain and the stores: no LDS staging, no barrier.  KS is exact per
 // instantiation for FP64 (padded K steps cost full MFMAs; a skipping branch
 // breaks the load batch).  Block order: workgroups are dealt out round-robin over
@@ -234,11 +235,12 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
     const int a0 = cg * 16;
     const int col = lane & 15, grp = lane >> 4;
     using u_t = typename Tr::u_t;
-    const u_t* Uo = static_cast<const u_t*>(a.U) + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0);
-    // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row col), k = j;
-    // addresses are clamped into the operands, values outside them are replaced by zeros
-    const bool col_ok = a0 + col < n;
-    const int ac = min(a0 + col, n - 1), rc = min(col, rows_here - 1);
+    // U' packed in fragment order (see pack_mode_operand): this lane's KS x E values, zero past n
+    const u_t* Up = static_cast<const u_t*>(a.U) + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0) +
+                    (int64_t(cg) * KS * 64 + lane) * E;
+    // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row col), k = j; In
+    // addresses are clamped into the operand and values past n replaced by zeros
+    const int rc = min(col, rows_here - 1);
     u_t ur[KS][E];
     Tin xr[KS][E];
 #pragma unroll
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int jc = min(ks * K + E * grp + e, n - 1);
-        ur[ks][e] = Uo[int64_t(jc) * n + ac];
+        ur[ks][e] = Up[ks * 64 * E + e];
         xr[ks][e] = src[int64_t(jc) * a.inner + rc];
       }
     // operands of the fused dot products (last backward product of a PCG iteration)
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const bool in_k = ks * K + E * grp + e < n;
-        ua[e] = to_op<PREC>((in_k && col_ok) ? ur[ks][e] : u_t(0));
+        ua[e] = to_op<PREC>(ur[ks][e]);
         xb[e] = to_op<PREC>(in_k ? xr[ks][e] : Tin(0));
       }
       if constexpr (PREC == MP_F64) {
@@ -1180,10 +1182,11 @@ struct stfd_problem {
   int max_nrhs = 1;
   int64_t n2 = 0;  // reals per vector (2 N)
   // device data
-  double* U_fwd[3] = {nullptr, nullptr, nullptr};  // U'[j][a] = U[j][a]  (apply U^T)
-  double* U_bwd[3] = {nullptr, nullptr, nullptr};  // U'[j][a] = U[a][j]  (apply U)
-  float* U_fwd32[3] = {nullptr, nullptr, nullptr};  // FP32 copies for the FP32 / BF16 products
-  float* U_bwd32[3] = {nullptr, nullptr, nullptr};
+  // mode-product operands packed in fragment order, per precision (MP_F64 / MP_F32 / MP_BF16) and
+  // direction: forward U'[j][a] = U[j][a] (apply U^T), backward U'[j][a] = U[a][j] (apply U)
+  void* Upk_fwd[3][3] = {};
+  void* Upk_bwd[3][3] = {};
+  int64_t upk_slice[3] = {0, 0, 0};  // packed elements per x_1 slice (mapped domain), per precision
   // segmented time-solve tables (layout: TimeSolvePlan in host_setup.h)
   double* TsL = nullptr;
   double* TsD = nullptr;
@@ -1249,6 +1252,37 @@ static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_p
   return int64_t((n + 15) / 16) * ((tiles + kXcds - 1) / kXcds * kXcds);
 }
 
+// K steps of one mode-product instantiation: exact for FP64 (K = 4) and BF16 (K = 16), buckets
+// of 4 steps for FP32 (K = 4); the operand is packed for exactly this count
+static int mode_product_ks(int prec, int n) {
+  if (prec == MP_BF16) return (n + 15) / 16;
+  const int nks = (n + 3) / 4;
+  return prec == MP_F32 ? (nks + 3) / 4 * 4 : nks;
+}
+
+// U' (nsl slices of n x n, U'[j][a] = Uop[(k n + j) n + a]) in the order the mode-product
+// lanes read it: [slice][column group][K step][lane][e] with j = ks K + E (lane / 16) + e and
+// a = 16 cg + lane % 16, zero where j or a >= n.  A lane's values for one K step are E
+// consecutive elements and a wave's loads cover whole, aligned cache lines (the rows of an
+// n x n operand are not multiples of 128 bytes); the zeros replace the masks of the padded
+// K steps and columns.
+template <typename T>
+static void pack_mode_operand(const double* Uop, int n, int nsl, int K, int E, int KS, std::vector<T>& out) {
+  const int groups = (n + 15) / 16;
+  const size_t per_slice = size_t(groups) * KS * 64 * E;
+  out.assign(per_slice * nsl, T(0));
+  for (int k = 0; k < nsl; ++k)
+    for (int cg = 0; cg < groups; ++cg)
+      for (int ks = 0; ks < KS; ++ks)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < E; ++e) {
+            const int j = ks * K + E * (lane >> 4) + e, a = cg * 16 + (lane & 15);
+            if (j < n && a < n)
+              out[size_t(k) * per_slice + ((size_t(cg) * KS + ks) * 64 + lane) * E + e] =
+                  T(Uop[(size_t(k) * n + j) * n + a]);
+          }
+}
+
 struct DotEpilogue {
   const double* r = nullptr;
   const double* zold = nullptr;
@@ -1291,6 +1325,7 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
     hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, (PREC == MP_F32 ? 4 * B : B)>), grid, block, 0, s, a); \
     break;
   const int sel = PREC == MP_F32 ? (nks + 3) / 4 : nks;
+  if ((PREC == MP_F32 ? 4 * sel : sel) != mode_product_ks(PREC, n)) return STFD_EINVAL;  // packing must match
   if constexpr (PREC == MP_F64) {
     switch (sel) {
       STFD_MP(1) STFD_MP(2) STFD_MP(3) STFD_MP(4) STFD_MP(5) STFD_MP(6) STFD_MP(7) STFD_MP(8)
@@ -1353,9 +1388,9 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
   int order[3] = {0, 1, 2};
   if (P->u_slice0)
     for (int k = 0; k < d; ++k) order[k] = d - 1 - k;
-  auto slice = [&](int l) -> int64_t { return l == 0 ? P->u_slice0 : 0; };
-  auto Ufwd = [&](int l) -> const void* { return PREC == MP_F64 ? (const void*)P->U_fwd[l] : (const void*)P->U_fwd32[l]; };
-  auto Ubwd = [&](int l) -> const void* { return PREC == MP_F64 ? (const void*)P->U_bwd[l] : (const void*)P->U_bwd32[l]; };
+  auto slice = [&](int l) -> int64_t { return l == 0 ? P->upk_slice[PREC] : 0; };
+  auto Ufwd = [&](int l) -> const void* { return P->Upk_fwd[PREC][l]; };
+  auto Ubwd = [&](int l) -> const void* { return P->Upk_bwd[PREC][l]; };
   int rc;
   // step 2: y = (U_s^T (x) I) r; r (FP64) -> w0 -> w1 -> ...
   TW* bufs[2] = {w0, w1};
@@ -1630,12 +1665,26 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       for (int j = 0; j < n; ++j)
         for (int a = 0; a < n; ++a)
           Ut[(size_t(k) * n + j) * n + a] = Uf[(size_t(k) * n + a) * n + j];
-    const std::vector<float> Uf32(Uf.begin(), Uf.end()), Ut32(Ut.begin(), Ut.end());
-    if ((rc = upload(P, &P->U_fwd[l], Uf.data(), Uf.size())) || (rc = upload(P, &P->U_bwd[l], Ut.data(), Ut.size())) ||
-        (rc = upload(P, &P->U_fwd32[l], Uf32.data(), Uf32.size())) ||
-        (rc = upload(P, &P->U_bwd32[l], Ut32.data(), Ut32.size()))) {
-      stfd_destroy(P);
-      return rc;
+    for (int prec = MP_F64; prec <= MP_BF16; ++prec) {
+      const int K = prec == MP_BF16 ? 16 : 4, E = K / 4, KS = mode_product_ks(prec, n);
+      if (prec == MP_F64) {
+        std::vector<double> pf, pb;
+        pack_mode_operand(Uf.data(), n, nsl, K, E, KS, pf);
+        pack_mode_operand(Ut.data(), n, nsl, K, E, KS, pb);
+        rc = upload(P, reinterpret_cast<double**>(&P->Upk_fwd[prec][l]), pf.data(), pf.size());
+        if (!rc) rc = upload(P, reinterpret_cast<double**>(&P->Upk_bwd[prec][l]), pb.data(), pb.size());
+      } else {
+        std::vector<float> pf, pb;
+        pack_mode_operand(Uf.data(), n, nsl, K, E, KS, pf);
+        pack_mode_operand(Ut.data(), n, nsl, K, E, KS, pb);
+        rc = upload(P, reinterpret_cast<float**>(&P->Upk_fwd[prec][l]), pf.data(), pf.size());
+        if (!rc) rc = upload(P, reinterpret_cast<float**>(&P->Upk_bwd[prec][l]), pb.data(), pb.size());
+      }
+      if (rc) {
+        stfd_destroy(P);
+        return rc;
+      }
+      if (sliced) P->upk_slice[prec] = int64_t((n + 15) / 16) * KS * 64 * E;
     }
     if (sliced) P->u_slice0 = int64_t(n) * n;
   }
