@@ -33,7 +33,7 @@ struct ModeProductArgs {
   int64_t inner;       // contiguous reals below the direction
   int64_t outer;       // number of outer slices (directions above, times nrhs)
   int64_t outer_per_rhs;
-  int64_t n_row_tiles;    // 16-row groups per outer slice, ceil(inner / 16)
+  int64_t n_row_tiles;    // row tiles (16 RT rows, RT = 1 or 2) per outer slice, ceil(inner / (16 RT))
   int64_t tiles_per_rhs;  // outer_per_rhs * n_row_tiles
   int64_t tiles_pad;      // tiles_per_rhs rounded up to a multiple of the XCD count
   int groups;             // 16-column groups, ceil(n / 16)

@@ -209,7 +209,7 @@ __device__ __forceinline__ typename MPTraits<PREC>::op_t to_op(float v) {
   else return f32_to_bf16(v);
 }
 
-template <int PREC, typename Tin, typename Tout, int KS>
+template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT>
 __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
   using Tr = MPTraits<PREC>;
   using op_t = typename Tr::op_t;
@@ -227,9 +227,11 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
   const int lane = threadIdx.x;
   double dot_a = 0.0, dot_b = 0.0;
   if (tile < a.tiles_per_rhs) {
+    // a tile is RT adjacent 16-row groups: one U' fragment load serves RT MFMA chains and a row of
+    // In is read as 16 RT consecutive values
     const int64_t o = rhs * a.outer_per_rhs + tile / a.n_row_tiles;
-    const int64_t row0 = (tile % a.n_row_tiles) * 16;
-    const int rows_here = int(min<int64_t>(16, a.inner - row0));
+    const int64_t row0 = (tile % a.n_row_tiles) * (16 * RT);
+    const int rows_here = int(min<int64_t>(16 * RT, a.inner - row0));
     const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
     Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
     const int a0 = cg * 16;
@@ -238,73 +240,94 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
     // U' packed in fragment order (see pack_mode_operand): this lane's KS x E values, zero past n
     const u_t* Up = static_cast<const u_t*>(a.U) + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0) +
                     (int64_t(cg) * KS * 64 + lane) * E;
-    // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row col), k = j; In
+    // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row 16 t + col), k = j; In
     // addresses are clamped into the operand and values past n replaced by zeros
-    const int rc = min(col, rows_here - 1);
+    int rc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) rc[t] = min(16 * t + col, rows_here - 1);
     u_t ur[KS][E];
-    Tin xr[KS][E];
+    Tin xr[RT][KS][E];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int jc = min(ks * K + E * grp + e, n - 1);
         ur[ks][e] = Up[ks * 64 * E + e];
-        xr[ks][e] = src[int64_t(jc) * a.inner + rc];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) xr[t][ks][e] = src[int64_t(jc) * a.inner + rc[t]];
       }
-    // operands of the fused dot products (last backward product of a PCG iteration)
-    double rv[4] = {0.0, 0.0, 0.0, 0.0}, zv[4] = {0.0, 0.0, 0.0, 0.0};
-    if (a.part_a) {
+    // operands of the fused dot products (last backward product of a PCG iteration; a template
+    // switch, so that no branch separates these loads from the operand loads)
+    double rv[RT][4], zv[RT][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int aa = min(a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
-        const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(aa) * a.inner + rc;
-        rv[v] = a.dot_r[g];
-        zv[v] = a.dot_z[g];
+        if constexpr (DOT) {
+          const int aa = min(a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
+          const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(aa) * a.inner + rc[t];
+          rv[t][v] = a.dot_r[g];
+          zv[t][v] = a.dot_z[g];
+        } else {
+          rv[t][v] = 0.0;
+          zv[t][v] = 0.0;
+        }
       }
-    }
-    // keep every load above the MFMA chain (the scheduler would otherwise interleave them to save
+    // keep every load above the MFMA chains (the scheduler would otherwise interleave them to save
     // registers, turning one memory latency into several); masking and conversion happen below
     __builtin_amdgcn_sched_barrier(0);
     STFD_STAMP(1, 5);
-    typename Tr::acc_t acc = {0, 0, 0, 0};
+    typename Tr::acc_t acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = typename Tr::acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      op_t ua[E], xb[E];
+      op_t ua[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const bool in_k = ks * K + E * grp + e < n;
-        ua[e] = to_op<PREC>(ur[ks][e]);
-        xb[e] = to_op<PREC>(in_k ? xr[ks][e] : Tin(0));
-      }
-      if constexpr (PREC == MP_F64) {
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0], xb[0], acc, 0, 0, 0);
-      } else if constexpr (PREC == MP_F32) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[0], xb[0], acc, 0, 0, 0);
-      } else {
-        s4_t av, bv;
+      for (int e = 0; e < E; ++e) ua[e] = to_op<PREC>(ur[ks][e]);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          av[e] = ua[e];
-          bv[e] = xb[e];
+      for (int t = 0; t < RT; ++t) {
+        op_t xb[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const bool in_k = ks * K + E * grp + e < n;
+          xb[e] = to_op<PREC>(in_k ? xr[t][ks][e] : Tin(0));
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        if constexpr (PREC == MP_F64) {
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0], xb[0], acc[t], 0, 0, 0);
+        } else if constexpr (PREC == MP_F32) {
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[0], xb[0], acc[t], 0, 0, 0);
+        } else {
+          s4_t av, bv;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            av[e] = ua[e];
+            bv[e] = xb[e];
+          }
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+        }
       }
     }
     STFD_STAMP(1, 6);
-    if (col < rows_here) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int aa = a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
-        if (aa < n) {
-          const int64_t off = int64_t(aa) * a.inner + col;
-          dst[off] = Tout(acc[v]);
-          dot_a += rv[v] * double(Tout(acc[v]));
-          dot_b += rv[v] * zv[v];
+    for (int t = 0; t < RT; ++t) {
+      if (16 * t + col < rows_here) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int aa = a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
+          if (aa < n) {
+            const int64_t off = int64_t(aa) * a.inner + 16 * t + col;
+            dst[off] = Tout(acc[t][v]);
+            if constexpr (DOT) {
+              dot_a += rv[t][v] * double(Tout(acc[t][v]));
+              dot_b += rv[t][v] * zv[t][v];
+            }
+          }
         }
       }
     }
   }
-  if (a.part_a) {
+  if constexpr (DOT) {
     dot_a = wave_sum(dot_a);
     dot_b = wave_sum(dot_b);
     if (lane == 0) {
@@ -1244,11 +1267,24 @@ static int upload(stfd_problem* P, T** ptr, const T* src, size_t count) {
   return STFD_OK;
 }
 
-// Blocks (one wave each) of one right-hand side of a mode product: 16-column groups x (16-row
-// groups of every outer slice, padded to a multiple of the XCD count).  Depends only on per-rhs
-// sizes, so the number of dot partials per right-hand side is fixed.
+// 16-row groups per mode-product wave.  Two (one U' load serves both MFMA chains, In rows are
+// read 32 values at a time) when the launch is large enough to keep the chip busy with half the
+// waves and n <= 80 (two FP64 chains of more K steps would spill); else one.  Measured: 3D p = 3
+// 48^4 (67k one-group waves per product) apply FP64 619 -> 603 us, FP32 457 -> 428 us, BF16 417
+// -> 375 us; 2D 64^3 (2960 waves) 38.7 -> 41.8 us, hence the threshold.  Depends on per-rhs
+// sizes only, so every precision writes the same dot partials.
+constexpr int64_t kMpTwoGroupMinWaves = 16384;
+static int mode_product_row_groups(int n, int64_t inner, int64_t outer_per_rhs) {
+  const int64_t waves1 = int64_t((n + 15) / 16) * outer_per_rhs * ((inner + 15) / 16);
+  return (n <= 80 && waves1 >= kMpTwoGroupMinWaves) ? 2 : 1;
+}
+
+// Blocks (one wave each) of one right-hand side of a mode product: 16-column groups x (tiles of
+// 16 RT rows of every outer slice, padded to a multiple of the XCD count).  Depends only on
+// per-rhs sizes, so the number of dot partials per right-hand side is fixed.
 static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_per_rhs) {
-  const int64_t tiles = outer_per_rhs * ((inner + 15) / 16);
+  const int rows = 16 * mode_product_row_groups(n, inner, outer_per_rhs);
+  const int64_t tiles = outer_per_rhs * ((inner + rows - 1) / rows);
   return int64_t((n + 15) / 16) * ((tiles + kXcds - 1) / kXcds * kXcds);
 }
 
@@ -1283,6 +1319,31 @@ static void pack_mode_operand(const double* Uop, int n, int nsl, int K, int E, i
           }
 }
 
+// launch with RT row groups per wave; the two-group variant exists only for the K-step counts of
+// n <= 80 (mode_product_row_groups never asks for it beyond)
+template <int PREC, typename Tin, typename Tout, int KS, bool DOT>
+static void launch_mode_product_rt_dot(int rt, dim3 grid, dim3 block, hipStream_t s, const ModeProductArgs& a) {
+  constexpr bool kTwo = (PREC == MP_BF16) ? (KS <= 5) : (KS <= 20);
+  if constexpr (kTwo) {
+    if (rt == 2) {
+      hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, 2, DOT>), grid, block, 0, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, 1, DOT>), grid, block, 0, s, a);
+}
+// the fused dot products exist only for the FP64 output of the last backward product
+template <int PREC, typename Tin, typename Tout, int KS>
+static void launch_mode_product_rt(int rt, dim3 grid, dim3 block, hipStream_t s, const ModeProductArgs& a) {
+  if constexpr (std::is_same<Tout, double>::value) {
+    if (a.part_a) {
+      launch_mode_product_rt_dot<PREC, Tin, Tout, KS, true>(rt, grid, block, s, a);
+      return;
+    }
+  }
+  launch_mode_product_rt_dot<PREC, Tin, Tout, KS, false>(rt, grid, block, s, a);
+}
+
 struct DotEpilogue {
   const double* r = nullptr;
   const double* zold = nullptr;
@@ -1304,7 +1365,8 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   a.inner = inner;
   a.outer = outer;
   a.outer_per_rhs = outer_per_rhs;
-  a.n_row_tiles = (inner + 15) / 16;
+  const int RTn = mode_product_row_groups(n, inner, outer_per_rhs);
+  a.n_row_tiles = (inner + 16 * RTn - 1) / (16 * RTn);
   a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
   a.tiles_pad = (a.tiles_per_rhs + kXcds - 1) / kXcds * kXcds;
   a.groups = (n + 15) / 16;
@@ -1312,6 +1374,7 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   a.dot_r = ep.r;
   a.dot_z = ep.zold;
   a.part_a = ep.part_a;
+  if (ep.part_a && !std::is_same<Tout, double>::value) return STFD_EINVAL;  // epilogue: FP64 output only
   a.part_b = ep.part_b;
   constexpr int K = MPTraits<PREC>::K;
   const int nks = (n + K - 1) / K;
@@ -1322,7 +1385,7 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   // FP64: one instantiation per K-step count; FP32 (K = 4): buckets of 4 steps; BF16 (K = 16): exact
 #define STFD_MP(B)                                                                                      \
   case B:                                                                                               \
-    hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, (PREC == MP_F32 ? 4 * B : B)>), grid, block, 0, s, a); \
+    launch_mode_product_rt<PREC, Tin, Tout, (PREC == MP_F32 ? 4 * B : B)>(RTn, grid, block, s, a);      \
     break;
   const int sel = PREC == MP_F32 ? (nks + 3) / 4 : nks;
   if ((PREC == MP_F32 ? 4 * sel : sel) != mode_product_ks(PREC, n)) return STFD_EINVAL;  // packing must match

@@ -47,3 +47,31 @@ def test_apply_3d_full_size_vs_oracle(n_el, p):
     print(f"N={lib.N}: relative error vs the FP64 oracle "
           + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
     lib.close()
+
+
+def test_pcg_3d_large_products_converge():
+    """FP64 PCG to 1e-8 on the 3D p = 4, 32^4 harmonic workload (about 1.4 million unknowns).
+
+    At this size the library runs its x_1 mode products with two 16-row groups per wave, the
+    last backward one included, whose fused partial sums give <r, z_new> and <r, z_old> for the
+    direction update.  A wrong partial changes beta and with it the iteration count: with one
+    row group per wave this solve took 57 iterations.  The final residual is recomputed here
+    with the library matvec (itself checked against the oracle in test_gpu_parity)."""
+    from paper_2311_18461_amd import stfd
+    print("3D PCG: n_el=32 p=4 harmonic potential", flush=True)
+    w = inputs.harmonic_3d_workload(0, n_el=32, p=4, with_potential=True)
+    ks = [w.knots_s()] * 3
+    prob = stfd.Problem(w.knots_t(), ks, 4, 4, w.T, w.nu, V_quad=stfd.sample_on_quad_grid(w.potential, ks, 4))
+    f = torch.empty(prob.N, dtype=torch.complex128, device=DEV)
+    prob.load_vector(f, u0_q=torch.from_numpy(prob.sample_space(w.u0)).to(DEV))
+    u = torch.empty_like(f)
+    rc, info = prob.pcg_solve(f, u, rtol=1e-8, maxit=200)
+    q = torch.empty_like(f)
+    prob.matvec(u, q)
+    torch.cuda.synchronize()
+    res = float(torch.linalg.vector_norm(f - q) / torch.linalg.vector_norm(f))
+    print(f"iterations {info[0]['iters']}, relative residual {res:.2e}", flush=True)
+    assert rc == stfd.OK
+    assert res <= 1.05e-8
+    assert info[0]["iters"] <= 70
+    prob.close()
