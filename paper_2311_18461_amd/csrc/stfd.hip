@@ -371,11 +371,6 @@ __device__ inline void ts_load(const double* p, int t, double& re, double& im) {
   re = v.x;
   im = v.y;
 }
-__device__ inline void ts_load(const float* p, int t, double& re, double& im) {
-  const float2 v = reinterpret_cast<const float2*>(p)[t];
-  re = double(v.x);
-  im = double(v.y);
-}
 __device__ inline void ts_store(double* p, int t, double re, double im) {
   reinterpret_cast<double2*>(p)[t] = make_double2(re, im);
 }
@@ -402,7 +397,13 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
   const double2* Tfb = reinterpret_cast<const double2*>(Tf) + blk * int64_t(P * P * kTsLanes);
   const double2* Tbb = reinterpret_cast<const double2*>(Tb) + blk * int64_t(P * P * kTsLanes);
 
+  // FP32 storage: rows of y are loaded as float2 and converted after the whole batch (the
+  // compiler moves a conversion next to its load, which made every row wait for its own round
+  // trip); clamped addresses, rows past n_t and idle lanes masked at the conversion.  FP64
+  // storage: loaded straight into the rows
+  constexpr bool kRaw = std::is_same<T, float>::value;
   double yr[LEN], yi[LEN], lr[LEN][P], li[LEN][P];
+  float2 yv[LEN];
 #pragma unroll
   for (int j = 0; j < LEN; ++j) {
 #pragma unroll
@@ -412,8 +413,12 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
       li[j][k] = v.y;
     }
     const int t = t0 + j;
-    yr[j] = yi[j] = 0.0;
-    if (live && t < n_t) ts_load(yb, t, yr[j], yi[j]);
+    if constexpr (kRaw) {
+      yv[j] = reinterpret_cast<const float2*>(yb)[min(t, n_t - 1)];
+    } else {
+      yr[j] = yi[j] = 0.0;
+      if (live && t < n_t) ts_load(yb, t, yr[j], yi[j]);
+    }
   }
   // L[t+k][t] for rows t+k of the next segment (rows jj < P of the neighbour lane)
   const bool has_next = s + 1 < segs;
@@ -430,6 +435,19 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
         nli[jj][k] = has_next ? v.y : 0.0;
       }
     }
+  // the transfers of the reduced recurrences and the inverse pivots are loaded where they are used:
+  // loading them with the rows above (one round trip instead of three) measured slower at P = 3,
+  // LEN = 12 (the extra registers spill into AGPR copies inside the dependent sweeps)
+  double tfr[P][P], tfi[P][P], tbr[P][P], tbi[P][P], dv[LEN];
+  if constexpr (kRaw) {
+    load_batch_end();
+#pragma unroll
+    for (int j = 0; j < LEN; ++j) {
+      const bool ok = live && t0 + j < n_t;
+      yr[j] = ok ? double(yv[j].x) : 0.0;
+      yi[j] = ok ? double(yv[j].y) : 0.0;
+    }
+  }
   double hr[P], hi[P];
 
   // z_t = y_t - sum_k L[t][t-k] z_{t-k}; h[k-1] = z_{t-k} (the z_{t-1} term last)
@@ -476,17 +494,21 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
   }
   // (2) reduced forward recurrence over the segments, then history = true tail of segment s-1
   {
-    double tr[P][P], ti[P][P], cr0[P], ci0[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const double2 v = Tfb[(a * P + c) * kTsLanes + lane];
+        tfr[a][c] = v.x;
+        tfi[a][c] = v.y;
+      }
+    const double(&tr)[P][P] = tfr;
+    const double(&ti)[P][P] = tfi;
+    double cr0[P], ci0[P];
 #pragma unroll
     for (int a = 0; a < P; ++a) {
       cr0[a] = hr[a];
       ci0[a] = hi[a];
-#pragma unroll
-      for (int c = 0; c < P; ++c) {
-        const double2 v = Tfb[(a * P + c) * kTsLanes + lane];
-        tr[a][c] = v.x;
-        ti[a][c] = v.y;
-      }
     }
     for (int r = 1; r < segs; ++r) {
       double pr[P], pi[P];
@@ -521,9 +543,9 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
 #pragma unroll
   for (int j = 0; j < LEN; ++j) {
     STFD_TS_FWD_ROW(j)
-    const double d = Db[j * kTsLanes + lane];
-    yr[j] = zr * d;
-    yi[j] = zi * d;
+    dv[j] = Db[j * kTsLanes + lane];
+    yr[j] = zr * dv[j];
+    yi[j] = zi * dv[j];
   }
   // (4) backward sweep from a zero future -> local head
 #pragma unroll
@@ -534,17 +556,21 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
   }
   // (5) reduced backward recurrence, then future = true head of segment s+1
   {
-    double tr[P][P], ti[P][P], cr0[P], ci0[P];
+#pragma unroll
+    for (int a = 0; a < P; ++a)
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const double2 v = Tbb[(a * P + c) * kTsLanes + lane];
+        tbr[a][c] = v.x;
+        tbi[a][c] = v.y;
+      }
+    const double(&tr)[P][P] = tbr;
+    const double(&ti)[P][P] = tbi;
+    double cr0[P], ci0[P];
 #pragma unroll
     for (int a = 0; a < P; ++a) {
       cr0[a] = hr[a];
       ci0[a] = hi[a];
-#pragma unroll
-      for (int c = 0; c < P; ++c) {
-        const double2 v = Tbb[(a * P + c) * kTsLanes + lane];
-        tr[a][c] = v.x;
-        ti[a][c] = v.y;
-      }
     }
     for (int r = 1; r < segs; ++r) {
       double pr[P], pi[P];
