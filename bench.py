@@ -34,9 +34,9 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the 2D p=3 matvec kernel on this workload: FETCH_SIZE and WRITE_SIZE passes
 # of rocprofv3 over `bench.py --profile`, each scaled by what the same counter reads for a 64 MiB
 # device copy in that run (x 1.999 and x 1.000); profiles/pcg_2d_p3_n64_gauss_traffic.md.  Valid for
-# the matvec kernel as profiled (12.59 MB read + 4.47 MB written per launch).
+# the matvec kernel as profiled (12.57 MB read + 4.47 MB written per launch, 705 blocks of 6 points).
 MATVEC_KERNEL = "matvec_kernel<2,3,3,1>"
-MATVEC_TRAFFIC_BYTES = 17.06e6
+MATVEC_TRAFFIC_BYTES = 17.04e6
 
 
 def build_workload(sample=0, n_el=64, p=3):
