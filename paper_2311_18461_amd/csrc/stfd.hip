@@ -821,12 +821,8 @@ struct PcgScalars {
   int iters;
   int status;
   int done;
-  int kcur;  // iteration index of the iteration in flight (set by pcg_update_r)
+  int kcur;  // iteration index of the iteration in flight (set by pcg_update_xr)
   double x0_scale;  // factor applied to a given initial guess (0: cold start)
-  double alpha;     // step length of the iteration in flight (pcg_update_r)
-  double beta;      // direction update of the iteration in flight (pcg_end_scalars)
-  int x_upd;        // 1: the iteration in flight applies x += alpha p
-  int p_upd;        // 1: the iteration in flight applies p = z + beta p
 };
 
 // partial sums of Re<a, b> (and optionally Re<a, c>) over this block's range
@@ -985,24 +981,26 @@ __global__ __launch_bounds__(kVecBlock) void pcg_first_p_kernel(const double* z,
   }
 }
 
-// alpha = rz / <p, q>; r -= alpha q; partial ||r||^2.  The matching x += alpha p is deferred
-// to pcg_update_xp, which reads p anyway for the direction update.  Every load the update
-// depends on (done flag, rz, this thread's share of the <p, q> partials and its first (r, q)
-// pair) is issued in one batch ahead of the block sum: one memory round trip before the update
-// instead of a chain of four.  Blocks of a finished right-hand side load and then leave.
-__global__ __launch_bounds__(kVecBlock) void pcg_update_r_kernel(const double* q, double* r, int64_t n2,
-                                                                  const double* ppq, int npq, PcgScalars* sc,
-                                                                  int parity, double* prr, const int* done, int* ctr) {
+// alpha = rz / <p, q>; x += alpha p; r -= alpha q; partial ||r||^2.  Every load the update
+// depends on (done flag, rz, this thread's share of the <p, q> partials and its first (p, q, r, x)
+// quadruple) is issued in one batch ahead of the block sum: one memory round trip before the
+// update instead of a chain of four.  Blocks of a finished right-hand side load and then leave.
+__global__ __launch_bounds__(kVecBlock) void pcg_update_xr_kernel(const double* p, const double* q, double* x,
+                                                                   double* r, int64_t n2, const double* ppq,
+                                                                   int npq, PcgScalars* sc, int parity,
+                                                                   double* prr, const int* done, int* ctr) {
   __shared__ double sh[kVecBlock / 64];
   const int rhs = blockIdx.y, tid = threadIdx.x;
-  // launch counter of this solve (read by pcg_end_scalars to pick its host ring slot)
+  // launch counter of this solve (read by pcg_end_iter to pick its host ring slot)
   if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) ctr[0] += 1;
+  const double2* pc = reinterpret_cast<const double2*>(p + rhs * n2);
   const double2* qc = reinterpret_cast<const double2*>(q + rhs * n2);
+  double2* xc = reinterpret_cast<double2*>(x + rhs * n2);
   double2* rc = reinterpret_cast<double2*>(r + rhs * n2);
   const int64_t m = n2 / 2, stride = int64_t(gridDim.x) * kVecBlock;
   const int64_t k0 = int64_t(blockIdx.x) * kVecBlock + tid;
   const double* pp = ppq + int64_t(rhs) * npq;
-  // partials: lanes past the count load nothing (exec mask); the (r, q) address is clamped
+  // partials: lanes past the count load nothing (exec mask); the vector address is clamped
   const int dn = done[rhs];
   const double rz = sc[rhs].rz[parity];
   const int iters = sc[rhs].iters;
@@ -1013,7 +1011,7 @@ __global__ __launch_bounds__(kVecBlock) void pcg_update_r_kernel(const double* q
     v[u] = idx < npq ? pp[idx] : 0.0;
   }
   const int64_t kc = min(k0, m - 1);
-  double2 rv = rc[kc], qv = qc[kc];
+  double2 rv = rc[kc], qv = qc[kc], pv = pc[kc], xv = xc[kc];
   load_batch_end();
   double t = v[0];
 #pragma unroll
@@ -1023,47 +1021,55 @@ __global__ __launch_bounds__(kVecBlock) void pcg_update_r_kernel(const double* q
   if (dn) return;
   const bool ok = (pq > 0.0) && std::isfinite(pq);
   const double alpha = ok ? rz / pq : 0.0;
-  if (blockIdx.x == 0 && tid == 0) {
-    sc[rhs].kcur = iters;
-    sc[rhs].alpha = alpha;
-    sc[rhs].x_upd = ok ? 1 : 0;
-  }
+  if (blockIdx.x == 0 && tid == 0) sc[rhs].kcur = iters;
   double s = 0.0;
   for (int64_t k = k0; k < m; k += stride) {
     if (k != k0) {
       rv = rc[k];
       qv = qc[k];
+      pv = pc[k];
+      xv = xc[k];
     }
     const double rr = rv.x - alpha * qv.x, ri = rv.y - alpha * qv.y;
-    if (ok) rc[k] = make_double2(rr, ri);
+    if (ok) {
+      rc[k] = make_double2(rr, ri);
+      xc[k] = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
+    }
     s += rr * rr + ri * ri;
   }
   s = block_sum<kVecBlock>(s, sh);
   if (tid == 0) prr[rhs * gridDim.x + blockIdx.x] = ok ? s : NAN;
 }
 
-// End of iteration k for one right-hand side (one block per right-hand side): convergence /
-// breakdown / iteration-limit test on ||r_{k+1}|| (partials of pcg_update_r), then
-// beta = (<r, z_new> - <r, z_old>) / rz_k (partials of the last mode product).  Records the
-// state, the per-rhs done flag, the vector updates pcg_update_xp applies and a copy in
-// host-mapped memory.  One block sums every partial once (a vector kernel whose blocks all
-// summed them would re-read them once per block); the state, the flag, the ring slot and the
-// partials are fetched in one batch.
-constexpr int kScalarBlock = 1024;
-__global__ __launch_bounds__(kScalarBlock) void pcg_end_scalars_kernel(const double* prr, int nrr, const double* pa,
-                                                                       const double* pb, int nab, PcgScalars* sc,
-                                                                       int parity, int* done, int maxit, double tol,
-                                                                       PcgScalars* host_ring, int ring_stride,
-                                                                       const int* ctr) {
-  constexpr int NT = kScalarBlock, NW = NT / 64;
+// End of iteration k for one right-hand side: convergence / breakdown / iteration-limit test on
+// ||r_{k+1}|| (partials of pcg_update_xr), then beta = (<r, z_new> - <r, z_old>) / rz_k (partials
+// of the last mode product) and p = z_new + beta p.  Every block sums every partial in the same
+// order (kEndBlock threads, one batch of loads that also holds the state and this thread's first
+// (z, p) pair) and so takes the same decision; block 0 records the state, the per-rhs done flag
+// and a copy in host-mapped memory.  Block 0 writes only what the other blocks do not read, and
+// the done flag it may raise only skips the direction update, which a finished system does not
+// need.  With kEndBlock threads per block the sums are those of a single-block reduction.
+constexpr int kEndBlock = 1024;
+constexpr int kEndGrid = 256;
+__global__ __launch_bounds__(kEndBlock) void pcg_end_iter_kernel(const double* znew, double* p, int64_t n2,
+                                                                  const double* prr, int nrr, const double* pa,
+                                                                  const double* pb, int nab, PcgScalars* sc,
+                                                                  int parity, int* done, int maxit, double tol,
+                                                                  PcgScalars* host_ring, int ring_stride,
+                                                                  const int* ctr) {
+  constexpr int NT = kEndBlock, NW = NT / 64;
   __shared__ double sh[3 * NW];
-  const int rhs = blockIdx.x, tid = threadIdx.x;
+  const int rhs = blockIdx.y, tid = threadIdx.x;
   const double* a = prr + int64_t(rhs) * nrr;
   const double* b = pa + int64_t(rhs) * nab;
   const double* c = pb + int64_t(rhs) * nab;
-  // ||r||^2 and, for the direction update, <r, z_new> and <r, z_old>: the first batch of partials
-  // (lanes past a count load nothing), the done flag, the ring counter and the state in one
-  // batch of loads; further batches only for more than NT * kSumBatch partials
+  const double2* zc = reinterpret_cast<const double2*>(znew + rhs * n2);
+  double2* pc = reinterpret_cast<double2*>(p + rhs * n2);
+  const int64_t m = n2 / 2, stride = int64_t(gridDim.x) * NT;
+  const int64_t k0 = int64_t(blockIdx.x) * NT + tid;
+  // ||r||^2, <r, z_new>, <r, z_old>: the first batch of partials (lanes past a count load
+  // nothing), the done flag, the ring counter, the state and this thread's first (z, p) pair in
+  // one batch of loads; further batches only for more than NT * kSumBatch partials
   double va[kSumBatch], vb[kSumBatch], vc[kSumBatch];
 #pragma unroll
   for (int u = 0; u < kSumBatch; ++u) {
@@ -1074,8 +1080,17 @@ __global__ __launch_bounds__(kScalarBlock) void pcg_end_scalars_kernel(const dou
   }
   const int dn = done[rhs];
   const int cnt = ctr[0];
-  PcgScalars st = sc[rhs];
+  const double nf2 = sc[rhs].nf2;
+  const double rzk = parity ? sc[rhs].rz[1] : sc[rhs].rz[0];
+  const int k = sc[rhs].kcur;
+  const int64_t kc = min(k0, m - 1);
+  double2 zv = zc[kc], pv = pc[kc];
   load_batch_end();
+  PcgScalars* host_slot = host_ring ? host_ring + ((cnt - 1) % kLag) * ring_stride : nullptr;
+  if (dn) {
+    if (blockIdx.x == 0 && tid == 0 && host_slot) host_slot[rhs] = sc[rhs];
+    return;
+  }
   double ta = va[0], tb = vb[0], tc = vc[0];
 #pragma unroll
   for (int u = 1; u < kSumBatch; ++u) {
@@ -1097,24 +1112,13 @@ __global__ __launch_bounds__(kScalarBlock) void pcg_end_scalars_kernel(const dou
     sh[2 * NW + (tid >> 6)] = tc;
   }
   __syncthreads();
-  if (tid != 0) return;
   double rr = 0.0, rzn_all = 0.0, rzm = 0.0;
   for (int i = 0; i < NW; ++i) {
     rr += sh[i];
     rzn_all += sh[NW + i];
     rzm += sh[2 * NW + i];
   }
-  PcgScalars* host_slot = host_ring ? host_ring + ((cnt - 1) % kLag) * ring_stride : nullptr;
-  if (dn) {
-    st.x_upd = 0;
-    st.p_upd = 0;
-    sc[rhs].x_upd = 0;
-    sc[rhs].p_upd = 0;
-    if (host_slot) host_slot[rhs] = st;
-    return;
-  }
-  const int k = st.kcur;
-  const double res = sqrt(rr / st.nf2);
+  const double res = sqrt(rr / nf2);
   int status = STFD_OK;
   bool finished = false;
   double rzn = 0.0, beta = 0.0;
@@ -1132,48 +1136,29 @@ __global__ __launch_bounds__(kScalarBlock) void pcg_end_scalars_kernel(const dou
       status = STFD_EBREAKDOWN;
       finished = true;
     } else {
-      beta = (rzn - rzm) / (parity ? st.rz[1] : st.rz[0]);
+      beta = (rzn - rzm) / rzk;
     }
   }
-  st.iters = k + 1;
-  if (std::isfinite(res)) st.res = res;
-  // (constant indices only: a dynamic index would keep st in scratch memory)
-  if (parity) st.rz[0] = rzn;
-  else st.rz[1] = rzn;
-  st.beta = beta;
-  st.p_upd = finished ? 0 : 1;
-  st.status = status;
-  st.done = finished ? 1 : 0;
-  sc[rhs] = st;
-  done[rhs] = st.done;
-  if (host_slot) host_slot[rhs] = st;
-}
-
-// x += alpha p (the step of pcg_update_r) and p = z_new + beta p, as pcg_end_scalars decided.
-// The flags, the scalars and this thread's first (p, x, z) triple (clamped address) are loaded
-// in one batch.
-__global__ __launch_bounds__(kVecBlock) void pcg_update_xp_kernel(const double* znew, double* p, double* x,
-                                                                   int64_t n2, const PcgScalars* sc) {
-  const int rhs = blockIdx.y;
-  const double2* zc = reinterpret_cast<const double2*>(znew + rhs * n2);
-  double2* pc = reinterpret_cast<double2*>(p + rhs * n2);
-  double2* xc = reinterpret_cast<double2*>(x + rhs * n2);
-  const int64_t m = n2 / 2, stride = int64_t(gridDim.x) * kVecBlock;
-  const int64_t k0 = int64_t(blockIdx.x) * kVecBlock + threadIdx.x;
-  const int xu = sc[rhs].x_upd, pu = sc[rhs].p_upd;
-  const double alpha = sc[rhs].alpha, beta = sc[rhs].beta;
-  const int64_t kc = min(k0, m - 1);
-  double2 pv = pc[kc], xv = xc[kc], zv = zc[kc];
-  load_batch_end();
-  if (!xu && !pu) return;
-  for (int64_t q = k0; q < m; q += stride) {
-    if (q != k0) {
-      pv = pc[q];
-      xv = xc[q];
-      zv = zc[q];
+  if (!finished) {
+    for (int64_t q = k0; q < m; q += stride) {
+      if (q != k0) {
+        zv = zc[q];
+        pv = pc[q];
+      }
+      pc[q] = make_double2(zv.x + beta * pv.x, zv.y + beta * pv.y);
     }
-    if (xu) xc[q] = make_double2(xv.x + alpha * pv.x, xv.y + alpha * pv.y);
-    if (pu) pc[q] = make_double2(zv.x + beta * pv.x, zv.y + beta * pv.y);
+  }
+  if (blockIdx.x == 0 && tid == 0) {
+    PcgScalars& st = sc[rhs];
+    st.iters = k + 1;
+    if (std::isfinite(res)) st.res = res;
+    // (constant indices only: a dynamic index would keep the state in scratch memory)
+    if (parity) st.rz[0] = rzn;
+    else st.rz[1] = rzn;
+    st.status = status;
+    st.done = finished ? 1 : 0;
+    done[rhs] = st.done;
+    if (host_slot) host_slot[rhs] = st;
   }
 }
 
@@ -2054,8 +2039,8 @@ static int pcg_init(const PcgJob& J, int flags, int precision, double rtol, hipS
   return STFD_OK;
 }
 
-// Iteration k (parity = k & 1): q = A p (+<p,q>), r update (+||r||^2),
-// z_new = P^{-1} r (+<r,z_new>, <r,z_old>), end-of-iteration test, x and p updates.  The
+// Iteration k (parity = k & 1): q = A p (+<p,q>), x/r update (+||r||^2),
+// z_new = P^{-1} r (+<r,z_new>, <r,z_old>), end-of-iteration test and p update.  The
 // iteration index, the ring slot and every scalar live on the device, so the same launch
 // sequence serves every iteration of a parity (and can be captured into a graph).
 static int pcg_iteration(const PcgJob& J, int parity, int precision, int maxit, double rtol, hipStream_t s) {
@@ -2069,27 +2054,26 @@ static int pcg_iteration(const PcgJob& J, int parity, int precision, int maxit, 
   const int64_t mp = P->max_parts;
   double* pa = P->parts;               // <r, z_new> partials (last mode product)
   double* pb = pa + mp * P->max_nrhs;  // <r, z_old> partials
-  double* pc = pb + mp * P->max_nrhs;  // ||r||^2 partials (pcg_update_r)
+  double* pc = pb + mp * P->max_nrhs;  // ||r||^2 partials (pcg_update_xr)
   double* pd = pc + mp * P->max_nrhs;  // <p, A p> partials (matvec)
   const dim3 vgrid(kVecGrid, unsigned(J.nrhs)), vblock(kVecBlock);
   // With one right-hand side the matvec and apply kernels skip the done-flag test: the few
   // iterations launched after convergence only overwrite q and z_new, while x, r and p are
-  // guarded by the flag in pcg_update_r / pcg_end_scalars / pcg_update_xp.
+  // guarded by the flag in pcg_update_xr / pcg_end_iter.
   const int* dflag = J.nrhs > 1 ? P->done : nullptr;
   int rc;
   if ((rc = matvec_dispatch(P, p, q, J.nrhs, pd, dflag, s))) return rc;
-  hipLaunchKernelGGL(pcg_update_r_kernel, vgrid, vblock, 0, s, q, r, n2, pd, int(P->mv_blocks), P->sc, parity, pc,
-                     P->done, P->ctr);
+  hipLaunchKernelGGL(pcg_update_xr_kernel, vgrid, vblock, 0, s, p, q, J.x, r, n2, pd, int(P->mv_blocks), P->sc,
+                     parity, pc, P->done, P->ctr);
   DotEpilogue ep;
   ep.r = r;
   ep.zold = zold;
   ep.part_a = pa;
   ep.part_b = pb;
   if ((rc = apply_dispatch(P, r, znew, J.nrhs, precision, dflag, s, ep))) return rc;
-  hipLaunchKernelGGL(pcg_end_scalars_kernel, dim3(unsigned(J.nrhs)), dim3(kScalarBlock), 0, s, pc, kVecGrid, pa, pb,
-                     int(P->mp_last_blocks), P->sc, parity, P->done, maxit, rtol, P->sc_host_dev, P->max_nrhs,
-                     (const int*)P->ctr);
-  hipLaunchKernelGGL(pcg_update_xp_kernel, vgrid, vblock, 0, s, znew, p, J.x, n2, (const PcgScalars*)P->sc);
+  hipLaunchKernelGGL(pcg_end_iter_kernel, dim3(kEndGrid, unsigned(J.nrhs)), dim3(kEndBlock), 0, s, znew, p, n2, pc,
+                     kVecGrid, pa, pb, int(P->mp_last_blocks), P->sc, parity, P->done, maxit, rtol, P->sc_host_dev,
+                     P->max_nrhs, (const int*)P->ctr);
   STFD_HIP(hipGetLastError());
   return STFD_OK;
 }
