@@ -2071,7 +2071,10 @@ static int pcg_iteration(const PcgJob& J, int parity, int precision, int maxit, 
   ep.part_a = pa;
   ep.part_b = pb;
   if ((rc = apply_dispatch(P, r, znew, J.nrhs, precision, dflag, s, ep))) return rc;
-  hipLaunchKernelGGL(pcg_end_iter_kernel, dim3(kEndGrid, unsigned(J.nrhs)), dim3(kEndBlock), 0, s, znew, p, n2, pc,
+  // blocks of the end-of-iteration kernel: one per kEndBlock elements, at most kEndGrid (every block
+  // repeats the reduction, so small systems take few)
+  const unsigned egrid = unsigned(std::min<int64_t>(kEndGrid, std::max<int64_t>(1, (n2 / 2 + kEndBlock - 1) / kEndBlock)));
+  hipLaunchKernelGGL(pcg_end_iter_kernel, dim3(egrid, unsigned(J.nrhs)), dim3(kEndBlock), 0, s, znew, p, n2, pc,
                      kVecGrid, pa, pb, int(P->mp_last_blocks), P->sc, parity, P->done, maxit, rtol, P->sc_host_dev,
                      P->max_nrhs, (const int*)P->ctr);
   STFD_HIP(hipGetLastError());
