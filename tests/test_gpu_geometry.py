@@ -16,6 +16,7 @@ from oracle.operators import (FastDiagonalization, MappedFastDiagonalization, Pr
 from oracle.pcg import pcg  # noqa: E402
 from oracle.rhs import SpaceTimeBasis, assemble_rhs  # noqa: E402
 from paper_2311_18461_amd import inputs  # noqa: E402
+from parity import abs_matvec, max_rel  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -64,8 +65,9 @@ def test_annulus_matvec_vs_oracle(n_el, p, with_V):
     y = torch.empty(pr.N, dtype=torch.complex128, device=DEV)
     pr.matvec(to_dev(x), y)
     want = ref.matvec(x)
-    err = np.linalg.norm(y.cpu().numpy() - want) / np.linalg.norm(want)
-    print(f"annulus n_el={n_el} p={p} V={with_V}: matvec rel err {err:.2e}")
+    # entrywise against |A| |x| (the device assembles the weighted stencils in another order)
+    err = float(np.max(np.abs(y.cpu().numpy() - want) / abs_matvec(ref, x)))
+    print(f"annulus n_el={n_el} p={p} V={with_V}: matvec max |dy| / (|A||x|) {err:.2e}")
     assert err < 1e-12
 
 
@@ -80,7 +82,7 @@ def test_annulus_pcg_and_load_vector_vs_oracle():
     kn = inputs.uniform_open_knots(n_el, p)
     stb = SpaceTimeBasis(kn, [kn, kn], p, p, geometry=QuarterAnnulus(*inputs.ANNULUS_RADII))
     fb_ref, _ = assemble_rhs(stb, 1.0, u0=u0, V=V)
-    err_f = np.linalg.norm(fb.cpu().numpy() - fb_ref) / np.linalg.norm(fb_ref)
+    err_f = max_rel(fb.cpu().numpy(), fb_ref)
     u = torch.empty_like(fb)
     rc, info = pr.pcg_solve(fb, u, rtol=1e-8, maxit=1000)
     # the oracle runs on to tol / 3 so that its residual history brackets the stopping point
@@ -151,8 +153,8 @@ def test_annulus_preconditioner_vs_oracle_fd(n_el, p):
     s = torch.empty(pr.N, dtype=torch.complex128, device=DEV)
     pr.apply_preconditioner(to_dev(r), s)
     want = MappedFastDiagonalization(ref).apply(r)
-    err = np.linalg.norm(s.cpu().numpy() - want) / np.linalg.norm(want)
-    print(f"annulus FD apply n_el={n_el} p={p}: {err:.2e}")
+    err = max_rel(s.cpu().numpy(), want)
+    print(f"annulus FD apply n_el={n_el} p={p}: max-norm {err:.2e}")
     assert err < 1e-10
 
 

@@ -8,7 +8,7 @@ gradient form of S_3 to the Laplacian form of K_V.
 import numpy as np
 import pytest
 
-from oracle.bspline import gauss_rule
+from oracle.bspline import basis, gauss_rule
 from oracle.geometry import QuarterAnnulus, laplacian_coefficients, mapped_spatial_factors
 from oracle.operators import Problem
 from oracle.spatial import system_spatial_factors
@@ -144,3 +144,144 @@ def test_mapped_fd_inverts_the_dense_mapped_preconditioner():
     s = MappedFastDiagonalization(pr).apply(r)
     assert np.linalg.norm(P @ s - r) < 1e-11 * np.linalg.norm(r)
     assert np.max(np.abs(P - P.conj().T)) < 1e-12 * np.max(np.abs(P))
+
+
+# ---------------------------------------------------------------------------------------------
+# Mapped-domain right-hand side (Section 2.2 lifting, Section 4.3 load vector) by brute force.
+# Nothing below uses the oracle's chain rule, Jacobian or Kronecker assembly: the map and its
+# inverse are written here from the arc's definition (rational quadratic Bernstein form with
+# weights 1, 1/sqrt(2), 1), every physical Laplacian is a fourth-order finite difference in
+# physical coordinates through the inverse map, and the measure is the determinant of a
+# finite-difference Jacobian.  Only the 1D B-spline values (pinned in test_oracle_bspline) and
+# NumPy's Gauss-Legendre nodes are shared.
+# ---------------------------------------------------------------------------------------------
+
+_W = 1.0 / np.sqrt(2.0)
+
+
+def _arc_point(t):
+    """Quarter circle as a rational quadratic: control points (1,0), (1,1), (0,1), weights 1, w, 1."""
+    b0, b1, b2 = (1 - t) ** 2, 2 * t * (1 - t) * _W, t ** 2
+    den = b0 + b1 + b2
+    return (b0 + b1) / den, (b1 + b2) / den
+
+
+def _map(xi1, xi2, r0=1.0, r1=2.0):
+    cx, cy = _arc_point(xi2)
+    r = r0 + (r1 - r0) * xi1
+    return r * cx, r * cy
+
+
+def _inverse_map(x, y, r0=1.0, r1=2.0):
+    """xi = F^{-1}(x): radius gives xi_1; the arc parameter solves tan(angle) = c_y(t) / c_x(t), which
+    with s = t / (1 - t) is the quadratic s^2 + sqrt(2) (1 - T) s - T = 0, T = y / x."""
+    xi1 = (np.hypot(x, y) - r0) / (r1 - r0)
+    T = y / x
+    s = 0.5 * (-np.sqrt(2.0) * (1 - T) + np.sqrt(2.0 * (1 - T) ** 2 + 4 * T))
+    return xi1, s / (1 + s)
+
+
+def _spatial_values(kn, p, xi1, xi2):
+    """phi_{i1,i2}(xi) for every spatial B-spline, shape (m2, m1) + xi.shape."""
+    sh = np.shape(xi1)
+    b1 = basis(kn, p, np.ravel(xi1), 0)[0]
+    b2 = basis(kn, p, np.ravel(xi2), 0)[0]
+    return np.einsum("jq,iq->jiq", b2, b1).reshape((b2.shape[0], b1.shape[0]) + sh)
+
+
+def _physical_laplacian(kn, p, x, y, h=1e-3):
+    """Lap_x of phi(F^{-1}(x)) by the fourth-order five-point second difference along x and y."""
+    c = (-1.0 / 12, 4.0 / 3, -5.0 / 2, 4.0 / 3, -1.0 / 12)
+    lap = 0.0
+    for dx, dy in ((1.0, 0.0), (0.0, 1.0)):
+        for k, ck in zip(range(-2, 3), c):
+            a, b = _inverse_map(x + k * h * dx, y + k * h * dy)
+            lap = lap + ck * _spatial_values(kn, p, a, b)
+    return lap / (h * h)
+
+
+def _jacobian_det(xi1, xi2, h=1e-4):
+    c = (1.0 / 12, -2.0 / 3, 0.0, 2.0 / 3, -1.0 / 12)
+    D = np.zeros(np.shape(xi1) + (2, 2))
+    for a, (d1, d2) in enumerate(((1.0, 0.0), (0.0, 1.0))):
+        for k, ck in zip(range(-2, 3), c):
+            fx, fy = _map(xi1 + k * h * d1, xi2 + k * h * d2)
+            D[..., 0, a] += ck * fx / h
+            D[..., 1, a] += ck * fy / h
+    return np.abs(np.linalg.det(D))
+
+
+def _element_gauss(kn, q):
+    z = np.unique(kn)
+    g, w = np.polynomial.legendre.leggauss(q)
+    pts = (0.5 * (z[:-1] + z[1:]))[:, None] + (0.5 * np.diff(z))[:, None] * g[None, :]
+    return pts.ravel(), ((0.5 * np.diff(z))[:, None] * w[None, :]).ravel()
+
+
+def test_annulus_right_hand_side_brute_force():
+    """f_bar_I = int (f - S_V u_bar) conj(S_V B_I) dx dt on the quarter annulus, with f = 0 and the lifting
+    u_bar of a wave packet, against the oracle's sum-factorised assembly (chain rule, Kronecker lifting)."""
+    from oracle.rhs import SpaceTimeBasis, assemble_rhs, fixed_mask
+    p, n_el_s, n_el_t, nu = 3, 3, 2, 1.0
+    ks = inputs.uniform_open_knots(n_el_s, p)
+    kt = inputs.uniform_open_knots(n_el_t, p)
+    V, u0 = inputs.annulus_sample(5003)
+    u0.sigma = 0.4  # a broad packet: every spatial function sees the datum on this coarse grid
+    stb = SpaceTimeBasis(kt, [ks, ks], p, p, geometry=QuarterAnnulus(1.0, 2.0))
+    fbar, G = assemble_rhs(stb, nu, u0=u0, V=V)
+
+    # 1) the lifting: joint L2 projection onto the functions not vanishing on Gamma (initial face and
+    #    lateral faces), parametric measure, data u0 at the mapped points, zero lateral data; dense
+    m, mt = len(ks) - p - 1, len(kt) - p - 1
+    mask = fixed_mask([m, m], mt)                       # (m2, m1, mt)
+    fixed = np.argwhere(mask)
+    xq, wq = _element_gauss(ks, p + 1)
+    tq, wt = _element_gauss(kt, p + 1)
+    Bt = basis(kt, p, tq, 1)                            # (2, mt, Qt)
+    X1, X2 = np.meshgrid(xq, xq, indexing="xy")         # (Q2, Q1)
+    Ws = np.outer(wq, wq)
+    phi = _spatial_values(ks, p, X1, X2)                # (m2, m1, Q2, Q1)
+    b0 = basis(kt, p, np.array([0.0]), 0)[0][:, 0]      # time functions at t = 0
+    nf = len(fixed)
+    Gram = np.zeros((nf, nf))
+    rhs = np.zeros(nf, dtype=np.complex128)
+    ux, uy = _map(X1, X2)
+    u0v = u0(ux, uy)
+    for a, (j2, j1, jt) in enumerate(fixed):
+        va = phi[j2, j1] * b0[jt]
+        rhs[a] = np.sum(Ws * u0v * va)
+        for b, (k2, k1, kt_) in enumerate(fixed):
+            g = np.sum(Ws * va * phi[k2, k1] * b0[kt_])     # initial face
+            # lateral faces xi_l in {0, 1}: trace of phi times the time Gram
+            mt_gram = np.sum(wt * Bt[0, jt] * Bt[0, kt_])
+            for l in range(2):
+                for side in (0, m - 1):
+                    if (j1 if l == 0 else j2) != side or (k1 if l == 0 else k2) != side:
+                        continue
+                    other_j, other_k = (j2, k2) if l == 0 else (j1, k1)
+                    bo = basis(ks, p, xq, 0)[0]
+                    g += mt_gram * np.sum(wq * bo[other_j] * bo[other_k])
+            Gram[a, b] = g
+    g_ref = np.linalg.solve(Gram, rhs)
+    assert np.max(np.abs(G[mask] - g_ref)) < 1e-12 * np.max(np.abs(g_ref))
+
+    # 2) the load vector by brute force over the space-time Gauss grid
+    J = _jacobian_det(X1, X2)
+    lap = _physical_laplacian(ks, p, ux, uy)            # (m2, m1, Q2, Q1)
+    Vq = V(ux, uy)
+    # S_V u_bar = i u_bar_t - nu Lap u_bar + V u_bar at (q2, q1, qt)
+    coef = np.where(mask, G, 0.0)
+    Su = (1j * np.einsum("jit,jiab,tc->abc", coef, phi, Bt[1])
+          - nu * np.einsum("jit,jiab,tc->abc", coef, lap, Bt[0])
+          + Vq[..., None] * np.einsum("jit,jiab,tc->abc", coef, phi, Bt[0]))
+    w = (Ws * J)[..., None] * wt[None, None, :]
+    out = np.zeros((m - 2, m - 2, mt - 1), dtype=np.complex128)
+    for i2 in range(1, m - 1):
+        for i1 in range(1, m - 1):
+            for it in range(1, mt):
+                conj_SB = (-1j * phi[i2, i1][..., None] * Bt[1, it] - nu * lap[i2, i1][..., None] * Bt[0, it]
+                           + (Vq * phi[i2, i1])[..., None] * Bt[0, it])
+                out[i2 - 1, i1 - 1, it - 1] = np.sum(w * (-Su) * conj_SB)
+    err = np.max(np.abs(fbar - out.ravel())) / np.max(np.abs(out))
+    assert err < 1e-7, err
+    assert np.max(np.abs(out)) > 1e-3  # the datum reaches the free functions
