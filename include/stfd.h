@@ -115,6 +115,10 @@ typedef struct {
   int geometry;   /* STFD_GEOM_UNIT_CUBE or STFD_GEOM_QUARTER_ANNULUS */
   double geom[2]; /* quarter annulus: inner and outer radius (0 < geom[0] < geom[1]) */
   int precond;    /* STFD_PRECOND_AUTO or STFD_PRECOND_PARAMETRIC */
+  int no_rhs_workspace; /* 0: allocate the workspace of stfd_load_vector now (the Gauss-grid
+                           scratch of one right-hand side, about 16 (prod_a Q_a + 4 m_t
+                           prod_l max(m_l, Q_l)) bytes, and max_nrhs lifting tensors); nonzero:
+                           skip it, stfd_load_vector then returns STFD_EINVAL on this handle */
 } stfd_setup_desc;
 
 typedef struct {
@@ -185,14 +189,22 @@ int stfd_sizes(const stfd_problem *P, int64_t *n_t, int64_t n_s[3], int64_t *n_d
  *   lift             host or NULL: nrhs full coefficient tensors of u_bar,
  *                    m_t m_1 ... m_d complex (m_t = n_t + 1, m_l = n_l + 2, time
  *                    fastest), zero at free positions (output).
- * The call allocates and frees device scratch (about 16 (prod_a Q_a + 4 m_t
- * prod_l max(m_l, Q_l)) bytes) and returns after the device work has finished;
- * the lifting solve synchronises the stream every few iterations.
- * Errors: STFD_EINVAL (NULL handle or output, nrhs < 1), STFD_ENOTSPD (breakdown
- * of the lifting solve), STFD_ENOMEM, STFD_EHIP. */
+ * The call uses the workspace allocated by stfd_setup (it allocates nothing), processes the
+ * right-hand sides one after the other and returns after the device work has finished; the
+ * lifting solve synchronises the stream every 4 iterations to test its convergence.
+ * Errors: STFD_EINVAL (NULL handle or output, nrhs < 1 or > max_nrhs, handle set up with
+ * no_rhs_workspace), STFD_ENOTSPD (breakdown of the lifting solve), STFD_NOT_CONVERGED (the
+ * lifting solve of some right-hand side reached its iteration limit, see
+ * stfd_set_lift_max_iterations; that f_bar is assembled from the last lifting iterate),
+ * STFD_EHIP. */
 int stfd_load_vector(const stfd_problem *P, const void *f_q_dev, const void *u0_q_dev,
                      const void *const *dirichlet_q_dev, void *fbar_dev, double *lift, int64_t nrhs,
                      void *stream);
+
+/* Iteration limit of the lifting CG inside stfd_load_vector (default 200; about 10 iterations
+ * reach its relative residual of 1e-14 on the grids of the paper).  Errors: STFD_EINVAL (NULL
+ * handle, max_iter < 1). */
+int stfd_set_lift_max_iterations(stfd_problem *P, int max_iter);
 
 /* s = P-hat^{-1} r by fast diagonalisation (Algorithm 1 steps 2-4,
  * eq. preconditioner_str2): mode products with U_l^T, N_s independent banded

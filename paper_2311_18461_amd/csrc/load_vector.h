@@ -84,10 +84,10 @@ size_t rhs_work_reals(const LoadPlan& plan);
 //   f_q device samples on the space-time grid or nullptr,
 //   G (out) the full coefficient tensor of the lifting, fbar (out) the free right-hand side.
 // status_dev / status_host: device and host address of one pinned int that the lifting CG
-// sets to 1 (converged), 2 (breakdown) or 3 (iteration limit); valid after a stream sync.
-// Returns 0 or a hipError_t.
+// sets to 1 (converged), 2 (breakdown) or 3 (max_iter iterations without convergence); valid
+// after a stream sync.  Returns 0 or a hipError_t.
 int rhs_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, const double* u0_q,
                const double* const* faces, double* G, double* fbar, double* work, int* status_dev,
-               volatile int* status_host, hipStream_t stream);
+               volatile int* status_host, int max_iter, hipStream_t stream);
 
 }  // namespace stfd

@@ -254,7 +254,6 @@ struct LiftArgs {
   const double* Minv[4];
 };
 
-constexpr int kLiftMaxIter = 200;
 constexpr double kLiftTol2 = 1e-28;  // (relative residual 1e-14)^2
 
 // Sum of one double over a 256-thread block (wave reductions, then LDS).
@@ -489,7 +488,7 @@ enum { LIFT_RESET = 0, LIFT_INIT = 1, LIFT_ALPHA = 2, LIFT_BETA = 3 };
 
 // Scalar step of the lifting CG (one thread): partials are summed in block order.
 __global__ void lift_scalar_kernel(int mode, const double* __restrict__ pa, const double* __restrict__ pb, int nparts,
-                                   LiftState* __restrict__ st, int* __restrict__ status_out) {
+                                   LiftState* __restrict__ st, int* __restrict__ status_out, int max_iter) {
   if (blockIdx.x != 0) return;
   // partial sums: lane l adds the partials l, l + 64, ... (in batches of loads), then a fixed-order
   // wave reduction
@@ -540,7 +539,7 @@ __global__ void lift_scalar_kernel(int mode, const double* __restrict__ pa, cons
       s.done = 1;
     } else if (!(b > 0.0)) {
       s.done = 2;
-    } else if (s.iters >= kLiftMaxIter) {
+    } else if (s.iters >= max_iter) {
       s.done = 3;
     } else {
       s.beta = b / s.rz;
@@ -823,7 +822,7 @@ namespace {
 
 // u_bar: b from the face data, then preconditioned CG on the fixed set, then G.
 int lifting_device(const LoadPlan& plan, const double* u0_q, const double* const* faces, double* G,
-                   const RhsWork& w, int* status_dev, volatile int* status_host, hipStream_t s) {
+                   const RhsWork& w, int* status_dev, volatile int* status_host, int max_iter, hipStream_t s) {
   const LiftArgs A = lift_args(plan);
   const int64_t nf = plan.n_fixed;
   const int nb = plan.lift_blocks;
@@ -831,7 +830,7 @@ int lifting_device(const LoadPlan& plan, const double* u0_q, const double* const
   const int64_t mvb = (nf + kLiftMvWaves - 1) / kLiftMvWaves;  // lifting-matvec blocks (one partial each)
   auto scalar = [&](int mode, const double* pa, const double* pb, int nparts = 0) -> int {
     hipLaunchKernelGGL(lift_scalar_kernel, dim3(1), dim3(64), 0, s, mode, pa, pb, nparts > 0 ? nparts : nb, w.st,
-                       status_dev);
+                       status_dev, max_iter);
     return int(hipGetLastError());
   };
   if ((rc = scalar(LIFT_RESET, nullptr, nullptr))) return rc;
@@ -881,7 +880,7 @@ int lifting_device(const LoadPlan& plan, const double* u0_q, const double* const
   if ((rc = int(hipGetLastError()))) return rc;
   // iterations in chunks; the host checks the device's status after each chunk
   constexpr int kChunk = 4;
-  for (int it = 0; it < kLiftMaxIter; it += kChunk) {
+  for (int it = 0; it < max_iter; it += kChunk) {
     for (int c = 0; c < kChunk; ++c) {
       hipLaunchKernelGGL(lift_matvec_kernel, dim3(static_cast<unsigned>(mvb)), dim3(64 * kLiftMvWaves), 0, s, A,
                          (const double2*)w.p, (double2*)w.q, w.part, (const LiftState*)w.st);
@@ -1012,10 +1011,10 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
 
 int rhs_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, const double* u0_q,
                const double* const* faces, double* G, double* fbar, double* work, int* status_dev,
-               volatile int* status_host, hipStream_t stream) {
+               volatile int* status_host, int max_iter, hipStream_t stream) {
   RhsWork w;
   work_layout(plan, &w, work);
-  int rc = lifting_device(plan, u0_q, faces, G, w, status_dev, status_host, stream);
+  int rc = lifting_device(plan, u0_q, faces, G, w, status_dev, status_host, max_iter, stream);
   if (rc) return rc;
   return load_vector_device(hp, plan, f_q, G, fbar, w, stream);
 }

@@ -1252,6 +1252,9 @@ struct stfd_problem {
   stfd::SpatialDevice sdev;   // device basis tables, base stencils and model arrays
   int* lift_status_host = nullptr;  // pinned: status of the last lifting CG, written by the device
   int* lift_status_dev = nullptr;   // device address of lift_status_host
+  int lift_max_iter = 200;          // iteration limit of the lifting CG
+  double* rhs_work = nullptr;       // load-vector scratch for one right-hand side (setup), or nullptr
+  double* rhs_lift = nullptr;       // lifting tensors of max_nrhs right-hand sides (setup), or nullptr
   std::vector<void*> allocs;
 };
 
@@ -1498,18 +1501,31 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
                                                outer_rhs[l], done, s, ep, slice(l));
 }
 
-static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64_t nrhs, int precision,
-                          const int* done, hipStream_t s, const DotEpilogue& ep = DotEpilogue()) {
+// Algorithm 1 steps 2-4 with the intermediates in w0 / w1 (each 2 N nrhs reals of the working
+// precision: doubles for FP64, floats otherwise)
+static int apply_with_buffers(stfd_problem* P, const double* r, double* s_out, int64_t nrhs, int precision,
+                              const int* done, hipStream_t s, void* w0, void* w1,
+                              const DotEpilogue& ep = DotEpilogue()) {
   switch (precision) {
     case STFD_FP64:
-      return apply_impl<MP_F64, double>(P, r, s_out, nrhs, done, s, P->work64[0], P->work64[1], ep);
+      return apply_impl<MP_F64, double>(P, r, s_out, nrhs, done, s, static_cast<double*>(w0),
+                                        static_cast<double*>(w1), ep);
     case STFD_FP32:
-      return apply_impl<MP_F32, float>(P, r, s_out, nrhs, done, s, P->work32[0], P->work32[1], ep);
+      return apply_impl<MP_F32, float>(P, r, s_out, nrhs, done, s, static_cast<float*>(w0), static_cast<float*>(w1),
+                                       ep);
     case STFD_BF16:
-      return apply_impl<MP_BF16, float>(P, r, s_out, nrhs, done, s, P->work32[0], P->work32[1], ep);
+      return apply_impl<MP_BF16, float>(P, r, s_out, nrhs, done, s, static_cast<float*>(w0), static_cast<float*>(w1),
+                                        ep);
     default:
       return STFD_EINVAL;
   }
+}
+
+static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64_t nrhs, int precision,
+                          const int* done, hipStream_t s, const DotEpilogue& ep = DotEpilogue()) {
+  const bool f64 = precision == STFD_FP64;
+  return apply_with_buffers(P, r, s_out, nrhs, precision, done, s, f64 ? (void*)P->work64[0] : (void*)P->work32[0],
+                            f64 ? (void*)P->work64[1] : (void*)P->work32[1], ep);
 }
 
 constexpr int kMvRowBatch = 1;  // stencil rows whose loads are issued together (measured best)
@@ -1885,13 +1901,28 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     stfd_destroy(P);
     return STFD_EHIP;
   }
+  // right-hand side workspace: the Gauss-grid scratch of one right-hand side and the lifting
+  // tensors of max_nrhs (stfd_load_vector allocates nothing)
+  if (!desc->no_rhs_workspace) {
+    if ((rc = dev_alloc(P, &P->rhs_work, rhs_work_reals(P->load))) ||
+        (rc = dev_alloc(P, &P->rhs_lift, size_t(2) * size_t(P->load.n_full) * size_t(P->max_nrhs)))) {
+      stfd_destroy(P);
+      return rc;
+    }
+  }
   *out = P;
+  return STFD_OK;
+}
+
+int stfd_set_lift_max_iterations(stfd_problem* P, int max_iter) {
+  if (!P || max_iter < 1) return STFD_EINVAL;
+  P->lift_max_iter = max_iter;
   return STFD_OK;
 }
 
 int stfd_load_vector(const stfd_problem* P, const void* f_q_dev, const void* u0_q_dev,
                      const void* const* dirichlet_q_dev, void* fbar_dev, double* lift, int64_t nrhs, void* stream) {
-  if (!P || !fbar_dev || nrhs < 1) return STFD_EINVAL;
+  if (!P || !fbar_dev || nrhs < 1 || nrhs > P->max_nrhs || !P->rhs_work) return STFD_EINVAL;
   const HostProblem& hp = P->hp;
   const LoadPlan& plan = P->load;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1907,22 +1938,9 @@ int stfd_load_vector(const stfd_problem* P, const void* f_q_dev, const void* u0_
     nq_face[2 * l] = nq_face[2 * l + 1] = c;
   }
   const size_t nfull = size_t(plan.n_full);
-  double* work = nullptr;
-  double* Gd = nullptr;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(&work), rhs_work_reals(plan) * sizeof(double));
-  if (e != hipSuccess) {
-    g_last_hip_error = int(e);
-    return STFD_ENOMEM;
-  }
-  e = hipMalloc(reinterpret_cast<void**>(&Gd), nfull * 2 * sizeof(double) * size_t(lift ? nrhs : 1));
-  if (e != hipSuccess) {
-    g_last_hip_error = int(e);
-    (void)hipFree(work);
-    return STFD_ENOMEM;
-  }
   int rc = STFD_OK;
   const double* faces[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  for (int64_t r = 0; r < nrhs && rc == STFD_OK; ++r) {
+  for (int64_t r = 0; r < nrhs && (rc == STFD_OK || rc == STFD_NOT_CONVERGED); ++r) {
     for (int k = 0; k < 2 * hp.d; ++k)
       faces[k] = (dirichlet_q_dev && dirichlet_q_dev[k])
                      ? static_cast<const double*>(dirichlet_q_dev[k]) + size_t(r) * 2 * nq_face[k]
@@ -1930,26 +1948,29 @@ int stfd_load_vector(const stfd_problem* P, const void* f_q_dev, const void* u0_
     const double* u0 = u0_q_dev ? static_cast<const double*>(u0_q_dev) + size_t(r) * 2 * nq_s : nullptr;
     const double* fq = f_q_dev ? static_cast<const double*>(f_q_dev) + size_t(r) * 2 * grid : nullptr;
     double* out = static_cast<double*>(fbar_dev) + size_t(r) * P->n2;
-    double* G = Gd + (lift ? size_t(r) * 2 * nfull : 0);
+    double* G = P->rhs_lift + size_t(r) * 2 * nfull;
     *P->lift_status_host = 0;
-    int he = rhs_device(hp, plan, fq, u0, faces, G, out, work, P->lift_status_dev, P->lift_status_host, s);
+    int he = rhs_device(hp, plan, fq, u0, faces, G, out, P->rhs_work, P->lift_status_dev, P->lift_status_host,
+                        P->lift_max_iter, s);
     if (he == 0) he = int(hipStreamSynchronize(s));
     if (he != 0) {
       g_last_hip_error = he;
       rc = STFD_EHIP;
     } else if (*P->lift_status_host == 2) {
       rc = STFD_ENOTSPD;
+    } else if (*P->lift_status_host == 3) {
+      rc = STFD_NOT_CONVERGED;  // this right-hand side is assembled from the last lifting iterate
     }
   }
-  if (rc == STFD_OK && lift) {
-    e = hipMemcpy(lift, Gd, nfull * 2 * sizeof(double) * size_t(nrhs), hipMemcpyDeviceToHost);
+  if ((rc == STFD_OK || rc == STFD_NOT_CONVERGED) && lift) {
+    hipError_t e = hipMemcpyAsync(lift, P->rhs_lift, nfull * 2 * sizeof(double) * size_t(nrhs),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       g_last_hip_error = int(e);
       rc = STFD_EHIP;
     }
   }
-  (void)hipFree(Gd);
-  (void)hipFree(work);
   return rc;
 }
 

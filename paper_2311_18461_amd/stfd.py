@@ -30,7 +30,7 @@ class SetupDesc(ctypes.Structure):
                 ("T", ctypes.c_double), ("nu", ctypes.c_double),
                 ("V_quad", ctypes.POINTER(ctypes.c_double)), ("n_quad", ctypes.c_int),
                 ("max_nrhs", ctypes.c_int), ("geometry", ctypes.c_int), ("geom", ctypes.c_double * 2),
-                ("precond", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("no_rhs_workspace", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -69,6 +69,7 @@ SIGNATURES = {
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
     "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
     "stfd_update_potential": (ctypes.c_int, [_VP, _DP, _VP]),
+    "stfd_set_lift_max_iterations": (ctypes.c_int, [_VP, ctypes.c_int]),
     "stfd_fno_create": (ctypes.c_int, [ctypes.POINTER(FnoDesc), ctypes.POINTER(_VP)]),
     "stfd_fno_num_params": (ctypes.c_int, [_VP, ctypes.POINTER(_I64)]),
     "stfd_fno_get_params": (ctypes.c_int, [_VP, _FP]),
@@ -164,7 +165,7 @@ class Problem:
 
     def __init__(self, knots_t, knots_s, p_t: int, p_s: int, T: float = 1.0, nu: float = 1.0,
                  V_quad=None, n_quad: int = 0, max_nrhs: int = 1, geometry=GEOM_UNIT_CUBE, radii=(1.0, 2.0),
-                 precond=PRECOND_AUTO):
+                 precond=PRECOND_AUTO, rhs_workspace: bool = True):
         d = len(knots_s)
         self._keep = [np.ascontiguousarray(knots_t, dtype=np.float64)]
         desc = SetupDesc()
@@ -188,6 +189,7 @@ class Problem:
         desc.geometry = geometry
         desc.geom[0], desc.geom[1] = radii
         desc.precond = precond
+        desc.no_rhs_workspace = 0 if rhs_workspace else 1
         h = ctypes.c_void_p()
         self._h = None
         _check(_lib().stfd_setup(ctypes.byref(desc), ctypes.byref(h)), "stfd_setup")
@@ -304,6 +306,10 @@ class Problem:
                                        lift.ctypes.data_as(_DP) if lift is not None else None, nrhs,
                                        _stream_ptr(stream)), "stfd_load_vector")
         return lift
+
+    def set_lift_max_iterations(self, max_iter: int):
+        """stfd_set_lift_max_iterations: iteration limit of the lifting CG in load_vector."""
+        return _check(_lib().stfd_set_lift_max_iterations(self._h, int(max_iter)), "stfd_set_lift_max_iterations")
 
     def apply_preconditioner(self, r, s, nrhs: int = 1, precision=FP64, stream=None):
         precision = PRECISIONS.get(precision, precision)

@@ -219,3 +219,33 @@ def test_load_vector_bench_workload_vs_oracle():
     e_f = max_rel(fbar.cpu().numpy(), want)
     print(f"lift {e_lift:.2e} fbar (max-norm) {e_f:.2e}")
     assert e_lift < 1e-10 and e_f < 1e-10
+
+
+def test_load_vector_workspace_and_lifting_limit():
+    """The load vector runs in the workspace of the setup: a handle set up without it, or more
+    right-hand sides than max_nrhs, are rejected; a lifting CG stopped by its iteration limit
+    returns STFD_NOT_CONVERGED (never a silent success), and the default limit converges."""
+    stfd = _stfd()
+    d, n_el, p = 2, 6, 3
+    kt, ks = inputs.uniform_open_knots(n_el, p), [inputs.uniform_open_knots(n_el, p)] * 2
+    u0 = inputs.wave_packet(2, 11)
+    bare = stfd.Problem(kt, ks, p, p, rhs_workspace=False)
+    fbar = torch.empty(bare.N, dtype=torch.complex128, device=DEV)
+    u0q = to_dev(bare.sample_space(u0))
+    with pytest.raises(stfd.StfdError) as e:
+        bare.load_vector(fbar, u0_q=u0q)
+    assert e.value.code == stfd.EINVAL
+    lib = stfd.Problem(kt, ks, p, p)
+    with pytest.raises(stfd.StfdError) as e:
+        lib.load_vector(torch.empty(2 * lib.N, dtype=torch.complex128, device=DEV),
+                        u0_q=to_dev(np.concatenate([lib.sample_space(u0)] * 2)), nrhs=2)
+    assert e.value.code == stfd.EINVAL
+    lib.load_vector(fbar, u0_q=u0q)
+    want = fbar.clone()
+    lib.set_lift_max_iterations(1)
+    with pytest.raises(stfd.StfdError) as e:
+        lib.load_vector(fbar, u0_q=u0q)
+    assert e.value.code == stfd.NOT_CONVERGED
+    lib.set_lift_max_iterations(200)
+    lib.load_vector(fbar, u0_q=u0q)
+    assert torch.equal(fbar, want)

@@ -152,7 +152,7 @@ def test_apply_and_matvec_vs_oracle(d, n_el, p, kind):
     # entrywise: |y_gpu - y| <= c eps (|A| |x|)_i at every entry
     e_mv = float(np.max(np.abs(y - ref.matvec(r)) / abs_matvec(ref, r)))
     print(f"d={d} n_el={n_el} p={p}: apply max {e_max:.2e} per-fibre {e_fib:.2e}; matvec / (|A||x|) {e_mv:.2e}")
-    assert e_max < 1e-11 and e_fib < 1e-9
+    assert e_max < 1e-11 and e_fib < 1e-10
     assert e_mv < 1e-13
 
 

@@ -31,7 +31,7 @@ def test_apply_3d_full_size_vs_oracle(n_el, p):
     from paper_2311_18461_amd import stfd
     print(f"3D apply precision: n_el={n_el} p={p}", flush=True)
     kn = inputs.uniform_open_knots(n_el, p)
-    lib = stfd.Problem(kn, [kn] * 3, p, p, 1.0, 1.0)
+    lib = stfd.Problem(kn, [kn] * 3, p, p, 1.0, 1.0, rhs_workspace=False)
     ref = OProblem(kn, [kn] * 3, p, p, 1.0, None)
     fd = FastDiagonalization(ref, precompute_inverse=False)
     r = inputs.random_complex(lib.N, 3999)
@@ -47,7 +47,7 @@ def test_apply_3d_full_size_vs_oracle(n_el, p):
         assert errs[prec] < bound, (prec, errs[prec])
         if prec == "fp64":
             e_fib = fiber_rel(z, z_ref, lib.n_t)
-            assert e_fib < 1e-9, e_fib
+            assert e_fib < 1e-10, e_fib
     print(f"N={lib.N}: max-norm relative error vs the FP64 oracle "
           + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()) + f"; fp64 per-fibre {e_fib:.2e}", flush=True)
     lib.close()
