@@ -214,6 +214,20 @@ int stfd_set_lift_max_iterations(stfd_problem *P, int max_iter);
 int stfd_apply_preconditioner(const stfd_problem *P, const void *r_dev, void *s_dev, int64_t nrhs,
                               int precision, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same operation, kernels and results as
+ * stfd_apply_preconditioner, with the two intermediate tensors of Algorithm 1 steps 2-4 in a
+ * fixed 64 MiB device array of the library (one per GPU, held until the process ends) instead of
+ * the handle's work buffers.  The call allocates nothing.  Limit: each intermediate holds
+ * 2 N nrhs reals of the working precision (8 bytes for STFD_FP64, 4 otherwise) in one 32 MiB
+ * half, so nrhs <= 32 MiB / (2 N * 8 or 4 bytes) (N = 278,850: nrhs <= 7 in FP64, 15 otherwise);
+ * nrhs is not limited by max_nrhs.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (two streams, two threads, two handles) race and must be ordered by the
+ * caller.  Errors: STFD_EINVAL (NULL pointer, nrhs < 1, nrhs above the limit, bad precision),
+ * STFD_EHIP. */
+int stfd_apply_preconditioner_static(const stfd_problem *P, const void *r_dev, void *s_dev, int64_t nrhs,
+                                     int precision, void *stream);
+
 /* y = A x with A = sum_k S_k (x) T_k applied matrix-free (Section 5.3, eq.
  * syst_mat with the potential terms): spatial tensor-banded stencils with
  * (2p_s+1)^d coefficients per row, then the banded time factors.  FP64.

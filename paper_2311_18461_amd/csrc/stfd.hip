@@ -16,6 +16,7 @@
 #include <type_traits>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1528,6 +1529,35 @@ static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64
                             f64 ? (void*)P->work64[1] : (void*)P->work32[1], ep);
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free apply (stfd_apply_preconditioner_static): the two intermediate
+// tensors of Algorithm 1 steps 2-4 live in a file-scope device array of fixed size instead of the
+// handle's work buffers.  Host code never passes the array's name to a kernel (on the host it is
+// a stand-in, not a device address): its device address is taken once per device with
+// hipGetSymbolAddress and kept in g_scratch_dev.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;  // 64 MiB per device, two halves of 32 MiB
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+static void* g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mutex;
+
+// Device address of `scratch` on the current device (looked up on the first use per device).
+static int scratch_address(void** out) {
+  int dev = 0;
+  STFD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return STFD_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    STFD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return STFD_EHIP;
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return STFD_OK;
+}
+
 constexpr int kMvRowBatch = 1;  // stencil rows whose loads are issued together (measured best)
 
 // spatial points per matvec block: whole points, at most kMvLanes lanes, coefficients (or Z) in
@@ -1901,6 +1931,14 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     stfd_destroy(P);
     return STFD_EHIP;
   }
+  // device address of the allocation-free apply's scratch on this device
+  {
+    void* sp = nullptr;
+    if ((rc = scratch_address(&sp))) {
+      stfd_destroy(P);
+      return rc;
+    }
+  }
   // right-hand side workspace: the Gauss-grid scratch of one right-hand side and the lifting
   // tensors of max_nrhs (stfd_load_vector allocates nothing)
   if (!desc->no_rhs_workspace) {
@@ -1997,6 +2035,21 @@ int stfd_apply_preconditioner(const stfd_problem* Pc, const void* r_dev, void* s
   if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
   return apply_dispatch(P, static_cast<const double*>(r_dev), static_cast<double*>(s_dev), nrhs, precision, nullptr,
                         static_cast<hipStream_t>(stream));
+}
+
+int stfd_apply_preconditioner_static(const stfd_problem* Pc, const void* r_dev, void* s_dev, int64_t nrhs,
+                                     int precision, void* stream) {
+  stfd_problem* P = const_cast<stfd_problem*>(Pc);
+  if (!P || !r_dev || !s_dev || nrhs < 1) return STFD_EINVAL;
+  if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
+  // each intermediate holds 2 N nrhs reals of the working precision in one half of the scratch
+  const size_t elem = precision == STFD_FP64 ? sizeof(double) : sizeof(float);
+  const size_t half = kScratchBytes / 2;
+  if (uint64_t(nrhs) > uint64_t(half / (size_t(P->n2) * elem))) return STFD_EINVAL;
+  void* base = nullptr;
+  if (int rc = scratch_address(&base)) return rc;
+  return apply_with_buffers(P, static_cast<const double*>(r_dev), static_cast<double*>(s_dev), nrhs, precision,
+                            nullptr, static_cast<hipStream_t>(stream), base, static_cast<char*>(base) + half);
 }
 
 int stfd_matvec(const stfd_problem* Pc, const void* x_dev, void* y_dev, int64_t nrhs, void* stream) {

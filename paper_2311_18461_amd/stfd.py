@@ -64,6 +64,7 @@ SIGNATURES = {
     "stfd_sizes": (ctypes.c_int, [_VP, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "stfd_apply_preconditioner": (ctypes.c_int, [_VP, _VP, _VP, _I64, ctypes.c_int, _VP]),
     "stfd_matvec": (ctypes.c_int, [_VP, _VP, _VP, _I64, _VP]),
+    "stfd_apply_preconditioner_static": (ctypes.c_int, [_VP, _VP, _VP, _I64, ctypes.c_int, _VP]),
     "stfd_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _I64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.POINTER(PcgInfo), _VP]),
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
@@ -316,6 +317,14 @@ class Problem:
         return _check(_lib().stfd_apply_preconditioner(self._h, _dev_ptr(r, self.N * nrhs, "r"),
                                                        _dev_ptr(s, self.N * nrhs, "s"), nrhs, precision,
                                                        _stream_ptr(stream)), "stfd_apply_preconditioner")
+
+    def apply_preconditioner_static(self, r, s, nrhs: int = 1, precision=FP64, stream=None):
+        """stfd_apply_preconditioner_static: the apply with the library's fixed device scratch."""
+        precision = PRECISIONS.get(precision, precision)
+        return _check(_lib().stfd_apply_preconditioner_static(self._h, _dev_ptr(r, self.N * nrhs, "r"),
+                                                              _dev_ptr(s, self.N * nrhs, "s"), nrhs, precision,
+                                                              _stream_ptr(stream)),
+                      "stfd_apply_preconditioner_static")
 
     def matvec(self, x, y, nrhs: int = 1, stream=None):
         return _check(_lib().stfd_matvec(self._h, _dev_ptr(x, self.N * nrhs, "x"), _dev_ptr(y, self.N * nrhs, "y"),
