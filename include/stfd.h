@@ -86,6 +86,16 @@ enum { STFD_GEOM_UNIT_CUBE = 0, STFD_GEOM_QUARTER_ANNULUS = 1 };
  * unit cube both choices are the paper's P-hat. */
 enum { STFD_PRECOND_AUTO = 0, STFD_PRECOND_PARAMETRIC = 1 };
 
+/* Form of the system matvec (Section 5.3: the residual is the dominant cost of an iteration).
+ * STFD_MATVEC_STENCIL stores the spatial factors S_1..S_3 as (2p_s+1)^d-point stencils with
+ * per-point coefficients.  STFD_MATVEC_SUMFAC (unit cube, d = 2 or 3, p_s <= 5, V = 0 or V a
+ * sum of one-dimensional functions V(x) = sum_l v_l(x_l), such as the harmonic potential) applies
+ * them sum-factorised: with h_l = -nu d_l^2 + v_l the factors are Kronecker sums of the 1D banded
+ * matrices M_l, G_l = int (h_l b_j) b_i and Jh_l = int (h_l b_j)(h_l b_i), applied in one pass along
+ * x_1 and time and one pass per further direction, each reading 2p_s+1 neighbours per entry.
+ * STFD_MATVEC_AUTO picks SUMFAC for d = 3 when it applies, else STENCIL. */
+enum { STFD_MATVEC_AUTO = 0, STFD_MATVEC_STENCIL = 1, STFD_MATVEC_SUMFAC = 2 };
+
 /* Problem description (Sections 2, 3.1-3.2, 4.3).
  * knots_t / knots_s[l]: open knot vectors on [0,1] (first and last p+1 knots
  *   repeated, non-decreasing), length m + p + 1.  The time basis is
@@ -115,6 +125,8 @@ typedef struct {
   int geometry;   /* STFD_GEOM_UNIT_CUBE or STFD_GEOM_QUARTER_ANNULUS */
   double geom[2]; /* quarter annulus: inner and outer radius (0 < geom[0] < geom[1]) */
   int precond;    /* STFD_PRECOND_AUTO or STFD_PRECOND_PARAMETRIC */
+  int matvec;     /* STFD_MATVEC_AUTO, STFD_MATVEC_STENCIL or STFD_MATVEC_SUMFAC (EINVAL where it
+                     does not apply) */
   int no_rhs_workspace; /* 0: allocate the workspace of stfd_load_vector now (the Gauss-grid
                            scratch of one right-hand side, about 16 (prod_a Q_a + 4 m_t
                            prod_l max(m_l, Q_l)) bytes, and max_nrhs lifting tensors); nonzero:
@@ -152,9 +164,12 @@ int stfd_setup(const stfd_setup_desc *desc, stfd_problem **out);
 
 /* Replace the potential of a set-up problem (same conventions as V_quad in
  * stfd_setup_desc; NULL: V = 0).  The spatial factors S_1..S_3 are rebuilt on
- * the device (one thread per stencil entry, d <= 2; host quadrature for d = 3);
- * the preconditioner does not depend on V and is kept.  Synchronises `stream`.
- * Errors: STFD_EINVAL (NULL handle, non-finite V), STFD_EHIP. */
+ * the device (one thread per stencil entry, d <= 2; host quadrature for d = 3; the 1D
+ * band matrices of a sum-factorised matvec); the potential samples are uploaded again (this
+ * call allocates device memory for them).  The preconditioner does not depend on V and is
+ * kept.  Synchronises `stream`.
+ * Errors: STFD_EINVAL (NULL handle, non-finite V, a V that is not a sum of 1D functions on a
+ * handle whose matvec is sum-factorised), STFD_EHIP. */
 int stfd_update_potential(stfd_problem *P, const double *V_quad, void *stream);
 
 /* Physical coordinates x = F(xi) of n parametric points (host arrays of n * d

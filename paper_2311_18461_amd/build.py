@@ -7,8 +7,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libstfd.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("stfd.hip", "load_vector.hip", "spatial.hip", "fno.hip", "host_setup.cpp",
-                                                     "spatial.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("stfd.hip", "load_vector.hip", "spatial.hip", "sumfac.hip", "fno.hip",
+                                                     "host_setup.cpp", "spatial.cpp")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions are disabled for every HIP translation unit
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

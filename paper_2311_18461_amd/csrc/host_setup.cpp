@@ -590,28 +590,35 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
       hp.Tband[(size_t(1) * nt + t) * wt + dt + pt] = hp.Mt[ix];
       hp.Tband[(size_t(2) * nt + t) * wt + dt + pt] = hp.Kt[ix];
     }
-  // spatial factors as stencils.  V = 0 part on the unit cube from the 1D matrices
-  // (on a mapped domain every part comes from weighted terms, added later):
-  //   S_1 = (x) M_l, S_3 = nu sum_l (L_l in slot l, M elsewhere),
-  //   S_2 = nu^2 B_s, B_s = sum_l (J_l in slot l) + sum_{l != k} (L_l, L_k in slots l, k)
-  //   (integration by parts on the Dirichlet-reduced basis).
-  const int ps = v.p_s, w2 = 2 * ps + 1;
   int stencil = 1;
-  for (int l = 0; l < v.d; ++l) stencil *= w2;
+  for (int l = 0; l < v.d; ++l) stencil *= 2 * v.p_s + 1;
   hp.stencil = stencil;
+  if (v.stencils) base_stencils(hp, v.kronecker_base);
+  return 0;
+}
+
+// Spatial factors as stencils.  V = 0 part on the unit cube from the 1D matrices
+// (on a mapped domain every part comes from weighted terms, added later):
+//   S_1 = (x) M_l, S_3 = nu sum_l (L_l in slot l, M elsewhere),
+//   S_2 = nu^2 B_s, B_s = sum_l (J_l in slot l) + sum_{l != k} (L_l, L_k in slots l, k)
+//   (integration by parts on the Dirichlet-reduced basis).
+void base_stencils(HostProblem& hp, bool kronecker_base) {
+  const int d = hp.d, ps = hp.p_s, w2 = 2 * ps + 1;
+  const double nu = hp.nu;
+  const int stencil = hp.stencil;
   hp.Sc.assign(size_t(3) * hp.N_s * stencil, 0.0);
   double* S1 = hp.Sc.data();
   double* S2 = S1 + size_t(hp.N_s) * stencil;
   double* S3 = S2 + size_t(hp.N_s) * stencil;
-  for (int64_t i = 0; i < (v.kronecker_base ? hp.N_s : 0); ++i) {
+  for (int64_t i = 0; i < (kronecker_base ? hp.N_s : 0); ++i) {
     int il[3] = {0, 0, 0};
     int64_t r = i;
-    for (int l = 0; l < v.d; ++l) { il[l] = int(r % hp.n_s[l]); r /= hp.n_s[l]; }
+    for (int l = 0; l < d; ++l) { il[l] = int(r % hp.n_s[l]); r /= hp.n_s[l]; }
     for (int s = 0; s < stencil; ++s) {
       int o[3] = {0, 0, 0};
       int rs = s;
       bool ok = true;
-      for (int l = 0; l < v.d; ++l) {
+      for (int l = 0; l < d; ++l) {
         o[l] = rs % w2 - ps;
         rs /= w2;
         int j = il[l] + o[l];
@@ -619,24 +626,24 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
       }
       if (!ok) continue;
       double Mv[3], Lv[3], Jv[3];
-      for (int l = 0; l < v.d; ++l) {
+      for (int l = 0; l < d; ++l) {
         size_t ix = size_t(il[l]) * hp.n_s[l] + (il[l] + o[l]);
         Mv[l] = hp.Ms1[l][ix];
         Lv[l] = hp.Ls1[l][ix];
         Jv[l] = hp.Js1[l][ix];
       }
       double m_all = 1.0, lsum = 0.0, bsum = 0.0;
-      for (int l = 0; l < v.d; ++l) m_all *= Mv[l];
-      for (int l = 0; l < v.d; ++l) {
+      for (int l = 0; l < d; ++l) m_all *= Mv[l];
+      for (int l = 0; l < d; ++l) {
         double pl = Lv[l], pj = Jv[l];
-        for (int k = 0; k < v.d; ++k)
+        for (int k = 0; k < d; ++k)
           if (k != l) { pl *= Mv[k]; pj *= Mv[k]; }
         lsum += pl;
         bsum += pj;
-        for (int k = 0; k < v.d; ++k) {
+        for (int k = 0; k < d; ++k) {
           if (k == l) continue;
           double c = Lv[l] * Lv[k];
-          for (int o2 = 0; o2 < v.d; ++o2)
+          for (int o2 = 0; o2 < d; ++o2)
             if (o2 != l && o2 != k) c *= Mv[o2];
           bsum += c;
         }
@@ -647,7 +654,6 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
       S3[ix] = nu * lsum;
     }
   }
-  return 0;
 }
 
 }  // namespace stfd

@@ -64,6 +64,8 @@ void gram_1d(const Direction& dir, Gram1D& g);
 int gauss_legendre(int q, double* x, double* w);  // on (-1,1)
 int gen_eig(int n, const double* L, const double* M, double* U, double* lam);  // 0 or -2
 int host_setup(const struct stfd_setup_desc_view& v, HostProblem& hp);
+// hp.Sc: the V-free unit-cube stencils from the 1D matrices (kronecker_base), else zeros.
+void base_stencils(HostProblem& hp, bool kronecker_base);
 int time_factors(HostProblem& hp);
 
 // Segmented layout of the banded time solves: each mode's n_t rows are cut into `segs`
@@ -96,6 +98,7 @@ struct stfd_setup_desc_view {
   double T, nu;
   int n_quad;
   bool kronecker_base;  // assemble the V-free unit-cube stencils from 1D matrices
+  bool stencils;        // build hp.Sc now (false: the caller decides later)
 };
 
 }  // namespace stfd

@@ -160,6 +160,7 @@ int spatial_device_apply(const HostProblem& hp, const SpatialModel& m, SpatialDe
     if (e != hipSuccess) return int(e);
   }
   const int64_t ns = hp.N_s * hp.stencil;
+  if (!Sc_dev) return 0;  // coefficient arrays only (the sum-factorised matvec has no stencils)
   if (hp.d > 2) {
     // three directions: sum-factorised host quadrature, then upload (layout [N_s][stencil][3])
     std::vector<double> S(hp.Sc);

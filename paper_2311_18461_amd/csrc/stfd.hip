@@ -26,6 +26,7 @@
 #include "load_vector.h"
 #include "spatial.h"
 #include "spatial_dev.h"
+#include "sumfac.h"
 
 namespace stfd {
 
@@ -1256,6 +1257,8 @@ struct stfd_problem {
   int lift_max_iter = 200;          // iteration limit of the lifting CG
   double* rhs_work = nullptr;       // load-vector scratch for one right-hand side (setup), or nullptr
   double* rhs_lift = nullptr;       // lifting tensors of max_nrhs right-hand sides (setup), or nullptr
+  bool sf_on = false;               // the matvec runs sum-factorised (no stencils are stored)
+  stfd::SumFacPlan sf;
   std::vector<void*> allocs;
 };
 
@@ -1585,6 +1588,14 @@ static int matvec_points_per_block(const HostProblem& hp, int n_cus) {
 
 static int matvec_dispatch(stfd_problem* P, const double* x, double* y, int64_t nrhs, double* partial,
                            const int* done, hipStream_t s) {
+  if (P->sf_on) {
+    const int he = sumfac_matvec(P->sf, x, y, nrhs, partial, done, s);
+    if (he != 0) {
+      g_last_hip_error = he;
+      return STFD_EHIP;
+    }
+    return STFD_OK;
+  }
   const HostProblem& hp = P->hp;
   MatvecArgs a;
   a.x = x;
@@ -1688,8 +1699,16 @@ int stfd_update_potential(stfd_problem* P, const double* V_quad, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   SpatialModel m;
   if (build_spatial_model(P->hp, P->geom, V_quad, m)) return STFD_EINVAL;
+  std::vector<double> bands[3];
+  if (P->sf_on) {
+    // the sum-factorised matvec needs V as a sum of 1D functions
+    if (sumfac_bands(P->hp, V_quad, bands)) return STFD_EINVAL;
+    STFD_HIP(hipStreamSynchronize(s));
+    for (int l = 0; l < P->hp.d; ++l)
+      STFD_HIP(hipMemcpy(P->sf.bands[l], bands[l].data(), bands[l].size() * sizeof(double), hipMemcpyHostToDevice));
+  }
   P->model = std::move(m);
-  int he = spatial_device_apply(P->hp, P->model, P->sdev, P->Sc, s);
+  int he = spatial_device_apply(P->hp, P->model, P->sdev, P->sf_on ? nullptr : P->Sc, s);
   if (he == 0) he = int(hipStreamSynchronize(s));
   stfd::set_plan_model(P);
   if (he != 0) {
@@ -1740,6 +1759,8 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
                                    geom.r1 > geom.r0 && std::isfinite(geom.r1)))
     return STFD_EINVAL;
   v.kronecker_base = (geom.kind == GEOM_UNIT);
+  v.stencils = false;  // built below unless the matvec runs sum-factorised
+  if (desc->matvec < STFD_MATVEC_AUTO || desc->matvec > STFD_MATVEC_SUMFAC) return STFD_EINVAL;
   stfd_problem* P = new (std::nothrow) stfd_problem;
   if (!P) return STFD_ENOMEM;
   int rc = host_setup(v, P->hp);
@@ -1761,6 +1782,18 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   if (build_spatial_model(hp, geom, desc->V_quad, P->model)) {
     delete P;
     return STFD_EINVAL;
+  }
+  // matvec form: sum-factorised on the unit cube in 3D (by default) when V is a sum of 1D functions
+  std::vector<double> sf_bands[3];
+  {
+    const bool want = desc->matvec == STFD_MATVEC_SUMFAC || (desc->matvec == STFD_MATVEC_AUTO && hp.d == 3);
+    const bool able = geom.kind == GEOM_UNIT && hp.d >= 2 && hp.p_s <= 5 && sumfac_bands(hp, desc->V_quad, sf_bands) == 0;
+    if (desc->matvec == STFD_MATVEC_SUMFAC && !able) {
+      delete P;
+      return STFD_EINVAL;
+    }
+    P->sf_on = want && able;
+    if (!P->sf_on) base_stencils(P->hp, v.kronecker_base);
   }
   P->max_nrhs = desc->max_nrhs;
   P->n2 = 2 * hp.N;
@@ -1839,8 +1872,9 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     }
     // spatial coefficients interleaved per row and stencil offset: [N_s][stencil][3];
     // V-free unit-cube base from the host, weighted terms (potential, geometry) added on the device
+    // (no stencils are stored for the sum-factorised matvec: hp.Sc is empty then)
     std::vector<double> ScI(hp.Sc.size());
-    const size_t ns = size_t(hp.N_s) * hp.stencil;
+    const size_t ns = hp.Sc.size() / 3;
     for (size_t is = 0; is < ns; ++is)
       for (int k = 0; k < 3; ++k) ScI[is * 3 + k] = hp.Sc[k * ns + is];
     // time bands in the matvec's LDS layout [t][dt][4] = (L_t, M_t, K_t, 0), zero where t + dt - p_t
@@ -1855,12 +1889,12 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
             TbL[(size_t(t) * wtb + dt) * 4 + k] = hp.Tband[(size_t(k) * hp.n_t + t) * wtb + dt];
         }
     if ((rc = upload(P, &P->TbL, TbL.data(), TbL.size())) ||
-        (rc = dev_alloc(P, &P->Sc, ScI.size()))) {
+        (!P->sf_on && (rc = dev_alloc(P, &P->Sc, ScI.size())))) {
       stfd_destroy(P);
       return rc;
     }
-    int he = spatial_device_init(hp, P->model.kronecker_base ? ScI.data() : nullptr, P->sdev);
-    if (he == 0) he = spatial_device_apply(hp, P->model, P->sdev, P->Sc, nullptr);
+    int he = spatial_device_init(hp, (P->model.kronecker_base && !P->sf_on) ? ScI.data() : nullptr, P->sdev);
+    if (he == 0) he = spatial_device_apply(hp, P->model, P->sdev, P->sf_on ? nullptr : P->Sc, nullptr);
     if (he == 0) he = int(hipDeviceSynchronize());
     if (he != 0) {
       g_last_hip_error = he;
@@ -1879,9 +1913,35 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       stfd_destroy(P);
       return rc;
     }
-  // matvec launch shape: whole spatial points per block
-  P->mv_points = matvec_points_per_block(hp, P->n_cus);
-  P->mv_blocks = (hp.N_s + P->mv_points - 1) / P->mv_points;
+  // matvec launch shape: whole spatial points per block (stencil form), or the sum-factorised plan
+  if (P->sf_on) {
+    SumFacPlan& sp = P->sf;
+    sp.d = hp.d;
+    sp.n_t = hp.n_t;
+    sp.pt = hp.p_t;
+    sp.ps = hp.p_s;
+    for (int l = 0; l < hp.d; ++l) sp.n[l] = hp.n_s[l];
+    sp.N = hp.N;
+    sp.tband = P->TbL;
+    sp.work_stride = P->n2 * P->max_nrhs;
+    if (sumfac_plan_shape(sp, P->max_lds) != 0) {
+      stfd_destroy(P);
+      return STFD_EINVAL;
+    }
+    for (int l = 0; l < hp.d; ++l)
+      if ((rc = upload(P, &sp.bands[l], sf_bands[l].data(), sf_bands[l].size()))) {
+        stfd_destroy(P);
+        return rc;
+      }
+    if ((rc = dev_alloc(P, &sp.work, size_t(hp.d == 3 ? 6 : 3) * size_t(sp.work_stride)))) {
+      stfd_destroy(P);
+      return rc;
+    }
+    P->mv_blocks = sp.last_grid;
+  } else {
+    P->mv_points = matvec_points_per_block(hp, P->n_cus);
+    P->mv_blocks = (hp.N_s + P->mv_points - 1) / P->mv_points;
+  }
   {
     // the last backward product runs along x_1 (unit cube) or along x_d (mapped domain)
     int64_t outer0 = 1;

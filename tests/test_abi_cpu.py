@@ -126,3 +126,23 @@ def test_fno_rejects_invalid_descriptors():
         with pytest.raises(stfd.StfdError) as ei:
             stfd.Fno(**args)
         assert ei.value.code == stfd.EINVAL
+
+
+def test_sumfac_matvec_rejected_where_it_does_not_apply():
+    """STFD_MATVEC_SUMFAC needs the unit cube, d >= 2 and a potential that is a sum of 1D functions;
+    the check runs on the host before any device work."""
+    stfd = _lib()
+    kn = inputs.uniform_open_knots(4, 3)
+    cases = [dict(knots_s=[kn]),                                            # d = 1
+             dict(knots_s=[kn, kn], geometry=stfd.GEOM_QUARTER_ANNULUS),    # mapped domain
+             dict(knots_s=[kn] * 3, V=inputs.gaussian_potential(3, 31, count=3))]  # not separable
+    for c in cases:
+        ks = c["knots_s"]
+        Vq = stfd.sample_on_quad_grid(c["V"], ks, 3) if "V" in c else None
+        with pytest.raises(stfd.StfdError) as ei:
+            stfd.Problem(kn, ks, 3, 3, V_quad=Vq, geometry=c.get("geometry", stfd.GEOM_UNIT_CUBE),
+                         matvec=stfd.MATVEC_SUMFAC)
+        assert ei.value.code == stfd.EINVAL
+    with pytest.raises(stfd.StfdError) as ei:
+        stfd.Problem(kn, [kn] * 2, 3, 3, matvec=7)
+    assert ei.value.code == stfd.EINVAL
