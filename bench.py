@@ -31,14 +31,19 @@ sys.path.insert(0, ROOT)
 METRIC = "FD precond apply Mdof/s + PCG time to 1e-8: FP64 vs mixed/batched/warm-start"
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and matrix peak
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per launch of the 2D p=3 matvec kernel on this workload: FETCH_SIZE and WRITE_SIZE passes
-# of rocprofv3 over `bench.py --profile`, each scaled by what the same counter reads for a 64 MiB
-# device copy in that run (x 1.999 and x 1.000); profiles/pcg_2d_p3_n64_gauss_traffic.md.  Valid for
-# the matvec kernel as profiled (12.57 MB read + 4.47 MB written per launch, 705 blocks of 6 points).
-MATVEC_KERNEL = "matvec_kernel<2,3,3,1>"
-MATVEC_TRAFFIC_BYTES = 17.04e6
-
-
+# Dominant kernel of the step: the FP64 mode product of the FD apply (Algorithm 1 steps 2 and 4;
+# rocprofv3 kernel statistics of `bench.py --profile 2d`: 26.8% of kernel time, plus 10.2% for its
+# variant with the fused PCG dot products).  Per launch on this workload (2D p=3 64^3, n = 65 per
+# direction), from profiles/fd_apply_2d_p3_n64_gauss.md (mean of its two launch shapes):
+#   HBM traffic: FETCH_SIZE x 1.999 + WRITE_SIZE x 1.000 (factors: what the counters read for a
+#   64 MiB device copy in the same run) = 9.43e6 bytes (algorithmic: 32 bytes per dof = 8.92e6);
+#   MFMA work: SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 = 9.77e7 flops (algorithmic 4 n = 260 flops per
+#   dof = 7.25e7; the rest is the padding of n = 65 to 68 rows of K and 80 output columns).
+# The bench times these launches with HIP events around each launch on its stream, which also
+# enclose the dispatch of the kernel (about 2.4 us above rocprofv3's kernel duration at this size).
+MODE_PRODUCT_KERNEL = "mode_product_kernel<0, double, double, 17, 1, false>"
+MODE_PRODUCT_TRAFFIC_BYTES = 9.43e6
+MODE_PRODUCT_MFMA_FLOPS = 9.77e7
 def build_workload(sample=0, n_el=64, p=3):
     from paper_2311_18461_amd import inputs, stfd
     w = inputs.gaussian_potential_2d_workload(sample, n_el=n_el, p=p)
@@ -151,6 +156,18 @@ def precision_3d_section(stream, cases=((48, 3), (32, 4)), bf16_maxit=300):
             row[prec] = {"apply_ms": round(ms, 4), "apply_mdofs": round(prob.N / (ms * 1e-3) / 1e6, 1),
                          "apply_relerr_vs_fp64": float(f"{err:.3e}")}
         row["matvec_ms"] = round(time_events(lambda: prob.matvec(r, z, stream=stream), 10, stream), 4)
+        # FP64 mode products timed one by one (HIP events on the launch stream), and the whole apply
+        # against its roof
+        prob.timing_begin(capacity=6 * 10)
+        for _ in range(10):
+            prob.apply_preconditioner(r, z, precision="fp64", stream=stream)
+        mp_ms, mp_n = prob.timing_end()
+        n_s = prob.n_s[0]
+        mp_us = mp_ms / mp_n * 1e3
+        row["mode_product_fp64"] = {"avg_launch_us": round(mp_us, 2),
+                                    "hbm_frac": round(32 * prob.N / (mp_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                                    "algorithmic_tflops": round(4 * n_s * prob.N / (mp_us * 1e-6) / 1e12, 3)}
+        row["fd_apply_roofline_fp64"] = fd_apply_roofline(prob.N, 3, n_s, p, row["fp64"]["apply_ms"] * 1e3)
         f = torch.empty_like(r)
         prob.load_vector(f, u0_q=torch.from_numpy(prob.sample_space(w.u0)).to(dev), stream=stream)
         u = torch.empty_like(r)
@@ -167,10 +184,68 @@ def precision_3d_section(stream, cases=((48, 3), (32, 4)), bf16_maxit=300):
     return out
 
 
-def cpu_baseline(w, budget_s=20.0):
-    """The oracle (FP64 NumPy/SciPy, all host cores): right-hand side with lifting, then PCG to 1e-8,
-    on the same workload (setup excluded)."""
-    from threadpoolctl import threadpool_info
+def mode_product_roofline(N, n, avg_us):
+    """HBM roofline of one FP64 mode product (read and write the complex FP64 tensor: 32 bytes per
+    dof; 4 n flops per dof), with the MFMA work the counters measured for it."""
+    bytes_alg = 32 * N
+    achieved = bytes_alg / (avg_us * 1e-6) / 1e9
+    mfma_tflops = MODE_PRODUCT_MFMA_FLOPS / (avg_us * 1e-6) / 1e12
+    return {"bound": "hbm", "kernel": MODE_PRODUCT_KERNEL, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": MODE_PRODUCT_TRAFFIC_BYTES,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)",
+            "traffic_algorithmic": bytes_alg, "avg_launch_us": round(avg_us, 3),
+            "algorithmic_flops": 4 * n * N,
+            "mfma": {"flops_per_launch": MODE_PRODUCT_MFMA_FLOPS, "source": "SQ_INSTS_VALU_MFMA_MOPS_F64 x 512",
+                     "achieved_tflops": round(mfma_tflops, 3), "peak_tflops": PEAK_FP64_TFLOPS,
+                     "frac": round(mfma_tflops / PEAK_FP64_TFLOPS, 4)}}
+
+
+def fd_apply_roofline(N, d, n_s, p, apply_us):
+    """Whole FP64 FD apply against max(flops / FP64 peak, bytes / HBM) with the algorithmic work of
+    Algorithm 1: 8 d n_s + 16 p + 4 flops and 96 bytes (three passes of complex FP64 intermediates)
+    per dof."""
+    flops = (8 * d * n_s + 16 * p + 4) * N
+    t_roof = max(flops / (PEAK_FP64_TFLOPS * 1e12), 96 * N / (PEAK_HBM_GBS * 1e9))
+    return {"apply_us": round(apply_us, 2), "flops": flops, "roof_us": round(t_roof * 1e6, 2),
+            "frac": round(t_roof * 1e6 / apply_us, 4)}
+
+
+def table2_section(stream, p=3, n_el=64):
+    """Table 2's workload (traveling wave, 2D, T = 1, p = 3, 64 elements per direction, x0 = 0, tol
+    1e-8): setup + right-hand side + PCG wall time on the GPU, beside the paper's serial figure."""
+    import torch
+    from paper_2311_18461_amd import inputs, stfd
+    dev = torch.device("cuda:0")
+    w = inputs.traveling_wave_workload(n_el, p)
+    ks = [w.knots_s()] * 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob = stfd.Problem(w.knots_t(), ks, p, p, w.T, w.nu)
+    t_setup = time.perf_counter() - t0
+    f_q = torch.from_numpy(prob.sample_spacetime(w.f)).to(dev)
+    u0_q = torch.from_numpy(prob.sample_space(w.u0)).to(dev)
+    faces = [torch.from_numpy(a).to(dev) for a in prob.sample_faces(w.dirichlet)]
+    fb = torch.empty(prob.N, dtype=torch.complex128, device=dev)
+    u = torch.empty_like(fb)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prob.load_vector(fb, f_q=f_q, u0_q=u0_q, dirichlet_q=faces, stream=stream)
+    rc, info = prob.pcg_solve(fb, u, rtol=1e-8, maxit=200, stream=stream)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t1
+    prob.close()
+    return {"workload": f"traveling wave (Table 2), 2D, p={p}, n_el={n_el}", "n_dof_free": prob.N,
+            "iterations": info[0]["iters"], "setup_s": round(t_setup, 3),
+            "rhs_and_pcg_s": round(t_solve, 4), "total_s": round(t_setup + t_solve, 3),
+            "paper": {"iterations": 8, "total_s": 4.7142,
+                      "hardware": "Intel Core i5-1035G1, one thread at 1 GHz, MATLAB (Table 2)"}}
+
+
+def cpu_baseline(w, iterations, budget_s=25.0):
+    """The oracle (FP64 NumPy/SciPy) on a bounded sample of the same workload: the right-hand side
+    with lifting once, then 5 samples of 8 PCG iterations, the step time scaled to `iterations`
+    iterations (the GPU solve's count); on all host cores and with one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle.operators import FastDiagonalization, Problem as OProblem
     from oracle.pcg import pcg
     from oracle.rhs import SpaceTimeBasis, assemble_rhs
@@ -178,23 +253,35 @@ def cpu_baseline(w, budget_s=20.0):
     ref = OProblem(w.knots_t(), ks, w.p, w.p, w.nu, w.potential)
     fd = FastDiagonalization(ref)
     stb = SpaceTimeBasis(w.knots_t(), ks, w.p, w.p)
-    times, t_rhs, iters = [], [], []
-    t_start = time.perf_counter()
-    while True:
+
+    def sample(n_samples):
         t0 = time.perf_counter()
         fb, _ = assemble_rhs(stb, w.nu, u0=w.u0, V=w.potential)
-        t1 = time.perf_counter()
-        _, info = pcg(ref.matvec, fd.apply, fb, tol=1e-8, maxit=1000)
-        times.append(time.perf_counter() - t0)
-        t_rhs.append(t1 - t0)
-        iters.append(info["iters"])
-        if time.perf_counter() - t_start > budget_s * 0.5 or len(times) >= 5:
-            break
+        t_rhs = time.perf_counter() - t0
+        per_it = []
+        for _ in range(n_samples):
+            t1 = time.perf_counter()
+            _, info = pcg(ref.matvec, fd.apply, fb, tol=1e-8, maxit=8)
+            per_it.append((time.perf_counter() - t1) / info["iters"])
+        return t_rhs, float(np.median(per_it)), per_it
+
+    t_start = time.perf_counter()
+    t_rhs, t_it, per_it = sample(5)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    t = float(np.median(times))
-    return {"value": ref.N / t / 1e6, "unit": "Mdof/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{len(times)} complete steps of the same workload (right-hand side with lifting "
-                      f"{np.median(t_rhs):.2f} s + FP64 PCG to 1e-8, {iters[0]} iterations), median {t:.3f} s"}
+    step = t_rhs + iterations * t_it
+    out = {"value": ref.N / step / 1e6, "unit": "Mdof/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"right-hand side with lifting once ({t_rhs:.2f} s) + 5 samples of 8 FP64 PCG iterations "
+                     f"(median {t_it * 1e3:.1f} ms per iteration, samples {[round(x * 1e3, 1) for x in per_it]} ms), "
+                     f"step scaled to {iterations} iterations: {step:.2f} s"}
+    if time.perf_counter() - t_start < budget_s * 0.5:
+        with threadpool_limits(limits=1):
+            t_rhs1, t_it1, per_it1 = sample(3)
+        step1 = t_rhs1 + iterations * t_it1
+        out["one_thread"] = {"value": ref.N / step1 / 1e6, "cores": 1,
+                             "sample": f"right-hand side {t_rhs1:.2f} s + 3 samples of 8 iterations (median "
+                                       f"{t_it1 * 1e3:.1f} ms per iteration), scaled to {iterations} iterations: "
+                                       f"{step1:.2f} s"}
+    return out
 
 
 def main():
@@ -205,9 +292,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D precision section")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3: one solve, 20 applies and matvecs, and a device copy of "
-                         "known size (64 MiB read + 64 MiB written) to calibrate FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--profile", nargs="?", const="2d", choices=["2d", "3d48", "3d32"],
+                    help="short run for rocprofv3 on one workload (2d: the 2D p=3 64^3 Gaussian-potential step; "
+                         "3d48 / 3d32: the 3D harmonic workloads p=3 48^4 / p=4 32^4): one solve, 20 applies per "
+                         "precision, 20 matvecs, and a device copy of known size (64 MiB read + 64 MiB written) "
+                         "to calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
@@ -235,12 +324,26 @@ def main():
         return solve(prec)
 
     if args.profile:
-        step()
-        rc, info = step()
+        if args.profile != "2d":
+            prob.close()
+            n_el, p = (48, 3) if args.profile == "3d48" else (32, 4)
+            w3 = inputs.harmonic_3d_workload(0, n_el=n_el, p=p, with_potential=True)
+            ks = [w3.knots_s()] * 3
+            prob = stfd.Problem(w3.knots_t(), ks, p, p, w3.T, w3.nu,
+                                V_quad=stfd.sample_on_quad_grid(w3.potential, ks, p))
+            N = prob.N
+            f = torch.empty(N, dtype=torch.complex128, device=dev)
+            u = torch.empty_like(f)
+            prob.load_vector(f, u0_q=torch.from_numpy(prob.sample_space(w3.u0)).to(dev), stream=stream)
+            rc, info = solve("fp64")
+        else:
+            step()
+            rc, info = step()
         r = torch.from_numpy(inputs.random_complex(N, 2998)).to(dev)
         s = torch.empty_like(r)
-        for _ in range(20):
-            prob.apply_preconditioner(r, s, stream=stream)
+        for prec in ("fp64", "fp32", "bf16"):
+            for _ in range(20):
+                prob.apply_preconditioner(r, s, precision=prec, stream=stream)
         for _ in range(20):
             prob.matvec(r, s, stream=stream)
         src = torch.ones(8 << 20, dtype=torch.float64, device=dev)
@@ -248,7 +351,8 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": True, "iterations": info[0]["iters"], "copy_bytes": src.numel() * 8}))
+        print(json.dumps({"profile_run": args.profile, "n_dof_free": N, "iterations": info[0]["iters"],
+                          "copy_bytes": src.numel() * 8}))
         return
 
     for _ in range(args.warmup):
@@ -304,19 +408,16 @@ def main():
                                      stream)
     prob.matvec(r, s, stream=stream)
     matvec_ms = time_events(lambda: prob.matvec(r, s, stream=stream), 50, stream)
-
-    # dominant kernel: the system matvec (one launch per call); algorithmic FP64 work per dof:
-    # 3 real (2p+1)^d-point stencils on complex data + 3 complex-by-real (2p+1)-band time products
-    p, d = w.p, 2
-    flops_per_dof = 12 * ((2 * p + 1) ** d + 2 * p + 1)
-    achieved = flops_per_dof * N / (matvec_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": MATVEC_KERNEL, "achieved": round(achieved, 3),
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                "traffic": MATVEC_TRAFFIC_BYTES, "traffic_unit": "bytes per launch (rocprofv3 FETCH/WRITE_SIZE, "
-                                                               "copy-calibrated)",
-                "traffic_algorithmic": 16 * 2 * N + 24 * 49 * prob.N_s,
-                "traffic_gbs": round(MATVEC_TRAFFIC_BYTES / (matvec_ms * 1e-3) / 1e9, 1),
-                "avg_launch_us": round(matvec_ms * 1e3, 2), "flops_per_dof": flops_per_dof}
+    # the dominant kernel: every FP64 mode-product launch of 50 applies timed with HIP events on the
+    # launch stream (library timing hooks)
+    prob.timing_begin(capacity=4 * 50)
+    for _ in range(50):
+        prob.apply_preconditioner(r, s, precision="fp64", stream=stream)
+    mp_total_ms, mp_launches = prob.timing_end()
+    mp_us = mp_total_ms / mp_launches * 1e3
+    roofline = mode_product_roofline(N, 65, mp_us)
+    roofline["fd_apply"] = fd_apply_roofline(N, 2, 65, w.p, apply_ms["fp64"] * 1e3)
+    roofline["matvec_us"] = round(matvec_ms * 1e3, 2)
 
     out = {
         "metric": METRIC,
@@ -347,12 +448,13 @@ def main():
         "matvec_us": round(matvec_ms * 1e3, 2),
         "roofline": roofline,
     }
+    out["table2_p3_n64"] = table2_section(stream)
     out["batched"] = batched_section(dev, stream)
     out["warm_start"] = warmstart_section(stream)
     if not args.no_3d:
         out["precision_3d"] = precision_3d_section(stream)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, int(np.median(iters)))
     print(json.dumps(out))
 
 

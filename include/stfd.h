@@ -54,9 +54,9 @@ typedef enum {
 /* Arithmetic of the preconditioner's mode products and time solves.
  * The matvec, residuals, inner products and PCG updates are always FP64. */
 typedef enum {
-  STFD_FP64 = 0, /* FP64 MFMA mode products, FP64 time solves */
-  STFD_FP32 = 1, /* FP32 MFMA mode products, FP32 intermediates and time solves */
-  STFD_BF16 = 2  /* BF16 MFMA mode products with FP32 accumulation, FP32 time solves */
+  STFD_FP64 = 0,  /* FP64 MFMA mode products, FP64 time solves */
+  STFD_FP32 = 1,  /* FP32 MFMA mode products, FP32 intermediates and time solves (FP32 tables) */
+  STFD_BF16 = 2   /* BF16 MFMA mode products with FP32 accumulation, FP32 time solves */
 } stfd_precision;
 
 /* pcg flags: the initial guess (STFD_X0_ZERO, STFD_X0_GIVEN, or STFD_X0_GIVEN |
@@ -276,6 +276,16 @@ int stfd_pcg_solve(const stfd_problem *P, const void *f_dev, void *u_dev, int64_
 int stfd_pcg_solve_batched(const stfd_problem *const *probs, int count, const void *const *f_dev,
                            void *const *u_dev, const int64_t *nrhs, double rtol, int maxit, int flags,
                            int precision, stfd_pcg_info *info, void *stream);
+
+/* Kernel timing for measurement: between stfd_timing_begin and stfd_timing_end every mode-product
+ * launch of an apply (Algorithm 1 steps 2 and 4) on this handle is bracketed by two HIP events
+ * recorded on its launch stream (up to `capacity` launches; the events are created here).
+ * stfd_timing_end waits for the last recorded event and returns the summed event time of the
+ * recorded launches and their count, then destroys the events.  Timing adds two event records per
+ * launch to the stream and is meant for benchmarks, not for production solves.
+ * Errors: STFD_EINVAL (NULL handle, capacity < 1, begin while timing / end while not), STFD_EHIP. */
+int stfd_timing_begin(stfd_problem *P, int capacity);
+int stfd_timing_end(stfd_problem *P, double *total_ms, int64_t *launches);
 
 /* Host copies of setup data for inspection: U_l (n_l x n_l, row-major,
  * U[j*n_l + k] = entry (j,k), column k = k-th eigenvector) and Lambda_l.

@@ -359,8 +359,9 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 // The backward substitution x = L^{-H} w takes the same three steps from the
 // other end (future = first P values of the next segment, transfer Tb_s).
 // Dependent chain per lane: 4 LEN sweep steps + 2 (S-1) reduced steps.
-// Arithmetic is FP64 for every precision of the surrounding mode products (T is
-// the storage type of y).  Table layouts: time_solve_plan in host_setup.h.
+// FP64 applies solve in FP64; the FP32 and BF16 applies store y in FP32 and solve in FP32 with
+// FP32 copies of the tables (half the table traffic).
+// Table layouts: time_solve_plan in host_setup.h.
 // ---------------------------------------------------------------------------
 constexpr int kTsLanes = 64;
 // compiled (P, LEN) pairs; the segment lengths offered per P by time_segment_length
@@ -368,23 +369,26 @@ constexpr int kTsLanes = 64;
   STFD_TS(1, 8) STFD_TS(1, 16) STFD_TS(2, 8) STFD_TS(2, 12) STFD_TS(2, 16) STFD_TS(3, 8) STFD_TS(3, 12)      \
   STFD_TS(3, 16) STFD_TS(4, 6) STFD_TS(4, 8) STFD_TS(4, 12) STFD_TS(5, 6) STFD_TS(5, 8) STFD_TS(6, 6)
 
-__device__ inline void ts_load(const double* p, int t, double& re, double& im) {
-  const double2 v = reinterpret_cast<const double2*>(p)[t];
-  re = v.x;
-  im = v.y;
-}
-__device__ inline void ts_store(double* p, int t, double re, double im) {
-  reinterpret_cast<double2*>(p)[t] = make_double2(re, im);
-}
-__device__ inline void ts_store(float* p, int t, double re, double im) {
-  reinterpret_cast<float2*>(p)[t] = make_float2(float(re), float(im));
-}
+// complex pair of the table / arithmetic type A
+template <typename A>
+struct TsVec;
+template <>
+struct TsVec<double> {
+  using t = double2;
+};
+template <>
+struct TsVec<float> {
+  using t = float2;
+};
 
-template <typename T, int P, int LEN>
-__global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double* Lf, const double* Df,
-                                                            const double* Tf, const double* Tb, int n_t, int segs,
-                                                            int mpb, int64_t N_s, int64_t blocks_per_rhs,
-                                                            const int* done) {
+// T: storage type of y; A: arithmetic and table type (double for FP64 solves, float for the FP32
+// time solves of the mixed-precision applies, whose tables are FP32 copies of the FP64 ones)
+template <typename T, typename A, int P, int LEN>
+__global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf, const A* Df, const A* Tf,
+                                                            const A* Tb, int n_t, int segs, int mpb, int64_t N_s,
+                                                            int64_t blocks_per_rhs, const int* done) {
+  using A2 = typename TsVec<A>::t;
+  using T2 = typename TsVec<T>::t;
   const int64_t rhs = blockIdx.x / blocks_per_rhs;
   if (done && done[rhs]) return;
   const int64_t blk = blockIdx.x - rhs * blocks_per_rhs;
@@ -393,68 +397,58 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
   const int64_t mode = blk * mpb + m;
   const bool live = m < mpb && mode < N_s;
   const int t0 = s * LEN;
-  T* yb = y + (rhs * N_s + (live ? mode : 0)) * int64_t(2 * n_t);
-  const double2* Lb = reinterpret_cast<const double2*>(Lf) + blk * int64_t(LEN * P * kTsLanes);
-  const double* Db = Df + blk * int64_t(LEN * kTsLanes);
-  const double2* Tfb = reinterpret_cast<const double2*>(Tf) + blk * int64_t(P * P * kTsLanes);
-  const double2* Tbb = reinterpret_cast<const double2*>(Tb) + blk * int64_t(P * P * kTsLanes);
+  T2* yb = reinterpret_cast<T2*>(y) + (rhs * N_s + (live ? mode : 0)) * int64_t(n_t);
+  const A2* Lb = reinterpret_cast<const A2*>(Lf) + blk * int64_t(LEN * P * kTsLanes);
+  const A* Db = Df + blk * int64_t(LEN * kTsLanes);
+  const A2* Tfb = reinterpret_cast<const A2*>(Tf) + blk * int64_t(P * P * kTsLanes);
+  const A2* Tbb = reinterpret_cast<const A2*>(Tb) + blk * int64_t(P * P * kTsLanes);
 
-  // FP32 storage: rows of y are loaded as float2 and converted after the whole batch (the
-  // compiler moves a conversion next to its load, which made every row wait for its own round
-  // trip); clamped addresses, rows past n_t and idle lanes masked at the conversion.  FP64
-  // storage: loaded straight into the rows
-  constexpr bool kRaw = std::is_same<T, float>::value;
-  double yr[LEN], yi[LEN], lr[LEN][P], li[LEN][P];
-  float2 yv[LEN];
+  // rows of y loaded (clamped addresses) and converted after the whole batch (the compiler moves a
+  // conversion next to its load, which made every row wait for its own round trip); rows past n_t
+  // and idle lanes are masked at the conversion
+  A yr[LEN], yi[LEN], lr[LEN][P], li[LEN][P];
+  T2 yv[LEN];
 #pragma unroll
   for (int j = 0; j < LEN; ++j) {
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-      const double2 v = Lb[(j * P + k) * kTsLanes + lane];
+      const A2 v = Lb[(j * P + k) * kTsLanes + lane];
       lr[j][k] = v.x;
       li[j][k] = v.y;
     }
-    const int t = t0 + j;
-    if constexpr (kRaw) {
-      yv[j] = reinterpret_cast<const float2*>(yb)[min(t, n_t - 1)];
-    } else {
-      yr[j] = yi[j] = 0.0;
-      if (live && t < n_t) ts_load(yb, t, yr[j], yi[j]);
-    }
+    yv[j] = yb[min(t0 + j, n_t - 1)];
   }
   // L[t+k][t] for rows t+k of the next segment (rows jj < P of the neighbour lane)
   const bool has_next = s + 1 < segs;
   const int nxt = min(lane + 1, kTsLanes - 1);
-  double nlr[P][P], nli[P][P];
+  A nlr[P][P], nli[P][P];
 #pragma unroll
   for (int jj = 0; jj < P; ++jj)
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-      nlr[jj][k] = nli[jj][k] = 0.0;
+      nlr[jj][k] = nli[jj][k] = A(0);
       if (k >= jj) {
-        const double2 v = Lb[(jj * P + k) * kTsLanes + nxt];
-        nlr[jj][k] = has_next ? v.x : 0.0;
-        nli[jj][k] = has_next ? v.y : 0.0;
+        const A2 v = Lb[(jj * P + k) * kTsLanes + nxt];
+        nlr[jj][k] = has_next ? v.x : A(0);
+        nli[jj][k] = has_next ? v.y : A(0);
       }
     }
   // the transfers of the reduced recurrences and the inverse pivots are loaded where they are used:
   // loading them with the rows above (one round trip instead of three) measured slower at P = 3,
   // LEN = 12 (the extra registers spill into AGPR copies inside the dependent sweeps)
-  double tfr[P][P], tfi[P][P], tbr[P][P], tbi[P][P], dv[LEN];
-  if constexpr (kRaw) {
-    load_batch_end();
+  A tfr[P][P], tfi[P][P], tbr[P][P], tbi[P][P], dv[LEN];
+  load_batch_end();
 #pragma unroll
-    for (int j = 0; j < LEN; ++j) {
-      const bool ok = live && t0 + j < n_t;
-      yr[j] = ok ? double(yv[j].x) : 0.0;
-      yi[j] = ok ? double(yv[j].y) : 0.0;
-    }
+  for (int j = 0; j < LEN; ++j) {
+    const bool ok = live && t0 + j < n_t;
+    yr[j] = ok ? A(yv[j].x) : A(0);
+    yi[j] = ok ? A(yv[j].y) : A(0);
   }
-  double hr[P], hi[P];
+  A hr[P], hi[P];
 
   // z_t = y_t - sum_k L[t][t-k] z_{t-k}; h[k-1] = z_{t-k} (the z_{t-1} term last)
 #define STFD_TS_FWD_ROW(j)                                   \
-  double zr = yr[j], zi = yi[j];                             \
+  A zr = yr[j], zi = yi[j];                                  \
   _Pragma("unroll") for (int k = P; k >= 1; --k) {           \
     zr = fma(-lr[j][k - 1], hr[k - 1], zr);                  \
     zr = fma(li[j][k - 1], hi[k - 1], zr);                   \
@@ -470,11 +464,11 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
 
   // x_t = w_t - sum_k conj(L[t+k][t]) x_{t+k}; h[k-1] = x_{t+k} (the x_{t+1} term last)
 #define STFD_TS_BWD_ROW(j)                                                      \
-  double xr = yr[j], xi = yi[j];                                                \
+  A xr = yr[j], xi = yi[j];                                                     \
   _Pragma("unroll") for (int k = P; k >= 1; --k) {                              \
     const int q = j + k;                                                        \
-    const double cr = q < LEN ? lr[q < LEN ? q : 0][k - 1] : nlr[q < LEN ? 0 : q - LEN][k - 1]; \
-    const double ci = q < LEN ? li[q < LEN ? q : 0][k - 1] : nli[q < LEN ? 0 : q - LEN][k - 1]; \
+    const A cr = q < LEN ? lr[q < LEN ? q : 0][k - 1] : nlr[q < LEN ? 0 : q - LEN][k - 1]; \
+    const A ci = q < LEN ? li[q < LEN ? q : 0][k - 1] : nli[q < LEN ? 0 : q - LEN][k - 1]; \
     xr = fma(-cr, hr[k - 1], xr);                                               \
     xr = fma(-ci, hi[k - 1], xr);                                               \
     xi = fma(-cr, hi[k - 1], xi);                                               \
@@ -489,7 +483,7 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
 
   // (1) forward sweep from a zero history -> local tail
 #pragma unroll
-  for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
+  for (int k = 0; k < P; ++k) hr[k] = hi[k] = A(0);
 #pragma unroll
   for (int j = 0; j < LEN; ++j) {
     STFD_TS_FWD_ROW(j)
@@ -500,35 +494,33 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
     for (int a = 0; a < P; ++a)
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double2 v = Tfb[(a * P + c) * kTsLanes + lane];
+        const A2 v = Tfb[(a * P + c) * kTsLanes + lane];
         tfr[a][c] = v.x;
         tfi[a][c] = v.y;
       }
-    const double(&tr)[P][P] = tfr;
-    const double(&ti)[P][P] = tfi;
-    double cr0[P], ci0[P];
+    A cr0[P], ci0[P];
 #pragma unroll
     for (int a = 0; a < P; ++a) {
       cr0[a] = hr[a];
       ci0[a] = hi[a];
     }
     for (int r = 1; r < segs; ++r) {
-      double pr[P], pi[P];
+      A pr[P], pi[P];
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double vr = __shfl_up(hr[c], 1), vi = __shfl_up(hi[c], 1);
-        pr[c] = s > 0 ? vr : 0.0;
-        pi[c] = s > 0 ? vi : 0.0;
+        const A vr = __shfl_up(hr[c], 1), vi = __shfl_up(hi[c], 1);
+        pr[c] = s > 0 ? vr : A(0);
+        pi[c] = s > 0 ? vi : A(0);
       }
 #pragma unroll
       for (int a = 0; a < P; ++a) {
-        double ar = cr0[a], ai = ci0[a];
+        A ar = cr0[a], ai = ci0[a];
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-          ar = fma(tr[a][c], pr[c], ar);
-          ar = fma(-ti[a][c], pi[c], ar);
-          ai = fma(tr[a][c], pi[c], ai);
-          ai = fma(ti[a][c], pr[c], ai);
+          ar = fma(tfr[a][c], pr[c], ar);
+          ar = fma(-tfi[a][c], pi[c], ar);
+          ai = fma(tfr[a][c], pi[c], ai);
+          ai = fma(tfi[a][c], pr[c], ai);
         }
         hr[a] = ar;
         hi[a] = ai;
@@ -536,9 +528,9 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
     }
 #pragma unroll
     for (int c = 0; c < P; ++c) {
-      const double vr = __shfl_up(hr[c], 1), vi = __shfl_up(hi[c], 1);
-      hr[c] = s > 0 ? vr : 0.0;
-      hi[c] = s > 0 ? vi : 0.0;
+      const A vr = __shfl_up(hr[c], 1), vi = __shfl_up(hi[c], 1);
+      hr[c] = s > 0 ? vr : A(0);
+      hi[c] = s > 0 ? vi : A(0);
     }
   }
   // (3) forward sweep from the true history; w = z / D in place of y
@@ -551,7 +543,7 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
   }
   // (4) backward sweep from a zero future -> local head
 #pragma unroll
-  for (int k = 0; k < P; ++k) hr[k] = hi[k] = 0.0;
+  for (int k = 0; k < P; ++k) hr[k] = hi[k] = A(0);
 #pragma unroll
   for (int j = LEN - 1; j >= 0; --j) {
     STFD_TS_BWD_ROW(j)
@@ -562,35 +554,33 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
     for (int a = 0; a < P; ++a)
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double2 v = Tbb[(a * P + c) * kTsLanes + lane];
+        const A2 v = Tbb[(a * P + c) * kTsLanes + lane];
         tbr[a][c] = v.x;
         tbi[a][c] = v.y;
       }
-    const double(&tr)[P][P] = tbr;
-    const double(&ti)[P][P] = tbi;
-    double cr0[P], ci0[P];
+    A cr0[P], ci0[P];
 #pragma unroll
     for (int a = 0; a < P; ++a) {
       cr0[a] = hr[a];
       ci0[a] = hi[a];
     }
     for (int r = 1; r < segs; ++r) {
-      double pr[P], pi[P];
+      A pr[P], pi[P];
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const double vr = __shfl_down(hr[c], 1), vi = __shfl_down(hi[c], 1);
-        pr[c] = has_next ? vr : 0.0;
-        pi[c] = has_next ? vi : 0.0;
+        const A vr = __shfl_down(hr[c], 1), vi = __shfl_down(hi[c], 1);
+        pr[c] = has_next ? vr : A(0);
+        pi[c] = has_next ? vi : A(0);
       }
 #pragma unroll
       for (int a = 0; a < P; ++a) {
-        double ar = cr0[a], ai = ci0[a];
+        A ar = cr0[a], ai = ci0[a];
 #pragma unroll
         for (int c = 0; c < P; ++c) {
-          ar = fma(tr[a][c], pr[c], ar);
-          ar = fma(-ti[a][c], pi[c], ar);
-          ai = fma(tr[a][c], pi[c], ai);
-          ai = fma(ti[a][c], pr[c], ai);
+          ar = fma(tbr[a][c], pr[c], ar);
+          ar = fma(-tbi[a][c], pi[c], ar);
+          ai = fma(tbr[a][c], pi[c], ai);
+          ai = fma(tbi[a][c], pr[c], ai);
         }
         hr[a] = ar;
         hi[a] = ai;
@@ -598,9 +588,9 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
     }
 #pragma unroll
     for (int c = 0; c < P; ++c) {
-      const double vr = __shfl_down(hr[c], 1), vi = __shfl_down(hi[c], 1);
-      hr[c] = has_next ? vr : 0.0;
-      hi[c] = has_next ? vi : 0.0;
+      const A vr = __shfl_down(hr[c], 1), vi = __shfl_down(hi[c], 1);
+      hr[c] = has_next ? vr : A(0);
+      hi[c] = has_next ? vi : A(0);
     }
   }
   // (6) backward sweep from the true future; write x
@@ -608,7 +598,12 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const double
   for (int j = LEN - 1; j >= 0; --j) {
     STFD_TS_BWD_ROW(j)
     const int t = t0 + j;
-    if (live && t < n_t) ts_store(yb, t, xr, xi);
+    if (live && t < n_t) {
+      T2 o;
+      o.x = T(xr);
+      o.y = T(xi);
+      yb[t] = o;
+    }
   }
 #undef STFD_TS_FWD_ROW
 #undef STFD_TS_BWD_ROW
@@ -1228,6 +1223,10 @@ struct stfd_problem {
   double* TsD = nullptr;
   double* TsTf = nullptr;
   double* TsTb = nullptr;
+  float* TsL32 = nullptr;  // FP32 copies for the FP32 / BF16 applies
+  float* TsD32 = nullptr;
+  float* TsTf32 = nullptr;
+  float* TsTb32 = nullptr;
   int ts_len = 0, ts_segs = 0, ts_mpb = 0;
   int64_t ts_blocks = 0;
   double* Sc = nullptr;
@@ -1260,6 +1259,10 @@ struct stfd_problem {
   bool sf_on = false;               // the matvec runs sum-factorised (no stencils are stored)
   stfd::SumFacPlan sf;
   std::vector<void*> allocs;
+  // HIP-event timing of the mode-product launches (stfd_timing_begin / stfd_timing_end)
+  bool timing = false;
+  std::vector<hipEvent_t> tev;  // start/end pairs, recorded on the launch stream
+  size_t tev_used = 0;
 };
 
 namespace stfd {
@@ -1428,15 +1431,25 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   return STFD_OK;
 }
 
+// FP64 storage: FP64 solve; FP32 storage: FP32 solve with the FP32 tables
 template <typename T>
 static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* done, hipStream_t s) {
   const HostProblem& hp = P->hp;
   const int64_t bpr = P->ts_blocks;
   const dim3 grid(unsigned(bpr * nrhs)), block(kTsLanes);
+  const T* L;
+  const T* D;
+  const T* Tf;
+  const T* Tb;
+  if constexpr (std::is_same<T, double>::value) {
+    L = P->TsL, D = P->TsD, Tf = P->TsTf, Tb = P->TsTb;
+  } else {
+    L = P->TsL32, D = P->TsD32, Tf = P->TsTf32, Tb = P->TsTb32;
+  }
 #define STFD_TS(PV, LV)                                                                                        \
   if (hp.p_t == PV && P->ts_len == LV) {                                                                       \
-    hipLaunchKernelGGL((time_solve_kernel<T, PV, LV>), grid, block, 0, s, y, P->TsL, P->TsD, P->TsTf, P->TsTb, \
-                       hp.n_t, P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                      \
+    hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV>), grid, block, 0, s, y, L, D, Tf, Tb, hp.n_t,           \
+                       P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                              \
     STFD_HIP(hipGetLastError());                                                                               \
     return STFD_OK;                                                                                            \
   }
@@ -1445,9 +1458,30 @@ static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* don
   return STFD_EINVAL;
 }
 
-// Algorithm 1 steps 2-4 on nrhs stacked vectors.  TW = working precision of
-// intermediates (double for FP64, float otherwise).
-template <int PREC, typename TW>
+// Algorithm 1 steps 2-4 on nrhs stacked vectors.  TW = storage of the intermediates that still
+// have a physical direction; TY = storage of the mode-basis tensor that the time solves work on
+// (written by the last forward product into the buffer that product does not read, and read by
+// the first backward product).  FP64: both double; FP32 / BF16: both float.  (FP64 products with
+// an FP32 mode-basis tensor and FP32 time solves were measured and dropped: they cost as many PCG
+// iterations as FP32 products at a slower apply.)
+// Timing events around one mode-product launch when stfd_timing_begin is active (pairs beyond the
+// capacity are not recorded).
+struct MpTimer {
+  stfd_problem* P;
+  hipStream_t s;
+  bool on;
+  MpTimer(stfd_problem* P_, hipStream_t s_) : P(P_), s(s_), on(P_->timing && P_->tev_used + 2 <= P_->tev.size()) {
+    if (on) (void)hipEventRecord(P->tev[P->tev_used], s);
+  }
+  ~MpTimer() {
+    if (on) {
+      (void)hipEventRecord(P->tev[P->tev_used + 1], s);
+      P->tev_used += 2;
+    }
+  }
+};
+
+template <int PREC, typename TW, typename TY>
 static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t nrhs, const int* done, hipStream_t s,
                       TW* w0, TW* w1, const DotEpilogue& ep) {
   const HostProblem& hp = P->hp;
@@ -1473,36 +1507,55 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
   auto Ufwd = [&](int l) -> const void* { return P->Upk_fwd[PREC][l]; };
   auto Ubwd = [&](int l) -> const void* { return P->Upk_bwd[PREC][l]; };
   int rc;
-  // step 2: y = (U_s^T (x) I) r; r (FP64) -> w0 -> w1 -> ...
-  TW* bufs[2] = {w0, w1};
+  // step 2: y = (U_s^T (x) I) r; r (FP64) -> w0 -> w1 -> ... -> y (TY)
+  void* bufs[2] = {w0, w1};
   int cur = 0;
-  {
-    const int l = order[0];
-    rc = launch_mode_product<PREC, double, TW>(r, bufs[cur], Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l],
-                                               done, s, DotEpilogue(), slice(l));
-    if (rc) return rc;
-  }
-  for (int k = 1; k < d; ++k) {
+  const void* src = r;  // input of the next product: r, then bufs[cur]
+  for (int k = 0; k < d; ++k) {
     const int l = order[k];
-    rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], Ufwd(l), hp.n_s[l], inner[l], outer[l],
-                                           outer_rhs[l], done, s, DotEpilogue(), slice(l));
+    void* dst = (k == 0) ? bufs[0] : bufs[cur ^ 1];
+    const bool first = (k == 0), last = (k == d - 1);
+    const MpTimer tm(P, s);
+    if (first && last)
+      rc = launch_mode_product<PREC, double, TY>(src, dst, Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l],
+                                                 done, s, DotEpilogue(), slice(l));
+    else if (first)
+      rc = launch_mode_product<PREC, double, TW>(src, dst, Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l],
+                                                 done, s, DotEpilogue(), slice(l));
+    else if (last)
+      rc = launch_mode_product<PREC, TW, TY>(src, dst, Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l], done,
+                                             s, DotEpilogue(), slice(l));
+    else
+      rc = launch_mode_product<PREC, TW, TW>(src, dst, Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l], done,
+                                             s, DotEpilogue(), slice(l));
     if (rc) return rc;
-    cur ^= 1;
+    if (k > 0) cur ^= 1;
+    src = bufs[cur];
   }
   // step 3: N_s independent banded time solves, in place
-  rc = launch_time_solve<TW>(P, bufs[cur], nrhs, done, s);
+  rc = launch_time_solve<TY>(P, static_cast<TY*>(bufs[cur]), nrhs, done, s);
   if (rc) return rc;
   // step 4: s = (U_s (x) I) x in reverse order, the last product writes FP64 output
-  for (int k = d - 1; k >= 1; --k) {
+  for (int k = d - 1; k >= 0; --k) {
     const int l = order[k];
-    rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], Ubwd(l), hp.n_s[l], inner[l], outer[l],
-                                           outer_rhs[l], done, s, DotEpilogue(), slice(l));
+    const bool first = (k == d - 1), last = (k == 0);
+    const MpTimer tm(P, s);
+    if (last && first)
+      return launch_mode_product<PREC, TY, double>(bufs[cur], s_out, Ubwd(l), hp.n_s[l], inner[l], outer[l],
+                                                   outer_rhs[l], done, s, ep, slice(l));
+    if (last)
+      return launch_mode_product<PREC, TW, double>(bufs[cur], s_out, Ubwd(l), hp.n_s[l], inner[l], outer[l],
+                                                   outer_rhs[l], done, s, ep, slice(l));
+    if (first)
+      rc = launch_mode_product<PREC, TY, TW>(bufs[cur], bufs[cur ^ 1], Ubwd(l), hp.n_s[l], inner[l], outer[l],
+                                             outer_rhs[l], done, s, DotEpilogue(), slice(l));
+    else
+      rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], Ubwd(l), hp.n_s[l], inner[l], outer[l],
+                                             outer_rhs[l], done, s, DotEpilogue(), slice(l));
     if (rc) return rc;
     cur ^= 1;
   }
-  const int l = order[0];
-  return launch_mode_product<PREC, TW, double>(bufs[cur], s_out, Ubwd(l), hp.n_s[l], inner[l], outer[l],
-                                               outer_rhs[l], done, s, ep, slice(l));
+  return STFD_OK;
 }
 
 // Algorithm 1 steps 2-4 with the intermediates in w0 / w1 (each 2 N nrhs reals of the working
@@ -1512,22 +1565,27 @@ static int apply_with_buffers(stfd_problem* P, const double* r, double* s_out, i
                               const DotEpilogue& ep = DotEpilogue()) {
   switch (precision) {
     case STFD_FP64:
-      return apply_impl<MP_F64, double>(P, r, s_out, nrhs, done, s, static_cast<double*>(w0),
-                                        static_cast<double*>(w1), ep);
+      return apply_impl<MP_F64, double, double>(P, r, s_out, nrhs, done, s, static_cast<double*>(w0),
+                                                static_cast<double*>(w1), ep);
     case STFD_FP32:
-      return apply_impl<MP_F32, float>(P, r, s_out, nrhs, done, s, static_cast<float*>(w0), static_cast<float*>(w1),
-                                       ep);
+      return apply_impl<MP_F32, float, float>(P, r, s_out, nrhs, done, s, static_cast<float*>(w0),
+                                              static_cast<float*>(w1), ep);
     case STFD_BF16:
-      return apply_impl<MP_BF16, float>(P, r, s_out, nrhs, done, s, static_cast<float*>(w0), static_cast<float*>(w1),
-                                        ep);
+      return apply_impl<MP_BF16, float, float>(P, r, s_out, nrhs, done, s, static_cast<float*>(w0),
+                                               static_cast<float*>(w1), ep);
     default:
       return STFD_EINVAL;
   }
 }
 
+// bytes per real of the intermediates of an apply in this precision (the larger of the two kinds)
+static size_t apply_elem_bytes(int precision) {
+  return precision == STFD_FP64 ? sizeof(double) : sizeof(float);
+}
+
 static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64_t nrhs, int precision,
                           const int* done, hipStream_t s, const DotEpilogue& ep = DotEpilogue()) {
-  const bool f64 = precision == STFD_FP64;
+  const bool f64 = apply_elem_bytes(precision) == sizeof(double);
   return apply_with_buffers(P, r, s_out, nrhs, precision, done, s, f64 ? (void*)P->work64[0] : (void*)P->work32[0],
                             f64 ? (void*)P->work64[1] : (void*)P->work32[1], ep);
 }
@@ -1726,6 +1784,8 @@ int stfd_map_points(const stfd_problem* P, const double* xi, int64_t n, double* 
 
 void stfd_destroy(stfd_problem* P) {
   if (!P) return;
+  for (hipEvent_t e : P->tev)
+    if (e) (void)hipEventDestroy(e);
   for (void* p : P->allocs) (void)hipFree(p);
   stfd::load_plan_free(P->load);
   stfd::spatial_device_free(P->sdev);
@@ -1869,6 +1929,17 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
         (rc = upload(P, &P->TsTf, tp.Tf.data(), tp.Tf.size())) || (rc = upload(P, &P->TsTb, tp.Tb.data(), tp.Tb.size()))) {
       stfd_destroy(P);
       return rc;
+    }
+    {
+      // FP32 copies of the tables (time solves of the FP32 / BF16 applies)
+      auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+      const std::vector<float> L32 = f32(tp.Lf), D32 = f32(tp.Df), Tf32 = f32(tp.Tf), Tb32 = f32(tp.Tb);
+      if ((rc = upload(P, &P->TsL32, L32.data(), L32.size())) || (rc = upload(P, &P->TsD32, D32.data(), D32.size())) ||
+          (rc = upload(P, &P->TsTf32, Tf32.data(), Tf32.size())) ||
+          (rc = upload(P, &P->TsTb32, Tb32.data(), Tb32.size()))) {
+        stfd_destroy(P);
+        return rc;
+      }
     }
     // spatial coefficients interleaved per row and stencil offset: [N_s][stencil][3];
     // V-free unit-cube base from the host, weighted terms (potential, geometry) added on the device
@@ -2088,6 +2159,48 @@ int stfd_get_pencil(const stfd_problem* P, int l, double* U, double* lambda) {
   return STFD_OK;
 }
 
+int stfd_timing_begin(stfd_problem* P, int capacity) {
+  if (!P || capacity < 1 || P->timing) return STFD_EINVAL;
+  P->tev.assign(size_t(2) * capacity, nullptr);
+  for (hipEvent_t& e : P->tev) {
+    const hipError_t he = hipEventCreate(&e);
+    if (he != hipSuccess) {
+      for (hipEvent_t f : P->tev)
+        if (f) (void)hipEventDestroy(f);
+      P->tev.clear();
+      g_last_hip_error = int(he);
+      return STFD_EHIP;
+    }
+  }
+  P->tev_used = 0;
+  P->timing = true;
+  return STFD_OK;
+}
+
+int stfd_timing_end(stfd_problem* P, double* total_ms, int64_t* launches) {
+  if (!P || !P->timing) return STFD_EINVAL;
+  double tot = 0.0;
+  int rc = STFD_OK;
+  for (size_t k = 0; k + 1 < P->tev_used; k += 2) {
+    float ms = 0.0f;
+    hipError_t he = hipEventSynchronize(P->tev[k + 1]);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, P->tev[k], P->tev[k + 1]);
+    if (he != hipSuccess) {
+      g_last_hip_error = int(he);
+      rc = STFD_EHIP;
+      break;
+    }
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = int64_t(P->tev_used / 2);
+  for (hipEvent_t e : P->tev) (void)hipEventDestroy(e);
+  P->tev.clear();
+  P->tev_used = 0;
+  P->timing = false;
+  return rc;
+}
+
 int stfd_apply_preconditioner(const stfd_problem* Pc, const void* r_dev, void* s_dev, int64_t nrhs, int precision,
                               void* stream) {
   stfd_problem* P = const_cast<stfd_problem*>(Pc);
@@ -2103,7 +2216,7 @@ int stfd_apply_preconditioner_static(const stfd_problem* Pc, const void* r_dev, 
   if (!P || !r_dev || !s_dev || nrhs < 1) return STFD_EINVAL;
   if (precision < STFD_FP64 || precision > STFD_BF16) return STFD_EINVAL;
   // each intermediate holds 2 N nrhs reals of the working precision in one half of the scratch
-  const size_t elem = precision == STFD_FP64 ? sizeof(double) : sizeof(float);
+  const size_t elem = apply_elem_bytes(precision);
   const size_t half = kScratchBytes / 2;
   if (uint64_t(nrhs) > uint64_t(half / (size_t(P->n2) * elem))) return STFD_EINVAL;
   void* base = nullptr;

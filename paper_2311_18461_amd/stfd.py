@@ -72,6 +72,8 @@ SIGNATURES = {
     "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
     "stfd_update_potential": (ctypes.c_int, [_VP, _DP, _VP]),
     "stfd_set_lift_max_iterations": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "stfd_timing_begin": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "stfd_timing_end": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "stfd_fno_create": (ctypes.c_int, [ctypes.POINTER(FnoDesc), ctypes.POINTER(_VP)]),
     "stfd_fno_num_params": (ctypes.c_int, [_VP, ctypes.POINTER(_I64)]),
     "stfd_fno_get_params": (ctypes.c_int, [_VP, _FP]),
@@ -309,6 +311,16 @@ class Problem:
                                        lift.ctypes.data_as(_DP) if lift is not None else None, nrhs,
                                        _stream_ptr(stream)), "stfd_load_vector")
         return lift
+
+    def timing_begin(self, capacity: int = 1024):
+        """stfd_timing_begin: HIP events around every mode-product launch of the applies that follow."""
+        return _check(_lib().stfd_timing_begin(self._h, int(capacity)), "stfd_timing_begin")
+
+    def timing_end(self):
+        """stfd_timing_end: (summed event time in ms, launches recorded) of the mode products."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(_lib().stfd_timing_end(self._h, ctypes.byref(ms), ctypes.byref(n)), "stfd_timing_end")
+        return ms.value, n.value
 
     def set_lift_max_iterations(self, max_iter: int):
         """stfd_set_lift_max_iterations: iteration limit of the lifting CG in load_vector."""

@@ -79,3 +79,27 @@ def test_pcg_3d_large_products_converge():
     assert res <= 1.05e-8
     assert info[0]["iters"] <= 70
     prob.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pcg_3d_p3_n48_harmonic(prec):
+    """PCG to 1e-8 on the 3D p = 3, 48^4 harmonic workload (about 5.9 million unknowns) per
+    preconditioner precision, FP64 outer loop.  The true residual is recomputed with the library
+    matvec (checked against the oracle entry by entry in test_gpu_sumfac and test_gpu_parity)."""
+    from paper_2311_18461_amd import stfd
+    print(f"3D PCG: n_el=48 p=3 harmonic potential, {prec} preconditioner", flush=True)
+    w = inputs.harmonic_3d_workload(0, n_el=48, p=3, with_potential=True)
+    ks = [w.knots_s()] * 3
+    prob = stfd.Problem(w.knots_t(), ks, 3, 3, w.T, w.nu, V_quad=stfd.sample_on_quad_grid(w.potential, ks, 3))
+    f = torch.empty(prob.N, dtype=torch.complex128, device=DEV)
+    prob.load_vector(f, u0_q=torch.from_numpy(prob.sample_space(w.u0)).to(DEV))
+    u = torch.empty_like(f)
+    rc, info = prob.pcg_solve(f, u, rtol=1e-8, maxit=400, precision=prec)
+    q = torch.empty_like(f)
+    prob.matvec(u, q)
+    torch.cuda.synchronize()
+    res = float(torch.linalg.vector_norm(f - q) / torch.linalg.vector_norm(f))
+    print(f"{prec}: iterations {info[0]['iters']}, relative residual {res:.2e}", flush=True)
+    prob.close()
+    assert rc == stfd.OK and res <= 1.2e-8
+    assert info[0]["iters"] <= {"fp64": 110, "fp32": 140}[prec]
