@@ -197,11 +197,45 @@ class ComplexGaussian1D:
         s = self.beta ** 2 - 1j * self.gamma * t
         return self.alpha * self.beta / np.sqrt(s) * np.exp(-x * x / s)
 
+    def u0(self, x):
+        return self.u(0.0, x)
+
     def f(self, t, x):
         s = self.beta ** 2 - 1j * self.gamma * t
         g = self.gamma
         fac = -g / (2 * s) + g * x * x / s ** 2 - self.nu * (4 * x * x / s ** 2 - 2 / s)
         return fac * self.u(t, x)
+
+
+class HighModeSeries1D:
+    """Truncated high-mode series of Section 6.1 (second test, from Demkowicz et al.) on (0,1),
+    T = 2, homogeneous Dirichlet data and u(0) = 0: with e_k = sqrt(2) sin(k pi x) and
+    w_k = k pi (the Dirichlet eigenpairs of -d_xx),
+        f(t,x) = sum_{k<=M} (1/k) exp(i w_k^2 t) e_k(x),
+        u(t,x) = sum_{k<=M} (-i t / k) exp(i w_k^2 t) e_k(x),
+    and S u = f for S = i d_t - d_xx (nu = 1).  The paper states M = 625 (and once 652); 625 here."""
+
+    def __init__(self, M: int = 625, chunk: int = 64):
+        self.M, self.chunk = int(M), int(chunk)
+
+    def _series(self, t, x, coef):
+        t, x = np.broadcast_arrays(np.asarray(t, dtype=np.float64), np.asarray(x, dtype=np.float64))
+        out = np.zeros(t.shape, dtype=np.complex128)
+        for k0 in range(1, self.M + 1, self.chunk):
+            k = np.arange(k0, min(self.M, k0 + self.chunk - 1) + 1, dtype=np.float64)
+            kk = k.reshape((-1,) + (1,) * t.ndim)
+            w2 = (np.pi * kk) ** 2
+            out += np.sum(coef(kk, t) * np.exp(1j * w2 * t) * np.sqrt(2.0) * np.sin(np.pi * kk * x), axis=0)
+        return out
+
+    def u(self, t, x):
+        return self._series(t, x, lambda k, t: -1j * t / k)
+
+    def f(self, t, x):
+        return self._series(t, x, lambda k, t: 1.0 / k + 0.0 * t)
+
+    def u0(self, x):
+        return np.zeros(np.shape(x), dtype=np.complex128)
 
 
 # ----------------------------------------------------------------------------

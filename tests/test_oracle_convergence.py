@@ -11,7 +11,8 @@ import pytest
 from oracle.operators import FastDiagonalization, Problem
 from oracle.pcg import pcg
 from oracle.rhs import SpaceTimeBasis, assemble_rhs, errors, full_coefficients
-from paper_2311_18461_amd.inputs import GaussianSum, SineMode1D, uniform_open_knots
+from paper_2311_18461_amd.inputs import (ComplexGaussian1D, GaussianSum, HighModeSeries1D, SineMode1D,
+                                         uniform_open_knots)
 
 
 def _solve(p, n, nu, V=None, T=1.0):
@@ -41,3 +42,22 @@ def test_config1_sine_solution_accuracy():
     """1D, p = 2, 16 x 16 elements, u = sin(pi x) exp(-i pi^2 t), tol 1e-10."""
     l2, vn = _solve(2, 16, 1.0)
     assert l2 < 1e-2 and vn < 1.0
+
+
+@pytest.mark.parametrize("name", ["gaussian", "high_mode"])
+def test_section61_data_satisfy_the_equation(name):
+    """The Section 6.1 solutions and right-hand sides: f = S u = i u_t - u_xx, checked by fourth-order
+    central differences at random points (independent of the closed forms of f)."""
+    m = ComplexGaussian1D() if name == "gaussian" else HighModeSeries1D(M=8)
+    rng = np.random.default_rng(5)
+    t, x = rng.uniform(0.2, 1.8, 20), rng.uniform(0.1, 0.9, 20)
+    h = 1e-3 if name == "gaussian" else 1e-5
+    c1 = np.array([1.0, -8.0, 0.0, 8.0, -1.0]) / 12.0
+    c2 = np.array([-1.0, 16.0, -30.0, 16.0, -1.0]) / 12.0
+    k = np.arange(-2, 3)
+    ut = sum(c * m.u(t + kk * h, x) for c, kk in zip(c1, k)) / h
+    uxx = sum(c * m.u(t, x + kk * h) for c, kk in zip(c2, k)) / h ** 2
+    err = np.max(np.abs(1j * ut - uxx - m.f(t, x))) / np.max(np.abs(m.f(t, x)))
+    assert err < (1e-8 if name == "gaussian" else 1e-4), err
+    if name == "high_mode":
+        assert np.max(np.abs(m.u(0.0, x))) == 0.0 and np.max(np.abs(m.u(t, 0.0 * x))) < 1e-12
