@@ -428,7 +428,7 @@ int time_segment_length(int n_t, int p_t) {
   return best;
 }
 
-int time_solve_plan(const HostProblem& hp, int len, TimeSolvePlan& out) {
+int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePlan& out) {
   const int nt = hp.n_t, P = hp.p_t;
   if (len < P || len < 1) return -1;
   const int segs = (nt + len - 1) / len;
@@ -441,8 +441,8 @@ int time_solve_plan(const HostProblem& hp, int len, TimeSolvePlan& out) {
   out.blocks = nblk;
   out.Lf.assign(size_t(nblk) * len * P * 64 * 2, 0.0);
   out.Df.assign(size_t(nblk) * len * 64, 0.0);
-  out.Tf.assign(size_t(nblk) * P * P * 64 * 2, 0.0);
-  out.Tb.assign(size_t(nblk) * P * P * 64 * 2, 0.0);
+  out.Tf.assign(transfers ? size_t(nblk) * P * P * 64 * 2 : 0, 0.0);
+  out.Tb.assign(transfers ? size_t(nblk) * P * P * 64 * 2 : 0, 0.0);
   // L[t][t-k] of mode i (zero outside the band and for padded rows t >= n_t)
   auto Lv = [&](int64_t i, int t, int k) -> cplx {
     if (t >= nt || t - k < 0) return cplx(0.0, 0.0);
@@ -464,6 +464,7 @@ int time_solve_plan(const HostProblem& hp, int len, TimeSolvePlan& out) {
           out.Lf[o + 1] = v.imag();
         }
       }
+      if (!transfers) continue;
       // forward transfer: last P values z_{t0+len-1-a} of the homogeneous forward recurrence
       // over the segment, started from the history z_{t0-1-c} = delta(c, col)
       for (int col = 0; col < P; ++col) {

@@ -75,6 +75,7 @@ int time_factors(HostProblem& hp);
 //   Df[blk][j][lane]       = 1 / D[t]                        (0 on padded rows)
 //   Tf[blk][a][c][lane]    = response of z_{t0+len-1-a} to the history z_{t0-1-c}  (complex)
 //   Tb[blk][a][c][lane]    = response of x_{t0+a} to the future x_{t0+len+c}        (complex)
+// Tf and Tb are built only on request (small grids; large grids compute them in the solve).
 struct TimeSolvePlan {
   int len = 0, segs = 0, mpb = 0;
   int64_t blocks = 0;
@@ -83,7 +84,7 @@ struct TimeSolvePlan {
 // Segment length for n_t rows of half-bandwidth p_t among the compiled ones, 0 if none fits.
 int time_segment_length(int n_t, int p_t);
 // 0, or -1 if len does not fit (len < p_t or more than 64 segments).
-int time_solve_plan(const HostProblem& hp, int len, TimeSolvePlan& out);
+int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePlan& out);
 // out_stencil[I][s] += int cq D^{ders[l][0]} phi_I D^{ders[l][1]} phi_J (element Gauss rule, cq on
 // the spatial grid or nullptr for 1), for the Dirichlet-reduced spatial basis.
 void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2], double* out_stencil);

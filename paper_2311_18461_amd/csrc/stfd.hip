@@ -354,7 +354,9 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 //      tail;
 //  (2) reduced recurrence tail_s = tail~_s + Tf_s tail_{s-1} over the segments,
 //      S-1 rounds of neighbour-lane shuffles (Tf_s = P x P response of the
-//      segment's last P values to its history, from setup);
+//      segment's last P values to its history, computed by the lane from its rows
+//      of L: P homogeneous sweeps that do not depend on y, so they overlap the
+//      sweep of step 1 and nothing but L and 1/D is read per row);
 //  (3) sweep again from the true history tail_{s-1}; w = z / D.
 // The backward substitution x = L^{-H} w takes the same three steps from the
 // other end (future = first P values of the next segment, transfer Tb_s).
@@ -383,7 +385,10 @@ struct TsVec<float> {
 
 // T: storage type of y; A: arithmetic and table type (double for FP64 solves, float for the FP32
 // time solves of the mixed-precision applies, whose tables are FP32 copies of the FP64 ones)
-template <typename T, typename A, int P, int LEN>
+// FLY: compute the transfers in the solve (large grids: the kernel is bound by table traffic) or
+// load them from the tables Tf, Tb (small grids: at most one wave per SIMD, bound by the dependent
+// chain, which the P extra sweeps per transfer would lengthen).
+template <typename T, typename A, int P, int LEN, bool FLY>
 __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf, const A* Df, const A* Tf,
                                                             const A* Tb, int n_t, int segs, int mpb, int64_t N_s,
                                                             int64_t blocks_per_rhs, const int* done) {
@@ -400,6 +405,7 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
   T2* yb = reinterpret_cast<T2*>(y) + (rhs * N_s + (live ? mode : 0)) * int64_t(n_t);
   const A2* Lb = reinterpret_cast<const A2*>(Lf) + blk * int64_t(LEN * P * kTsLanes);
   const A* Db = Df + blk * int64_t(LEN * kTsLanes);
+  __shared__ A2 Tsh[P * P * kTsLanes];  // this lane's transfer matrix, [a][c][lane]
   const A2* Tfb = reinterpret_cast<const A2*>(Tf) + blk * int64_t(P * P * kTsLanes);
   const A2* Tbb = reinterpret_cast<const A2*>(Tb) + blk * int64_t(P * P * kTsLanes);
 
@@ -433,9 +439,8 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
         nli[jj][k] = has_next ? v.y : A(0);
       }
     }
-  // the transfers of the reduced recurrences and the inverse pivots are loaded where they are used:
-  // loading them with the rows above (one round trip instead of three) measured slower at P = 3,
-  // LEN = 12 (the extra registers spill into AGPR copies inside the dependent sweeps)
+  // the inverse pivots are loaded where they are used (with the rows above, the extra registers
+  // spilled into AGPR copies inside the dependent sweeps)
   A tfr[P][P], tfi[P][P], tbr[P][P], tbi[P][P], dv[LEN];
   load_batch_end();
 #pragma unroll
@@ -488,13 +493,50 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
   for (int j = 0; j < LEN; ++j) {
     STFD_TS_FWD_ROW(j)
   }
-  // (2) reduced forward recurrence over the segments, then history = true tail of segment s-1
+  // (2) reduced forward recurrence over the segments, then history = true tail of segment s-1.
+  // Transfer Tf[a][c]: response of z_{t0+LEN-1-a} to the history z_{t0-1-c} = 1 (the others 0),
+  // from P homogeneous sweeps over the segment's rows of L, one column at a time, parked in LDS
+  // (each lane reads back only its own entries) so that one sweep state is live at a time.
   {
+#pragma unroll 1
+    for (int c = 0; c < P && FLY; ++c) {
+      A gr[P], gi[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        gr[k] = k == c ? A(1) : A(0);
+        gi[k] = A(0);
+      }
+#pragma unroll
+      for (int j = 0; j < LEN; ++j) {
+        A zr = A(0), zi = A(0);
+#pragma unroll
+        for (int k = P; k >= 1; --k) {
+          zr = fma(-lr[j][k - 1], gr[k - 1], zr);
+          zr = fma(li[j][k - 1], gi[k - 1], zr);
+          zi = fma(-lr[j][k - 1], gi[k - 1], zi);
+          zi = fma(-li[j][k - 1], gr[k - 1], zi);
+        }
+#pragma unroll
+        for (int k = P - 1; k >= 1; --k) {
+          gr[k] = gr[k - 1];
+          gi[k] = gi[k - 1];
+        }
+        gr[0] = zr;
+        gi[0] = zi;
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        A2 v;
+        v.x = gr[a];
+        v.y = gi[a];
+        Tsh[(a * P + c) * kTsLanes + lane] = v;
+      }
+    }
 #pragma unroll
     for (int a = 0; a < P; ++a)
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const A2 v = Tfb[(a * P + c) * kTsLanes + lane];
+        const A2 v = FLY ? Tsh[(a * P + c) * kTsLanes + lane] : Tfb[(a * P + c) * kTsLanes + lane];
         tfr[a][c] = v.x;
         tfi[a][c] = v.y;
       }
@@ -548,13 +590,53 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
   for (int j = LEN - 1; j >= 0; --j) {
     STFD_TS_BWD_ROW(j)
   }
-  // (5) reduced backward recurrence, then future = true head of segment s+1
+  // (5) reduced backward recurrence, then future = true head of segment s+1.
+  // Transfer Tb[a][c]: response of x_{t0+a} to the future x_{t0+LEN+c} = 1 (the others 0), from P
+  // homogeneous backward sweeps (the rows of L past the segment come from the next lane), parked
+  // in LDS like Tf.
   {
+#pragma unroll 1
+    for (int c = 0; c < P && FLY; ++c) {
+      A gr[P], gi[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        gr[k] = k == c ? A(1) : A(0);
+        gi[k] = A(0);
+      }
+#pragma unroll
+      for (int j = LEN - 1; j >= 0; --j) {
+        A xr = A(0), xi = A(0);
+#pragma unroll
+        for (int k = P; k >= 1; --k) {
+          const int q = j + k;
+          const A cr = q < LEN ? lr[q < LEN ? q : 0][k - 1] : nlr[q < LEN ? 0 : q - LEN][k - 1];
+          const A ci = q < LEN ? li[q < LEN ? q : 0][k - 1] : nli[q < LEN ? 0 : q - LEN][k - 1];
+          xr = fma(-cr, gr[k - 1], xr);
+          xr = fma(-ci, gi[k - 1], xr);
+          xi = fma(-cr, gi[k - 1], xi);
+          xi = fma(ci, gr[k - 1], xi);
+        }
+#pragma unroll
+        for (int k = P - 1; k >= 1; --k) {
+          gr[k] = gr[k - 1];
+          gi[k] = gi[k - 1];
+        }
+        gr[0] = xr;
+        gi[0] = xi;
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        A2 v;
+        v.x = gr[a];
+        v.y = gi[a];
+        Tsh[(a * P + c) * kTsLanes + lane] = v;
+      }
+    }
 #pragma unroll
     for (int a = 0; a < P; ++a)
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const A2 v = Tbb[(a * P + c) * kTsLanes + lane];
+        const A2 v = FLY ? Tsh[(a * P + c) * kTsLanes + lane] : Tbb[(a * P + c) * kTsLanes + lane];
         tbr[a][c] = v.x;
         tbi[a][c] = v.y;
       }
@@ -1220,13 +1302,13 @@ struct stfd_problem {
   int64_t upk_slice[3] = {0, 0, 0};  // packed elements per x_1 slice (mapped domain), per precision
   // segmented time-solve tables (layout: TimeSolvePlan in host_setup.h)
   double* TsL = nullptr;
-  double* TsD = nullptr;
-  double* TsTf = nullptr;
+  double* TsTf = nullptr;  // segment transfers (small grids only, else null)
   double* TsTb = nullptr;
-  float* TsL32 = nullptr;  // FP32 copies for the FP32 / BF16 applies
-  float* TsD32 = nullptr;
+  double* TsD = nullptr;
+  float* TsL32 = nullptr;
   float* TsTf32 = nullptr;
-  float* TsTb32 = nullptr;
+  float* TsTb32 = nullptr;  // FP32 copies for the FP32 / BF16 applies
+  float* TsD32 = nullptr;
   int ts_len = 0, ts_segs = 0, ts_mpb = 0;
   int64_t ts_blocks = 0;
   double* Sc = nullptr;
@@ -1446,10 +1528,17 @@ static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* don
   } else {
     L = P->TsL32, D = P->TsD32, Tf = P->TsTf32, Tb = P->TsTb32;
   }
+  // transfer tables exist for small grids only (built at setup when one right-hand side's grid holds
+  // at most one wave per SIMD)
+  const bool fly = Tf == nullptr;
 #define STFD_TS(PV, LV)                                                                                        \
   if (hp.p_t == PV && P->ts_len == LV) {                                                                       \
-    hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV>), grid, block, 0, s, y, L, D, Tf, Tb, hp.n_t,           \
-                       P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                              \
+    if (fly)                                                                                                   \
+      hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV, true>), grid, block, 0, s, y, L, D, Tf, Tb, hp.n_t,   \
+                         P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                            \
+    else                                                                                                       \
+      hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV, false>), grid, block, 0, s, y, L, D, Tf, Tb, hp.n_t,  \
+                         P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                            \
     STFD_HIP(hipGetLastError());                                                                               \
     return STFD_OK;                                                                                            \
   }
@@ -1918,7 +2007,10 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   // segmented time-solve tables, time bands, spatial coefficients
   {
     TimeSolvePlan tp;
-    if (time_solve_plan(hp, P->ts_len, tp) != 0) {
+    // transfer tables only where one right-hand side's grid holds at most one wave per SIMD
+    const int mpb = 64 / ((hp.n_t + P->ts_len - 1) / P->ts_len);  // modes per block
+    const bool transfers = (hp.N_s + mpb - 1) / mpb <= 4 * int64_t(P->n_cus);
+    if (time_solve_plan(hp, P->ts_len, transfers, tp) != 0) {
       stfd_destroy(P);
       return STFD_EINVAL;
     }
@@ -1926,7 +2018,8 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     P->ts_mpb = tp.mpb;
     P->ts_blocks = tp.blocks;
     if ((rc = upload(P, &P->TsL, tp.Lf.data(), tp.Lf.size())) || (rc = upload(P, &P->TsD, tp.Df.data(), tp.Df.size())) ||
-        (rc = upload(P, &P->TsTf, tp.Tf.data(), tp.Tf.size())) || (rc = upload(P, &P->TsTb, tp.Tb.data(), tp.Tb.size()))) {
+        (transfers && ((rc = upload(P, &P->TsTf, tp.Tf.data(), tp.Tf.size())) ||
+                       (rc = upload(P, &P->TsTb, tp.Tb.data(), tp.Tb.size()))))) {
       stfd_destroy(P);
       return rc;
     }
@@ -1935,8 +2028,8 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
       const std::vector<float> L32 = f32(tp.Lf), D32 = f32(tp.Df), Tf32 = f32(tp.Tf), Tb32 = f32(tp.Tb);
       if ((rc = upload(P, &P->TsL32, L32.data(), L32.size())) || (rc = upload(P, &P->TsD32, D32.data(), D32.size())) ||
-          (rc = upload(P, &P->TsTf32, Tf32.data(), Tf32.size())) ||
-          (rc = upload(P, &P->TsTb32, Tb32.data(), Tb32.size()))) {
+          (transfers && ((rc = upload(P, &P->TsTf32, Tf32.data(), Tf32.size())) ||
+                         (rc = upload(P, &P->TsTb32, Tb32.data(), Tb32.size()))))) {
         stfd_destroy(P);
         return rc;
       }
