@@ -15,6 +15,8 @@ Module map (paper sections):
               fast-diagonalisation apply (Section 5, Algorithm 1)
   pcg       - preconditioned conjugate gradients (Section 5.3)
   rhs       - load vector and lifting of initial/boundary data (Section 2.2, 4.3)
+  ultraweak - ultraweak method: final-condition test space, right-hand side with the
+              initial data, solution u_h = S_V z_h (Section 4.4)
   norms     - L2(Q) and V-norm errors (Section 2.1)
 
 Every function states the passage it follows.  Functions without an

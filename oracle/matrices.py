@@ -42,14 +42,15 @@ def space_1d(knots, p: int, q: int | None = None) -> dict:
     return {k: v[s, s].copy() for k, v in full.items()}
 
 
-def time_1d(knots_t, p_t: int, q: int | None = None) -> dict:
-    """Reduced time matrices of eq. time_mat (Section 3.2: drop the first function, u(0) = 0).
+def time_1d(knots_t, p_t: int, q: int | None = None, final: bool = False) -> dict:
+    """Reduced time matrices of eq. time_mat (Section 3.2: drop the first function, u(0) = 0;
+    final=True: drop the last one, w(T) = 0, the test space of the ultraweak method of Section 4.4).
 
     M_t[i,j] = int b_i b_j, L_t[i,j] = int b_j' b_i', W_t[i,j] = i int b_j' b_i,
     and T3 = W_t + W_t^* (the time factor of the third Kronecker term).
     """
     full = gram_1d(knots_t, p_t, q)
-    s = slice(1, None)
+    s = slice(None, -1) if final else slice(1, None)
     M, L, G = full["M"][s, s], full["L"][s, s], full["G"][s, s]
     W = 1j * G
     return {"M": M.copy(), "L": L.copy(), "W": W, "T3": W + W.conj().T}

@@ -27,14 +27,16 @@ class Problem:
     """
 
     def __init__(self, knots_t, knots_s: list, p_t: int, p_s: int, nu: float = 1.0,
-                 V=None, q: int | None = None, geometry=None):
-        self.geometry, self.q = geometry, q
+                 V=None, q: int | None = None, geometry=None, final: bool = False):
+        """final=True: time basis with the final condition w(T) = 0 (the ultraweak method of
+        Section 4.4, whose matrix has the same Kronecker form; see oracle.ultraweak)."""
+        self.geometry, self.q, self.final = geometry, q, final
         self.d = len(knots_s)
         self.nu = float(nu)
         self.p_t, self.p_s = p_t, p_s
         self.knots_t = np.asarray(knots_t, dtype=np.float64)
         self.knots_s = [np.asarray(k, dtype=np.float64) for k in knots_s]
-        self.time = time_1d(self.knots_t, p_t, None if q is None else q)
+        self.time = time_1d(self.knots_t, p_t, None if q is None else q, final=final)
         self.space1d = [space_1d(k, p_s, q) for k in self.knots_s]
         self.n_t = self.time["M"].shape[0]
         self.n_s = [s["M"].shape[0] for s in self.space1d]
