@@ -96,6 +96,18 @@ enum { STFD_PRECOND_AUTO = 0, STFD_PRECOND_PARAMETRIC = 1 };
  * STFD_MATVEC_AUTO picks SUMFAC for d = 3 when it applies, else STENCIL. */
 enum { STFD_MATVEC_AUTO = 0, STFD_MATVEC_STENCIL = 1, STFD_MATVEC_SUMFAC = 2 };
 
+/* Time condition of the discrete space (Sections 3.2 and 4.4).
+ * STFD_TIME_INITIAL: the least-squares method; the time basis drops its first function
+ *   (u(0) = 0 on the free space; the initial data enter through the lifting of stfd_load_vector).
+ * STFD_TIME_FINAL: the ultraweak method (eq. uw-discrete-system); the time basis drops its last
+ *   function (test space W_h with w(T) = 0).  The system matrix has the same Kronecker form
+ *   (eq. syst_mat with the potential terms, on this basis) and the same preconditioner; the
+ *   solution x holds the coefficients of z_h in W_h and the discrete solution is u_h = S_V z_h
+ *   (i d_t z_h - nu Lap z_h + V z_h).  stfd_load_vector then assembles
+ *   (f, B_I) + i (u_0, B_I(., 0)) with no lifting.  Unit cube only (geometry must be
+ *   STFD_GEOM_UNIT_CUBE) and homogeneous Dirichlet data. */
+enum { STFD_TIME_INITIAL = 0, STFD_TIME_FINAL = 1 };
+
 /* Problem description (Sections 2, 3.1-3.2, 4.3).
  * knots_t / knots_s[l]: open knot vectors on [0,1] (first and last p+1 knots
  *   repeated, non-decreasing), length m + p + 1.  The time basis is
@@ -131,6 +143,7 @@ typedef struct {
                            scratch of one right-hand side, about 16 (prod_a Q_a + 4 m_t
                            prod_l max(m_l, Q_l)) bytes, and max_nrhs lifting tensors); nonzero:
                            skip it, stfd_load_vector then returns STFD_EINVAL on this handle */
+  int time_condition; /* STFD_TIME_INITIAL or STFD_TIME_FINAL (see below) */
 } stfd_setup_desc;
 
 typedef struct {
@@ -211,7 +224,10 @@ int stfd_sizes(const stfd_problem *P, int64_t *n_t, int64_t n_s[3], int64_t *n_d
  * no_rhs_workspace), STFD_ENOTSPD (breakdown of the lifting solve), STFD_NOT_CONVERGED (the
  * lifting solve of some right-hand side reached its iteration limit, see
  * stfd_set_lift_max_iterations; that f_bar is assembled from the last lifting iterate),
- * STFD_EHIP. */
+ * STFD_EHIP.
+ * Ultraweak problems (time_condition STFD_TIME_FINAL): fbar = (f, B_I) + i (u_0, B_I(., 0))
+ * over the free basis of W_h; dirichlet_q_dev must be NULL or all-NULL (else STFD_EINVAL); no
+ * lifting runs and lift, if given, is set to zeros. */
 int stfd_load_vector(const stfd_problem *P, const void *f_q_dev, const void *u0_q_dev,
                      const void *const *dirichlet_q_dev, void *fbar_dev, double *lift, int64_t nrhs,
                      void *stream);

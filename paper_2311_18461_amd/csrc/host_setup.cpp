@@ -525,18 +525,20 @@ int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
   for (int l = 0; l < v.d; ++l)
     if (build_direction(v.knots_s[l], v.n_knots_s[l], v.p_s, qs, 1.0, hp.dir_s[l])) return -1;
 
-  // time (Section 3.2: drop the first function; eq. time_mat)
+  // time (Section 3.2: drop the first function; eq. time_mat); the ultraweak method of Section
+  // 4.4 drops the last one (final condition of the test space)
   Gram1D gt;
   gram_1d(hp.dir_t, gt);
   hp.Mfull_t = gt.M;
-  const int mt = gt.m, nt = mt - 1;
+  hp.time_final = v.time_final;
+  const int mt = gt.m, nt = mt - 1, t_off = v.time_final ? 0 : 1;
   hp.n_t = nt;
   hp.Mt.assign(size_t(nt) * nt, 0.0);
   hp.Lt.assign(size_t(nt) * nt, 0.0);
   hp.Kt.assign(size_t(nt) * nt, 0.0);
   for (int i = 0; i < nt; ++i)
     for (int j = 0; j < nt; ++j) {
-      size_t f = size_t(i + 1) * mt + (j + 1), fT = size_t(j + 1) * mt + (i + 1);
+      size_t f = size_t(i + t_off) * mt + (j + t_off), fT = size_t(j + t_off) * mt + (i + t_off);
       hp.Mt[size_t(i) * nt + j] = gt.M[f];
       hp.Lt[size_t(i) * nt + j] = gt.L[f];
       hp.Kt[size_t(i) * nt + j] = gt.G[f] - gt.G[fT];  // W_t + W_t^* = i (G - G^T)

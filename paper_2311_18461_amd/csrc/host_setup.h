@@ -31,6 +31,7 @@ struct Gram1D {
 struct HostProblem {
   int d = 0, p_t = 0, p_s = 0;
   double T = 1, nu = 1;
+  bool time_final = false;  // time basis without its last function (ultraweak method, Section 4.4)
   Direction dir_t;
   Direction dir_s[3];
   int n_t = 0;
@@ -100,6 +101,7 @@ struct stfd_setup_desc_view {
   int n_quad;
   bool kronecker_base;  // assemble the V-free unit-cube stencils from 1D matrices
   bool stencils;        // build hp.Sc now (false: the caller decides later)
+  bool time_final;      // drop the last time function instead of the first (Section 4.4)
 };
 
 }  // namespace stfd

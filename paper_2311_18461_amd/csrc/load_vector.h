@@ -90,4 +90,11 @@ int rhs_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, c
                const double* const* faces, double* G, double* fbar, double* work, int* status_dev,
                volatile int* status_host, int max_iter, hipStream_t stream);
 
+// Load vector of the ultraweak method (Section 4.4, eq. uw-discrete-system) for one right-hand
+// side on the unit cube: fbar = (f, B_I) + i (u0, B_I(., 0)) over the free basis of W_h (time
+// without its last function).  f_q / u0_q as for rhs_device (nullptr: zero).  Returns 0 or a
+// hipError_t.
+int ultraweak_rhs_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, const double* u0_q,
+                         double* fbar, double* work, hipStream_t stream);
+
 }  // namespace stfd

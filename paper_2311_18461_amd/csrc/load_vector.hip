@@ -715,7 +715,9 @@ int load_plan_build(const HostProblem& hp, LoadPlan& plan) {
           wf[size_t(i) * Q + q] = D.w[q] * D.b(e, g, 0, k);
           wlo[i] = std::min(wlo[i], q);
           whi[i] = std::max(whi[i], q + 1);
-          const int fi = i - 1;  // free index (first function dropped)
+          // free index: the first function dropped (space; time of the least-squares method) or
+          // the last one (time of the ultraweak method)
+          const int fi = (a == 0 && hp.time_final) ? i : i - 1;
           if (fi < 0 || fi >= n) continue;
           for (int r = 0; r < 3; ++r) ld[r][size_t(fi) * Q + q] = D.w[q] * D.b(e, g, r, k);
           llo[fi] = std::min(llo[fi], q);
@@ -1008,6 +1010,62 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
 }
 
 }  // namespace
+
+// X0[o][0] += i u0[o] for every spatial grid point o (time row 0 of the free basis of W_h: the
+// only time function that is non-zero at t = 0, where it equals 1)
+__global__ void __launch_bounds__(256) uw_initial_kernel(const double2* __restrict__ u0, double2* __restrict__ X0,
+                                                         int64_t npts, int n_t) {
+  const int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (o >= npts) return;
+  const double2 u = u0[o];
+  double2 x = X0[o * n_t];
+  x.x -= u.y;  // + i (u.x + i u.y)
+  x.y += u.x;
+  X0[o * n_t] = x;
+}
+
+int ultraweak_rhs_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, const double* u0_q,
+                         double* fbar, double* work, hipStream_t s) {
+  (void)hp;
+  RhsWork w;
+  work_layout(plan, &w, work);
+  const int na = plan.na;
+  int64_t npts = 1;
+  for (int a = 1; a < na; ++a) npts *= plan.Q[a];
+  const int Q0 = plan.Q[0], n0 = plan.n[0];
+  double* X0 = w.A0;
+  int rc;
+  // time: X0[o][i_t] = sum_q w_q b_{i_t}(t_q) f(t_q, x_o) (free time rows of W_h)
+  if (f_q) {
+    hipLaunchKernelGGL(time_load_kernel, dim3(static_cast<unsigned>(npts)), dim3(128), Q0 * sizeof(double2), s,
+                       (const double2*)f_q, (double2*)X0, (double2*)w.A2, plan.tband_load[0], plan.tband_load[1],
+                       plan.load_lo[0], plan.tband_lw, Q0, n0, (const double*)nullptr, (const double*)nullptr);
+  } else {
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(2 * npts * n0)), dim3(256), 0, s, X0, 2 * npts * n0);
+  }
+  if ((rc = int(hipGetLastError()))) return rc;
+  if (u0_q) {
+    hipLaunchKernelGGL(uw_initial_kernel, dim3(unsigned((npts + 255) / 256)), dim3(256), 0, s, (const double2*)u0_q,
+                       (double2*)X0, npts, n0);
+    if ((rc = int(hipGetLastError()))) return rc;
+  }
+  // space: contract every spatial axis with the weighted free functions (order 0)
+  Shape sh;
+  sh.na = na;
+  sh.dims[0] = n0;
+  for (int a = 1; a < na; ++a) sh.dims[a] = plan.Q[a];
+  double* T[2] = {w.T0, w.T1};
+  const double* src = X0;
+  for (int a = 1; a < na; ++a) {
+    const bool last = (a == na - 1);
+    double* o = last ? fbar : T[a & 1];
+    if ((rc = contract(src, o, sh, a, plan.load[a][0], plan.load_lo[a], plan.load_hi[a], plan.Q[a], plan.n[a], 1.0,
+                       0.0, false, s)))
+      return rc;
+    src = o;
+  }
+  return 0;
+}
 
 int rhs_device(const HostProblem& hp, const LoadPlan& plan, const double* f_q, const double* u0_q,
                const double* const* faces, double* G, double* fbar, double* work, int* status_dev,

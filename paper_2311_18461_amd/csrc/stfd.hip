@@ -1910,6 +1910,9 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   v.kronecker_base = (geom.kind == GEOM_UNIT);
   v.stencils = false;  // built below unless the matvec runs sum-factorised
   if (desc->matvec < STFD_MATVEC_AUTO || desc->matvec > STFD_MATVEC_SUMFAC) return STFD_EINVAL;
+  if (desc->time_condition != STFD_TIME_INITIAL && desc->time_condition != STFD_TIME_FINAL) return STFD_EINVAL;
+  if (desc->time_condition == STFD_TIME_FINAL && geom.kind != GEOM_UNIT) return STFD_EINVAL;
+  v.time_final = desc->time_condition == STFD_TIME_FINAL;
   stfd_problem* P = new (std::nothrow) stfd_problem;
   if (!P) return STFD_ENOMEM;
   int rc = host_setup(v, P->hp);
@@ -2202,6 +2205,29 @@ int stfd_load_vector(const stfd_problem* P, const void* f_q_dev, const void* u0_
   const size_t nfull = size_t(plan.n_full);
   int rc = STFD_OK;
   const double* faces[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (hp.time_final) {
+    // ultraweak method: (f, B_I) + i (u_0, B_I(0)), homogeneous Dirichlet data, no lifting
+    if (dirichlet_q_dev)
+      for (int k = 0; k < 2 * hp.d; ++k)
+        if (dirichlet_q_dev[k]) return STFD_EINVAL;
+    for (int64_t r = 0; r < nrhs; ++r) {
+      const double* u0 = u0_q_dev ? static_cast<const double*>(u0_q_dev) + size_t(r) * 2 * nq_s : nullptr;
+      const double* fq = f_q_dev ? static_cast<const double*>(f_q_dev) + size_t(r) * 2 * grid : nullptr;
+      double* out = static_cast<double*>(fbar_dev) + size_t(r) * P->n2;
+      const int he = ultraweak_rhs_device(hp, plan, fq, u0, out, P->rhs_work, s);
+      if (he != 0) {
+        g_last_hip_error = he;
+        return STFD_EHIP;
+      }
+    }
+    const hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      g_last_hip_error = int(e);
+      return STFD_EHIP;
+    }
+    if (lift) std::memset(lift, 0, nfull * 2 * sizeof(double) * size_t(nrhs));
+    return STFD_OK;
+  }
   for (int64_t r = 0; r < nrhs && (rc == STFD_OK || rc == STFD_NOT_CONVERGED); ++r) {
     for (int k = 0; k < 2 * hp.d; ++k)
       faces[k] = (dirichlet_q_dev && dirichlet_q_dev[k])

@@ -20,6 +20,7 @@ FP64, FP32, BF16 = 0, 1, 2
 GEOM_UNIT_CUBE, GEOM_QUARTER_ANNULUS = 0, 1
 PRECOND_AUTO, PRECOND_PARAMETRIC = 0, 1
 MATVEC_AUTO, MATVEC_STENCIL, MATVEC_SUMFAC = 0, 1, 2
+TIME_INITIAL, TIME_FINAL = 0, 1  # least-squares method / ultraweak method (Section 4.4)
 X0_ZERO, X0_GIVEN, PCG_GRAPH, X0_SCALED = 0, 1, 2, 4
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
@@ -31,7 +32,8 @@ class SetupDesc(ctypes.Structure):
                 ("T", ctypes.c_double), ("nu", ctypes.c_double),
                 ("V_quad", ctypes.POINTER(ctypes.c_double)), ("n_quad", ctypes.c_int),
                 ("max_nrhs", ctypes.c_int), ("geometry", ctypes.c_int), ("geom", ctypes.c_double * 2),
-                ("precond", ctypes.c_int), ("matvec", ctypes.c_int), ("no_rhs_workspace", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("matvec", ctypes.c_int), ("no_rhs_workspace", ctypes.c_int),
+                ("time_condition", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -169,7 +171,8 @@ class Problem:
 
     def __init__(self, knots_t, knots_s, p_t: int, p_s: int, T: float = 1.0, nu: float = 1.0,
                  V_quad=None, n_quad: int = 0, max_nrhs: int = 1, geometry=GEOM_UNIT_CUBE, radii=(1.0, 2.0),
-                 precond=PRECOND_AUTO, rhs_workspace: bool = True, matvec=MATVEC_AUTO):
+                 precond=PRECOND_AUTO, rhs_workspace: bool = True, matvec=MATVEC_AUTO,
+                 time_condition=TIME_INITIAL):
         d = len(knots_s)
         self._keep = [np.ascontiguousarray(knots_t, dtype=np.float64)]
         desc = SetupDesc()
@@ -194,6 +197,7 @@ class Problem:
         desc.geom[0], desc.geom[1] = radii
         desc.precond = precond
         desc.no_rhs_workspace = 0 if rhs_workspace else 1
+        desc.time_condition = time_condition
         desc.matvec = matvec
         h = ctypes.c_void_p()
         self._h = None

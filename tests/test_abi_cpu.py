@@ -146,3 +146,16 @@ def test_sumfac_matvec_rejected_where_it_does_not_apply():
     with pytest.raises(stfd.StfdError) as ei:
         stfd.Problem(kn, [kn] * 2, 3, 3, matvec=7)
     assert ei.value.code == stfd.EINVAL
+
+
+def test_time_condition_rejected_where_it_does_not_apply():
+    """The ultraweak method (final time condition) runs on the unit cube only; unknown values of
+    the time condition are rejected."""
+    stfd = _lib()
+    kn = inputs.uniform_open_knots(4, 3)
+    with pytest.raises(stfd.StfdError) as ei:
+        stfd.Problem(kn, [kn, kn], 3, 3, geometry=stfd.GEOM_QUARTER_ANNULUS, time_condition=stfd.TIME_FINAL)
+    assert ei.value.code == stfd.EINVAL
+    with pytest.raises(stfd.StfdError) as ei:
+        stfd.Problem(kn, [kn], 3, 3, time_condition=2)
+    assert ei.value.code == stfd.EINVAL
