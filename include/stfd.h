@@ -282,13 +282,17 @@ int stfd_pcg_solve(const stfd_problem *P, const void *f_dev, void *u_dev, int64_
 /* Batched PCG over several problems (uneven grids), each with its own stack of
  * right-hand sides: job k solves A_k u = f on handle probs[k] for nrhs[k]
  * systems stored at f_dev[k] / u_dev[k] (device, layout as stfd_pcg_solve).
- * Same algorithm and stopping rule as stfd_pcg_solve, per system.  Each PCG
- * iteration of the whole batch is one captured HIP graph (one per iteration
- * parity) in which every job runs on its own stream, so the small grids
- * overlap the large ones on the device; converged systems are masked by
- * their done flags.  The handles must be distinct (each owns one set of work
- * buffers).  info: host array of sum_k nrhs[k] entries in job order (may be
- * NULL).  count <= 64.  Returns as stfd_pcg_solve. */
+ * Same algorithm and stopping rule as stfd_pcg_solve, per system.  Every job
+ * runs on a stream of its handle (created on first use, forked from `stream`
+ * and joined back into it), so the small, latency-bound grids run beside the
+ * large ones; each job stops launching iterations once all its systems have
+ * converged (converged systems of a job still running are masked by their done
+ * flags).  flags as stfd_pcg_solve: with STFD_PCG_GRAPH each job's iteration
+ * is replayed from its own captured graph on its stream.  The host polls the
+ * jobs' progress without blocking.  The handles must be distinct (each owns
+ * one set of work buffers and one stream); a handle must not be used
+ * concurrently from another thread.  info: host array of sum_k nrhs[k] entries
+ * in job order (may be NULL).  count <= 64.  Returns as stfd_pcg_solve. */
 int stfd_pcg_solve_batched(const stfd_problem *const *probs, int count, const void *const *f_dev,
                            void *const *u_dev, const int64_t *nrhs, double rtol, int maxit, int flags,
                            int precision, stfd_pcg_info *info, void *stream);

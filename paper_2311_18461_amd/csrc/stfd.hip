@@ -18,6 +18,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/stfd.h"
@@ -1322,6 +1323,9 @@ struct stfd_problem {
   int* done = nullptr;
   int* ctr = nullptr;  // iterations launched in the current solve (device)
   stfd::PcgScalars* sc_host = nullptr;  // pinned host ring [kLag][max_nrhs], written by kernels
+  // stream and events of this handle's job in a batched solve (created on first use)
+  hipStream_t job_stream = nullptr;
+  hipEvent_t job_ev[stfd::kLag + 1] = {};
   stfd::PcgScalars* sc_host_dev = nullptr;  // device address of sc_host
   int64_t mp_last_blocks = 0;            // blocks per rhs of the last mode product (dot partials)
   int64_t u_slice0 = 0;                  // per-mode pencils along x_1 (mapped domain): n_1^2, else 0
@@ -1875,6 +1879,9 @@ void stfd_destroy(stfd_problem* P) {
   if (!P) return;
   for (hipEvent_t e : P->tev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : P->job_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (P->job_stream) (void)hipStreamDestroy(P->job_stream);
   for (void* p : P->allocs) (void)hipFree(p);
   stfd::load_plan_free(P->load);
   stfd::spatial_device_free(P->sdev);
@@ -2613,6 +2620,90 @@ static int pcg_run(std::vector<PcgJob>& jobs, double rtol, int maxit, int flags,
   return status;
 }
 
+// Batched driver: every job runs on its handle's own stream, forked from and joined back into `s`,
+// so that the grids execute concurrently (a multi-stream graph is replayed with its branches one
+// after the other, which leaves the small latency-bound grids serialised behind the large one).
+// Each job keeps kLag iterations in flight and stops at its own convergence: the host polls the
+// jobs' events without blocking and launches the next iteration of whichever job may proceed.
+// graph: each job's iteration is a captured linear graph launched on the job's stream.
+static int pcg_run_streams(std::vector<PcgJob>& jobs, double rtol, int maxit, int flags, int precision, bool graph,
+                           stfd_pcg_info* info, hipStream_t s) {
+  const size_t nj = jobs.size();
+  for (PcgJob& J : jobs) {
+    stfd_problem* P = J.P;
+    if (!P->job_stream) STFD_HIP(hipStreamCreateWithFlags(&P->job_stream, hipStreamNonBlocking));
+    for (hipEvent_t& e : P->job_ev)
+      if (!e) STFD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  // fork: every job stream starts after the work already on s
+  hipEvent_t fork = jobs[0].P->job_ev[kLag];
+  STFD_HIP(hipEventRecord(fork, s));
+  for (PcgJob& J : jobs) STFD_HIP(hipStreamWaitEvent(J.P->job_stream, fork, 0));
+  int rc;
+  for (PcgJob& J : jobs)
+    if ((rc = pcg_init(J, flags, precision, rtol, J.P->job_stream))) return rc;
+  std::vector<IterationGraphs> G(graph && maxit > 0 ? nj : 0);
+  for (size_t j = 0; j < G.size(); ++j) {
+    std::vector<PcgJob> one(1, jobs[j]);
+    if ((rc = capture_iterations(one, precision, maxit, rtol, G[j]))) return rc;
+  }
+  std::vector<int> launched(nj, 0);
+  std::vector<char> active(nj, maxit > 0 ? 1 : 0);
+  size_t n_active = maxit > 0 ? nj : 0;
+  while (n_active > 0) {
+    bool progressed = false;
+    for (size_t j = 0; j < nj; ++j) {
+      if (!active[j]) continue;
+      PcgJob& J = jobs[j];
+      stfd_problem* P = J.P;
+      const int k = launched[j];
+      bool stop = k >= maxit;
+      if (!stop && k >= kLag) {
+        const int slot = (k - kLag) % kLag;
+        const hipError_t q = hipEventQuery(P->job_ev[slot]);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) {
+          g_last_hip_error = int(q);
+          return STFD_EHIP;
+        }
+        bool all = true;
+        for (int64_t rr = 0; rr < J.nrhs; ++rr) all = all && P->sc_host[slot * P->max_nrhs + rr].done;
+        stop = all;
+      }
+      if (stop) {
+        active[j] = 0;
+        --n_active;
+        continue;
+      }
+      if (graph) {
+        STFD_HIP(hipGraphLaunch(G[j].exec[k & 1], P->job_stream));
+      } else if ((rc = pcg_iteration(J, k & 1, precision, maxit, rtol, P->job_stream))) {
+        return rc;
+      }
+      STFD_HIP(hipEventRecord(P->job_ev[k % kLag], P->job_stream));
+      launched[j] = k + 1;
+      progressed = true;
+    }
+    if (!progressed && n_active > 0) std::this_thread::yield();
+  }
+  int status = STFD_OK;
+  int64_t off = 0;
+  for (PcgJob& J : jobs) {
+    const int st = pcg_finish(J, info ? info + off : nullptr, J.P->job_stream);
+    off += J.nrhs;
+    if (st < 0) return st;
+    if (st == STFD_NOT_CONVERGED && status == STFD_OK) status = st;
+  }
+  // join: later work on s sees the solutions
+  for (PcgJob& J : jobs) {
+    STFD_HIP(hipEventRecord(J.P->job_ev[kLag], J.P->job_stream));
+    STFD_HIP(hipStreamWaitEvent(s, J.P->job_ev[kLag], 0));
+  }
+  for (int64_t k = 0; k < off && info; ++k)
+    if (info[k].status == STFD_EBREAKDOWN) return STFD_EBREAKDOWN;
+  return status;
+}
+
 }  // namespace stfd
 
 int stfd_pcg_solve(const stfd_problem* Pc, const void* f_dev, void* u_dev, int64_t nrhs, double rtol, int maxit,
@@ -2654,7 +2745,8 @@ int stfd_pcg_solve_batched(const stfd_problem* const* probs, int count, const vo
     total += nrhs[k];
   }
   std::vector<stfd_pcg_info> tmp(info ? 0 : size_t(total));
-  return pcg_run(jobs, rtol, maxit, x0, precision, true, info ? info : tmp.data(), static_cast<hipStream_t>(stream));
+  return pcg_run_streams(jobs, rtol, maxit, x0, precision, (flags & STFD_PCG_GRAPH) != 0, info ? info : tmp.data(),
+                         static_cast<hipStream_t>(stream));
 }
 
 #ifdef STFD_PHASE_TIMING

@@ -368,7 +368,7 @@ def _infos(info):
 
 
 def pcg_solve_batched(problems, fs, us, nrhs=None, rtol: float = 1e-8, maxit: int = 200, x0_given: bool = False,
-                      precision=FP64, stream=None, check=True):
+                      precision=FP64, stream=None, check=True, graph: bool = False):
     """stfd_pcg_solve_batched: job k solves problems[k] for nrhs[k] stacked systems fs[k] -> us[k]."""
     count = len(problems)
     nrhs = list(nrhs) if nrhs is not None else [1] * count
@@ -378,8 +378,9 @@ def pcg_solve_batched(problems, fs, us, nrhs=None, rtol: float = 1e-8, maxit: in
     up = (_VP * count)(*[_dev_ptr(u, pr.N * n, "u").value for pr, u, n in zip(problems, us, nrhs)])
     nr = (_I64 * count)(*nrhs)
     info = (PcgInfo * sum(nrhs))()
-    rc = _lib().stfd_pcg_solve_batched(handles, count, fp, up, nr, rtol, maxit,
-                                       X0_GIVEN if x0_given else X0_ZERO, precision, info, _stream_ptr(stream))
+    flags = (X0_GIVEN if x0_given else X0_ZERO) | (PCG_GRAPH if graph else 0)
+    rc = _lib().stfd_pcg_solve_batched(handles, count, fp, up, nr, rtol, maxit, flags, precision, info,
+                                       _stream_ptr(stream))
     if check:
         _check(rc, "stfd_pcg_solve_batched", allow=(OK, NOT_CONVERGED))
     return rc, _infos(info)
