@@ -144,6 +144,8 @@ typedef struct {
                            prod_l max(m_l, Q_l)) bytes, and max_nrhs lifting tensors); nonzero:
                            skip it, stfd_load_vector then returns STFD_EINVAL on this handle */
   int time_condition; /* STFD_TIME_INITIAL or STFD_TIME_FINAL (see below) */
+  int autotune;       /* 0: launch shapes from heuristics; 1: stfd_setup times the candidate shapes
+                         on the current device and keeps the fastest (see stfd_get_tuning) */
 } stfd_setup_desc;
 
 typedef struct {
@@ -306,6 +308,23 @@ int stfd_pcg_solve_batched(const stfd_problem *const *probs, int count, const vo
  * Errors: STFD_EINVAL (NULL handle, capacity < 1, begin while timing / end while not), STFD_EHIP. */
 int stfd_timing_begin(stfd_problem *P, int capacity);
 int stfd_timing_end(stfd_problem *P, double *total_ms, int64_t *launches);
+
+/* Launch shapes of a problem.  With stfd_setup_desc.autotune = 1 the setup timed on the device
+ * (2 untimed and 5 timed launches per candidate on a private stream, median kept):
+ *   the row groups (1 or 2 sixteen-row groups per wave) of every mode product, per precision and
+ *   direction, for directions with n_l <= 80;
+ *   the segment length of the time solve and whether its segment transfers are read from tables or
+ *   computed in the kernel, for problems with N_s n_t <= 2^21 (larger ones keep the heuristics).
+ * Otherwise the values are the heuristics'.  tune_ms: host wall time of the tuning runs. */
+typedef struct {
+  int autotuned;
+  int mode_product_row_groups[3][3]; /* [precision STFD_FP64/FP32/BF16][direction], 0 past d */
+  int time_segment_length;
+  int time_transfers_in_kernel;      /* 1: computed in the solve, 0: read from tables */
+  double tune_ms;
+} stfd_tuning;
+/* Errors: STFD_EINVAL (NULL argument). */
+int stfd_get_tuning(const stfd_problem *P, stfd_tuning *out);
 
 /* Host copies of setup data for inspection: U_l (n_l x n_l, row-major,
  * U[j*n_l + k] = entry (j,k), column k = k-th eigenvector) and Lambda_l.

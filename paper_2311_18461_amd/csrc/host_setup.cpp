@@ -407,11 +407,22 @@ int time_factors(HostProblem& hp) {
   return 0;
 }
 
+// segment lengths compiled per half-bandwidth P (one lane keeps len rows of y, L and 1/D plus two
+// P x P transfers in registers)
+static const int kSegCand[7][3] = {{0, 0, 0}, {8, 16, 0}, {8, 12, 16}, {8, 12, 16}, {6, 8, 12}, {6, 8, 0}, {6, 0, 0}};
+
+int time_segment_candidates(int n_t, int p_t, int out[3]) {
+  if (p_t < 1 || p_t > 6 || n_t < 1) return 0;
+  int c = 0;
+  for (int len : kSegCand[p_t])
+    if (len > 0 && (n_t + len - 1) / len <= 64) out[c++] = len;
+  return c;
+}
+
 int time_segment_length(int n_t, int p_t) {
-  // segment lengths compiled per half-bandwidth P (one lane keeps len rows of y, L and 1/D
-  // plus two P x P transfers in registers); cost = dependent FP64 work per lane: four sweeps of
-  // len rows (4P fused multiply-adds each) and two reduced recurrences of S-1 steps (4P^2 + 4P)
-  static const int cand[7][3] = {{0, 0, 0}, {8, 16, 0}, {8, 12, 16}, {8, 12, 16}, {6, 8, 12}, {6, 8, 0}, {6, 0, 0}};
+  // cost = dependent FP64 work per lane: four sweeps of len rows (4P fused multiply-adds each) and
+  // two reduced recurrences of S-1 steps (4P^2 + 4P)
+  static const int (&cand)[7][3] = kSegCand;
   if (p_t < 1 || p_t > 6 || n_t < 1) return 0;
   int best = 0;
   double best_cost = 0.0;

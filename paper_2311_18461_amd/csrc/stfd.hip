@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <type_traits>
@@ -1327,7 +1328,11 @@ struct stfd_problem {
   hipStream_t job_stream = nullptr;
   hipEvent_t job_ev[stfd::kLag + 1] = {};
   stfd::PcgScalars* sc_host_dev = nullptr;  // device address of sc_host
-  int64_t mp_last_blocks = 0;            // blocks per rhs of the last mode product (dot partials)
+  int64_t mp_last_blocks[3] = {0, 0, 0};  // per precision: blocks per rhs of the last mode product (dot partials)
+  int mp_rt[3][3] = {};                   // [precision][direction]: row groups per wave of the mode products
+  bool ts_transfers = false;              // time solve reads transfer tables (else computes them)
+  bool autotuned = false;
+  double tune_ms = 0.0;                   // device time spent by the setup's tuning runs
   int64_t u_slice0 = 0;                  // per-mode pencils along x_1 (mapped domain): n_1^2, else 0
   int64_t mv_blocks = 0;
   int mv_points = 1;  // spatial points per matvec block
@@ -1389,8 +1394,8 @@ static int mode_product_row_groups(int n, int64_t inner, int64_t outer_per_rhs) 
 // Blocks (one wave each) of one right-hand side of a mode product: 16-column groups x (tiles of
 // 16 RT rows of every outer slice, padded to a multiple of the XCD count).  Depends only on
 // per-rhs sizes, so the number of dot partials per right-hand side is fixed.
-static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_per_rhs) {
-  const int rows = 16 * mode_product_row_groups(n, inner, outer_per_rhs);
+static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_per_rhs, int rt = 0) {
+  const int rows = 16 * (rt > 0 ? rt : mode_product_row_groups(n, inner, outer_per_rhs));
   const int64_t tiles = outer_per_rhs * ((inner + rows - 1) / rows);
   return int64_t((n + 15) / 16) * ((tiles + kXcds - 1) / kXcds * kXcds);
 }
@@ -1461,8 +1466,8 @@ struct DotEpilogue {
 template <int PREC, typename Tin, typename Tout>
 static int launch_mode_product(const void* in, void* out, const void* U, int n, int64_t inner, int64_t outer,
                                int64_t outer_per_rhs, const int* done, hipStream_t s,
-                               const DotEpilogue& ep = DotEpilogue(), int64_t u_slice_stride = 0) {
-  if (n < 1 || n > kMaxModeN || outer_per_rhs < 1) return STFD_EINVAL;
+                               const DotEpilogue& ep = DotEpilogue(), int64_t u_slice_stride = 0, int rt = 0) {
+  if (n < 1 || n > kMaxModeN || outer_per_rhs < 1 || rt < 0 || rt > 2 || (rt == 2 && n > 80)) return STFD_EINVAL;
   ModeProductArgs a;
   a.in = in;
   a.out = out;
@@ -1472,7 +1477,7 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   a.inner = inner;
   a.outer = outer;
   a.outer_per_rhs = outer_per_rhs;
-  const int RTn = mode_product_row_groups(n, inner, outer_per_rhs);
+  const int RTn = rt > 0 ? rt : mode_product_row_groups(n, inner, outer_per_rhs);
   a.n_row_tiles = (inner + 16 * RTn - 1) / (16 * RTn);
   a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
   a.tiles_pad = (a.tiles_per_rhs + kXcds - 1) / kXcds * kXcds;
@@ -1515,6 +1520,31 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
 #undef STFD_MP
   STFD_HIP(hipGetLastError());
   return STFD_OK;
+}
+
+// reals below and slices above direction l of one right-hand side (the mode product's inner and
+// outer extents)
+static int64_t mp_inner(const HostProblem& hp, int l) {
+  int64_t v = 2 * int64_t(hp.n_t);
+  for (int k = 0; k < l; ++k) v *= hp.n_s[k];
+  return v;
+}
+static int64_t mp_outer(const HostProblem& hp, int l) {
+  int64_t v = 1;
+  for (int k = l + 1; k < hp.d; ++k) v *= hp.n_s[k];
+  return v;
+}
+// direction of the last backward product (x_1 on the unit cube, x_d on a mapped domain)
+static int mp_last_dir(const stfd_problem* P) { return P->u_slice0 ? P->hp.d - 1 : 0; }
+static void set_last_blocks(stfd_problem* P) {
+  const int l = mp_last_dir(P);
+  for (int prec = MP_F64; prec <= MP_BF16; ++prec)
+    P->mp_last_blocks[prec] = mode_product_blocks_per_rhs(P->hp.n_s[l], mp_inner(P->hp, l), mp_outer(P->hp, l),
+                                                          P->mp_rt[prec][l]);
+}
+static int64_t mp_last_blocks_bound(const stfd_problem* P) {
+  const int l = mp_last_dir(P);
+  return mode_product_blocks_per_rhs(P->hp.n_s[l], mp_inner(P->hp, l), mp_outer(P->hp, l), 1);
 }
 
 // FP64 storage: FP64 solve; FP32 storage: FP32 solve with the FP32 tables
@@ -1611,16 +1641,16 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
     const MpTimer tm(P, s);
     if (first && last)
       rc = launch_mode_product<PREC, double, TY>(src, dst, Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l],
-                                                 done, s, DotEpilogue(), slice(l));
+                                                 done, s, DotEpilogue(), slice(l), P->mp_rt[PREC][l]);
     else if (first)
       rc = launch_mode_product<PREC, double, TW>(src, dst, Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l],
-                                                 done, s, DotEpilogue(), slice(l));
+                                                 done, s, DotEpilogue(), slice(l), P->mp_rt[PREC][l]);
     else if (last)
       rc = launch_mode_product<PREC, TW, TY>(src, dst, Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l], done,
-                                             s, DotEpilogue(), slice(l));
+                                             s, DotEpilogue(), slice(l), P->mp_rt[PREC][l]);
     else
       rc = launch_mode_product<PREC, TW, TW>(src, dst, Ufwd(l), hp.n_s[l], inner[l], outer[l], outer_rhs[l], done,
-                                             s, DotEpilogue(), slice(l));
+                                             s, DotEpilogue(), slice(l), P->mp_rt[PREC][l]);
     if (rc) return rc;
     if (k > 0) cur ^= 1;
     src = bufs[cur];
@@ -1635,16 +1665,16 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
     const MpTimer tm(P, s);
     if (last && first)
       return launch_mode_product<PREC, TY, double>(bufs[cur], s_out, Ubwd(l), hp.n_s[l], inner[l], outer[l],
-                                                   outer_rhs[l], done, s, ep, slice(l));
+                                                   outer_rhs[l], done, s, ep, slice(l), P->mp_rt[PREC][l]);
     if (last)
       return launch_mode_product<PREC, TW, double>(bufs[cur], s_out, Ubwd(l), hp.n_s[l], inner[l], outer[l],
-                                                   outer_rhs[l], done, s, ep, slice(l));
+                                                   outer_rhs[l], done, s, ep, slice(l), P->mp_rt[PREC][l]);
     if (first)
       rc = launch_mode_product<PREC, TY, TW>(bufs[cur], bufs[cur ^ 1], Ubwd(l), hp.n_s[l], inner[l], outer[l],
-                                             outer_rhs[l], done, s, DotEpilogue(), slice(l));
+                                             outer_rhs[l], done, s, DotEpilogue(), slice(l), P->mp_rt[PREC][l]);
     else
       rc = launch_mode_product<PREC, TW, TW>(bufs[cur], bufs[cur ^ 1], Ubwd(l), hp.n_s[l], inner[l], outer[l],
-                                             outer_rhs[l], done, s, DotEpilogue(), slice(l));
+                                             outer_rhs[l], done, s, DotEpilogue(), slice(l), P->mp_rt[PREC][l]);
     if (rc) return rc;
     cur ^= 1;
   }
@@ -1681,6 +1711,143 @@ static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64
   const bool f64 = apply_elem_bytes(precision) == sizeof(double);
   return apply_with_buffers(P, r, s_out, nrhs, precision, done, s, f64 ? (void*)P->work64[0] : (void*)P->work32[0],
                             f64 ? (void*)P->work64[1] : (void*)P->work32[1], ep);
+}
+
+// ---------------------------------------------------------------------------
+// Setup-time autotuning (stfd_setup_desc.autotune): the launch shapes that have a choice are timed
+// on the device on this problem's own sizes and the fastest is kept.
+//  * mode products: one or two 16-row groups per wave (n <= 80), per direction and precision;
+//  * time solve: segment length (every compiled one with at most 64 segments) x transfers read
+//    from tables or computed in the solve, where the tables of every candidate are cheap to build
+//    (N_s n_t <= kTuneTsRows); larger problems keep the heuristics.
+// Each candidate runs 2 untimed and 5 timed launches on a private stream; the median decides.
+// ---------------------------------------------------------------------------
+constexpr int64_t kTuneTsRows = int64_t(1) << 21;
+
+struct TuneClock {
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  ~TuneClock() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (s) (void)hipStreamDestroy(s);
+  }
+  int init() {
+    STFD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    STFD_HIP(hipEventCreate(&a));
+    STFD_HIP(hipEventCreate(&b));
+    return STFD_OK;
+  }
+  // median time (ms) of 5 launches after 2 untimed ones
+  template <typename F>
+  int median(F launch, float* ms) {
+    for (int w = 0; w < 2; ++w)
+      if (int rc = launch()) return rc;
+    float t[5];
+    for (int r = 0; r < 5; ++r) {
+      STFD_HIP(hipEventRecord(a, s));
+      if (int rc = launch()) return rc;
+      STFD_HIP(hipEventRecord(b, s));
+      STFD_HIP(hipEventSynchronize(b));
+      STFD_HIP(hipEventElapsedTime(&t[r], a, b));
+    }
+    std::sort(t, t + 5);
+    *ms = t[2];
+    return STFD_OK;
+  }
+};
+
+// Row groups of every mode product (forward operand, one right-hand side, FP64 in FP64 out or
+// FP32 in FP32 out as inside the applies); x, y: device buffers of 2 N doubles.
+static int tune_mode_products(stfd_problem* P, TuneClock& C, void* x, void* y) {
+  const HostProblem& hp = P->hp;
+  for (int prec = MP_F64; prec <= MP_BF16; ++prec)
+    for (int l = 0; l < hp.d; ++l) {
+      const int n = hp.n_s[l];
+      if (n > 80) continue;  // one row group only
+      const int64_t inner = mp_inner(hp, l), outer = mp_outer(hp, l);
+      const int64_t slice = l == 0 ? P->upk_slice[prec] : 0;
+      const void* U = P->Upk_fwd[prec][l];
+      float best = 0.0f;
+      int best_rt = P->mp_rt[prec][l];
+      for (int rt = 1; rt <= 2; ++rt) {
+        auto launch = [&]() -> int {
+          if (prec == MP_F64)
+            return launch_mode_product<MP_F64, double, double>(x, y, U, n, inner, outer, outer, nullptr, C.s,
+                                                               DotEpilogue(), slice, rt);
+          if (prec == MP_F32)
+            return launch_mode_product<MP_F32, float, float>(x, y, U, n, inner, outer, outer, nullptr, C.s,
+                                                             DotEpilogue(), slice, rt);
+          return launch_mode_product<MP_BF16, float, float>(x, y, U, n, inner, outer, outer, nullptr, C.s,
+                                                            DotEpilogue(), slice, rt);
+        };
+        float ms = 0.0f;
+        if (int rc = C.median(launch, &ms)) return rc;
+        if (rt == 1 || ms < best) {
+          best = ms;
+          best_rt = rt;
+        }
+      }
+      P->mp_rt[prec][l] = best_rt;
+    }
+  set_last_blocks(P);
+  return STFD_OK;
+}
+
+// Segment length and transfer mode of the FP64 time solve (sets P->ts_len and P->ts_transfers).
+static int tune_time_solve(stfd_problem* P, TuneClock& C) {
+  const HostProblem& hp = P->hp;
+  int cand[3];
+  const int nc = time_segment_candidates(hp.n_t, hp.p_t, cand);
+  double* y = nullptr;
+  STFD_HIP(hipMalloc(&y, sizeof(double) * 2 * size_t(hp.N)));
+  STFD_HIP(hipMemsetAsync(y, 0, sizeof(double) * 2 * size_t(hp.N), C.s));
+  float best = 0.0f;
+  int best_len = P->ts_len, rc = STFD_OK;
+  bool best_tr = P->ts_transfers, have = false;
+  for (int c = 0; c < nc && rc == STFD_OK; ++c)
+    for (int tr = 0; tr < 2 && rc == STFD_OK; ++tr) {
+      TimeSolvePlan tp;
+      if (time_solve_plan(hp, cand[c], tr != 0, tp) != 0) continue;
+      double* buf[4] = {nullptr, nullptr, nullptr, nullptr};
+      const std::vector<double>* src[4] = {&tp.Lf, &tp.Df, &tp.Tf, &tp.Tb};
+      for (int k = 0; k < 4 && rc == STFD_OK; ++k) {
+        if (src[k]->empty()) continue;
+        hipError_t e = hipMalloc(&buf[k], sizeof(double) * src[k]->size());
+        if (e == hipSuccess) e = hipMemcpy(buf[k], src[k]->data(), sizeof(double) * src[k]->size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+          g_last_hip_error = int(e);
+          rc = STFD_EHIP;
+        }
+      }
+      if (rc == STFD_OK) {
+        P->TsL = buf[0];
+        P->TsD = buf[1];
+        P->TsTf = buf[2];
+        P->TsTb = buf[3];
+        P->ts_len = tp.len;
+        P->ts_segs = tp.segs;
+        P->ts_mpb = tp.mpb;
+        P->ts_blocks = tp.blocks;
+        float ms = 0.0f;
+        rc = C.median([&]() { return launch_time_solve<double>(P, y, 1, nullptr, C.s); }, &ms);
+        if (rc == STFD_OK && (!have || ms < best)) {
+          have = true;
+          best = ms;
+          best_len = tp.len;
+          best_tr = tr != 0;
+        }
+      }
+      (void)hipStreamSynchronize(C.s);
+      for (double* b : buf)
+        if (b) (void)hipFree(b);
+      P->TsL = P->TsD = P->TsTf = P->TsTb = nullptr;
+    }
+  (void)hipFree(y);
+  if (rc != STFD_OK) return rc;
+  P->ts_len = best_len;
+  P->ts_transfers = best_tr;
+  return STFD_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1918,6 +2085,7 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   v.stencils = false;  // built below unless the matvec runs sum-factorised
   if (desc->matvec < STFD_MATVEC_AUTO || desc->matvec > STFD_MATVEC_SUMFAC) return STFD_EINVAL;
   if (desc->time_condition != STFD_TIME_INITIAL && desc->time_condition != STFD_TIME_FINAL) return STFD_EINVAL;
+  if (desc->autotune != 0 && desc->autotune != 1) return STFD_EINVAL;
   if (desc->time_condition == STFD_TIME_FINAL && geom.kind != GEOM_UNIT) return STFD_EINVAL;
   v.time_final = desc->time_condition == STFD_TIME_FINAL;
   stfd_problem* P = new (std::nothrow) stfd_problem;
@@ -2019,7 +2187,18 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     TimeSolvePlan tp;
     // transfer tables only where one right-hand side's grid holds at most one wave per SIMD
     const int mpb = 64 / ((hp.n_t + P->ts_len - 1) / P->ts_len);  // modes per block
-    const bool transfers = (hp.N_s + mpb - 1) / mpb <= 4 * int64_t(P->n_cus);
+    P->ts_transfers = (hp.N_s + mpb - 1) / mpb <= 4 * int64_t(P->n_cus);
+    if (desc->autotune && hp.N_s * hp.n_t <= kTuneTsRows) {
+      const auto t0 = std::chrono::steady_clock::now();
+      TuneClock C;
+      if ((rc = C.init()) || (rc = tune_time_solve(P, C))) {
+        stfd_destroy(P);
+        return rc;
+      }
+      P->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      P->autotuned = true;
+    }
+    const bool transfers = P->ts_transfers;
     if (time_solve_plan(hp, P->ts_len, transfers, tp) != 0) {
       stfd_destroy(P);
       return STFD_EINVAL;
@@ -2116,16 +2295,12 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     P->mv_points = matvec_points_per_block(hp, P->n_cus);
     P->mv_blocks = (hp.N_s + P->mv_points - 1) / P->mv_points;
   }
-  {
-    // the last backward product runs along x_1 (unit cube) or along x_d (mapped domain)
-    int64_t outer0 = 1;
-    for (int l = 1; l < hp.d; ++l) outer0 *= hp.n_s[l];
-    if (P->u_slice0)
-      P->mp_last_blocks = mode_product_blocks_per_rhs(hp.n_s[hp.d - 1], 2 * int64_t(hp.n_t) * (hp.N_s / hp.n_s[hp.d - 1]), 1);
-    else
-      P->mp_last_blocks = mode_product_blocks_per_rhs(hp.n_s[0], 2 * int64_t(hp.n_t), outer0);
-  }
-  P->max_parts = std::max<int64_t>(std::max<int64_t>(P->mv_blocks, P->mp_last_blocks), kVecGrid);
+  // row groups of every product from the heuristic (the autotune below may change them); the dot
+  // partials are sized for one row group, the largest block count
+  for (int prec = MP_F64; prec <= MP_BF16; ++prec)
+    for (int l = 0; l < hp.d; ++l) P->mp_rt[prec][l] = mode_product_row_groups(hp.n_s[l], mp_inner(hp, l), mp_outer(hp, l));
+  set_last_blocks(P);
+  P->max_parts = std::max<int64_t>(std::max<int64_t>(P->mv_blocks, mp_last_blocks_bound(P)), kVecGrid);
   if ((rc = dev_alloc(P, &P->parts, size_t(6) * P->max_parts * P->max_nrhs)) ||
       (rc = dev_alloc(P, &P->sc, size_t(P->max_nrhs))) || (rc = dev_alloc(P, &P->done, size_t(P->max_nrhs))) ||
       (rc = dev_alloc(P, &P->ctr, size_t(1)))) {
@@ -2181,6 +2356,22 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       stfd_destroy(P);
       return rc;
     }
+  }
+  if (desc->autotune) {
+    const auto t0 = std::chrono::steady_clock::now();
+    TuneClock C;
+    if ((rc = C.init())) {
+      stfd_destroy(P);
+      return rc;
+    }
+    STFD_HIP(hipMemsetAsync(P->vec[0], 0, sizeof(double) * size_t(P->n2), C.s));
+    if ((rc = tune_mode_products(P, C, P->vec[0], P->vec[1]))) {
+      stfd_destroy(P);
+      return rc;
+    }
+    STFD_HIP(hipStreamSynchronize(C.s));
+    P->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    P->autotuned = true;
   }
   *out = P;
   return STFD_OK;
@@ -2275,6 +2466,18 @@ int stfd_sizes(const stfd_problem* P, int64_t* n_t, int64_t n_s[3], int64_t* n_d
   if (n_s)
     for (int l = 0; l < 3; ++l) n_s[l] = (l < P->hp.d) ? P->hp.n_s[l] : 1;
   if (n_dof) *n_dof = P->hp.N;
+  return STFD_OK;
+}
+
+int stfd_get_tuning(const stfd_problem* P, stfd_tuning* out) {
+  if (!P || !out) return STFD_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->autotuned = P->autotuned ? 1 : 0;
+  for (int prec = 0; prec < 3; ++prec)
+    for (int l = 0; l < 3; ++l) out->mode_product_row_groups[prec][l] = l < P->hp.d ? P->mp_rt[prec][l] : 0;
+  out->time_segment_length = P->ts_len;
+  out->time_transfers_in_kernel = P->ts_transfers ? 0 : 1;
+  out->tune_ms = P->tune_ms;
   return STFD_OK;
 }
 
@@ -2448,7 +2651,7 @@ static int pcg_iteration(const PcgJob& J, int parity, int precision, int maxit, 
   // repeats the reduction, so small systems take few)
   const unsigned egrid = unsigned(std::min<int64_t>(kEndGrid, std::max<int64_t>(1, (n2 / 2 + kEndBlock - 1) / kEndBlock)));
   hipLaunchKernelGGL(pcg_end_iter_kernel, dim3(egrid, unsigned(J.nrhs)), dim3(kEndBlock), 0, s, znew, p, n2, pc,
-                     kVecGrid, pa, pb, int(P->mp_last_blocks), P->sc, parity, P->done, maxit, rtol, P->sc_host_dev,
+                     kVecGrid, pa, pb, int(P->mp_last_blocks[precision]), P->sc, parity, P->done, maxit, rtol, P->sc_host_dev,
                      P->max_nrhs, (const int*)P->ctr);
   STFD_HIP(hipGetLastError());
   return STFD_OK;

@@ -33,7 +33,13 @@ class SetupDesc(ctypes.Structure):
                 ("V_quad", ctypes.POINTER(ctypes.c_double)), ("n_quad", ctypes.c_int),
                 ("max_nrhs", ctypes.c_int), ("geometry", ctypes.c_int), ("geom", ctypes.c_double * 2),
                 ("precond", ctypes.c_int), ("matvec", ctypes.c_int), ("no_rhs_workspace", ctypes.c_int),
-                ("time_condition", ctypes.c_int)]
+                ("time_condition", ctypes.c_int), ("autotune", ctypes.c_int)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("autotuned", ctypes.c_int), ("mode_product_row_groups", (ctypes.c_int * 3) * 3),
+                ("time_segment_length", ctypes.c_int), ("time_transfers_in_kernel", ctypes.c_int),
+                ("tune_ms", ctypes.c_double)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -71,6 +77,7 @@ SIGNATURES = {
     "stfd_pcg_solve": (ctypes.c_int, [_VP, _VP, _VP, _I64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                       ctypes.c_int, ctypes.POINTER(PcgInfo), _VP]),
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
+    "stfd_get_tuning": (ctypes.c_int, [_VP, _VP]),
     "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
     "stfd_update_potential": (ctypes.c_int, [_VP, _DP, _VP]),
     "stfd_set_lift_max_iterations": (ctypes.c_int, [_VP, ctypes.c_int]),
@@ -172,7 +179,7 @@ class Problem:
     def __init__(self, knots_t, knots_s, p_t: int, p_s: int, T: float = 1.0, nu: float = 1.0,
                  V_quad=None, n_quad: int = 0, max_nrhs: int = 1, geometry=GEOM_UNIT_CUBE, radii=(1.0, 2.0),
                  precond=PRECOND_AUTO, rhs_workspace: bool = True, matvec=MATVEC_AUTO,
-                 time_condition=TIME_INITIAL):
+                 time_condition=TIME_INITIAL, autotune: bool = False):
         d = len(knots_s)
         self._keep = [np.ascontiguousarray(knots_t, dtype=np.float64)]
         desc = SetupDesc()
@@ -198,6 +205,7 @@ class Problem:
         desc.precond = precond
         desc.no_rhs_workspace = 0 if rhs_workspace else 1
         desc.time_condition = time_condition
+        desc.autotune = 1 if autotune else 0
         desc.matvec = matvec
         h = ctypes.c_void_p()
         self._h = None
@@ -222,6 +230,16 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    def get_tuning(self):
+        """stfd_get_tuning: the launch shapes in use (timed at setup when autotune was set)."""
+        t = Tuning()
+        _check(_lib().stfd_get_tuning(self._h, ctypes.byref(t)), "stfd_get_tuning")
+        return {"autotuned": bool(t.autotuned),
+                "mode_product_row_groups": {name: [t.mode_product_row_groups[k][l] for l in range(self.d)]
+                                            for k, name in enumerate(("fp64", "fp32", "bf16"))},
+                "time_segment_length": t.time_segment_length,
+                "time_transfers_in_kernel": bool(t.time_transfers_in_kernel), "tune_ms": t.tune_ms}
 
     def get_pencil(self, l: int):
         n = self.n_s[l]
