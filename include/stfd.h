@@ -311,8 +311,10 @@ int stfd_timing_end(stfd_problem *P, double *total_ms, int64_t *launches);
 
 /* Launch shapes of a problem.  With stfd_setup_desc.autotune = 1 the setup timed on the device
  * (2 untimed and 5 timed launches per candidate on a private stream, median kept):
- *   the row groups (1 or 2 sixteen-row groups per wave) of every mode product, per precision and
- *   direction, for directions with n_l <= 80;
+ *   the shape of every mode product, per precision and direction, for directions with n_l <= 80:
+ *   1 or 2 = one 16-column group per wave with 1 or 2 sixteen-row groups; 3 = the wide form (every
+ *   column group of a 16-row tile in one wave, the packed operand staged in LDS per block; not for
+ *   the per-mode operand of a mapped domain's x_1);
  *   the segment length of the time solve and whether its segment transfers are read from tables or
  *   computed in the kernel, for problems with N_s n_t <= 2^21 (larger ones keep the heuristics).
  * Otherwise the values are the heuristics'.  tune_ms: host wall time of the tuning runs. */
@@ -325,6 +327,13 @@ typedef struct {
 } stfd_tuning;
 /* Errors: STFD_EINVAL (NULL argument). */
 int stfd_get_tuning(const stfd_problem *P, stfd_tuning *out);
+/* Sets the mode-product shapes (for instance from a committed tile table) without timing; the
+ * time-solve fields must equal the handle's (its tables are built at setup); directions past d
+ * are ignored.  The results do not depend on the shapes beyond summation order of the dot-product
+ * partials.  Not to be called while a solve on this handle is in flight.
+ * Errors: STFD_EINVAL (NULL argument, a shape outside 1..3 or not allowed for that direction,
+ * time-solve fields that differ). */
+int stfd_set_tuning(stfd_problem *P, const stfd_tuning *in);
 
 /* Host copies of setup data for inspection: U_l (n_l x n_l, row-major,
  * U[j*n_l + k] = entry (j,k), column k = k-th eigenvector) and Lambda_l.

@@ -343,6 +343,125 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Mode product, wide form (large launches with one operand): a wave computes all G = ceil(n / 16)
+// column groups of a 16-row tile, so every In fragment it loads feeds G MFMA chains instead of one,
+// and the packed operand U' of all groups is staged in LDS once per block of 4 waves.  A block
+// walks the tiles of its right-hand side in rounds of 4 consecutive tiles (which share the cache
+// lines straddling their boundaries) with a stride of 4 blocks_per_rhs tiles.  Per tile the vector
+// memory pipeline moves 1/G of the In bytes and none of the U' bytes of the one-group form.
+// Grid (blocks_per_rhs, nrhs); the fused dot products write one partial pair per block.
+// ---------------------------------------------------------------------------
+template <int PREC, typename Tin, typename Tout, int KS, bool DOT>
+__global__ __launch_bounds__(256) void mode_product_wide_kernel(ModeProductArgs a, int64_t blocks_per_rhs) {
+  using Tr = MPTraits<PREC>;
+  using op_t = typename Tr::op_t;
+  using u_t = typename Tr::u_t;
+  constexpr int K = Tr::K;
+  constexpr int E = K / 4;
+  constexpr int G = PREC == MP_BF16 ? KS : (KS + 3) / 4;  // column groups of the packed operand
+  __shared__ u_t Us[G * KS * 64 * E];
+  __shared__ double red[2][4];
+  const int64_t rhs = blockIdx.y;
+  if (a.done && a.done[rhs]) return;  // uniform per block
+  const u_t* Ug = static_cast<const u_t*>(a.U);
+  for (int i = threadIdx.x; i < G * KS * 64 * E; i += blockDim.x) Us[i] = Ug[i];
+  __syncthreads();
+  const int n = a.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, grp = lane >> 4;
+  double dot_a = 0.0, dot_b = 0.0;
+  for (int64_t t0 = int64_t(blockIdx.x) * 4; t0 < a.tiles_per_rhs; t0 += blocks_per_rhs * 4) {
+    const int64_t tile = t0 + wave;
+    if (tile >= a.tiles_per_rhs) break;
+    const int64_t o = rhs * a.outer_per_rhs + tile / a.n_row_tiles;
+    const int64_t row0 = (tile % a.n_row_tiles) * 16;
+    const int rows_here = int(min<int64_t>(16, a.inner - row0));
+    const int64_t base = o * int64_t(n) * a.inner + row0;
+    const Tin* src = static_cast<const Tin*>(a.in) + base;
+    Tout* dst = static_cast<Tout*>(a.out) + base;
+    const int rc = min(col, rows_here - 1);
+    Tin xr[KS][E];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int e = 0; e < E; ++e) xr[ks][e] = src[int64_t(min(ks * K + E * grp + e, n - 1)) * a.inner + rc];
+    // operands of the fused dot products, in the same batch as In (loaded after the stores they
+    // would wait behind every store: the compiler cannot tell that r, z_old and Out do not overlap)
+    double rv[DOT ? G : 1][4], zv[DOT ? G : 1][4];
+    if constexpr (DOT) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int aa = min(16 * g + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
+          const int64_t off = base + int64_t(aa) * a.inner + rc;
+          rv[g][v] = a.dot_r[off];
+          zv[g][v] = a.dot_z[off];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    typename Tr::acc_t acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = typename Tr::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      op_t xb[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) xb[e] = to_op<PREC>(ks * K + E * grp + e < n ? xr[ks][e] : Tin(0));
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        op_t ua[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) ua[e] = to_op<PREC>(Us[((g * KS + ks) * 64 + lane) * E + e]);
+        if constexpr (PREC == MP_F64) {
+          acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0], xb[0], acc[g], 0, 0, 0);
+        } else if constexpr (PREC == MP_F32) {
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[0], xb[0], acc[g], 0, 0, 0);
+        } else {
+          s4_t av, bv;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            av[e] = ua[e];
+            bv[e] = xb[e];
+          }
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[g], 0, 0, 0);
+        }
+      }
+    }
+    if (col < rows_here) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int aa = 16 * g + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
+          if (aa < n) {
+            const int64_t off = int64_t(aa) * a.inner + col;
+            const Tout val = Tout(acc[g][v]);
+            dst[off] = val;
+            if constexpr (DOT) {
+              dot_a += rv[DOT ? g : 0][v] * double(val);
+              dot_b += rv[DOT ? g : 0][v] * zv[DOT ? g : 0][v];
+            }
+          }
+        }
+    }
+  }
+  if constexpr (DOT) {
+    dot_a = wave_sum(dot_a);
+    dot_b = wave_sum(dot_b);
+    if (lane == 0) {
+      red[0][wave] = dot_a;
+      red[1][wave] = dot_b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.part_a[rhs * blocks_per_rhs + blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+      a.part_b[rhs * blocks_per_rhs + blockIdx.x] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Banded time solves (Algorithm 1 step 3): for every spatial mode i solve
 // H_i x_i = y_i, H_i = L_t + mu_i^2 M_t + i mu_i K_t (Section 5.2), Hermitian
 // positive definite with half-bandwidth P, factorised at setup as L D L^H
@@ -1394,7 +1513,16 @@ static int mode_product_row_groups(int n, int64_t inner, int64_t outer_per_rhs) 
 // Blocks (one wave each) of one right-hand side of a mode product: 16-column groups x (tiles of
 // 16 RT rows of every outer slice, padded to a multiple of the XCD count).  Depends only on
 // per-rhs sizes, so the number of dot partials per right-hand side is fixed.
+// Launch shapes of a mode product: 1 or 2 = one column group per wave with that many 16-row groups,
+// kMpWide = every column group per wave (mode_product_wide_kernel, n <= 80, one operand).
+constexpr int kMpWide = 3;
+constexpr int64_t kMpWideBlocks = 1024;  // blocks per right-hand side of the wide form at most
+static int64_t mode_product_wide_blocks(int64_t inner, int64_t outer_per_rhs) {
+  const int64_t tiles = outer_per_rhs * ((inner + 15) / 16);
+  return std::min<int64_t>((tiles + 3) / 4, kMpWideBlocks);
+}
 static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_per_rhs, int rt = 0) {
+  if (rt == kMpWide) return mode_product_wide_blocks(inner, outer_per_rhs);
   const int rows = 16 * (rt > 0 ? rt : mode_product_row_groups(n, inner, outer_per_rhs));
   const int64_t tiles = outer_per_rhs * ((inner + rows - 1) / rows);
   return int64_t((n + 15) / 16) * ((tiles + kXcds - 1) / kXcds * kXcds);
@@ -1464,10 +1592,77 @@ struct DotEpilogue {
 };
 
 template <int PREC, typename Tin, typename Tout>
+static int launch_mode_product_wide(const void* in, void* out, const void* U, int n, int64_t inner, int64_t outer,
+                                    int64_t outer_per_rhs, const int* done, hipStream_t s, const DotEpilogue& ep) {
+  ModeProductArgs a;
+  a.in = in;
+  a.out = out;
+  a.U = U;
+  a.u_slice_stride = 0;
+  a.n = n;
+  a.inner = inner;
+  a.outer = outer;
+  a.outer_per_rhs = outer_per_rhs;
+  a.n_row_tiles = (inner + 15) / 16;
+  a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
+  a.tiles_pad = a.tiles_per_rhs;
+  a.groups = (n + 15) / 16;
+  a.done = done;
+  a.dot_r = ep.r;
+  a.dot_z = ep.zold;
+  a.part_a = ep.part_a;
+  a.part_b = ep.part_b;
+  if (ep.part_a && !std::is_same<Tout, double>::value) return STFD_EINVAL;
+  const int64_t nrhs = outer / outer_per_rhs;
+  const int64_t bpr = mode_product_wide_blocks(inner, outer_per_rhs);
+  if (nrhs < 1 || nrhs > 65535 || bpr < 1) return nrhs < 1 ? STFD_OK : STFD_EINVAL;
+  const dim3 grid(static_cast<unsigned>(bpr), static_cast<unsigned>(nrhs)), block(256);
+  const int ks = mode_product_ks(PREC, n);
+  const bool dot = ep.part_a != nullptr;
+#define STFD_MPW(KV)                                                                                       \
+  case KV:                                                                                                 \
+    if constexpr (std::is_same<Tout, double>::value) {                                                     \
+      if (dot) {                                                                                           \
+        hipLaunchKernelGGL((mode_product_wide_kernel<PREC, Tin, Tout, KV, true>), grid, block, 0, s, a, bpr); \
+        break;                                                                                             \
+      }                                                                                                    \
+    }                                                                                                      \
+    hipLaunchKernelGGL((mode_product_wide_kernel<PREC, Tin, Tout, KV, false>), grid, block, 0, s, a, bpr);  \
+    break;
+  if constexpr (PREC == MP_F64) {
+    switch (ks) {
+      STFD_MPW(1) STFD_MPW(2) STFD_MPW(3) STFD_MPW(4) STFD_MPW(5) STFD_MPW(6) STFD_MPW(7) STFD_MPW(8)
+      STFD_MPW(9) STFD_MPW(10) STFD_MPW(11) STFD_MPW(12) STFD_MPW(13) STFD_MPW(14) STFD_MPW(15) STFD_MPW(16)
+      STFD_MPW(17) STFD_MPW(18) STFD_MPW(19) STFD_MPW(20)
+      default:
+        return STFD_EINVAL;
+    }
+  } else if constexpr (PREC == MP_F32) {
+    switch (ks) {
+      STFD_MPW(4) STFD_MPW(8) STFD_MPW(12) STFD_MPW(16) STFD_MPW(20)
+      default:
+        return STFD_EINVAL;
+    }
+  } else {
+    switch (ks) {
+      STFD_MPW(1) STFD_MPW(2) STFD_MPW(3) STFD_MPW(4) STFD_MPW(5)
+      default:
+        return STFD_EINVAL;
+    }
+  }
+#undef STFD_MPW
+  STFD_HIP(hipGetLastError());
+  return STFD_OK;
+}
+
+template <int PREC, typename Tin, typename Tout>
 static int launch_mode_product(const void* in, void* out, const void* U, int n, int64_t inner, int64_t outer,
                                int64_t outer_per_rhs, const int* done, hipStream_t s,
                                const DotEpilogue& ep = DotEpilogue(), int64_t u_slice_stride = 0, int rt = 0) {
-  if (n < 1 || n > kMaxModeN || outer_per_rhs < 1 || rt < 0 || rt > 2 || (rt == 2 && n > 80)) return STFD_EINVAL;
+  if (n < 1 || n > kMaxModeN || outer_per_rhs < 1 || rt < 0 || rt > kMpWide || (rt >= 2 && n > 80) ||
+      (rt == kMpWide && u_slice_stride != 0))
+    return STFD_EINVAL;
+  if (rt == kMpWide) return launch_mode_product_wide<PREC, Tin, Tout>(in, out, U, n, inner, outer, outer_per_rhs, done, s, ep);
   ModeProductArgs a;
   a.in = in;
   a.out = out;
@@ -1716,7 +1911,8 @@ static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64
 // ---------------------------------------------------------------------------
 // Setup-time autotuning (stfd_setup_desc.autotune): the launch shapes that have a choice are timed
 // on the device on this problem's own sizes and the fastest is kept.
-//  * mode products: one or two 16-row groups per wave (n <= 80), per direction and precision;
+//  * mode products: one or two 16-row groups per wave, or the wide form (every column group per
+//    wave), for n <= 80, per direction and precision;
 //  * time solve: segment length (every compiled one with at most 64 segments) x transfers read
 //    from tables or computed in the solve, where the tables of every candidate are cheap to build
 //    (N_s n_t <= kTuneTsRows); larger problems keep the heuristics.
@@ -1770,7 +1966,8 @@ static int tune_mode_products(stfd_problem* P, TuneClock& C, void* x, void* y) {
       const void* U = P->Upk_fwd[prec][l];
       float best = 0.0f;
       int best_rt = P->mp_rt[prec][l];
-      for (int rt = 1; rt <= 2; ++rt) {
+      for (int rt = 1; rt <= kMpWide; ++rt) {
+        if (rt == kMpWide && slice != 0) continue;  // the wide form takes one operand
         auto launch = [&]() -> int {
           if (prec == MP_F64)
             return launch_mode_product<MP_F64, double, double>(x, y, U, n, inner, outer, outer, nullptr, C.s,
@@ -2298,7 +2495,12 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   // row groups of every product from the heuristic (the autotune below may change them); the dot
   // partials are sized for one row group, the largest block count
   for (int prec = MP_F64; prec <= MP_BF16; ++prec)
-    for (int l = 0; l < hp.d; ++l) P->mp_rt[prec][l] = mode_product_row_groups(hp.n_s[l], mp_inner(hp, l), mp_outer(hp, l));
+    for (int l = 0; l < hp.d; ++l) {
+      const int rt = mode_product_row_groups(hp.n_s[l], mp_inner(hp, l), mp_outer(hp, l));
+      // large launches take the wide form where the operand is one matrix (measured at 3D p = 3
+      // 48^4: FP64 apply 532 -> 468 us, FP32 369 -> 305 us, BF16 321 -> 276 us)
+      P->mp_rt[prec][l] = (rt == 2 && !(l == 0 && P->u_slice0)) ? kMpWide : rt;
+    }
   set_last_blocks(P);
   P->max_parts = std::max<int64_t>(std::max<int64_t>(P->mv_blocks, mp_last_blocks_bound(P)), kVecGrid);
   if ((rc = dev_alloc(P, &P->parts, size_t(6) * P->max_parts * P->max_nrhs)) ||
@@ -2478,6 +2680,23 @@ int stfd_get_tuning(const stfd_problem* P, stfd_tuning* out) {
   out->time_segment_length = P->ts_len;
   out->time_transfers_in_kernel = P->ts_transfers ? 0 : 1;
   out->tune_ms = P->tune_ms;
+  return STFD_OK;
+}
+
+int stfd_set_tuning(stfd_problem* P, const stfd_tuning* in) {
+  if (!P || !in) return STFD_EINVAL;
+  const HostProblem& hp = P->hp;
+  if (in->time_segment_length != P->ts_len || in->time_transfers_in_kernel != (P->ts_transfers ? 0 : 1))
+    return STFD_EINVAL;
+  for (int prec = 0; prec < 3; ++prec)
+    for (int l = 0; l < hp.d; ++l) {
+      const int rt = in->mode_product_row_groups[prec][l];
+      if (rt < 1 || rt > kMpWide || (rt >= 2 && hp.n_s[l] > 80) || (rt == kMpWide && l == 0 && P->u_slice0))
+        return STFD_EINVAL;
+    }
+  for (int prec = 0; prec < 3; ++prec)
+    for (int l = 0; l < hp.d; ++l) P->mp_rt[prec][l] = in->mode_product_row_groups[prec][l];
+  set_last_blocks(P);
   return STFD_OK;
 }
 

@@ -78,6 +78,7 @@ SIGNATURES = {
                                       ctypes.c_int, ctypes.POINTER(PcgInfo), _VP]),
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
     "stfd_get_tuning": (ctypes.c_int, [_VP, _VP]),
+    "stfd_set_tuning": (ctypes.c_int, [_VP, _VP]),
     "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
     "stfd_update_potential": (ctypes.c_int, [_VP, _DP, _VP]),
     "stfd_set_lift_max_iterations": (ctypes.c_int, [_VP, ctypes.c_int]),
@@ -240,6 +241,16 @@ class Problem:
                                             for k, name in enumerate(("fp64", "fp32", "bf16"))},
                 "time_segment_length": t.time_segment_length,
                 "time_transfers_in_kernel": bool(t.time_transfers_in_kernel), "tune_ms": t.tune_ms}
+
+    def set_mode_product_shapes(self, shapes):
+        """stfd_set_tuning: {"fp64"|"fp32"|"bf16": [shape per direction]} (1, 2 = row groups per wave of
+        the one-group form, 3 = the wide form); the time-solve fields are kept."""
+        t = Tuning()
+        _check(_lib().stfd_get_tuning(self._h, ctypes.byref(t)), "stfd_get_tuning")
+        for k, name in enumerate(("fp64", "fp32", "bf16")):
+            for l, v in enumerate(shapes.get(name, [t.mode_product_row_groups[k][l] for l in range(self.d)])):
+                t.mode_product_row_groups[k][l] = int(v)
+        return _check(_lib().stfd_set_tuning(self._h, ctypes.byref(t)), "stfd_set_tuning")
 
     def get_pencil(self, l: int):
         n = self.n_s[l]

@@ -116,6 +116,7 @@ def test_handle_entry_points_reject_null_handle():
     assert lib.stfd_pcg_solve(None, None, None, 1, 1e-8, 10, 0, 0, None, None) == stfd.EINVAL
     assert lib.stfd_set_lift_max_iterations(None, 10) == stfd.EINVAL
     assert lib.stfd_get_tuning(None, ctypes.byref(stfd.Tuning())) == stfd.EINVAL
+    assert lib.stfd_set_tuning(None, ctypes.byref(stfd.Tuning())) == stfd.EINVAL
 
 
 def test_fno_rejects_invalid_descriptors():

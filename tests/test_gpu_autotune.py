@@ -41,7 +41,7 @@ def test_tuned_shapes_valid_and_apply_matches_oracle(d, n_el, p, kind):
     assert t["autotuned"] and not h["autotuned"]
     for prec, rts in t["mode_product_row_groups"].items():
         for l, rt in enumerate(rts):
-            assert rt in (1, 2) and (rt == 1 or lib.n_s[l] <= 80)
+            assert rt in (1, 2, 3) and (rt == 1 or lib.n_s[l] <= 80)
     assert t["time_segment_length"] >= p and (lib.n_t + t["time_segment_length"] - 1) // t["time_segment_length"] <= 64
     r = inputs.random_complex(lib.N, 51)
     rd = torch.from_numpy(r).to(DEV)
@@ -73,3 +73,54 @@ def test_tuned_pcg_matches_heuristic():
         assert rc == 0 and rc_h == 0
         assert abs(info[0]["iters"] - info_h[0]["iters"]) <= max(1, info_h[0]["iters"] // 50)
         assert (torch.linalg.vector_norm(u - u_h) / torch.linalg.vector_norm(u_h)).item() < 1e-6
+
+
+@pytest.mark.parametrize("d,n_el,p,n_el_t", [(2, 64, 3, 64), (2, 15, 3, 21), (3, 16, 2, 11), (3, 31, 3, 7),
+                                             (3, 48, 3, 9)])
+def test_every_shape_gives_the_same_apply(d, n_el, p, n_el_t):
+    """Shapes 1, 2 (one column group per wave, 1 or 2 row groups) and 3 (every column group per wave,
+    U' in LDS) accumulate every output over the same K steps in the same order: the applies agree
+    bit for bit in every precision, and the FP64 one matches the oracle.  The PCG with the fused dot
+    products (whose partials depend on the shape) takes the same iteration count up to one."""
+    from paper_2311_18461_amd import stfd
+    kt = inputs.uniform_open_knots(n_el_t, p)
+    ks = [inputs.uniform_open_knots(n_el, p) for _ in range(d)]
+    lib = stfd.Problem(kt, ks, p, p, 1.0, 1.0)
+    r = inputs.random_complex(lib.N, 61)
+    rd = torch.from_numpy(r).to(DEV)
+    outs = {}
+    for shape in (1, 2, 3):
+        lib.set_mode_product_shapes({prec: [shape] * d for prec in ("fp64", "fp32", "bf16")})
+        assert all(v == [shape] * d for v in lib.get_tuning()["mode_product_row_groups"].values())
+        for prec in ("fp64", "fp32", "bf16"):
+            out = torch.empty_like(rd)
+            lib.apply_preconditioner(rd, out, precision=prec)
+            outs[(shape, prec)] = out
+    torch.cuda.synchronize()
+    for prec in ("fp64", "fp32", "bf16"):
+        assert torch.equal(outs[(1, prec)], outs[(2, prec)]) and torch.equal(outs[(1, prec)], outs[(3, prec)])
+    if lib.N <= 400_000:
+        ref = OProblem(kt, ks, p, p, 1.0)
+        s_ref = FastDiagonalization(ref, precompute_inverse=False).apply(r)
+        s = outs[(3, "fp64")].cpu().numpy()
+        assert max_rel(s, s_ref) < 1e-11 and fiber_rel(s, s_ref, lib.n_t) < 1e-10
+    its = []
+    f = torch.from_numpy(inputs.random_complex(lib.N, 62)).to(DEV)
+    u = torch.empty_like(f)
+    for shape in (1, 3):
+        lib.set_mode_product_shapes({prec: [shape] * d for prec in ("fp64", "fp32", "bf16")})
+        rc, info = lib.pcg_solve(f, u, rtol=1e-9, maxit=500)
+        assert rc == 0
+        its.append(info[0]["iters"])
+    assert abs(its[0] - its[1]) <= 1
+
+
+def test_set_tuning_rejects_invalid_shapes():
+    from paper_2311_18461_amd import stfd
+    kt = inputs.uniform_open_knots(6, 3)
+    lib = stfd.Problem(kt, [inputs.uniform_open_knots(90, 3), kt], 3, 3)  # n_1 = 91 > 80
+    with pytest.raises(stfd.StfdError):
+        lib.set_mode_product_shapes({"fp64": [2, 1]})
+    with pytest.raises(stfd.StfdError):
+        lib.set_mode_product_shapes({"fp64": [1, 4]})
+    lib.set_mode_product_shapes({"fp64": [1, 3]})
