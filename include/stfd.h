@@ -315,8 +315,10 @@ int stfd_timing_end(stfd_problem *P, double *total_ms, int64_t *launches);
  *   1 or 2 = one 16-column group per wave with 1 or 2 sixteen-row groups; 3 = the wide form (every
  *   column group of a 16-row tile in one wave, the packed operand staged in LDS per block; not for
  *   the per-mode operand of a mapped domain's x_1);
- *   the segment length of the time solve and whether its segment transfers are read from tables or
- *   computed in the kernel, for problems with N_s n_t <= 2^21 (larger ones keep the heuristics).
+ *   the segment length of the time solve and its form (every table read; rows of L and 1/D read and
+ *   the segment transfers computed; or all of them computed, the factor rows from the last P rows
+ *   before each segment), for problems with N_s n_t <= 2^21 (larger ones keep the heuristics:
+ *   tables where one right-hand side's grid holds at most one wave per SIMD, else all computed).
  * Otherwise the values are the heuristics'.  tune_ms: host wall time of the tuning runs. */
 typedef struct {
   int autotuned;
@@ -324,6 +326,8 @@ typedef struct {
   int time_segment_length;
   int time_transfers_in_kernel;      /* 1: computed in the solve, 0: read from tables */
   double tune_ms;
+  int time_factors_in_kernel;        /* 1: the rows of L and 1/D are factorised in the solve from a
+                                        per-segment state (implies transfers in kernel) */
 } stfd_tuning;
 /* Errors: STFD_EINVAL (NULL argument). */
 int stfd_get_tuning(const stfd_problem *P, stfd_tuning *out);

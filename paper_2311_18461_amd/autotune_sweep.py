@@ -29,6 +29,13 @@ def _potential(kind, d):
     return None
 
 
+def _form(t):
+    """tables: L, 1/D and transfers read; transfers: L and 1/D read; factor: all computed."""
+    if t["time_factors_in_kernel"]:
+        return "factor"
+    return "transfers" if t["time_transfers_in_kernel"] else "tables"
+
+
 def _apply_us(pr, prec, reps, torch):
     r = torch.from_numpy(inputs.random_complex(pr.N, 1)).to("cuda")
     z = torch.empty_like(r)
@@ -50,7 +57,7 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     args = ap.parse_args()
     print("| workload | d | n_s | n_t | p | precision | row groups (heuristic -> tuned) | time segment "
-          "(heuristic -> tuned) | transfers in kernel (heuristic -> tuned) | apply us heuristic | "
+          "(heuristic -> tuned) | time-solve form (heuristic -> tuned) | apply us heuristic | "
           "apply us tuned | tune ms |")
     print("|---|---|---|---|---|---|---|---|---|---|---|---|")
     for label, d, n_el, p, kind in WORKLOADS:
@@ -67,7 +74,7 @@ def main():
             print(f"| {label} | {d} | {heur.n_s[0]} | {heur.n_t} | {p} | {prec} | "
                   f"{th['mode_product_row_groups'][prec]} -> {tt['mode_product_row_groups'][prec]} | "
                   f"{th['time_segment_length']} -> {tt['time_segment_length']} | "
-                  f"{th['time_transfers_in_kernel']} -> {tt['time_transfers_in_kernel']} | "
+                  f"{_form(th)} -> {_form(tt)} | "
                   f"{uh:.1f} | {ut:.1f} | {tt['tune_ms']:.0f} |", flush=True)
         heur.close()
         tuned.close()

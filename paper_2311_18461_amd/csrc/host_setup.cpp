@@ -517,6 +517,57 @@ int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePla
   return 0;
 }
 
+int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out) {
+  const int nt = hp.n_t, P = hp.p_t;
+  if (len < P || len < 1) return -1;
+  const int segs = (nt + len - 1) / len;
+  if (segs > 64) return -1;
+  const int mpb = 64 / segs;
+  const int64_t nblk = (hp.N_s + mpb - 1) / mpb;
+  out.len = len;
+  out.segs = segs;
+  out.mpb = mpb;
+  out.blocks = nblk;
+  out.Lf.clear();
+  out.Df.clear();
+  out.Tf.clear();
+  out.Tb.clear();
+  out.Sf.assign(size_t(nblk) * P * P * 64, 0.0);
+  const int rows = segs * len;
+  out.Hb.assign(size_t(rows) * (P + 1) * 3, 0.0);
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k <= P && k <= t; ++k) {
+      const size_t ix = size_t(t) * nt + (t - k), o = (size_t(t) * (P + 1) + k) * 3;
+      out.Hb[o] = hp.Lt[ix];
+      out.Hb[o + 1] = hp.Mt[ix];
+      out.Hb[o + 2] = hp.Kt[ix];
+    }
+  out.mu.resize(size_t(hp.N_s));
+  for (int64_t i = 0; i < hp.N_s; ++i) out.mu[size_t(i)] = hp.nu * hp.lam[size_t(i)];
+  for (int64_t i = 0; i < hp.N_s; ++i) {
+    const int64_t b = i / mpb;
+    const int m = int(i - b * mpb);
+    for (int s = 0; s < segs; ++s) {
+      const int lane = m * segs + s, t0 = s * len;
+      int q = 0;
+      auto put = [&](double v) { out.Sf[(size_t(b) * P * P + q++) * 64 + lane] = v; };
+      for (int a = 1; a <= P; ++a)
+        for (int k = 1; k <= P - a; ++k) {
+          const int t = t0 - a;
+          cplx v(0.0, 0.0);
+          if (t >= 0 && t - k >= 0 && t < nt) v = hp.Lfac[(size_t(t) * P + (k - 1)) * hp.N_s + i];
+          put(v.real());
+          put(v.imag());
+        }
+      for (int a = 1; a <= P; ++a) {
+        const int t = t0 - a;
+        put(t >= 0 && t < nt ? 1.0 / hp.Dinv[size_t(t) * hp.N_s + i] : 1.0);
+      }
+    }
+  }
+  return 0;
+}
+
 int host_setup(const stfd_setup_desc_view& v, HostProblem& hp) {
   if (v.d < 1 || v.d > 3 || v.p_t < 1 || v.p_s < 2 || v.p_t > kMaxDeg || v.p_s > kMaxDeg) return -1;
   if (!(v.T > 0.0) || !(v.nu > 0.0) || !std::isfinite(v.T) || !std::isfinite(v.nu)) return -1;

@@ -77,11 +77,20 @@ int time_factors(HostProblem& hp);
 //   Tf[blk][a][c][lane]    = response of z_{t0+len-1-a} to the history z_{t0-1-c}  (complex)
 //   Tb[blk][a][c][lane]    = response of x_{t0+a} to the future x_{t0+len+c}        (complex)
 // Tf and Tb are built only on request (small grids; large grids compute them in the solve).
+// The factor-in-kernel form (large grids) stores no rows of L or 1/D but, per (mode, segment),
+// the part of the factor that the rows of the segment depend on:
+//   Sf[blk][q][lane], q < P^2: the entries L[t0-a][t0-a-k] (a = 1..P, k = 1..P-a; complex, in
+//     that order; zero before t = 0), then D[t0-a] (a = 1..P; 1 before t = 0);
+//   Hb[t][k][3] = (L_t, M_t, K_t)[t][t-k] for k = 0..P (zero outside the matrix and past n_t);
+//   mu[i] = nu lambda_i, so that H_i[t][t-k] = L_t + mu^2 M_t + i mu K_t.
 struct TimeSolvePlan {
   int len = 0, segs = 0, mpb = 0;
   int64_t blocks = 0;
   std::vector<double> Lf, Df, Tf, Tb;
+  std::vector<double> Sf, Hb, mu;
 };
+// State form of the plan (Sf, Hb, mu; no Lf, Df, Tf, Tb).  0, or -1 as time_solve_plan.
+int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out);
 // Segment length for n_t rows of half-bandwidth p_t among the compiled ones, 0 if none fits.
 int time_segment_length(int n_t, int p_t);
 // The compiled segment lengths for half-bandwidth p_t with at most 64 segments (count returned).

@@ -506,13 +506,41 @@ struct TsVec<float> {
 
 // T: storage type of y; A: arithmetic and table type (double for FP64 solves, float for the FP32
 // time solves of the mixed-precision applies, whose tables are FP32 copies of the FP64 ones)
-// FLY: compute the transfers in the solve (large grids: the kernel is bound by table traffic) or
-// load them from the tables Tf, Tb (small grids: at most one wave per SIMD, bound by the dependent
-// chain, which the P extra sweeps per transfer would lengthen).
-template <typename T, typename A, int P, int LEN, bool FLY>
+// MODE 0: rows of L, 1/D and the transfers Tf, Tb read from tables (small grids: at most one wave
+// per SIMD, bound by the dependent chain, which computing them would lengthen);
+// MODE 1: rows of L and 1/D from tables, transfers computed in the solve;
+// MODE 2: transfers computed and the rows of L and 1/D factorised in the solve from the segment's
+// entry state Sf (the last P rows of the factor before the segment) and the time bands Hb (large
+// grids: the kernel is bound by table traffic, and the state is P^2 values per segment instead of
+// LEN (2P + 1)).  The row recurrence is the banded LDL^H step of the host factorisation:
+//   L[t][t-k] = (H[t][t-k] - sum_{kk > k} L[t][t-kk] D[t-kk] conj(L[t-k][t-kk])) / D[t-k],
+//   D[t] = Re H[t][t] - sum_k |L[t][t-k]|^2 D[t-k].
+// 1 / x from the hardware reciprocal refined by Newton steps (two in FP64, one in FP32): within
+// an ulp of the quotient, without the scaling and fix-up sequence of an IEEE division (x > 0 and
+// normal here: the pivots of a Hermitian positive definite matrix)
+__device__ __forceinline__ double ts_recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float ts_recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+template <int MODE>
+struct TsMode {
+  static constexpr bool kFlyTransfers = MODE >= 1;
+  static constexpr bool kFactor = MODE == 2;
+};
+
+template <typename T, typename A, int P, int LEN, int MODE>
 __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf, const A* Df, const A* Tf,
-                                                            const A* Tb, int n_t, int segs, int mpb, int64_t N_s,
+                                                            const A* Tb, const A* Sf, const A* Hb, const A* Mu,
+                                                            int n_t, int segs, int mpb, int64_t N_s,
                                                             int64_t blocks_per_rhs, const int* done) {
+  constexpr bool FLY = TsMode<MODE>::kFlyTransfers;
+  constexpr bool FACTOR = TsMode<MODE>::kFactor;
   using A2 = typename TsVec<A>::t;
   using T2 = typename TsVec<T>::t;
   const int64_t rhs = blockIdx.x / blocks_per_rhs;
@@ -527,6 +555,7 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
   const A2* Lb = reinterpret_cast<const A2*>(Lf) + blk * int64_t(LEN * P * kTsLanes);
   const A* Db = Df + blk * int64_t(LEN * kTsLanes);
   __shared__ A2 Tsh[P * P * kTsLanes];  // this lane's transfer matrix, [a][c][lane]
+  __shared__ A Dsh[FACTOR ? LEN * kTsLanes : 1];  // factor form: this lane's 1/D rows, [j][lane]
   const A2* Tfb = reinterpret_cast<const A2*>(Tf) + blk * int64_t(P * P * kTsLanes);
   const A2* Tbb = reinterpret_cast<const A2*>(Tb) + blk * int64_t(P * P * kTsLanes);
 
@@ -535,34 +564,124 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
   // and idle lanes are masked at the conversion
   A yr[LEN], yi[LEN], lr[LEN][P], li[LEN][P];
   T2 yv[LEN];
-#pragma unroll
-  for (int j = 0; j < LEN; ++j) {
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-      const A2 v = Lb[(j * P + k) * kTsLanes + lane];
-      lr[j][k] = v.x;
-      li[j][k] = v.y;
-    }
-    yv[j] = yb[min(t0 + j, n_t - 1)];
-  }
-  // L[t+k][t] for rows t+k of the next segment (rows jj < P of the neighbour lane)
+  // the inverse pivots of the table forms are loaded where they are used (with the rows above, the
+  // extra registers spilled into AGPR copies inside the dependent sweeps)
+  A tfr[P][P], tfi[P][P], tbr[P][P], tbi[P][P], dv[LEN];
   const bool has_next = s + 1 < segs;
   const int nxt = min(lane + 1, kTsLanes - 1);
   A nlr[P][P], nli[P][P];
+  if constexpr (!FACTOR) {
 #pragma unroll
-  for (int jj = 0; jj < P; ++jj)
+    for (int j = 0; j < LEN; ++j) {
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-      nlr[jj][k] = nli[jj][k] = A(0);
-      if (k >= jj) {
-        const A2 v = Lb[(jj * P + k) * kTsLanes + nxt];
-        nlr[jj][k] = has_next ? v.x : A(0);
-        nli[jj][k] = has_next ? v.y : A(0);
+      for (int k = 0; k < P; ++k) {
+        const A2 v = Lb[(j * P + k) * kTsLanes + lane];
+        lr[j][k] = v.x;
+        li[j][k] = v.y;
+      }
+      yv[j] = yb[min(t0 + j, n_t - 1)];
+    }
+    // L[t+k][t] for rows t+k of the next segment (rows jj < P of the neighbour lane)
+#pragma unroll
+    for (int jj = 0; jj < P; ++jj)
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        nlr[jj][k] = nli[jj][k] = A(0);
+        if (k >= jj) {
+          const A2 v = Lb[(jj * P + k) * kTsLanes + nxt];
+          nlr[jj][k] = has_next ? v.x : A(0);
+          nli[jj][k] = has_next ? v.y : A(0);
+        }
+      }
+  } else {
+    // entry state: window row a - 1 = row t0 - a (a = 1..P) with its entries L[t0-a][t0-a-k]
+    // (k = 1..P-a) and D[t0-a], 1/D[t0-a]
+    A wr[P][P], wi[P][P], wd[P], wdi[P];
+    const A* Sb = Sf + blk * int64_t(P * P * kTsLanes) + lane;
+    const A mu = live ? Mu[mode] : A(0);
+    {
+      int q = 0;
+#pragma unroll
+      for (int a = 1; a <= P; ++a)
+#pragma unroll
+        for (int k = 1; k <= P; ++k) {
+          wr[a - 1][k - 1] = wi[a - 1][k - 1] = A(0);
+          if (k <= P - a) {
+            wr[a - 1][k - 1] = Sb[(q++) * kTsLanes];
+            wi[a - 1][k - 1] = Sb[(q++) * kTsLanes];
+          }
+        }
+#pragma unroll
+      for (int a = 1; a <= P; ++a) {
+        wd[a - 1] = Sb[(q++) * kTsLanes];
+        wdi[a - 1] = ts_recip(wd[a - 1]);
       }
     }
-  // the inverse pivots are loaded where they are used (with the rows above, the extra registers
-  // spilled into AGPR copies inside the dependent sweeps)
-  A tfr[P][P], tfi[P][P], tbr[P][P], tbi[P][P], dv[LEN];
+    const A mu2 = mu * mu;
+#pragma unroll
+    for (int j = 0; j < LEN; ++j) {
+      const int t = t0 + j;
+      const A* hb = Hb + int64_t(t) * ((P + 1) * 3);  // padded rows carry zeros
+      A nr[P + 1], ni[P + 1];  // nr[k] + i ni[k] = L[t][t-k]
+#pragma unroll
+      for (int k = P; k >= 1; --k) {
+        // H[t][t-k] = L_t + mu^2 M_t + i mu K_t
+        A sr = fma(mu2, hb[k * 3 + 1], hb[k * 3]);
+        A si = mu * hb[k * 3 + 2];
+#pragma unroll
+        for (int kk = k + 1; kk <= P; ++kk) {
+          // L[t][t-kk] D[t-kk] conj(L[t-k][t-kk]); row t-k is window row k-1, entry kk-k
+          const A pr = nr[kk] * wd[kk - 1], pi = ni[kk] * wd[kk - 1];
+          const A cr = wr[k - 1][kk - k - 1], ci = wi[k - 1][kk - k - 1];
+          sr -= fma(pr, cr, pi * ci);
+          si -= fma(pi, cr, -pr * ci);
+        }
+        nr[k] = sr * wdi[k - 1];
+        ni[k] = si * wdi[k - 1];
+      }
+      A dt = fma(mu2, hb[1], hb[0]);
+#pragma unroll
+      for (int k = 1; k <= P; ++k) dt -= fma(nr[k], nr[k], ni[k] * ni[k]) * wd[k - 1];
+      const bool row = t < n_t;
+      const A dinv = row ? ts_recip(dt) : A(0);
+#pragma unroll
+      for (int k = 1; k <= P; ++k) {
+        lr[j][k - 1] = row ? nr[k] : A(0);
+        li[j][k - 1] = row ? ni[k] : A(0);
+      }
+      Dsh[j * kTsLanes + lane] = dinv;  // parked until step 3 (registers are the occupancy limit)
+      // shift the window: row t becomes window row 0 with its entries k = 1..P-1
+#pragma unroll
+      for (int a = P - 1; a >= 1; --a) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          wr[a][k] = wr[a - 1][k];
+          wi[a][k] = wi[a - 1][k];
+        }
+        wd[a] = wd[a - 1];
+        wdi[a] = wdi[a - 1];
+      }
+#pragma unroll
+      for (int k = 1; k <= P; ++k) {
+        wr[0][k - 1] = k < P ? nr[k] : A(0);
+        wi[0][k - 1] = k < P ? ni[k] : A(0);
+      }
+      wd[0] = row ? dt : A(1);
+      wdi[0] = row ? dinv : A(1);
+    }
+    // rows of y after the factorisation (its registers are free by then)
+#pragma unroll
+    for (int j = 0; j < LEN; ++j) yv[j] = yb[min(t0 + j, n_t - 1)];
+    // L[t+k][t] of the next segment's first P rows, from the neighbour lane
+#pragma unroll
+    for (int jj = 0; jj < P; ++jj)
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const A vr = __shfl_down(lr[jj < LEN ? jj : 0][k], 1), vi = __shfl_down(li[jj < LEN ? jj : 0][k], 1);
+        nlr[jj][k] = (k >= jj && has_next) ? vr : A(0);
+        nli[jj][k] = (k >= jj && has_next) ? vi : A(0);
+      }
+  }
   load_batch_end();
 #pragma unroll
   for (int j = 0; j < LEN; ++j) {
@@ -700,7 +819,8 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
 #pragma unroll
   for (int j = 0; j < LEN; ++j) {
     STFD_TS_FWD_ROW(j)
-    dv[j] = Db[j * kTsLanes + lane];
+    if constexpr (!FACTOR) dv[j] = Db[j * kTsLanes + lane];
+    else dv[j] = Dsh[j * kTsLanes + lane];
     yr[j] = zr * dv[j];
     yi[j] = zi * dv[j];
   }
@@ -1423,6 +1543,12 @@ struct stfd_problem {
   int64_t upk_slice[3] = {0, 0, 0};  // packed elements per x_1 slice (mapped domain), per precision
   // segmented time-solve tables (layout: TimeSolvePlan in host_setup.h)
   double* TsL = nullptr;
+  double* TsS = nullptr;   // factor-in-kernel form: segment entry states, time bands, nu lambda_i
+  double* TsH = nullptr;
+  double* TsMu = nullptr;
+  float* TsS32 = nullptr;
+  float* TsH32 = nullptr;
+  float* TsMu32 = nullptr;
   double* TsTf = nullptr;  // segment transfers (small grids only, else null)
   double* TsTb = nullptr;
   double* TsD = nullptr;
@@ -1449,7 +1575,7 @@ struct stfd_problem {
   stfd::PcgScalars* sc_host_dev = nullptr;  // device address of sc_host
   int64_t mp_last_blocks[3] = {0, 0, 0};  // per precision: blocks per rhs of the last mode product (dot partials)
   int mp_rt[3][3] = {};                   // [precision][direction]: row groups per wave of the mode products
-  bool ts_transfers = false;              // time solve reads transfer tables (else computes them)
+  int ts_mode = 0;                        // time solve: 0 tables, 1 transfers computed, 2 factor computed
   bool autotuned = false;
   double tune_ms = 0.0;                   // device time spent by the setup's tuning runs
   int64_t u_slice0 = 0;                  // per-mode pencils along x_1 (mapped domain): n_1^2, else 0
@@ -1748,26 +1874,24 @@ static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* don
   const HostProblem& hp = P->hp;
   const int64_t bpr = P->ts_blocks;
   const dim3 grid(unsigned(bpr * nrhs)), block(kTsLanes);
-  const T* L;
-  const T* D;
-  const T* Tf;
-  const T* Tb;
+  const T *L, *D, *Tf, *Tb, *S, *H, *Mu;
   if constexpr (std::is_same<T, double>::value) {
-    L = P->TsL, D = P->TsD, Tf = P->TsTf, Tb = P->TsTb;
+    L = P->TsL, D = P->TsD, Tf = P->TsTf, Tb = P->TsTb, S = P->TsS, H = P->TsH, Mu = P->TsMu;
   } else {
-    L = P->TsL32, D = P->TsD32, Tf = P->TsTf32, Tb = P->TsTb32;
+    L = P->TsL32, D = P->TsD32, Tf = P->TsTf32, Tb = P->TsTb32, S = P->TsS32, H = P->TsH32, Mu = P->TsMu32;
   }
-  // transfer tables exist for small grids only (built at setup when one right-hand side's grid holds
-  // at most one wave per SIMD)
-  const bool fly = Tf == nullptr;
+  const int mode = P->ts_mode;
 #define STFD_TS(PV, LV)                                                                                        \
   if (hp.p_t == PV && P->ts_len == LV) {                                                                       \
-    if (fly)                                                                                                   \
-      hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV, true>), grid, block, 0, s, y, L, D, Tf, Tb, hp.n_t,   \
-                         P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                            \
+    if (mode == 0)                                                                                             \
+      hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV, 0>), grid, block, 0, s, y, L, D, Tf, Tb, S, H, Mu,    \
+                         hp.n_t, P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                    \
+    else if (mode == 1)                                                                                        \
+      hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV, 1>), grid, block, 0, s, y, L, D, Tf, Tb, S, H, Mu,    \
+                         hp.n_t, P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                    \
     else                                                                                                       \
-      hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV, false>), grid, block, 0, s, y, L, D, Tf, Tb, hp.n_t,  \
-                         P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                            \
+      hipLaunchKernelGGL((time_solve_kernel<T, T, PV, LV, 2>), grid, block, 0, s, y, L, D, Tf, Tb, S, H, Mu,    \
+                         hp.n_t, P->ts_segs, P->ts_mpb, hp.N_s, bpr, done);                                    \
     STFD_HIP(hipGetLastError());                                                                               \
     return STFD_OK;                                                                                            \
   }
@@ -1991,7 +2115,13 @@ static int tune_mode_products(stfd_problem* P, TuneClock& C, void* x, void* y) {
   return STFD_OK;
 }
 
-// Segment length and transfer mode of the FP64 time solve (sets P->ts_len and P->ts_transfers).
+// Host tables of the time solve for segment length len and form mode (0: L, 1/D and transfers;
+// 1: L and 1/D; 2: entry states, time bands and nu lambda_i).
+static int time_tables(const HostProblem& hp, int len, int mode, TimeSolvePlan& tp) {
+  return mode == 2 ? time_solve_state_plan(hp, len, tp) : time_solve_plan(hp, len, mode == 0, tp);
+}
+
+// Segment length and form of the FP64 time solve (sets P->ts_len and P->ts_mode).
 static int tune_time_solve(stfd_problem* P, TuneClock& C) {
   const HostProblem& hp = P->hp;
   int cand[3];
@@ -2001,14 +2131,15 @@ static int tune_time_solve(stfd_problem* P, TuneClock& C) {
   STFD_HIP(hipMemsetAsync(y, 0, sizeof(double) * 2 * size_t(hp.N), C.s));
   float best = 0.0f;
   int best_len = P->ts_len, rc = STFD_OK;
-  bool best_tr = P->ts_transfers, have = false;
+  int best_mode = P->ts_mode;
+  bool have = false;
   for (int c = 0; c < nc && rc == STFD_OK; ++c)
-    for (int tr = 0; tr < 2 && rc == STFD_OK; ++tr) {
+    for (int mode = 0; mode < 3 && rc == STFD_OK; ++mode) {
       TimeSolvePlan tp;
-      if (time_solve_plan(hp, cand[c], tr != 0, tp) != 0) continue;
-      double* buf[4] = {nullptr, nullptr, nullptr, nullptr};
-      const std::vector<double>* src[4] = {&tp.Lf, &tp.Df, &tp.Tf, &tp.Tb};
-      for (int k = 0; k < 4 && rc == STFD_OK; ++k) {
+      if (time_tables(hp, cand[c], mode, tp) != 0) continue;
+      double* buf[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+      const std::vector<double>* src[7] = {&tp.Lf, &tp.Df, &tp.Tf, &tp.Tb, &tp.Sf, &tp.Hb, &tp.mu};
+      for (int k = 0; k < 7 && rc == STFD_OK; ++k) {
         if (src[k]->empty()) continue;
         hipError_t e = hipMalloc(&buf[k], sizeof(double) * src[k]->size());
         if (e == hipSuccess) e = hipMemcpy(buf[k], src[k]->data(), sizeof(double) * src[k]->size(), hipMemcpyHostToDevice);
@@ -2022,6 +2153,10 @@ static int tune_time_solve(stfd_problem* P, TuneClock& C) {
         P->TsD = buf[1];
         P->TsTf = buf[2];
         P->TsTb = buf[3];
+        P->TsS = buf[4];
+        P->TsH = buf[5];
+        P->TsMu = buf[6];
+        P->ts_mode = mode;
         P->ts_len = tp.len;
         P->ts_segs = tp.segs;
         P->ts_mpb = tp.mpb;
@@ -2032,18 +2167,18 @@ static int tune_time_solve(stfd_problem* P, TuneClock& C) {
           have = true;
           best = ms;
           best_len = tp.len;
-          best_tr = tr != 0;
+          best_mode = mode;
         }
       }
       (void)hipStreamSynchronize(C.s);
       for (double* b : buf)
         if (b) (void)hipFree(b);
-      P->TsL = P->TsD = P->TsTf = P->TsTb = nullptr;
+      P->TsL = P->TsD = P->TsTf = P->TsTb = P->TsS = P->TsH = P->TsMu = nullptr;
     }
   (void)hipFree(y);
   if (rc != STFD_OK) return rc;
   P->ts_len = best_len;
-  P->ts_transfers = best_tr;
+  P->ts_mode = best_mode;
   return STFD_OK;
 }
 
@@ -2382,9 +2517,10 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   // segmented time-solve tables, time bands, spatial coefficients
   {
     TimeSolvePlan tp;
-    // transfer tables only where one right-hand side's grid holds at most one wave per SIMD
+    // all tables where one right-hand side's grid holds at most one wave per SIMD (the solve is
+    // bound by its dependent chain), else the factor-in-kernel form (bound by table traffic)
     const int mpb = 64 / ((hp.n_t + P->ts_len - 1) / P->ts_len);  // modes per block
-    P->ts_transfers = (hp.N_s + mpb - 1) / mpb <= 4 * int64_t(P->n_cus);
+    P->ts_mode = (hp.N_s + mpb - 1) / mpb <= 4 * int64_t(P->n_cus) ? 0 : 2;
     if (desc->autotune && hp.N_s * hp.n_t <= kTuneTsRows) {
       const auto t0 = std::chrono::steady_clock::now();
       TuneClock C;
@@ -2395,27 +2531,22 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       P->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       P->autotuned = true;
     }
-    const bool transfers = P->ts_transfers;
-    if (time_solve_plan(hp, P->ts_len, transfers, tp) != 0) {
+    if (time_tables(hp, P->ts_len, P->ts_mode, tp) != 0) {
       stfd_destroy(P);
       return STFD_EINVAL;
     }
     P->ts_segs = tp.segs;
     P->ts_mpb = tp.mpb;
     P->ts_blocks = tp.blocks;
-    if ((rc = upload(P, &P->TsL, tp.Lf.data(), tp.Lf.size())) || (rc = upload(P, &P->TsD, tp.Df.data(), tp.Df.size())) ||
-        (transfers && ((rc = upload(P, &P->TsTf, tp.Tf.data(), tp.Tf.size())) ||
-                       (rc = upload(P, &P->TsTb, tp.Tb.data(), tp.Tb.size()))))) {
-      stfd_destroy(P);
-      return rc;
-    }
-    {
-      // FP32 copies of the tables (time solves of the FP32 / BF16 applies)
-      auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
-      const std::vector<float> L32 = f32(tp.Lf), D32 = f32(tp.Df), Tf32 = f32(tp.Tf), Tb32 = f32(tp.Tb);
-      if ((rc = upload(P, &P->TsL32, L32.data(), L32.size())) || (rc = upload(P, &P->TsD32, D32.data(), D32.size())) ||
-          (transfers && ((rc = upload(P, &P->TsTf32, Tf32.data(), Tf32.size())) ||
-                         (rc = upload(P, &P->TsTb32, Tb32.data(), Tb32.size()))))) {
+    // FP64 tables and FP32 copies (time solves of the FP32 / BF16 applies); empty ones stay null
+    auto f32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+    const std::vector<double>* src[7] = {&tp.Lf, &tp.Df, &tp.Tf, &tp.Tb, &tp.Sf, &tp.Hb, &tp.mu};
+    double** d64[7] = {&P->TsL, &P->TsD, &P->TsTf, &P->TsTb, &P->TsS, &P->TsH, &P->TsMu};
+    float** d32[7] = {&P->TsL32, &P->TsD32, &P->TsTf32, &P->TsTb32, &P->TsS32, &P->TsH32, &P->TsMu32};
+    for (int k = 0; k < 7; ++k) {
+      if (src[k]->empty()) continue;
+      const std::vector<float> v32 = f32(*src[k]);
+      if ((rc = upload(P, d64[k], src[k]->data(), src[k]->size())) || (rc = upload(P, d32[k], v32.data(), v32.size()))) {
         stfd_destroy(P);
         return rc;
       }
@@ -2678,7 +2809,8 @@ int stfd_get_tuning(const stfd_problem* P, stfd_tuning* out) {
   for (int prec = 0; prec < 3; ++prec)
     for (int l = 0; l < 3; ++l) out->mode_product_row_groups[prec][l] = l < P->hp.d ? P->mp_rt[prec][l] : 0;
   out->time_segment_length = P->ts_len;
-  out->time_transfers_in_kernel = P->ts_transfers ? 0 : 1;
+  out->time_transfers_in_kernel = P->ts_mode >= 1 ? 1 : 0;
+  out->time_factors_in_kernel = P->ts_mode == 2 ? 1 : 0;
   out->tune_ms = P->tune_ms;
   return STFD_OK;
 }
@@ -2686,7 +2818,8 @@ int stfd_get_tuning(const stfd_problem* P, stfd_tuning* out) {
 int stfd_set_tuning(stfd_problem* P, const stfd_tuning* in) {
   if (!P || !in) return STFD_EINVAL;
   const HostProblem& hp = P->hp;
-  if (in->time_segment_length != P->ts_len || in->time_transfers_in_kernel != (P->ts_transfers ? 0 : 1))
+  if (in->time_segment_length != P->ts_len || in->time_transfers_in_kernel != (P->ts_mode >= 1 ? 1 : 0) ||
+      in->time_factors_in_kernel != (P->ts_mode == 2 ? 1 : 0))
     return STFD_EINVAL;
   for (int prec = 0; prec < 3; ++prec)
     for (int l = 0; l < hp.d; ++l) {

@@ -39,7 +39,7 @@ class SetupDesc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("autotuned", ctypes.c_int), ("mode_product_row_groups", (ctypes.c_int * 3) * 3),
                 ("time_segment_length", ctypes.c_int), ("time_transfers_in_kernel", ctypes.c_int),
-                ("tune_ms", ctypes.c_double)]
+                ("tune_ms", ctypes.c_double), ("time_factors_in_kernel", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -240,7 +240,8 @@ class Problem:
                 "mode_product_row_groups": {name: [t.mode_product_row_groups[k][l] for l in range(self.d)]
                                             for k, name in enumerate(("fp64", "fp32", "bf16"))},
                 "time_segment_length": t.time_segment_length,
-                "time_transfers_in_kernel": bool(t.time_transfers_in_kernel), "tune_ms": t.tune_ms}
+                "time_transfers_in_kernel": bool(t.time_transfers_in_kernel),
+                "time_factors_in_kernel": bool(t.time_factors_in_kernel), "tune_ms": t.tune_ms}
 
     def set_mode_product_shapes(self, shapes):
         """stfd_set_tuning: {"fp64"|"fp32"|"bf16": [shape per direction]} (1, 2 = row groups per wave of
