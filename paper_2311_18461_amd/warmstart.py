@@ -11,8 +11,12 @@ are FP64 PCG solutions (tol 1e-8) of the training seeds stored as FP32; the loss
 relative l2 error; Adam with a cosine learning-rate decay.  At solve time the prediction is
 an initial guess, scaled by the library to the multiple closest to the solution in the A-norm
 (STFD_X0_SCALED); a useless guess gets the factor 0, i.e. the cold start (the fallback).
+Losses: "l2" (relative l2), "energy" (relative energy norm of the potential-free operator of the
+grid), "energy_v" (relative energy norm of each sample's own operator A_V, the norm PCG minimises
+on that sample: the library's matvec after stfd_update_potential with the sample's V).
 
-    python -m paper_2311_18461_amd.warmstart train --out W.npz [--n-train 2000 --epochs 150 --lr 2e-3]
+    python -m paper_2311_18461_amd.warmstart train --out W.npz [--n-train 2000 --epochs 150 --lr 2e-3
+        --loss energy|energy_v|l2 --init W0.npz]
     python -m paper_2311_18461_amd.warmstart evaluate --weights W.npz [--n-test 200]
 """
 from __future__ import annotations
@@ -66,8 +70,12 @@ class AnnulusWorkload:
         f = np.stack([V(*self.feat_xy) * V_SCALE, u.real, u.imag, self.rt[:, 0], self.rt[:, 1]], axis=1)
         return f.astype(np.float32).reshape(self.ns, self.ns, 5)
 
+    def quad_potential(self, V):
+        """V on the spatial Gauss grid (the samples stfd_update_potential takes)."""
+        return np.ascontiguousarray(V(*self.quad_xy), dtype=np.float64)
+
     def rhs(self, V, u0, fbar):
-        self.prob.update_potential(V(*self.quad_xy), stream=self.stream)
+        self.prob.update_potential(self.quad_potential(V), stream=self.stream)
         u0q = self.torch.from_numpy(np.ascontiguousarray(u0(*self.quad_xy))).to(self.dev)
         self.prob.load_vector(fbar, u0_q=u0q, stream=self.stream)
 
@@ -87,6 +95,22 @@ def make_net(wl, max_batch, seed=0):
     cfg["modes1"] = min(cfg["modes1"], wl.ns // 2 + 1)
     cfg["modes2"] = min(cfg["modes2"], wl.ns - wl.ns % 2)
     return stfd.Fno(H=wl.ns, W=wl.ns, c_in=5, c_out=wl.c_out, max_batch=max_batch, seed=seed, **cfg)
+
+
+def sample_energies(wl, targets, Vqs):
+    """t_k^H A_V(k) t_k of every target with its own potential (device float64)."""
+    torch = wl.torch
+    n = targets.shape[1]
+    out = torch.empty(targets.shape[0], dtype=torch.float64, device=wl.dev)
+    e = torch.empty(wl.N, dtype=torch.complex128, device=wl.dev)
+    Ae = torch.empty_like(e)
+    for k in range(targets.shape[0]):
+        wl.prob.update_potential(Vqs[k], stream=wl.stream)
+        stfd.fno_diff_f64(targets[k].contiguous(), None, e, stream=wl.stream)
+        wl.prob.matvec(e, Ae, stream=wl.stream)
+        _, en = stfd.fno_energy_loss(e, Ae, n, 1, stream=wl.stream)
+        out[k] = float(en[0])
+    return out
 
 
 def generate(wl, seed0, count, log=None):
@@ -131,10 +155,18 @@ def target_energies(wl, targets, batch):
     return out
 
 
-def train(wl, feats, targets, epochs=60, batch=16, lr=1e-3, seed=0, loss="energy", log=None):
+def train(wl, feats, targets, epochs=60, batch=16, lr=1e-3, seed=0, loss="energy", log=None, init=None,
+          seed0=TRAIN_SEED0):
     torch = wl.torch
     n = feats.shape[0]
     net = make_net(wl, batch, seed)
+    if init is not None:
+        net.set_params(np.load(init)["theta"])
+    if loss == "energy_v":
+        Vqs = [wl.quad_potential(inputs.annulus_sample(seed0 + k)[0]) for k in range(n)]
+        tE = sample_energies(wl, targets, Vqs)
+        e = torch.empty(batch * wl.N, dtype=torch.complex128, device=wl.dev)
+        Ae = torch.empty_like(e)
     X = torch.from_numpy(feats).to(wl.dev)
     y = torch.empty((batch, wl.ns * wl.ns * wl.c_out), dtype=torch.float32, device=wl.dev)
     dy = torch.empty_like(y)
@@ -157,7 +189,14 @@ def train(wl, feats, targets, epochs=60, batch=16, lr=1e-3, seed=0, loss="energy
             xb = X[idx].contiguous().view(-1)
             tb = targets[idx].contiguous().view(-1)
             net.forward(xb, y.view(-1), batch, stream=wl.stream)
-            if loss == "energy":
+            if loss == "energy_v":
+                stfd.fno_diff_f64(y.view(-1), tb, e, stream=wl.stream)
+                for b, k in enumerate(perm[b0:b0 + batch]):
+                    wl.prob.update_potential(Vqs[int(k)], stream=wl.stream)
+                    wl.prob.matvec(e[b * wl.N:(b + 1) * wl.N], Ae[b * wl.N:(b + 1) * wl.N], stream=wl.stream)
+                lv, _ = stfd.fno_energy_loss(e, Ae, nval, batch, t_energy=tE[idx].contiguous(), dy=dy.view(-1),
+                                             stream=wl.stream)
+            elif loss == "energy":
                 stfd.fno_diff_f64(y.view(-1), tb, e, stream=wl.stream)
                 A0.matvec(e, Ae, nrhs=batch, stream=wl.stream)
                 lv, _ = stfd.fno_energy_loss(e, Ae, nval, batch, t_energy=tE[idx].contiguous(), dy=dy.view(-1),
@@ -238,7 +277,8 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--n-el", type=int, default=N_EL)
-    ap.add_argument("--loss", default="energy", choices=["energy", "l2"])
+    ap.add_argument("--loss", default="energy", choices=["energy", "energy_v", "l2"])
+    ap.add_argument("--init", default=None, help="start the training from these weights")
     ap.add_argument("--results", default=None, help="write per-seed evaluation rows (JSON) here")
     args = ap.parse_args(argv)
     import torch
@@ -251,7 +291,7 @@ def main(argv=None):
         feats, targets, iters = generate(wl, TRAIN_SEED0, args.n_train, log)
         log({"phase": "data_done", "mean_iters": float(np.mean(iters)), "max_iters": int(np.max(iters))})
         net, hist = train(wl, feats, targets, epochs=args.epochs, batch=args.batch, lr=args.lr, loss=args.loss,
-                          log=log)
+                          log=log, init=args.init)
         np.savez_compressed(args.out, theta=net.get_params(), loss=np.array(hist))
         del targets
         rows = evaluate(wl, net, TEST_SEED0, args.n_test, log)
