@@ -317,8 +317,9 @@ int stfd_timing_end(stfd_problem *P, double *total_ms, int64_t *launches);
  *   the per-mode operand of a mapped domain's x_1);
  *   the segment length of the time solve and its form (every table read; rows of L and 1/D read and
  *   the segment transfers computed; or all of them computed, the factor rows from the last P rows
- *   before each segment), for problems with N_s n_t <= 2^21 (larger ones keep the heuristics:
- *   tables where one right-hand side's grid holds at most one wave per SIMD, else all computed).
+ *   before each segment), every form for problems with N_s n_t <= 2^21, the last form only for
+ *   larger ones.  Heuristics without autotune: tables where one right-hand side's grid holds at
+ *   most one wave per SIMD, else all computed.
  * Otherwise the values are the heuristics'.  tune_ms: host wall time of the tuning runs. */
 typedef struct {
   int autotuned;

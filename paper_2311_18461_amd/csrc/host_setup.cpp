@@ -409,9 +409,10 @@ int time_factors(HostProblem& hp) {
 
 // segment lengths compiled per half-bandwidth P (one lane keeps len rows of y, L and 1/D plus two
 // P x P transfers in registers)
-static const int kSegCand[7][3] = {{0, 0, 0}, {8, 16, 0}, {8, 12, 16}, {8, 12, 16}, {6, 8, 12}, {6, 8, 0}, {6, 0, 0}};
+static const int kSegCand[7][4] = {{0, 0, 0, 0}, {8, 16, 0, 0}, {8, 12, 16, 0}, {6, 8, 12, 16},
+                                   {6, 8, 12, 0},  {6, 8, 0, 0},  {6, 0, 0, 0}};
 
-int time_segment_candidates(int n_t, int p_t, int out[3]) {
+int time_segment_candidates(int n_t, int p_t, int out[4]) {
   if (p_t < 1 || p_t > 6 || n_t < 1) return 0;
   int c = 0;
   for (int len : kSegCand[p_t])
@@ -422,7 +423,7 @@ int time_segment_candidates(int n_t, int p_t, int out[3]) {
 int time_segment_length(int n_t, int p_t) {
   // cost = dependent FP64 work per lane: four sweeps of len rows (4P fused multiply-adds each) and
   // two reduced recurrences of S-1 steps (4P^2 + 4P)
-  static const int (&cand)[7][3] = kSegCand;
+  static const int (&cand)[7][4] = kSegCand;
   if (p_t < 1 || p_t > 6 || n_t < 1) return 0;
   int best = 0;
   double best_cost = 0.0;

@@ -94,7 +94,7 @@ int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out);
 // Segment length for n_t rows of half-bandwidth p_t among the compiled ones, 0 if none fits.
 int time_segment_length(int n_t, int p_t);
 // The compiled segment lengths for half-bandwidth p_t with at most 64 segments (count returned).
-int time_segment_candidates(int n_t, int p_t, int out[3]);
+int time_segment_candidates(int n_t, int p_t, int out[4]);
 // 0, or -1 if len does not fit (len < p_t or more than 64 segments).
 int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePlan& out);
 // out_stencil[I][s] += int cq D^{ders[l][0]} phi_I D^{ders[l][1]} phi_J (element Gauss rule, cq on

@@ -489,7 +489,8 @@ __global__ __launch_bounds__(256) void mode_product_wide_kernel(ModeProductArgs 
 constexpr int kTsLanes = 64;
 // compiled (P, LEN) pairs; the segment lengths offered per P by time_segment_length
 #define STFD_TS_INSTANCES                                                                                    \
-  STFD_TS(1, 8) STFD_TS(1, 16) STFD_TS(2, 8) STFD_TS(2, 12) STFD_TS(2, 16) STFD_TS(3, 8) STFD_TS(3, 12)      \
+  STFD_TS(1, 8) STFD_TS(1, 16) STFD_TS(2, 8) STFD_TS(2, 12) STFD_TS(2, 16) STFD_TS(3, 6) STFD_TS(3, 8)       \
+  STFD_TS(3, 12)                                                                                               \
   STFD_TS(3, 16) STFD_TS(4, 6) STFD_TS(4, 8) STFD_TS(4, 12) STFD_TS(5, 6) STFD_TS(5, 8) STFD_TS(6, 6)
 
 // complex pair of the table / arithmetic type A
@@ -2039,7 +2040,8 @@ static int apply_dispatch(stfd_problem* P, const double* r, double* s_out, int64
 //    wave), for n <= 80, per direction and precision;
 //  * time solve: segment length (every compiled one with at most 64 segments) x transfers read
 //    from tables or computed in the solve, where the tables of every candidate are cheap to build
-//    (N_s n_t <= kTuneTsRows); larger problems keep the heuristics.
+//    (N_s n_t <= kTuneTsRows); larger problems try the segment lengths of the factor-in-kernel
+//    form only (its tables are P^2 values per segment).
 // Each candidate runs 2 untimed and 5 timed launches on a private stream; the median decides.
 // ---------------------------------------------------------------------------
 constexpr int64_t kTuneTsRows = int64_t(1) << 21;
@@ -2124,7 +2126,7 @@ static int time_tables(const HostProblem& hp, int len, int mode, TimeSolvePlan& 
 // Segment length and form of the FP64 time solve (sets P->ts_len and P->ts_mode).
 static int tune_time_solve(stfd_problem* P, TuneClock& C) {
   const HostProblem& hp = P->hp;
-  int cand[3];
+  int cand[4];
   const int nc = time_segment_candidates(hp.n_t, hp.p_t, cand);
   double* y = nullptr;
   STFD_HIP(hipMalloc(&y, sizeof(double) * 2 * size_t(hp.N)));
@@ -2135,6 +2137,7 @@ static int tune_time_solve(stfd_problem* P, TuneClock& C) {
   bool have = false;
   for (int c = 0; c < nc && rc == STFD_OK; ++c)
     for (int mode = 0; mode < 3 && rc == STFD_OK; ++mode) {
+      if (mode < 2 && hp.N_s * hp.n_t > kTuneTsRows) continue;  // full tables: large grids skip them
       TimeSolvePlan tp;
       if (time_tables(hp, cand[c], mode, tp) != 0) continue;
       double* buf[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -2521,7 +2524,7 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     // bound by its dependent chain), else the factor-in-kernel form (bound by table traffic)
     const int mpb = 64 / ((hp.n_t + P->ts_len - 1) / P->ts_len);  // modes per block
     P->ts_mode = (hp.N_s + mpb - 1) / mpb <= 4 * int64_t(P->n_cus) ? 0 : 2;
-    if (desc->autotune && hp.N_s * hp.n_t <= kTuneTsRows) {
+    if (desc->autotune) {
       const auto t0 = std::chrono::steady_clock::now();
       TuneClock C;
       if ((rc = C.init()) || (rc = tune_time_solve(P, C))) {
