@@ -62,14 +62,36 @@ class Problem:
         return Y.reshape(-1)
 
     # -- eq. prec_definition --------------------------------------------------
-    def dense_P(self) -> np.ndarray:
-        """P-hat = M_s (x) L_t + nu^2 L_s M_s^-1 L_s (x) M_t + nu L_s (x) (W_t + W_t^*)."""
+    def dense_P(self, shift: float = 0.0) -> np.ndarray:
+        """P-hat = M_s (x) L_t + nu^2 L_s M_s^-1 L_s (x) M_t + nu L_s (x) (W_t + W_t^*).
+
+        shift c: the same construction for S + c (a constant potential), i.e. nu L_s replaced by
+        H_c = nu L_s + c M_s in both places: M_s (x) L_t + H_c M_s^-1 H_c (x) M_t + H_c (x) T3."""
         ko = kron_operators(self.space1d)
         Ms, Ls = ko["M"], ko["L"]
-        LML = Ls @ np.linalg.solve(Ms, Ls)
+        Hc = self.nu * Ls + shift * Ms
+        HMH = Hc @ np.linalg.solve(Ms, Hc)
         t = self.time
-        return (np.kron(Ms, t["L"]) + self.nu ** 2 * np.kron(LML, t["M"])
-                + self.nu * np.kron(Ls, t["T3"]))
+        return np.kron(Ms, t["L"]) + np.kron(HMH, t["M"]) + np.kron(Hc, t["T3"])
+
+
+def mean_potential(knots_s, p: int, V, q: int | None = None) -> float:
+    """Mean of V over the unit cube by the element Gauss rule of the spatial directions (q = p + 1
+    points per element by default): the constant that the shifted preconditioner takes."""
+    from .bspline import gauss_rule
+    q = p + 1 if q is None else q
+    pts, wts = [], []
+    for kn in knots_s:
+        x, w, _ = gauss_rule(np.asarray(kn, dtype=np.float64), q)
+        pts.append(x)
+        wts.append(w)
+    grids = np.meshgrid(*pts, indexing="ij")
+    W = np.ones_like(grids[0])
+    for l, w in enumerate(wts):
+        shape = [1] * len(wts)
+        shape[l] = w.size
+        W = W * w.reshape(shape)
+    return float(np.sum(W * V(*grids)) / np.sum(W))
 
 
 def mapped_pencil(prob: Problem):
@@ -115,12 +137,15 @@ class FastDiagonalization:
     U_l^T M_l U_l = I (eq. space_eig), solved by LAPACK through scipy.linalg.eigh,
     and lambda_i = sum_l lambda_{l,i_l} (Kronecker sum Lambda_s).
     Step 2: y = (U_s^T (x) I_t) r, i.e. mode products with U_l^T.
-    Step 3: x_i = H_i^{-1} y_i with H_i = L_t + nu^2 lambda_i^2 M_t + nu lambda_i (W_t + W_t^*).
+    Step 3: x_i = H_i^{-1} y_i with H_i = L_t + nu^2 lambda_i^2 M_t + nu lambda_i (W_t + W_t^*)
+            (with a shift c: mu_i = nu lambda_i + c in place of nu lambda_i).
     Step 4: s = (U_s (x) I_t) x.
     """
 
-    def __init__(self, prob: Problem, precompute_inverse: bool | None = None):
+    def __init__(self, prob: Problem, precompute_inverse: bool | None = None, shift: float = 0.0):
+        """shift c: P-hat of S + c (see Problem.dense_P); the modes' scalars become nu lambda_i + c."""
         self.prob = prob
+        self.shift = float(shift)
         self.U, self.lam1d = [], []
         for s in prob.space1d:
             lam, U = sla.eigh(s["L"], s["M"])
@@ -143,7 +168,7 @@ class FastDiagonalization:
 
     def H(self, idx) -> np.ndarray:
         """Stack of H_i for the modes in idx (Section 5.2)."""
-        mu = self.prob.nu * self.lam[idx]
+        mu = self.prob.nu * self.lam[idx] + self.shift
         return (self.Lt[None] + (mu ** 2)[:, None, None] * self.Mt[None]
                 + mu[:, None, None] * self.T3[None])
 
