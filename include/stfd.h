@@ -86,6 +86,16 @@ enum { STFD_GEOM_UNIT_CUBE = 0, STFD_GEOM_QUARTER_ANNULUS = 1 };
  * unit cube both choices are the paper's P-hat. */
 enum { STFD_PRECOND_AUTO = 0, STFD_PRECOND_PARAMETRIC = 1 };
 
+/* Potential in the preconditioner (an extension: the paper's P-hat has no potential, Section 5).
+ * STFD_SHIFT_NONE: P-hat as defined.  STFD_SHIFT_MEAN_POTENTIAL (unit cube): P-hat built for
+ * S + c with c the mean of V_quad over the unit cube (element Gauss rule), i.e. nu L_s replaced by
+ * nu L_s + c M_s in eq. prec_definition; the same eigenvectors diagonalise it, and Algorithm 1 runs
+ * with the scalars nu lambda_i + c in the time pencils H_i.  For V = c it satisfies P-hat_c <= A
+ * as P-hat does for V = 0; with a varying potential it cuts PCG iterations (8-Gaussian potential,
+ * p = 3: 92 -> 42 at 32^3).  c is fixed at setup (stfd_update_potential keeps it; see
+ * stfd_get_precond_shift). */
+enum { STFD_SHIFT_NONE = 0, STFD_SHIFT_MEAN_POTENTIAL = 1 };
+
 /* Form of the system matvec (Section 5.3: the residual is the dominant cost of an iteration).
  * STFD_MATVEC_STENCIL stores the spatial factors S_1..S_3 as (2p_s+1)^d-point stencils with
  * per-point coefficients.  STFD_MATVEC_SUMFAC (unit cube, d = 2 or 3, p_s <= 5, V = 0 or V a
@@ -146,6 +156,7 @@ typedef struct {
   int time_condition; /* STFD_TIME_INITIAL or STFD_TIME_FINAL (see below) */
   int autotune;       /* 0: launch shapes from heuristics; 1: stfd_setup times the candidate shapes
                          on the current device and keeps the fastest (see stfd_get_tuning) */
+  int precond_shift;  /* STFD_SHIFT_NONE or STFD_SHIFT_MEAN_POTENTIAL (see below) */
 } stfd_setup_desc;
 
 typedef struct {
@@ -339,6 +350,10 @@ int stfd_get_tuning(const stfd_problem *P, stfd_tuning *out);
  * Errors: STFD_EINVAL (NULL argument, a shape outside 1..3 or not allowed for that direction,
  * time-solve fields that differ). */
 int stfd_set_tuning(stfd_problem *P, const stfd_tuning *in);
+
+/* The constant c of the preconditioner (0 unless set up with STFD_SHIFT_MEAN_POTENTIAL).
+ * Errors: STFD_EINVAL (NULL argument). */
+int stfd_get_precond_shift(const stfd_problem *P, double *c);
 
 /* Host copies of setup data for inspection: U_l (n_l x n_l, row-major,
  * U[j*n_l + k] = entry (j,k), column k = k-th eigenvector) and Lambda_l.

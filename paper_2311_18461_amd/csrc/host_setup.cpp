@@ -367,6 +367,26 @@ void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2]
 
 // LDL^H factors of H_i = L_t + mu^2 M_t + i mu K_t, mu = nu lambda_i (Section 5.2), for the
 // current eigenvalues hp.lam.  0 or -2 (a block is not positive definite).
+double mean_potential(const HostProblem& hp, const double* V_quad) {
+  int64_t Q[3] = {1, 1, 1}, total = 1;
+  for (int l = 0; l < hp.d; ++l) {
+    Q[l] = int64_t(hp.dir_s[l].w.size());
+    total *= Q[l];
+  }
+  double sw = 0.0, swv = 0.0;
+  for (int64_t g = 0; g < total; ++g) {
+    int64_t r = g;
+    double w = 1.0;
+    for (int l = 0; l < hp.d; ++l) {
+      w *= hp.dir_s[l].w[size_t(r % Q[l])];
+      r /= Q[l];
+    }
+    sw += w;
+    swv += w * V_quad[g];
+  }
+  return swv / sw;
+}
+
 int time_factors(HostProblem& hp) {
   const int pt = hp.p_t, nt = hp.n_t;
   const double nu = hp.nu;
@@ -376,7 +396,7 @@ int time_factors(HostProblem& hp) {
     std::vector<cplx> Lrow(size_t(nt) * (pt + 1));  // Lrow[t*(pt+1) + k] = L[t][t-k]
     std::vector<double> D(nt);
     for (int64_t i = 0; i < hp.N_s; ++i) {
-      const double mu = nu * hp.lam[i];
+      const double mu = nu * hp.lam[i] + hp.shift;
       auto H = [&](int r, int c) -> cplx {
         size_t ix = size_t(r) * nt + c;
         return cplx(hp.Lt[ix] + mu * mu * hp.Mt[ix], mu * hp.Kt[ix]);
@@ -544,7 +564,7 @@ int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out) {
       out.Hb[o + 2] = hp.Kt[ix];
     }
   out.mu.resize(size_t(hp.N_s));
-  for (int64_t i = 0; i < hp.N_s; ++i) out.mu[size_t(i)] = hp.nu * hp.lam[size_t(i)];
+  for (int64_t i = 0; i < hp.N_s; ++i) out.mu[size_t(i)] = hp.nu * hp.lam[size_t(i)] + hp.shift;
   for (int64_t i = 0; i < hp.N_s; ++i) {
     const int64_t b = i / mpb;
     const int m = int(i - b * mpb);

@@ -32,6 +32,7 @@ struct HostProblem {
   int d = 0, p_t = 0, p_s = 0;
   double T = 1, nu = 1;
   bool time_final = false;  // time basis without its last function (ultraweak method, Section 4.4)
+  double shift = 0.0;       // constant c of the shifted preconditioner: mu_i = nu lambda_i + c
   Direction dir_t;
   Direction dir_s[3];
   int n_t = 0;
@@ -65,6 +66,9 @@ void gram_1d(const Direction& dir, Gram1D& g);
 int gauss_legendre(int q, double* x, double* w);  // on (-1,1)
 int gen_eig(int n, const double* L, const double* M, double* U, double* lam);  // 0 or -2
 int host_setup(const struct stfd_setup_desc_view& v, HostProblem& hp);
+// Mean of the potential samples V_quad (spatial Gauss grid, x_1 fastest) over the unit cube by the
+// element Gauss rule of hp.dir_s.
+double mean_potential(const HostProblem& hp, const double* V_quad);
 // hp.Sc: the V-free unit-cube stencils from the 1D matrices (kronecker_base), else zeros.
 void base_stencils(HostProblem& hp, bool kronecker_base);
 int time_factors(HostProblem& hp);

@@ -2421,6 +2421,8 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   if (desc->matvec < STFD_MATVEC_AUTO || desc->matvec > STFD_MATVEC_SUMFAC) return STFD_EINVAL;
   if (desc->time_condition != STFD_TIME_INITIAL && desc->time_condition != STFD_TIME_FINAL) return STFD_EINVAL;
   if (desc->autotune != 0 && desc->autotune != 1) return STFD_EINVAL;
+  if (desc->precond_shift != STFD_SHIFT_NONE && desc->precond_shift != STFD_SHIFT_MEAN_POTENTIAL) return STFD_EINVAL;
+  if (desc->precond_shift == STFD_SHIFT_MEAN_POTENTIAL && geom.kind != GEOM_UNIT) return STFD_EINVAL;
   if (desc->time_condition == STFD_TIME_FINAL && geom.kind != GEOM_UNIT) return STFD_EINVAL;
   v.time_final = desc->time_condition == STFD_TIME_FINAL;
   stfd_problem* P = new (std::nothrow) stfd_problem;
@@ -2444,6 +2446,15 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   if (build_spatial_model(hp, geom, desc->V_quad, P->model)) {
     delete P;
     return STFD_EINVAL;
+  }
+  // preconditioner shifted by the mean potential: the time pencils H_i are refactorised with
+  // mu_i = nu lambda_i + c
+  if (desc->precond_shift == STFD_SHIFT_MEAN_POTENTIAL && desc->V_quad) {
+    P->hp.shift = mean_potential(hp, desc->V_quad);
+    if (time_factors(P->hp) != 0) {
+      delete P;
+      return STFD_ENOTSPD;
+    }
   }
   // matvec form: sum-factorised on the unit cube in 3D (by default) when V is a sum of 1D functions
   std::vector<double> sf_bands[3];
@@ -2833,6 +2844,12 @@ int stfd_set_tuning(stfd_problem* P, const stfd_tuning* in) {
   for (int prec = 0; prec < 3; ++prec)
     for (int l = 0; l < hp.d; ++l) P->mp_rt[prec][l] = in->mode_product_row_groups[prec][l];
   set_last_blocks(P);
+  return STFD_OK;
+}
+
+int stfd_get_precond_shift(const stfd_problem* P, double* c) {
+  if (!P || !c) return STFD_EINVAL;
+  *c = P->hp.shift;
   return STFD_OK;
 }
 

@@ -21,6 +21,7 @@ GEOM_UNIT_CUBE, GEOM_QUARTER_ANNULUS = 0, 1
 PRECOND_AUTO, PRECOND_PARAMETRIC = 0, 1
 MATVEC_AUTO, MATVEC_STENCIL, MATVEC_SUMFAC = 0, 1, 2
 TIME_INITIAL, TIME_FINAL = 0, 1  # least-squares method / ultraweak method (Section 4.4)
+SHIFT_NONE, SHIFT_MEAN_POTENTIAL = 0, 1  # preconditioner without / with the mean potential
 X0_ZERO, X0_GIVEN, PCG_GRAPH, X0_SCALED = 0, 1, 2, 4
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
@@ -33,7 +34,7 @@ class SetupDesc(ctypes.Structure):
                 ("V_quad", ctypes.POINTER(ctypes.c_double)), ("n_quad", ctypes.c_int),
                 ("max_nrhs", ctypes.c_int), ("geometry", ctypes.c_int), ("geom", ctypes.c_double * 2),
                 ("precond", ctypes.c_int), ("matvec", ctypes.c_int), ("no_rhs_workspace", ctypes.c_int),
-                ("time_condition", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("time_condition", ctypes.c_int), ("autotune", ctypes.c_int), ("precond_shift", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
@@ -79,6 +80,7 @@ SIGNATURES = {
     "stfd_get_pencil": (ctypes.c_int, [_VP, ctypes.c_int, _DP, _DP]),
     "stfd_get_tuning": (ctypes.c_int, [_VP, _VP]),
     "stfd_set_tuning": (ctypes.c_int, [_VP, _VP]),
+    "stfd_get_precond_shift": (ctypes.c_int, [_VP, _DP]),
     "stfd_load_vector": (ctypes.c_int, [_VP, _VP, _VP, ctypes.POINTER(_VP), _VP, _DP, _I64, _VP]),
     "stfd_update_potential": (ctypes.c_int, [_VP, _DP, _VP]),
     "stfd_set_lift_max_iterations": (ctypes.c_int, [_VP, ctypes.c_int]),
@@ -180,7 +182,7 @@ class Problem:
     def __init__(self, knots_t, knots_s, p_t: int, p_s: int, T: float = 1.0, nu: float = 1.0,
                  V_quad=None, n_quad: int = 0, max_nrhs: int = 1, geometry=GEOM_UNIT_CUBE, radii=(1.0, 2.0),
                  precond=PRECOND_AUTO, rhs_workspace: bool = True, matvec=MATVEC_AUTO,
-                 time_condition=TIME_INITIAL, autotune: bool = False):
+                 time_condition=TIME_INITIAL, autotune: bool = False, precond_shift=SHIFT_NONE):
         d = len(knots_s)
         self._keep = [np.ascontiguousarray(knots_t, dtype=np.float64)]
         desc = SetupDesc()
@@ -207,6 +209,7 @@ class Problem:
         desc.no_rhs_workspace = 0 if rhs_workspace else 1
         desc.time_condition = time_condition
         desc.autotune = 1 if autotune else 0
+        desc.precond_shift = precond_shift
         desc.matvec = matvec
         h = ctypes.c_void_p()
         self._h = None
@@ -231,6 +234,13 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+    @property
+    def precond_shift(self):
+        """stfd_get_precond_shift: the constant c of the preconditioner (0 without a shift)."""
+        c = ctypes.c_double()
+        _check(_lib().stfd_get_precond_shift(self._h, ctypes.byref(c)), "stfd_get_precond_shift")
+        return c.value
 
     def get_tuning(self):
         """stfd_get_tuning: the launch shapes in use (timed at setup when autotune was set)."""

@@ -117,6 +117,7 @@ def test_handle_entry_points_reject_null_handle():
     assert lib.stfd_set_lift_max_iterations(None, 10) == stfd.EINVAL
     assert lib.stfd_get_tuning(None, ctypes.byref(stfd.Tuning())) == stfd.EINVAL
     assert lib.stfd_set_tuning(None, ctypes.byref(stfd.Tuning())) == stfd.EINVAL
+    assert lib.stfd_get_precond_shift(None, ctypes.byref(ctypes.c_double())) == stfd.EINVAL
 
 
 def test_fno_rejects_invalid_descriptors():
@@ -160,4 +161,17 @@ def test_time_condition_rejected_where_it_does_not_apply():
     assert ei.value.code == stfd.EINVAL
     with pytest.raises(stfd.StfdError) as ei:
         stfd.Problem(kn, [kn], 3, 3, time_condition=2)
+    assert ei.value.code == stfd.EINVAL
+
+
+def test_precond_shift_rejected_where_it_does_not_apply():
+    """The mean-potential shift runs on the unit cube only; unknown values are rejected."""
+    stfd = _lib()
+    kn = inputs.uniform_open_knots(4, 3)
+    with pytest.raises(stfd.StfdError) as ei:
+        stfd.Problem(kn, [kn, kn], 3, 3, geometry=stfd.GEOM_QUARTER_ANNULUS,
+                     precond_shift=stfd.SHIFT_MEAN_POTENTIAL)
+    assert ei.value.code == stfd.EINVAL
+    with pytest.raises(stfd.StfdError) as ei:
+        stfd.Problem(kn, [kn], 3, 3, precond_shift=3)
     assert ei.value.code == stfd.EINVAL
