@@ -66,7 +66,8 @@ def time_events(fn, reps, stream):
 
 def batched_section(dev, stream, reps=3):
     """64 wave-packet systems (V = 0, p = 3) dealt over the grids 16^3 .. 64^3: one batched call
-    (graph per iteration, one stream per grid) vs the same systems solved grid by grid and one by one."""
+    (one stream per grid; also with each grid's iteration replayed from a captured graph) vs the same
+    systems solved grid by grid and one by one."""
     import torch
     from paper_2311_18461_amd import inputs, stfd
     work = inputs.batched_2d_workload()
@@ -94,6 +95,8 @@ def batched_section(dev, stream, reps=3):
 
     t_batch, (rc, info) = timed(lambda: stfd.pcg_solve_batched(probs, fs, us, nr, rtol=1e-8, maxit=1000,
                                                                 stream=stream))
+    t_batch_graph, _ = timed(lambda: stfd.pcg_solve_batched(probs, fs, us, nr, rtol=1e-8, maxit=1000,
+                                                           stream=stream, graph=True))
     t_grid, _ = timed(lambda: [pr.pcg_solve(f, u, nrhs=n, rtol=1e-8, maxit=1000, stream=stream)
                                for pr, f, u, n in zip(probs, fs, us, nr)])
 
@@ -106,6 +109,7 @@ def batched_section(dev, stream, reps=3):
     its = [i["iters"] for i in info]
     return {"systems": len(its), "grids": list(work.keys()), "systems_per_grid": nr, "total_dofs": total,
             "batched_ms": round(t_batch, 3), "batched_mdofs": round(total / (t_batch * 1e-3) / 1e6, 2),
+            "batched_graph_ms": round(t_batch_graph, 3),
             "grid_by_grid_ms": round(t_grid, 3), "one_by_one_ms": round(t_one, 3),
             "iterations_min_max": [min(its), max(its)],
             "max_true_rel_res": float(f"{max(i['true_rel_res'] for i in info):.3e}")}
@@ -129,6 +133,89 @@ def warmstart_section(stream, n_eval=20):
     return out
 
 
+def shifted_section(stream, reps=5):
+    """The 2D Gaussian-potential step (right-hand side with lifting + FP64 PCG to 1e-8) with the
+    preconditioner built for S + c, c = mean of V (STFD_SHIFT_MEAN_POTENTIAL), and the 3D p = 3 48^4
+    harmonic solve with it; the headline step keeps the V-free preconditioner of the workload."""
+    import torch
+    from paper_2311_18461_amd import inputs, stfd
+    dev = torch.device("cuda:0")
+    out = {}
+    w = inputs.gaussian_potential_2d_workload(0)
+    ks = [w.knots_s()] * 2
+    prob = stfd.Problem(w.knots_t(), ks, w.p, w.p, w.T, w.nu, V_quad=stfd.sample_on_quad_grid(w.potential, ks, w.p),
+                        precond_shift=stfd.SHIFT_MEAN_POTENTIAL)
+    u0 = torch.from_numpy(prob.sample_space(w.u0)).to(dev)
+    f = torch.empty(prob.N, dtype=torch.complex128, device=dev)
+    u = torch.empty_like(f)
+
+    def step():
+        prob.load_vector(f, u0_q=u0, stream=stream)
+        return prob.pcg_solve(f, u, rtol=1e-8, maxit=1000, stream=stream)
+    step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        rc, info = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) / reps * 1e3
+    out["gauss2d_p3_n64"] = {"shift": round(prob.precond_shift, 6), "step_ms": round(ms, 3),
+                             "mdofs": round(prob.N / (ms * 1e-3) / 1e6, 2), "iterations": info[0]["iters"],
+                             "true_rel_res": float(f"{info[0]['true_rel_res']:.3e}")}
+    prob.close()
+    w = inputs.harmonic_3d_workload(0, n_el=48, p=3, with_potential=True)
+    ks = [w.knots_s()] * 3
+    prob = stfd.Problem(w.knots_t(), ks, 3, 3, w.T, w.nu, V_quad=stfd.sample_on_quad_grid(w.potential, ks, 3),
+                        precond_shift=stfd.SHIFT_MEAN_POTENTIAL, autotune=True)
+    f = torch.empty(prob.N, dtype=torch.complex128, device=dev)
+    u = torch.empty_like(f)
+    prob.load_vector(f, u0_q=torch.from_numpy(prob.sample_space(w.u0)).to(dev), stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rc, info = prob.pcg_solve(f, u, rtol=1e-8, maxit=1000, stream=stream)
+    torch.cuda.synchronize()
+    out["harm3d_p3_n48"] = {"shift": round(prob.precond_shift, 6),
+                            "pcg_ms": round((time.perf_counter() - t1) * 1e3, 2), "iterations": info[0]["iters"],
+                            "true_rel_res": float(f"{info[0]['true_rel_res']:.3e}")}
+    prob.close()
+    return out
+
+
+def ultraweak_section(stream, reps=5):
+    """The 2D Gaussian-potential workload solved by the ultraweak method (Section 4.4): final-condition
+    test space, load vector (f, B_I) + i (u_0, B_I(0)) with no lifting, FP64 PCG to 1e-8 (same
+    preconditioner and kernels as the least-squares solve)."""
+    import torch
+    from paper_2311_18461_amd import inputs, stfd
+    dev = torch.device("cuda:0")
+    w = inputs.gaussian_potential_2d_workload(0)
+    ks = [w.knots_s()] * 2
+    t0 = time.perf_counter()
+    prob = stfd.Problem(w.knots_t(), ks, w.p, w.p, w.T, w.nu, V_quad=stfd.sample_on_quad_grid(w.potential, ks, w.p),
+                        time_condition=stfd.TIME_FINAL)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    u0 = torch.from_numpy(prob.sample_space(w.u0)).to(dev)
+    f = torch.empty(prob.N, dtype=torch.complex128, device=dev)
+    z = torch.empty_like(f)
+
+    def step():
+        prob.load_vector(f, u0_q=u0, stream=stream)
+        return prob.pcg_solve(f, z, rtol=1e-8, maxit=1000, stream=stream)
+    step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        rc, info = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) / reps * 1e3
+    prob.close()
+    return {"workload": "2D p=3 64^3 8-Gaussian potential, wave-packet u_0, f = 0 (ultraweak method)",
+            "n_dof_free": prob.N, "setup_s": round(setup_s, 3), "rhs_and_pcg_ms": round(ms, 3),
+            "mdofs": round(prob.N / (ms * 1e-3) / 1e6, 2), "iterations": info[0]["iters"], "converged": rc == 0,
+            "true_rel_res": float(f"{info[0]['true_rel_res']:.3e}")}
+
+
 def precision_3d_section(stream, cases=((48, 3), (32, 4)), bf16_maxit=300):
     """3D space + time with the seeded harmonic potential (p = 3 at 48^4 elements, p = 4 at 32^4):
     FD apply throughput and error of the FP32 and BF16 mode products against the FP64 apply on the
@@ -141,9 +228,10 @@ def precision_3d_section(stream, cases=((48, 3), (32, 4)), bf16_maxit=300):
         w = inputs.harmonic_3d_workload(0, n_el=n_el, p=p, with_potential=True)
         ks = [w.knots_s()] * 3
         t0 = time.perf_counter()
-        prob = stfd.Problem(w.knots_t(), ks, p, p, w.T, w.nu, V_quad=stfd.sample_on_quad_grid(w.potential, ks, p))
+        prob = stfd.Problem(w.knots_t(), ks, p, p, w.T, w.nu, V_quad=stfd.sample_on_quad_grid(w.potential, ks, p),
+                            autotune=True)
         torch.cuda.synchronize()
-        row = {"n_dof_free": prob.N, "setup_s": round(time.perf_counter() - t0, 2)}
+        row = {"n_dof_free": prob.N, "setup_s": round(time.perf_counter() - t0, 2), "tuning": prob.get_tuning()}
         r = torch.from_numpy(inputs.random_complex(prob.N, 3999)).to(dev)
         z = torch.empty_like(r)
         z64 = torch.empty_like(r)
@@ -449,6 +537,8 @@ def main():
         "roofline": roofline,
     }
     out["table2_p3_n64"] = table2_section(stream)
+    out["ultraweak"] = ultraweak_section(stream)
+    out["mean_potential_preconditioner"] = shifted_section(stream)
     out["batched"] = batched_section(dev, stream)
     out["warm_start"] = warmstart_section(stream)
     if not args.no_3d:
