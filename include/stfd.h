@@ -61,11 +61,12 @@ typedef enum {
 
 /* pcg flags: the initial guess (STFD_X0_ZERO, STFD_X0_GIVEN, or STFD_X0_GIVEN |
  * STFD_X0_SCALED), optionally or-ed with STFD_PCG_GRAPH to replay each iteration from a
- * captured HIP graph.  STFD_X0_SCALED replaces the given x0 by alpha x0 with
- * alpha = Re<x0, f> / <x0, A x0>, the multiple closest to the solution in the A-norm (the
- * norm CG minimises); alpha = 0 (a cold start) when Re<x0, f> <= 0 or when the residual of
- * alpha x0 exceeds ||f||, so a poor guess (for instance a learned prediction) never starts CG
- * farther from the solution, or with a larger residual, than x0 = 0. */
+ * captured HIP graph.  STFD_X0_SCALED replaces the given x0 by alpha x0 with the complex
+ * alpha = <x0, f> / <x0, A x0>, the complex multiple closest to the solution in the A-norm (the
+ * norm CG minimises; it corrects the modulus and the phase of a guess); alpha = 0 (a cold start)
+ * when <x0, A x0> <= 0 or when the residual of alpha x0 exceeds ||f||, so a poor guess (for
+ * instance a learned prediction) never starts CG farther from the solution, or with a larger
+ * residual, than x0 = 0. */
 enum { STFD_X0_ZERO = 0, STFD_X0_GIVEN = 1, STFD_PCG_GRAPH = 2, STFD_X0_SCALED = 4 };
 
 /* Physical domain.  STFD_GEOM_UNIT_CUBE: Omega = (0,1)^d, x = xi.
@@ -164,7 +165,8 @@ typedef struct {
   int status;          /* stfd_status of this right-hand side */
   double rel_res;      /* ||r_k||_2 / ||f||_2 of the recursively updated residual */
   double true_rel_res; /* ||f - A u||_2 / ||f||_2 recomputed with the FP64 matvec */
-  double x0_scale;     /* factor applied to the initial guess (0: cold start, 1: as given) */
+  double x0_scale;     /* modulus |alpha| of the factor applied to the initial guess (0: cold
+                          start; 1 for STFD_X0_GIVEN without scaling) */
 } stfd_pcg_info;
 
 /* Element-wise Gauss-Legendre rule on the non-empty knot spans of an open

@@ -1194,20 +1194,46 @@ __global__ __launch_bounds__(kVecBlock) void pcg_init_kernel(const double* f, co
   if (threadIdx.x == 0) pf[rhs * gridDim.x + blockIdx.x] = s;
 }
 
-// scalar bookkeeping after the initial residual: ||f||^2, ||r_0||, convergence at k = 0
-// Energy-optimal scaling of a given initial guess: with q = A x0, alpha = Re<x0, f> / <x0, q>
-// minimises ||u - alpha x0||_A (u = A^{-1} f); alpha <= 0 (or a non-finite value) means x0 does
-// not help and the start becomes x0 = 0.  x <- alpha x, r = f - alpha q, partials of ||f||^2.
-__global__ __launch_bounds__(kVecBlock) void pcg_x0_scale_kernel(const double* f, const double* q, double* r,
-                                                                  double* x, int64_t n2, const double* pxf,
-                                                                  const double* pxq, int nparts, double* pf,
-                                                                  PcgScalars* sc) {
+// partial sums of <x, f> (real and imaginary part) and Re<x, q> over this block's range
+__global__ __launch_bounds__(kVecBlock) void dot_x0_kernel(const double* x, const double* f, const double* q,
+                                                            int64_t n2, double* pre, double* pim, double* pq) {
   __shared__ double sh[kVecBlock / 64];
   const int rhs = blockIdx.y;
-  const double xf = sum_partials<kVecBlock>(pxf + rhs * nparts, nparts, sh);
+  const double* X = x + rhs * n2;
+  const double* F = f + rhs * n2;
+  const double* Q = q + rhs * n2;
+  double sr = 0.0, si = 0.0, sq = 0.0;
+  for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
+    const double xr = X[k], xi = X[k + 1];
+    sr += xr * F[k] + xi * F[k + 1];  // conj(x) f
+    si += xr * F[k + 1] - xi * F[k];
+    sq += xr * Q[k] + xi * Q[k + 1];
+  }
+  sr = block_sum<kVecBlock>(sr, sh);
+  if (threadIdx.x == 0) pre[rhs * gridDim.x + blockIdx.x] = sr;
+  si = block_sum<kVecBlock>(si, sh);
+  if (threadIdx.x == 0) pim[rhs * gridDim.x + blockIdx.x] = si;
+  sq = block_sum<kVecBlock>(sq, sh);
+  if (threadIdx.x == 0) pq[rhs * gridDim.x + blockIdx.x] = sq;
+}
+
+// scalar bookkeeping after the initial residual: ||f||^2, ||r_0||, convergence at k = 0
+// Energy-optimal scaling of a given initial guess: with q = A x0, the complex factor
+// alpha = <x0, f> / <x0, q> minimises ||u - alpha x0||_A over complex multiples (u = A^{-1} f; it
+// corrects the modulus and the phase of a guess); <x0, q> <= 0 or a non-finite value gives
+// alpha = 0, the cold start.  x <- alpha x, r = f - alpha q, partials of ||f||^2; the scalar
+// state records |alpha|.
+__global__ __launch_bounds__(kVecBlock) void pcg_x0_scale_kernel(const double* f, const double* q, double* r,
+                                                                  double* x, int64_t n2, const double* pxf_re,
+                                                                  const double* pxf_im, const double* pxq, int nparts,
+                                                                  double* pf, PcgScalars* sc) {
+  __shared__ double sh[kVecBlock / 64];
+  const int rhs = blockIdx.y;
+  const double xfr = sum_partials<kVecBlock>(pxf_re + rhs * nparts, nparts, sh);
+  const double xfi = sum_partials<kVecBlock>(pxf_im + rhs * nparts, nparts, sh);
   const double xq = sum_partials<kVecBlock>(pxq + rhs * nparts, nparts, sh);
-  double alpha = xf / xq;
-  if (!(xq > 0.0) || !(xf > 0.0) || !std::isfinite(alpha)) alpha = 0.0;
+  double ar = xfr / xq, ai = xfi / xq;
+  if (!(xq > 0.0) || !std::isfinite(ar) || !std::isfinite(ai)) ar = ai = 0.0;
   const double* F = f + rhs * n2;
   const double* Q = q + rhs * n2;
   double* R = r + rhs * n2;
@@ -1216,14 +1242,15 @@ __global__ __launch_bounds__(kVecBlock) void pcg_x0_scale_kernel(const double* f
   for (int64_t k = (int64_t(blockIdx.x) * kVecBlock + threadIdx.x) * 2; k < n2; k += int64_t(gridDim.x) * kVecBlock * 2) {
     const double fr = F[k], fi = F[k + 1];
     s += fr * fr + fi * fi;
-    R[k] = fr - alpha * Q[k];
-    R[k + 1] = fi - alpha * Q[k + 1];
-    X[k] *= alpha;
-    X[k + 1] *= alpha;
+    const double qr = Q[k], qi = Q[k + 1], xr = X[k], xi = X[k + 1];
+    R[k] = fr - (ar * qr - ai * qi);
+    R[k + 1] = fi - (ar * qi + ai * qr);
+    X[k] = ar * xr - ai * xi;
+    X[k + 1] = ar * xi + ai * xr;
   }
   s = block_sum<kVecBlock>(s, sh);
   if (threadIdx.x == 0) pf[rhs * gridDim.x + blockIdx.x] = s;
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc[rhs].x0_scale = alpha;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[rhs].x0_scale = std::sqrt(ar * ar + ai * ai);
 }
 // A scaled initial guess whose residual exceeds ||f|| is dropped: x = 0, r = f (the cold start),
 // so the residual-based stopping test never starts behind the cold start either.
@@ -2960,8 +2987,10 @@ static int pcg_init(const PcgJob& J, int flags, int precision, double rtol, hipS
     int mode = 1;
     if (flags & STFD_X0_SCALED) {
       double* pc = pb + P->max_parts * P->max_nrhs;
-      hipLaunchKernelGGL(dot2_kernel, vgrid, vblock, 0, s, J.x, J.f, q, n2, pb, pc, nullptr);
-      hipLaunchKernelGGL(pcg_x0_scale_kernel, vgrid, vblock, 0, s, J.f, q, r, J.x, n2, pb, pc, kVecGrid, pa, P->sc);
+      double* pd = pc + P->max_parts * P->max_nrhs;
+      hipLaunchKernelGGL(dot_x0_kernel, vgrid, vblock, 0, s, J.x, J.f, q, n2, pb, pc, pd);
+      hipLaunchKernelGGL(pcg_x0_scale_kernel, vgrid, vblock, 0, s, J.f, q, r, J.x, n2, pb, pc, pd, kVecGrid, pa,
+                         P->sc);
       mode = 2;
     } else {
       hipLaunchKernelGGL(pcg_init_kernel, vgrid, vblock, 0, s, J.f, q, r, J.x, n2, pa);
