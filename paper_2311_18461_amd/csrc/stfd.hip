@@ -535,30 +535,46 @@ struct TsMode {
   static constexpr bool kFactor = MODE == 2;
 };
 
+// One lane of the segmented solve: segment s of one mode, whose n_t rows start at yb (global or
+// LDS memory).  tl: the lane's slot in the table layout (rows of L, 1/D, transfers, entry states;
+// tl + 1 holds the next segment of the same mode); pl: the lane in its wave (shuffles exchange
+// with pl +- 1, which must hold the neighbouring segments of the same mode, and the parking slots
+// Tsh / Dsh of the wave are indexed by it).  Table pointers are offset to the lane's table block.
+template <typename T, typename A>
+struct TsLaneArgs {
+  typename TsVec<T>::t* yb;
+  bool live;
+  int s, segs, n_t;
+  int tl, pl;
+  const A* Lf;
+  const A* Df;
+  const A* Tf;
+  const A* Tb;
+  const A* Sf;
+  const A* Hb;
+  A mu;
+  typename TsVec<A>::t* Tsh;  // [P * P][64] of the wave
+  A* Dsh;                     // [LEN][64] of the wave (factor form)
+};
+
 template <typename T, typename A, int P, int LEN, int MODE>
-__global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf, const A* Df, const A* Tf,
-                                                            const A* Tb, const A* Sf, const A* Hb, const A* Mu,
-                                                            int n_t, int segs, int mpb, int64_t N_s,
-                                                            int64_t blocks_per_rhs, const int* done) {
+__device__ __forceinline__ void time_solve_lane(const TsLaneArgs<T, A>& g) {
   constexpr bool FLY = TsMode<MODE>::kFlyTransfers;
   constexpr bool FACTOR = TsMode<MODE>::kFactor;
   using A2 = typename TsVec<A>::t;
   using T2 = typename TsVec<T>::t;
-  const int64_t rhs = blockIdx.x / blocks_per_rhs;
-  if (done && done[rhs]) return;
-  const int64_t blk = blockIdx.x - rhs * blocks_per_rhs;
-  const int lane = threadIdx.x;
-  const int m = lane / segs, s = lane - m * segs;
-  const int64_t mode = blk * mpb + m;
-  const bool live = m < mpb && mode < N_s;
+  const int s = g.s, segs = g.segs, n_t = g.n_t;
+  const bool live = g.live;
+  const int lane = g.tl;
   const int t0 = s * LEN;
-  T2* yb = reinterpret_cast<T2*>(y) + (rhs * N_s + (live ? mode : 0)) * int64_t(n_t);
-  const A2* Lb = reinterpret_cast<const A2*>(Lf) + blk * int64_t(LEN * P * kTsLanes);
-  const A* Db = Df + blk * int64_t(LEN * kTsLanes);
-  __shared__ A2 Tsh[P * P * kTsLanes];  // this lane's transfer matrix, [a][c][lane]
-  __shared__ A Dsh[FACTOR ? LEN * kTsLanes : 1];  // factor form: this lane's 1/D rows, [j][lane]
-  const A2* Tfb = reinterpret_cast<const A2*>(Tf) + blk * int64_t(P * P * kTsLanes);
-  const A2* Tbb = reinterpret_cast<const A2*>(Tb) + blk * int64_t(P * P * kTsLanes);
+  T2* yb = g.yb;
+  const A2* Lb = reinterpret_cast<const A2*>(g.Lf);
+  const A* Db = g.Df;
+  A2* Tsh = g.Tsh;
+  A* Dsh = g.Dsh;
+  const A2* Tfb = reinterpret_cast<const A2*>(g.Tf);
+  const A2* Tbb = reinterpret_cast<const A2*>(g.Tb);
+  const A* Hb = g.Hb;
 
   // rows of y loaded (clamped addresses) and converted after the whole batch (the compiler moves a
   // conversion next to its load, which made every row wait for its own round trip); rows past n_t
@@ -598,8 +614,8 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
     // entry state: window row a - 1 = row t0 - a (a = 1..P) with its entries L[t0-a][t0-a-k]
     // (k = 1..P-a) and D[t0-a], 1/D[t0-a]
     A wr[P][P], wi[P][P], wd[P], wdi[P];
-    const A* Sb = Sf + blk * int64_t(P * P * kTsLanes) + lane;
-    const A mu = live ? Mu[mode] : A(0);
+    const A* Sb = g.Sf + lane;
+    const A mu = g.mu;
     {
       int q = 0;
 #pragma unroll
@@ -650,7 +666,7 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
         lr[j][k - 1] = row ? nr[k] : A(0);
         li[j][k - 1] = row ? ni[k] : A(0);
       }
-      Dsh[j * kTsLanes + lane] = dinv;  // parked until step 3 (registers are the occupancy limit)
+      Dsh[j * kTsLanes + g.pl] = dinv;  // parked until step 3 (registers are the occupancy limit)
       // shift the window: row t becomes window row 0 with its entries k = 1..P-1
 #pragma unroll
       for (int a = P - 1; a >= 1; --a) {
@@ -770,14 +786,14 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
         A2 v;
         v.x = gr[a];
         v.y = gi[a];
-        Tsh[(a * P + c) * kTsLanes + lane] = v;
+        Tsh[(a * P + c) * kTsLanes + g.pl] = v;
       }
     }
 #pragma unroll
     for (int a = 0; a < P; ++a)
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const A2 v = FLY ? Tsh[(a * P + c) * kTsLanes + lane] : Tfb[(a * P + c) * kTsLanes + lane];
+        const A2 v = FLY ? Tsh[(a * P + c) * kTsLanes + g.pl] : Tfb[(a * P + c) * kTsLanes + lane];
         tfr[a][c] = v.x;
         tfi[a][c] = v.y;
       }
@@ -821,7 +837,7 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
   for (int j = 0; j < LEN; ++j) {
     STFD_TS_FWD_ROW(j)
     if constexpr (!FACTOR) dv[j] = Db[j * kTsLanes + lane];
-    else dv[j] = Dsh[j * kTsLanes + lane];
+    else dv[j] = Dsh[j * kTsLanes + g.pl];
     yr[j] = zr * dv[j];
     yi[j] = zi * dv[j];
   }
@@ -871,14 +887,14 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
         A2 v;
         v.x = gr[a];
         v.y = gi[a];
-        Tsh[(a * P + c) * kTsLanes + lane] = v;
+        Tsh[(a * P + c) * kTsLanes + g.pl] = v;
       }
     }
 #pragma unroll
     for (int a = 0; a < P; ++a)
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const A2 v = FLY ? Tsh[(a * P + c) * kTsLanes + lane] : Tbb[(a * P + c) * kTsLanes + lane];
+        const A2 v = FLY ? Tsh[(a * P + c) * kTsLanes + g.pl] : Tbb[(a * P + c) * kTsLanes + lane];
         tbr[a][c] = v.x;
         tbi[a][c] = v.y;
       }
@@ -931,6 +947,42 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
   }
 #undef STFD_TS_FWD_ROW
 #undef STFD_TS_BWD_ROW
+}
+
+template <typename T, typename A, int P, int LEN, int MODE>
+__global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf, const A* Df, const A* Tf,
+                                                            const A* Tb, const A* Sf, const A* Hb, const A* Mu,
+                                                            int n_t, int segs, int mpb, int64_t N_s,
+                                                            int64_t blocks_per_rhs, const int* done) {
+  using A2 = typename TsVec<A>::t;
+  using T2 = typename TsVec<T>::t;
+  constexpr bool FACTOR = TsMode<MODE>::kFactor;
+  const int64_t rhs = blockIdx.x / blocks_per_rhs;
+  if (done && done[rhs]) return;
+  const int64_t blk = blockIdx.x - rhs * blocks_per_rhs;
+  const int lane = threadIdx.x;
+  const int m = lane / segs;
+  const int64_t mode = blk * mpb + m;
+  const bool live = m < mpb && mode < N_s;
+  __shared__ A2 Tsh[P * P * kTsLanes];            // the lanes' transfer matrices, [a][c][lane]
+  __shared__ A Dsh[FACTOR ? LEN * kTsLanes : 1];  // factor form: the lanes' 1/D rows, [j][lane]
+  TsLaneArgs<T, A> g;
+  g.yb = reinterpret_cast<T2*>(y) + (rhs * N_s + (live ? mode : 0)) * int64_t(n_t);
+  g.live = live;
+  g.s = lane - m * segs;
+  g.segs = segs;
+  g.n_t = n_t;
+  g.tl = g.pl = lane;
+  g.Lf = Lf ? Lf + blk * int64_t(2 * LEN * P * kTsLanes) : nullptr;
+  g.Df = Df ? Df + blk * int64_t(LEN * kTsLanes) : nullptr;
+  g.Tf = Tf ? Tf + blk * int64_t(2 * P * P * kTsLanes) : nullptr;
+  g.Tb = Tb ? Tb + blk * int64_t(2 * P * P * kTsLanes) : nullptr;
+  g.Sf = Sf ? Sf + blk * int64_t(P * P * kTsLanes) : nullptr;
+  g.Hb = Hb;
+  g.mu = (FACTOR && live) ? Mu[mode] : A(0);
+  g.Tsh = Tsh;
+  g.Dsh = Dsh;
+  time_solve_lane<T, A, P, LEN, MODE>(g);
 }
 
 // ---------------------------------------------------------------------------
