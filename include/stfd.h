@@ -158,6 +158,9 @@ typedef struct {
   int autotune;       /* 0: launch shapes from heuristics; 1: stfd_setup times the candidate shapes
                          on the current device and keeps the fastest (see stfd_get_tuning) */
   int precond_shift;  /* STFD_SHIFT_NONE or STFD_SHIFT_MEAN_POTENTIAL (see below) */
+  int fused_segment_length; /* 0: the fused last-direction launch (stfd_tuning.fused_time) takes
+                         its segment length from the heuristic or the autotune; > 0: that length
+                         (STFD_EINVAL where no compiled fused shape with it fits the problem) */
 } stfd_setup_desc;
 
 typedef struct {
@@ -286,7 +289,12 @@ int stfd_matvec(const stfd_problem *P, const void *x_dev, void *y_dev, int64_t n
  * iterations; beta uses the Polak-Ribiere form <r_k+1, z_k+1 - z_k>/<r_k, z_k>.
  * flags: STFD_X0_ZERO (u_dev is overwritten) or STFD_X0_GIVEN (u_dev holds
  * the initial guess), optionally | STFD_PCG_GRAPH (each iteration replayed
- * from a captured HIP graph; same results).  Each right-hand side converges independently (a
+ * from a captured HIP graph; same results).  The captured iterations are kept in the handle (up
+ * to 4 argument sets: f_dev, u_dev, nrhs, precision, rtol, maxit; the least recently used is
+ * dropped) and replayed by later solves with the same arguments, which read the data then in the
+ * buffers (a replay touches only the buffers passed to the call that replays it);
+ * stfd_set_tuning, stfd_update_potential and stfd_timing_begin / _end drop them.  Each
+ * right-hand side converges independently (a
  * converged system is frozen).  info: host array of nrhs entries (may be NULL).
  * precision: arithmetic of the preconditioner (stfd_precision); everything
  * else is FP64.  Returns STFD_OK if all systems converged, STFD_NOT_CONVERGED
@@ -303,7 +311,8 @@ int stfd_pcg_solve(const stfd_problem *P, const void *f_dev, void *u_dev, int64_
  * large ones; each job stops launching iterations once all its systems have
  * converged (converged systems of a job still running are masked by their done
  * flags).  flags as stfd_pcg_solve: with STFD_PCG_GRAPH each job's iteration
- * is replayed from its own captured graph on its stream.  The host polls the
+ * is replayed from its own captured graph on its stream (cached in the job's handle as for
+ * stfd_pcg_solve).  The host polls the
  * jobs' progress without blocking.  The handles must be distinct (each owns
  * one set of work buffers and one stream); a handle must not be used
  * concurrently from another thread.  info: host array of sum_k nrhs[k] entries
@@ -333,7 +342,10 @@ int stfd_timing_end(stfd_problem *P, double *total_ms, int64_t *launches);
  *   before each segment), every form for problems with N_s n_t <= 2^21, the last form only for
  *   larger ones.  Heuristics without autotune: tables where one right-hand side's grid holds at
  *   most one wave per SIMD, else all computed.
- * Otherwise the values are the heuristics'.  tune_ms: host wall time of the tuning runs. */
+ *   and whether the fused form of the last direction (fused_time) beats the separate launches,
+ *   each compiled fused shape that fits timed as a whole FP64 apply.
+ * Otherwise the values are the heuristics' (fused form built where it fits, and off).  The BF16
+ * applies always run separate launches.  tune_ms: host wall time of the tuning runs. */
 typedef struct {
   int autotuned;
   int mode_product_row_groups[3][3]; /* [precision STFD_FP64/FP32/BF16][direction], 0 past d */
@@ -342,15 +354,27 @@ typedef struct {
   double tune_ms;
   int time_factors_in_kernel;        /* 1: the rows of L and 1/D are factorised in the solve from a
                                         per-segment state (implies transfers in kernel) */
+  int fused_time;                    /* 1: the FP64 and FP32 applies run the products along x_d and
+                                        the time solves (Algorithm 1 steps 2-4 of direction d and
+                                        step 3) as one launch, one block per spatial column
+                                        (m_1 .. m_{d-1}) holding its n_d x n_t slab in LDS */
+  int fused_segment_length;          /* segment length of that launch's time solves; 0 where the
+                                        fused form does not apply (d = 1, mapped domain, no compiled
+                                        shape fits) */
+  int fused_factors_in_kernel;       /* its time-solve form, as time_factors_in_kernel (else all
+                                        tables read) */
 } stfd_tuning;
 /* Errors: STFD_EINVAL (NULL argument). */
 int stfd_get_tuning(const stfd_problem *P, stfd_tuning *out);
-/* Sets the mode-product shapes (for instance from a committed tile table) without timing; the
- * time-solve fields must equal the handle's (its tables are built at setup); directions past d
- * are ignored.  The results do not depend on the shapes beyond summation order of the dot-product
- * partials.  Not to be called while a solve on this handle is in flight.
+/* Sets the mode-product shapes (for instance from a committed tile table) and switches the fused
+ * form of the last direction on or off, without timing; the time-solve and fused segment fields
+ * must equal the handle's (their tables are built at setup); directions past d are ignored.  The
+ * results do not depend on the shapes beyond summation order of the dot-product partials; the
+ * fused form rounds as the separate launches with its segment length.  Not to be called while a
+ * solve on this handle is in flight.
  * Errors: STFD_EINVAL (NULL argument, a shape outside 1..3 or not allowed for that direction,
- * time-solve fields that differ). */
+ * time-solve or fused segment fields that differ, fused_time not 0 / 1 or 1 where the fused form
+ * does not apply). */
 int stfd_set_tuning(stfd_problem *P, const stfd_tuning *in);
 
 /* The constant c of the preconditioner (0 unless set up with STFD_SHIFT_MEAN_POTENTIAL).

@@ -460,13 +460,32 @@ int time_segment_length(int n_t, int p_t) {
   return best;
 }
 
-int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePlan& out) {
+// Lane slots of a plan: slot q = block * mpb + m holds mode slot_mode[q] (-1: empty); without a
+// slot list, slot q holds mode q.  Returns the number of blocks, or -1 if the list does not fill
+// whole blocks.
+static int64_t plan_slots(const HostProblem& hp, int mpb, const std::vector<int64_t>* slot_mode,
+                          std::vector<int64_t>& modes) {
+  if (slot_mode) {
+    if (slot_mode->size() % size_t(mpb) != 0) return -1;
+    modes = *slot_mode;
+  } else {
+    const int64_t nblk = (hp.N_s + mpb - 1) / mpb;
+    modes.resize(size_t(nblk * mpb));
+    for (int64_t q = 0; q < nblk * mpb; ++q) modes[size_t(q)] = q < hp.N_s ? q : -1;
+  }
+  return int64_t(modes.size()) / mpb;
+}
+
+int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePlan& out,
+                    const std::vector<int64_t>* slot_mode) {
   const int nt = hp.n_t, P = hp.p_t;
   if (len < P || len < 1) return -1;
   const int segs = (nt + len - 1) / len;
   if (segs > 64) return -1;
   const int mpb = 64 / segs;
-  const int64_t nblk = (hp.N_s + mpb - 1) / mpb;
+  std::vector<int64_t> modes;
+  const int64_t nblk = plan_slots(hp, mpb, slot_mode, modes);
+  if (nblk < 0) return -1;
   out.len = len;
   out.segs = segs;
   out.mpb = mpb;
@@ -481,9 +500,11 @@ int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePla
     return hp.Lfac[(size_t(t) * P + (k - 1)) * hp.N_s + i];
   };
   std::vector<cplx> h(P), g(P);
-  for (int64_t i = 0; i < hp.N_s; ++i) {
-    const int64_t b = i / mpb;
-    const int m = int(i - b * mpb);
+  for (int64_t q = 0; q < nblk * mpb; ++q) {
+    const int64_t i = modes[size_t(q)];
+    if (i < 0) continue;
+    const int64_t b = q / mpb;
+    const int m = int(q - b * mpb);
     for (int s = 0; s < segs; ++s) {
       const int lane = m * segs + s, t0 = s * len;
       for (int j = 0; j < len; ++j) {
@@ -538,13 +559,16 @@ int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePla
   return 0;
 }
 
-int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out) {
+int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out,
+                          const std::vector<int64_t>* slot_mode) {
   const int nt = hp.n_t, P = hp.p_t;
   if (len < P || len < 1) return -1;
   const int segs = (nt + len - 1) / len;
   if (segs > 64) return -1;
   const int mpb = 64 / segs;
-  const int64_t nblk = (hp.N_s + mpb - 1) / mpb;
+  std::vector<int64_t> modes;
+  const int64_t nblk = plan_slots(hp, mpb, slot_mode, modes);
+  if (nblk < 0) return -1;
   out.len = len;
   out.segs = segs;
   out.mpb = mpb;
@@ -565,9 +589,11 @@ int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out) {
     }
   out.mu.resize(size_t(hp.N_s));
   for (int64_t i = 0; i < hp.N_s; ++i) out.mu[size_t(i)] = hp.nu * hp.lam[size_t(i)] + hp.shift;
-  for (int64_t i = 0; i < hp.N_s; ++i) {
-    const int64_t b = i / mpb;
-    const int m = int(i - b * mpb);
+  for (int64_t qs = 0; qs < nblk * mpb; ++qs) {
+    const int64_t i = modes[size_t(qs)];
+    if (i < 0) continue;
+    const int64_t b = qs / mpb;
+    const int m = int(qs - b * mpb);
     for (int s = 0; s < segs; ++s) {
       const int lane = m * segs + s, t0 = s * len;
       int q = 0;

@@ -94,13 +94,17 @@ struct TimeSolvePlan {
   std::vector<double> Sf, Hb, mu;
 };
 // State form of the plan (Sf, Hb, mu; no Lf, Df, Tf, Tb).  0, or -1 as time_solve_plan.
-int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out);
+int time_solve_state_plan(const HostProblem& hp, int len, TimeSolvePlan& out,
+                          const std::vector<int64_t>* slot_mode = nullptr);
 // Segment length for n_t rows of half-bandwidth p_t among the compiled ones, 0 if none fits.
 int time_segment_length(int n_t, int p_t);
 // The compiled segment lengths for half-bandwidth p_t with at most 64 segments (count returned).
 int time_segment_candidates(int n_t, int p_t, int out[4]);
-// 0, or -1 if len does not fit (len < p_t or more than 64 segments).
-int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePlan& out);
+// 0, or -1 if len does not fit (len < p_t or more than 64 segments).  slot_mode (optional): the
+// mode of every lane slot q = blk * mpb + m (-1 for an empty slot; a whole number of blocks), for
+// launches that deal the modes to blocks in another order; by default slot q holds mode q.
+int time_solve_plan(const HostProblem& hp, int len, bool transfers, TimeSolvePlan& out,
+                    const std::vector<int64_t>* slot_mode = nullptr);
 // out_stencil[I][s] += int cq D^{ders[l][0]} phi_I D^{ders[l][1]} phi_J (element Gauss rule, cq on
 // the spatial grid or nullptr for 1), for the Dirichlet-reduced spatial basis.
 void weighted_form(const HostProblem& hp, const double* cq, const int (*ders)[2], double* out_stencil);

@@ -986,6 +986,246 @@ __global__ __launch_bounds__(kTsLanes) void time_solve_kernel(T* y, const A* Lf,
 }
 
 // ---------------------------------------------------------------------------
+// Last direction fused with the time solves (Algorithm 1: the forward product along x_d, step 3
+// and the backward product along x_d in one launch).  The products along x_d and the time solves
+// act on the spatial column (m_1 .. m_{d-1}) alone: the n_d rows of 2 n_t reals of one column,
+// X[j][2t + c], are all that the three steps read and write.  One block per column and
+// right-hand side loads them once into LDS (the slab), then
+//   (1) forward product Y[m][.] = sum_j U'_f[j][m] X[j][.], MFMA tiles (16 modes x 16 reals),
+//       results kept in registers until every wave has read the slab, then written over it;
+//   (2) time solves of the column's n_d modes, H_i x_i = y_i in place in the slab, the lanes laid
+//       out as in time_solve_kernel (mpb modes of `segs` segments per wave); the tables are stored
+//       in a layout of their own (block = column * waves + wave) so that each wave reads whole
+//       table lines;
+//   (3) backward product Z[j][.] = sum_m U'_b[m][j] Y[m][.] from the slab, stored to global memory.
+// The tensor crosses HBM once each way instead of three times, and the intermediate never leaves
+// the CU.  LDS: the slab (n_d rows, ld reals each), the packed backward operand, and one region
+// holding first the packed forward operand, then the waves' transfer / pivot parking of the time
+// solve.  FP64 products solve in FP64; FP32 products store the slab in FP32 and solve in FP32
+// with the FP32 tables (the rounding points of the three-launch path).  Every MFMA chain runs its
+// K steps in the order of the mode-product kernels, so with the same segment length the result
+// equals the three-launch path bit for bit.
+// ---------------------------------------------------------------------------
+struct FusedTimeArgs {
+  const void* in;   // tensor after the forward products of x_1 .. x_{d-1}
+  void* out;        // may equal in (each block reads its column before it writes it)
+  const void* Uf;   // packed forward operand of x_d (fragment order, mode_product_ks K steps)
+  const void* Ub;   // packed backward operand of x_d
+  int n;            // n_d
+  int n_t;
+  int ld;           // slab row stride (reals), even and >= 2 n_t; the MFMA tiles of a row run to
+                    // the next multiple of 16 (into the next row, or the operand after the last
+                    // one: such columns feed only outputs that are not stored)
+  int ks;           // K steps of the packed operands
+  int segs, mpb;    // time-solve lane layout
+  int64_t n_cols;   // columns per right-hand side (N_s / n_d)
+  size_t u_bytes;   // bytes of one packed operand
+  size_t park_off;  // byte offset of the parking region (after the slab and the backward operand)
+  const int* done;
+  const void* Lf;   // time-solve tables in the fused layout (the form's unused ones null)
+  const void* Df;
+  const void* Tf;
+  const void* Tb;
+  const void* Sf;
+  const void* Hb;
+  const void* Mu;   // indexed by spatial mode
+};
+
+constexpr int kFusedTiles = 8;    // output tiles (16 x 16) per wave and product at most (even)
+constexpr int kFusedLoads = 12;   // complex slab entries loaded per thread at most
+constexpr int kFusedULoads = 20;  // packed operand values staged per thread and operand at most
+
+template <int PREC, typename T, int P, int LEN, int MODE, int NW>
+__global__ __launch_bounds__(NW * 64) void fused_time_kernel(FusedTimeArgs a) {
+  static_assert(PREC != MP_BF16, "the fused form runs the FP64 and FP32 products");
+  using Tr = MPTraits<PREC>;
+  using op_t = typename Tr::op_t;
+  using u_t = typename Tr::u_t;
+  using acc_t = typename Tr::acc_t;
+  using T2 = typename TsVec<T>::t;
+  constexpr int K = Tr::K;
+  extern __shared__ __align__(16) unsigned char fz_smem[];
+  const int64_t col = blockIdx.x, rhs = blockIdx.y;
+  if (a.done && a.done[rhs]) return;  // uniform per block
+  const int n = a.n, n_t = a.n_t, ld = a.ld, KS = a.ks;
+  const int KS4 = (KS + 3) / 4 * 4;  // K steps staged in LDS (zeros past KS)
+  const int W = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col16 = lane & 15, grp = lane >> 4;
+  const int64_t row = 2 * int64_t(n_t), inner = a.n_cols * row;
+  T* S = reinterpret_cast<T*>(fz_smem);
+  u_t* Ubs = reinterpret_cast<u_t*>(fz_smem + size_t(n) * ld * sizeof(T));
+  unsigned char* park = fz_smem + a.park_off;  // forward operand, then the time-solve parking
+  u_t* Ufs = reinterpret_cast<u_t*>(park);
+  const T2* src = reinterpret_cast<const T2*>(static_cast<const T*>(a.in) + rhs * int64_t(n) * inner + col * row);
+  T* dst = static_cast<T*>(a.out) + rhs * int64_t(n) * inner + col * row;
+
+  // (0) the slab and both packed operands ([group][K step, padded to KS4][lane]), every load of a
+  // thread issued before its first store
+  {
+    const int ncplx = n * n_t;
+    const int nu = int(a.u_bytes / sizeof(u_t));  // G * KS4 * 64
+    const u_t* Ufg = static_cast<const u_t*>(a.Uf);
+    const u_t* Ubg = static_cast<const u_t*>(a.Ub);
+    T2 v[kFusedLoads];
+    u_t uf[kFusedULoads], ub[kFusedULoads];
+#pragma unroll
+    for (int u = 0; u < kFusedLoads; ++u) {
+      const int i = min(int(threadIdx.x) + u * int(blockDim.x), ncplx - 1);
+      const int j = i / n_t, t = i - j * n_t;
+      v[u] = src[int64_t(j) * (inner / 2) + t];
+    }
+#pragma unroll
+    for (int u = 0; u < kFusedULoads; ++u) {
+      const int i = min(int(threadIdx.x) + u * int(blockDim.x), nu - 1);
+      const int gk = i >> 6, g = gk / KS4, ks = gk - g * KS4;
+      const int src_i = ((g * KS + min(ks, KS - 1)) << 6) + (i & 63);
+      uf[u] = ks < KS ? Ufg[src_i] : u_t(0);
+      ub[u] = ks < KS ? Ubg[src_i] : u_t(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kFusedLoads; ++u) {
+      const int i = int(threadIdx.x) + u * int(blockDim.x);
+      if (i < ncplx) {
+        const int j = i / n_t, t = i - j * n_t;
+        reinterpret_cast<T2*>(S + j * ld)[t] = v[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kFusedULoads; ++u) {
+      const int i = int(threadIdx.x) + u * int(blockDim.x);
+      if (i < nu) {
+        Ufs[i] = uf[u];
+        Ubs[i] = ub[u];
+      }
+    }
+    // padding reals of every row: zeros (they feed only padding outputs, never stored)
+    const int padc = ld - int(row);
+    for (int i = threadIdx.x; i < n * padc; i += blockDim.x) {
+      const int j = i / padc;
+      S[j * ld + int(row) + (i - j * padc)] = T(0);
+    }
+  }
+  __syncthreads();
+
+  const int G = (n + 15) / 16, CT = int(row + 15) / 16, ntiles = G * CT;
+  // two MFMA chains at once (tiles t0, t1 < ntiles): D[16 g + m][16 ct + c] = sum_k U'[k][16 g + m]
+  // B[k][16 ct + c], B from the slab; four K steps of operands loaded per round, the zero steps
+  // past KS add exact zeros
+  auto chain2 = [&](const u_t* Us, int t0, int t1, acc_t& c0, acc_t& c1) {
+    c0 = acc_t{0, 0, 0, 0};
+    c1 = acc_t{0, 0, 0, 0};
+    const int g0 = t0 / CT, g1 = t1 / CT;
+    const u_t* U0 = Us + g0 * KS4 * 64 + lane;
+    const u_t* U1 = Us + g1 * KS4 * 64 + lane;
+    const T* B0 = S + 16 * (t0 - g0 * CT) + col16;
+    const T* B1 = S + 16 * (t1 - g1 * CT) + col16;
+    for (int k4 = 0; k4 < KS4; k4 += 4) {
+      u_t ua0[4], ua1[4];
+      T b0[4], b1[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = min((k4 + e) * K + grp, n - 1);
+        ua0[e] = U0[(k4 + e) * 64];
+        ua1[e] = U1[(k4 + e) * 64];
+        b0[e] = B0[k * ld];
+        b1[e] = B1[k * ld];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool in_k = (k4 + e) * K + grp < n;
+        const op_t x0 = to_op<PREC>(in_k ? b0[e] : T(0)), x1 = to_op<PREC>(in_k ? b1[e] : T(0));
+        if constexpr (PREC == MP_F64) {
+          c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ua0[e], x0, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ua1[e], x1, c1, 0, 0, 0);
+        } else {
+          c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ua0[e], x0, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ua1[e], x1, c1, 0, 0, 0);
+        }
+      }
+    }
+  };
+  // (1) forward product into registers, then over the slab
+  {
+    acc_t acc[kFusedTiles];
+#pragma unroll
+    for (int q = 0; q < kFusedTiles; q += 2) {
+      const int t0 = wave + q * W, t1 = wave + (q + 1) * W;
+      if (t0 < ntiles) chain2(Ufs, t0, min(t1, ntiles - 1), acc[q], acc[q + 1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kFusedTiles; ++q) {
+      const int tile = wave + q * W;
+      if (tile < ntiles) {
+        const int g = tile / CT, ct = tile % CT;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * g + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
+          if (m < n && 16 * ct + col16 < row) S[m * ld + 16 * ct + col16] = T(acc[q][v]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // (2) time solves of the column's modes, in place in the slab
+  {
+    using A2 = typename TsVec<T>::t;
+    const int segs = a.segs, mpb = a.mpb;
+    const int ml = lane / segs;
+    const int m = wave * mpb + ml;
+    const bool live = ml < mpb && m < n;
+    const int64_t blk = col * W + wave;
+    TsLaneArgs<T, T> g;
+    g.yb = reinterpret_cast<T2*>(S + (live ? m : 0) * ld);
+    g.live = live;
+    g.s = lane - ml * segs;
+    g.segs = segs;
+    g.n_t = n_t;
+    g.tl = g.pl = lane;
+    const T* Lf = static_cast<const T*>(a.Lf);
+    const T* Df = static_cast<const T*>(a.Df);
+    const T* Tf = static_cast<const T*>(a.Tf);
+    const T* Tb = static_cast<const T*>(a.Tb);
+    const T* Sf = static_cast<const T*>(a.Sf);
+    g.Lf = Lf ? Lf + blk * int64_t(2 * LEN * P * kTsLanes) : nullptr;
+    g.Df = Df ? Df + blk * int64_t(LEN * kTsLanes) : nullptr;
+    g.Tf = Tf ? Tf + blk * int64_t(2 * P * P * kTsLanes) : nullptr;
+    g.Tb = Tb ? Tb + blk * int64_t(2 * P * P * kTsLanes) : nullptr;
+    g.Sf = Sf ? Sf + blk * int64_t(P * P * kTsLanes) : nullptr;
+    g.Hb = static_cast<const T*>(a.Hb);
+    g.mu = (TsMode<MODE>::kFactor && live) ? static_cast<const T*>(a.Mu)[col + a.n_cols * m] : T(0);
+    // parking of this wave: transfers [P * P][64] (transfers computed), then pivots [LEN][64]
+    // (factor computed)
+    constexpr size_t kTsh = TsMode<MODE>::kFlyTransfers ? P * P * kTsLanes * sizeof(A2) : 0;
+    constexpr size_t kDsh = TsMode<MODE>::kFactor ? LEN * kTsLanes * sizeof(T) : 0;
+    unsigned char* pw = park + size_t(wave) * (kTsh + kDsh);
+    g.Tsh = reinterpret_cast<A2*>(pw);
+    g.Dsh = reinterpret_cast<T*>(pw + kTsh);
+    time_solve_lane<T, T, P, LEN, MODE>(g);
+  }
+  __syncthreads();
+  // (3) backward product from the slab to global memory, two tiles per round
+  for (int t0 = wave; t0 < ntiles; t0 += 2 * W) {
+    const int t1 = t0 + W;
+    acc_t acc[2];
+    chain2(Ubs, t0, min(t1, ntiles - 1), acc[0], acc[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int tile = h ? t1 : t0;
+      const int g = tile / CT, c = 16 * (tile - g * CT) + col16;
+      if (tile < ntiles && c < row) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = 16 * g + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
+          if (j < n) dst[int64_t(j) * inner + c] = T(acc[h][v]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Matrix-free system matvec (Section 5.3, eq. syst_mat with potential terms):
 //   Y = sum_k T_k X S_k^T, X viewed as n_t x N_s (time fastest).
 // Lanes run over the flat (spatial point, t) index of X, so that no lane idles
@@ -1638,6 +1878,24 @@ struct stfd_problem {
   float* TsD32 = nullptr;
   int ts_len = 0, ts_segs = 0, ts_mpb = 0;
   int64_t ts_blocks = 0;
+  // last direction fused with the time solves (fused_time_kernel): tables in the fused layout
+  // (the form's used ones; Mu indexed by spatial mode), launch shape, and whether applies use it
+  double* FzL = nullptr;
+  double* FzD = nullptr;
+  double* FzTf = nullptr;
+  double* FzTb = nullptr;
+  double* FzS = nullptr;
+  double* FzH = nullptr;
+  double* FzMu = nullptr;
+  float* FzL32 = nullptr;
+  float* FzD32 = nullptr;
+  float* FzTf32 = nullptr;
+  float* FzTb32 = nullptr;
+  float* FzS32 = nullptr;
+  float* FzH32 = nullptr;
+  float* FzMu32 = nullptr;
+  int fz_len = 0, fz_mode = 0, fz_nw = 0, fz_waves = 0, fz_segs = 0, fz_mpb = 0;
+  bool fz_on = false;
   double* Sc = nullptr;
   double* TbL = nullptr;  // time bands in the matvec's LDS layout
   double* work64[2] = {nullptr, nullptr};
@@ -1675,6 +1933,19 @@ struct stfd_problem {
   bool sf_on = false;               // the matvec runs sum-factorised (no stencils are stored)
   stfd::SumFacPlan sf;
   std::vector<void*> allocs;
+  // captured PCG iterations (STFD_PCG_GRAPH), kept for later solves with the same arguments: the
+  // two graph executables of one job (iteration parities) and what their kernels were captured with
+  struct CachedIterations {
+    const double* f = nullptr;
+    double* x = nullptr;
+    int64_t nrhs = 0;
+    int precision = 0, maxit = 0;
+    double rtol = 0.0;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    uint64_t used = 0;
+  };
+  std::vector<CachedIterations> graphs;
+  uint64_t graph_clock = 0;
   // HIP-event timing of the mode-product launches (stfd_timing_begin / stfd_timing_end)
   bool timing = false;
   std::vector<hipEvent_t> tev;  // start/end pairs, recorded on the launch stream
@@ -1682,6 +1953,8 @@ struct stfd_problem {
 };
 
 namespace stfd {
+
+static void graph_cache_clear(stfd_problem* P);  // drops the captured PCG iterations of a handle
 
 template <typename T>
 static int dev_alloc(stfd_problem* P, T** ptr, size_t count) {
@@ -1980,6 +2253,115 @@ static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* don
   return STFD_EINVAL;
 }
 
+// Fused last-direction launches (fused_time_kernel): the compiled (P, LEN, form, waves per block
+// at most).  Four-wave blocks leave each wave the whole register file of its SIMD (long segments);
+// eight-wave blocks take the columns whose modes need more waves.
+#define STFD_FZ_INSTANCES                                                                              \
+  STFD_FZ(3, 8, 2, 8) STFD_FZ(3, 16, 2, 4) STFD_FZ(4, 8, 2, 4) STFD_FZ(4, 12, 2, 4)
+
+struct FusedShape {
+  int len = 0, mode = 0, nw = 0, waves = 0, segs = 0, mpb = 0, ld = 0;
+  size_t lds = 0, u_bytes = 0, park_off = 0;
+};
+
+// Launch shape of the fused form (segment length len, time-solve form mode, block bound nw) in
+// precision prec; false where it does not apply or fit (waves, tiles, loads, LDS).
+static bool fused_shape(const stfd_problem* P, int prec, int len, int mode, int nw, FusedShape& f) {
+  const HostProblem& hp = P->hp;
+  if (hp.d < 2 || P->u_slice0 || prec == MP_BF16 || len < hp.p_t) return false;
+  const int n = hp.n_s[hp.d - 1], nt = hp.n_t, pt = hp.p_t;
+  const int segs = (nt + len - 1) / len;
+  if (segs > 64) return false;
+  const int mpb = 64 / segs, waves = (n + mpb - 1) / mpb;
+  if (waves > nw) return false;
+  const int G = (n + 15) / 16, CT = (2 * nt + 15) / 16;
+  const int ks4 = (mode_product_ks(prec, n) + 3) / 4 * 4;
+  if (G * CT > kFusedTiles * waves || int64_t(n) * nt > int64_t(kFusedLoads) * waves * 64 ||
+      G * ks4 * 64 > kFusedULoads * waves * 64)
+    return false;
+  const size_t tb = prec == MP_F64 ? sizeof(double) : sizeof(float);
+  f.len = len;
+  f.mode = mode;
+  f.nw = nw;
+  f.waves = waves;
+  f.segs = segs;
+  f.mpb = mpb;
+  f.ld = 2 * nt;
+  f.u_bytes = size_t(G) * ks4 * 64 * tb;  // one value per lane and K step, K steps padded to 4
+  f.park_off = (size_t(n) * f.ld * tb + f.u_bytes + 15) / 16 * 16;
+  const size_t tsh = mode >= 1 ? size_t(pt) * pt * 64 * 2 * tb : 0;
+  const size_t dsh = mode == 2 ? size_t(len) * 64 * tb : 0;
+  f.lds = f.park_off + std::max(f.u_bytes, size_t(waves) * (tsh + dsh));
+  return f.lds <= P->max_lds;
+}
+
+template <int PREC, typename T>
+static const void* fused_kernel(int p, int len, int mode, int nw) {
+#define STFD_FZ(PV, LV, MV, NV)                                  \
+  if (p == PV && len == LV && mode == MV && nw == NV)           \
+    return reinterpret_cast<const void*>(&fused_time_kernel<PREC, T, PV, LV, MV, NV>);
+  STFD_FZ_INSTANCES
+#undef STFD_FZ
+  return nullptr;
+}
+
+// Tables of the fused form in its lane layout: block = column * waves + wave, slot m of a wave =
+// mode wave * mpb + m of x_d in that column (spatial mode column + n_cols * m).
+static int fused_tables(const HostProblem& hp, const FusedShape& f, TimeSolvePlan& tp) {
+  const int n = hp.n_s[hp.d - 1];
+  const int64_t ncols = hp.N_s / n;
+  std::vector<int64_t> slots(size_t(ncols) * f.waves * f.mpb, -1);
+  for (int64_t c = 0; c < ncols; ++c)
+    for (int w = 0; w < f.waves; ++w)
+      for (int ml = 0; ml < f.mpb; ++ml) {
+        const int m = w * f.mpb + ml;
+        if (m < n) slots[size_t((c * f.waves + w) * f.mpb + ml)] = c + ncols * m;
+      }
+  return f.mode == 2 ? time_solve_state_plan(hp, f.len, tp, &slots)
+                     : time_solve_plan(hp, f.len, f.mode == 0, tp, &slots);
+}
+
+// Fused x_d products and time solves, in place allowed (in == out).
+template <int PREC, typename T>
+static int launch_fused_time(stfd_problem* P, const T* in, T* out, int64_t nrhs, const int* done, hipStream_t s) {
+  const HostProblem& hp = P->hp;
+  FusedShape f;
+  if (!fused_shape(P, PREC, P->fz_len, P->fz_mode, P->fz_nw, f)) return STFD_EINVAL;
+  if (nrhs < 1) return STFD_OK;
+  if (nrhs > 65535) return STFD_EINVAL;
+  const void* fn = fused_kernel<PREC, T>(hp.p_t, f.len, f.mode, f.nw);
+  if (!fn) return STFD_EINVAL;
+  const int l = hp.d - 1;
+  FusedTimeArgs a;
+  a.in = in;
+  a.out = out;
+  a.Uf = P->Upk_fwd[PREC][l];
+  a.Ub = P->Upk_bwd[PREC][l];
+  a.n = hp.n_s[l];
+  a.n_t = hp.n_t;
+  a.ld = f.ld;
+  a.ks = mode_product_ks(PREC, a.n);
+  a.segs = f.segs;
+  a.mpb = f.mpb;
+  a.n_cols = hp.N_s / a.n;
+  a.u_bytes = f.u_bytes;
+  a.park_off = f.park_off;
+  a.done = done;
+  if constexpr (std::is_same<T, double>::value) {
+    a.Lf = P->FzL, a.Df = P->FzD, a.Tf = P->FzTf, a.Tb = P->FzTb, a.Sf = P->FzS, a.Hb = P->FzH, a.Mu = P->FzMu;
+  } else {
+    a.Lf = P->FzL32, a.Df = P->FzD32, a.Tf = P->FzTf32, a.Tb = P->FzTb32, a.Sf = P->FzS32, a.Hb = P->FzH32,
+    a.Mu = P->FzMu32;
+  }
+  if ((f.mode == 2 && (!a.Sf || !a.Hb || !a.Mu)) || (f.mode < 2 && (!a.Lf || !a.Df)) ||
+      (f.mode == 0 && (!a.Tf || !a.Tb)))
+    return STFD_EINVAL;
+  void* args[] = {&a};
+  STFD_HIP(hipLaunchKernel(fn, dim3(unsigned(a.n_cols), unsigned(nrhs)), dim3(unsigned(f.waves * 64)), args,
+                           f.lds, s));
+  return STFD_OK;
+}
+
 // Algorithm 1 steps 2-4 on nrhs stacked vectors.  TW = storage of the intermediates that still
 // have a physical direction; TY = storage of the mode-basis tensor that the time solves work on
 // (written by the last forward product into the buffer that product does not read, and read by
@@ -2029,11 +2411,15 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
   auto Ufwd = [&](int l) -> const void* { return P->Upk_fwd[PREC][l]; };
   auto Ubwd = [&](int l) -> const void* { return P->Upk_bwd[PREC][l]; };
   int rc;
+  // the last direction fused with the time solves: x_1 .. x_{d-1} run as separate products
+  static_assert(std::is_same<TW, TY>::value, "the fused form works in one storage type");
+  const bool fused = P->fz_on && PREC != MP_BF16 && d >= 2 && !P->u_slice0;
+  const int kf = fused ? d - 1 : d;  // directions with separate forward / backward products
   // step 2: y = (U_s^T (x) I) r; r (FP64) -> w0 -> w1 -> ... -> y (TY)
   void* bufs[2] = {w0, w1};
   int cur = 0;
   const void* src = r;  // input of the next product: r, then bufs[cur]
-  for (int k = 0; k < d; ++k) {
+  for (int k = 0; k < kf; ++k) {
     const int l = order[k];
     void* dst = (k == 0) ? bufs[0] : bufs[cur ^ 1];
     const bool first = (k == 0), last = (k == d - 1);
@@ -2054,13 +2440,19 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
     if (k > 0) cur ^= 1;
     src = bufs[cur];
   }
-  // step 3: N_s independent banded time solves, in place
-  rc = launch_time_solve<TY>(P, static_cast<TY*>(bufs[cur]), nrhs, done, s);
+  // step 3: N_s independent banded time solves, in place (fused: with the x_d products around
+  // them, in place)
+  if (fused) {
+    if constexpr (PREC != MP_BF16)
+      rc = launch_fused_time<PREC, TY>(P, static_cast<TY*>(bufs[cur]), static_cast<TY*>(bufs[cur]), nrhs, done, s);
+  } else {
+    rc = launch_time_solve<TY>(P, static_cast<TY*>(bufs[cur]), nrhs, done, s);
+  }
   if (rc) return rc;
   // step 4: s = (U_s (x) I) x in reverse order, the last product writes FP64 output
-  for (int k = d - 1; k >= 0; --k) {
+  for (int k = kf - 1; k >= 0; --k) {
     const int l = order[k];
-    const bool first = (k == d - 1), last = (k == 0);
+    const bool first = (k == kf - 1), last = (k == 0);
     const MpTimer tm(P, s);
     if (last && first)
       return launch_mode_product<PREC, TY, double>(bufs[cur], s_out, Ubwd(l), hp.n_s[l], inner[l], outer[l],
@@ -2264,6 +2656,134 @@ static int tune_time_solve(stfd_problem* P, TuneClock& C) {
   return STFD_OK;
 }
 
+// Fused form: the compiled candidates that fit this problem (FP64 shape), in the order of the
+// default choice: the time-solve form the grid calls for (factor in kernel for more columns than
+// 4 blocks per CU, else tables), then four-wave blocks, then the longer segment.
+static std::vector<FusedShape> fused_candidates(const stfd_problem* P) {
+  std::vector<FusedShape> c;
+  FusedShape f, f32;
+#define STFD_FZ(PV, LV, MV, NV)                                                                   \
+  if (P->hp.p_t == PV && fused_shape(P, MP_F64, LV, MV, NV, f) && fused_shape(P, MP_F32, LV, MV, NV, f32)) \
+    c.push_back(f);
+  STFD_FZ_INSTANCES
+#undef STFD_FZ
+  if (c.empty()) return c;
+  const int64_t ncols = P->hp.N_s / P->hp.n_s[P->hp.d - 1];
+  const int want = ncols > 4 * int64_t(P->n_cus) ? 2 : 0;
+  std::stable_sort(c.begin(), c.end(), [&](const FusedShape& x, const FusedShape& y) {
+    if ((x.mode == want) != (y.mode == want)) return x.mode == want;
+    if (x.nw != y.nw) return x.nw < y.nw;
+    return x.len > y.len;
+  });
+  return c;
+}
+
+// Device tables of the fused form f (FP64 and FP32 copies).  keep: handle-owned (freed with the
+// handle); else plain allocations the caller frees with fused_free.
+static int fused_upload(stfd_problem* P, const FusedShape& f, bool keep) {
+  TimeSolvePlan tp;
+  if (fused_tables(P->hp, f, tp) != 0) return STFD_EINVAL;
+  const std::vector<double>* src[7] = {&tp.Lf, &tp.Df, &tp.Tf, &tp.Tb, &tp.Sf, &tp.Hb, &tp.mu};
+  double** d64[7] = {&P->FzL, &P->FzD, &P->FzTf, &P->FzTb, &P->FzS, &P->FzH, &P->FzMu};
+  float** d32[7] = {&P->FzL32, &P->FzD32, &P->FzTf32, &P->FzTb32, &P->FzS32, &P->FzH32, &P->FzMu32};
+  for (int k = 0; k < 7; ++k) {
+    *d64[k] = nullptr;
+    *d32[k] = nullptr;
+  }
+  for (int k = 0; k < 7; ++k) {
+    if (src[k]->empty()) continue;
+    const std::vector<float> v32(src[k]->begin(), src[k]->end());
+    int rc;
+    if (keep) {
+      if ((rc = upload(P, d64[k], src[k]->data(), src[k]->size())) || (rc = upload(P, d32[k], v32.data(), v32.size())))
+        return rc;
+    } else {
+      hipError_t e = hipMalloc(d64[k], sizeof(double) * src[k]->size());
+      if (e == hipSuccess) e = hipMalloc(d32[k], sizeof(float) * v32.size());
+      if (e == hipSuccess)
+        e = hipMemcpy(*d64[k], src[k]->data(), sizeof(double) * src[k]->size(), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(*d32[k], v32.data(), sizeof(float) * v32.size(), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        g_last_hip_error = int(e);
+        return STFD_EHIP;
+      }
+    }
+  }
+  P->fz_len = f.len;
+  P->fz_mode = f.mode;
+  P->fz_nw = f.nw;
+  P->fz_waves = f.waves;
+  P->fz_segs = f.segs;
+  P->fz_mpb = f.mpb;
+  return STFD_OK;
+}
+static void fused_free(stfd_problem* P) {
+  void* p[14] = {P->FzL, P->FzD, P->FzTf, P->FzTb, P->FzS, P->FzH, P->FzMu,
+                 P->FzL32, P->FzD32, P->FzTf32, P->FzTb32, P->FzS32, P->FzH32, P->FzMu32};
+  for (void* q : p)
+    if (q) (void)hipFree(q);
+  P->FzL = P->FzD = P->FzTf = P->FzTb = P->FzS = P->FzH = P->FzMu = nullptr;
+  P->FzL32 = P->FzD32 = P->FzTf32 = P->FzTb32 = P->FzS32 = P->FzH32 = P->FzMu32 = nullptr;
+  P->fz_len = 0;
+}
+// LDS beyond the default per-block limit is granted per kernel
+static int fused_allow_lds(const stfd_problem* P, const FusedShape& f) {
+  const void* k64 = fused_kernel<MP_F64, double>(P->hp.p_t, f.len, f.mode, f.nw);
+  const void* k32 = fused_kernel<MP_F32, float>(P->hp.p_t, f.len, f.mode, f.nw);
+  if (!k64 || !k32) return STFD_EINVAL;
+  STFD_HIP(hipFuncSetAttribute(k64, hipFuncAttributeMaxDynamicSharedMemorySize, int(f.lds)));
+  FusedShape f32;
+  if (!fused_shape(P, MP_F32, f.len, f.mode, f.nw, f32)) return STFD_EINVAL;
+  STFD_HIP(hipFuncSetAttribute(k32, hipFuncAttributeMaxDynamicSharedMemorySize, int(f32.lds)));
+  return STFD_OK;
+}
+
+// Fused form at setup: tables of the chosen candidate; with the autotune, every candidate and the
+// separate launches are timed as whole FP64 applies (x, y: 2 N doubles) and the fastest is kept,
+// else the first candidate is built and left off: on the 3D workloads the fused launch takes
+// longer than the three it replaces (one block per CU, whose latency-bound time solves no other
+// block's products overlap), so the heuristic keeps the separate launches.
+static int setup_fused(stfd_problem* P, int want_len, bool autotune, TuneClock* C, double* x, double* y) {
+  std::vector<FusedShape> cand = fused_candidates(P);
+  P->fz_on = false;
+  if (want_len > 0) {
+    cand.erase(std::remove_if(cand.begin(), cand.end(), [&](const FusedShape& f) { return f.len != want_len; }),
+               cand.end());
+    if (cand.empty()) return STFD_EINVAL;
+  }
+  if (cand.empty()) return STFD_OK;
+  int rc;
+  size_t pick = 0;
+  bool on = false;
+  if (autotune) {
+    auto apply = [&]() { return apply_dispatch(P, x, y, 1, STFD_FP64, nullptr, C->s); };
+    float best = 0.0f;
+    if ((rc = C->median(apply, &best))) return rc;  // separate launches
+    on = false;
+    for (size_t k = 0; k < cand.size(); ++k) {
+      if ((rc = fused_allow_lds(P, cand[k]))) return rc;
+      rc = fused_upload(P, cand[k], false);
+      float ms = 0.0f;
+      if (rc == STFD_OK) {
+        P->fz_on = true;
+        rc = C->median(apply, &ms);
+        P->fz_on = false;
+      }
+      (void)hipStreamSynchronize(C->s);
+      fused_free(P);
+      if (rc) return rc;
+      if (ms < best) {
+        best = ms;
+        pick = k;
+        on = true;
+      }
+    }
+  }
+  if ((rc = fused_allow_lds(P, cand[pick])) || (rc = fused_upload(P, cand[pick], true))) return rc;
+  P->fz_on = on;
+  return STFD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Scratch of the allocation-free apply (stfd_apply_preconditioner_static): the two intermediate
 // tensors of Algorithm 1 steps 2-4 live in a file-scope device array of fixed size instead of the
@@ -2428,6 +2948,7 @@ static void set_plan_model(stfd_problem* P) {
 
 int stfd_update_potential(stfd_problem* P, const double* V_quad, void* stream) {
   if (!P) return STFD_EINVAL;
+  stfd::graph_cache_clear(P);
   hipStream_t s = static_cast<hipStream_t>(stream);
   SpatialModel m;
   if (build_spatial_model(P->hp, P->geom, V_quad, m)) return STFD_EINVAL;
@@ -2458,6 +2979,7 @@ int stfd_map_points(const stfd_problem* P, const double* xi, int64_t n, double* 
 
 void stfd_destroy(stfd_problem* P) {
   if (!P) return;
+  stfd::graph_cache_clear(P);
   for (hipEvent_t e : P->tev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : P->job_ev)
@@ -2502,6 +3024,7 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   if (desc->autotune != 0 && desc->autotune != 1) return STFD_EINVAL;
   if (desc->precond_shift != STFD_SHIFT_NONE && desc->precond_shift != STFD_SHIFT_MEAN_POTENTIAL) return STFD_EINVAL;
   if (desc->precond_shift == STFD_SHIFT_MEAN_POTENTIAL && geom.kind != GEOM_UNIT) return STFD_EINVAL;
+  if (desc->fused_segment_length < 0) return STFD_EINVAL;
   if (desc->time_condition == STFD_TIME_FINAL && geom.kind != GEOM_UNIT) return STFD_EINVAL;
   v.time_final = desc->time_condition == STFD_TIME_FINAL;
   stfd_problem* P = new (std::nothrow) stfd_problem;
@@ -2791,13 +3314,17 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       return rc;
     }
     STFD_HIP(hipMemsetAsync(P->vec[0], 0, sizeof(double) * size_t(P->n2), C.s));
-    if ((rc = tune_mode_products(P, C, P->vec[0], P->vec[1]))) {
+    if ((rc = tune_mode_products(P, C, P->vec[0], P->vec[1])) ||
+        (rc = setup_fused(P, desc->fused_segment_length, true, &C, P->vec[0], P->vec[1]))) {
       stfd_destroy(P);
       return rc;
     }
     STFD_HIP(hipStreamSynchronize(C.s));
     P->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     P->autotuned = true;
+  } else if ((rc = setup_fused(P, desc->fused_segment_length, false, nullptr, nullptr, nullptr))) {
+    stfd_destroy(P);
+    return rc;
   }
   *out = P;
   return STFD_OK;
@@ -2905,6 +3432,9 @@ int stfd_get_tuning(const stfd_problem* P, stfd_tuning* out) {
   out->time_transfers_in_kernel = P->ts_mode >= 1 ? 1 : 0;
   out->time_factors_in_kernel = P->ts_mode == 2 ? 1 : 0;
   out->tune_ms = P->tune_ms;
+  out->fused_time = P->fz_on ? 1 : 0;
+  out->fused_segment_length = P->fz_len;
+  out->fused_factors_in_kernel = P->fz_len && P->fz_mode == 2 ? 1 : 0;
   return STFD_OK;
 }
 
@@ -2914,6 +3444,10 @@ int stfd_set_tuning(stfd_problem* P, const stfd_tuning* in) {
   if (in->time_segment_length != P->ts_len || in->time_transfers_in_kernel != (P->ts_mode >= 1 ? 1 : 0) ||
       in->time_factors_in_kernel != (P->ts_mode == 2 ? 1 : 0))
     return STFD_EINVAL;
+  if (in->fused_segment_length != P->fz_len ||
+      in->fused_factors_in_kernel != (P->fz_len && P->fz_mode == 2 ? 1 : 0) ||
+      (in->fused_time != 0 && in->fused_time != 1) || (in->fused_time && !P->fz_len))
+    return STFD_EINVAL;
   for (int prec = 0; prec < 3; ++prec)
     for (int l = 0; l < hp.d; ++l) {
       const int rt = in->mode_product_row_groups[prec][l];
@@ -2922,7 +3456,9 @@ int stfd_set_tuning(stfd_problem* P, const stfd_tuning* in) {
     }
   for (int prec = 0; prec < 3; ++prec)
     for (int l = 0; l < hp.d; ++l) P->mp_rt[prec][l] = in->mode_product_row_groups[prec][l];
+  P->fz_on = in->fused_time != 0;
   set_last_blocks(P);
+  graph_cache_clear(P);  // captured iterations hold the previous launch shapes
   return STFD_OK;
 }
 
@@ -2941,6 +3477,7 @@ int stfd_get_pencil(const stfd_problem* P, int l, double* U, double* lambda) {
 
 int stfd_timing_begin(stfd_problem* P, int capacity) {
   if (!P || capacity < 1 || P->timing) return STFD_EINVAL;
+  stfd::graph_cache_clear(P);  // captured iterations carry no timing events
   P->tev.assign(size_t(2) * capacity, nullptr);
   for (hipEvent_t& e : P->tev) {
     const hipError_t he = hipEventCreate(&e);
@@ -2959,6 +3496,7 @@ int stfd_timing_begin(stfd_problem* P, int capacity) {
 
 int stfd_timing_end(stfd_problem* P, double* total_ms, int64_t* launches) {
   if (!P || !P->timing) return STFD_EINVAL;
+  stfd::graph_cache_clear(P);  // iterations captured while timing record its events
   double tot = 0.0;
   int rc = STFD_OK;
   for (size_t k = 0; k + 1 < P->tev_used; k += 2) {
@@ -3211,6 +3749,53 @@ static int capture_iterations(const std::vector<PcgJob>& jobs, int precision, in
   return STFD_OK;
 }
 
+// Captured iterations of one job, from the handle's cache or captured now and cached (at most
+// kGraphCache per handle; the least recently used is dropped).  The graphs hold the job's buffers,
+// sizes, precision and stopping parameters; anything else they depend on (launch shapes, potential,
+// timing) drops the whole cache when it changes (graph_cache_clear).
+constexpr size_t kGraphCache = 4;
+static void graph_cache_clear(stfd_problem* P) {
+  for (auto& g : P->graphs)
+    for (auto& e : g.exec)
+      if (e) (void)hipGraphExecDestroy(e);
+  P->graphs.clear();
+}
+static int cached_iterations(const PcgJob& J, int precision, int maxit, double rtol, hipGraphExec_t** out) {
+  stfd_problem* P = J.P;
+  for (auto& g : P->graphs)
+    if (g.f == J.f && g.x == J.x && g.nrhs == J.nrhs && g.precision == precision && g.maxit == maxit &&
+        g.rtol == rtol) {
+      g.used = ++P->graph_clock;
+      *out = g.exec;
+      return STFD_OK;
+    }
+  IterationGraphs G;
+  const std::vector<PcgJob> one(1, J);
+  if (int rc = capture_iterations(one, precision, maxit, rtol, G)) return rc;
+  if (P->graphs.size() >= kGraphCache) {
+    auto lru = std::min_element(P->graphs.begin(), P->graphs.end(),
+                                [](const auto& a, const auto& b) { return a.used < b.used; });
+    for (auto& e : lru->exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    P->graphs.erase(lru);
+  }
+  stfd_problem::CachedIterations c;
+  c.f = J.f;
+  c.x = J.x;
+  c.nrhs = J.nrhs;
+  c.precision = precision;
+  c.maxit = maxit;
+  c.rtol = rtol;
+  for (int k = 0; k < 2; ++k) {
+    c.exec[k] = G.exec[k];
+    G.exec[k] = nullptr;  // owned by the cache now
+  }
+  c.used = ++P->graph_clock;
+  P->graphs.push_back(c);
+  *out = P->graphs.back().exec;
+  return STFD_OK;
+}
+
 // Shared driver of stfd_pcg_solve and stfd_pcg_solve_batched.  The host launches iteration k
 // (directly or as a graph), records an event, and before iteration k reads the pinned ring
 // slot that iteration k - kLag wrote; the loop ends when every system of every job is done.
@@ -3220,8 +3805,14 @@ static int pcg_run(std::vector<PcgJob>& jobs, double rtol, int maxit, int flags,
   for (const PcgJob& J : jobs)
     if ((rc = pcg_init(J, flags, precision, rtol, s))) return rc;
   IterationGraphs G;
-  if (use_graph && maxit > 0)
-    if ((rc = capture_iterations(jobs, precision, maxit, rtol, G))) return rc;
+  hipGraphExec_t* exec = G.exec;
+  if (use_graph && maxit > 0) {
+    if (jobs.size() == 1) {
+      if ((rc = cached_iterations(jobs[0], precision, maxit, rtol, &exec))) return rc;
+    } else if ((rc = capture_iterations(jobs, precision, maxit, rtol, G))) {
+      return rc;
+    }
+  }
   std::vector<hipEvent_t> ev(kLag, nullptr);
   auto cleanup = [&]() {
     for (auto e : ev)
@@ -3246,7 +3837,7 @@ static int pcg_run(std::vector<PcgJob>& jobs, double rtol, int maxit, int flags,
     }
     const int par = k & 1;
     if (use_graph) {
-      if (hipGraphLaunch(G.exec[par], s) != hipSuccess) {
+      if (hipGraphLaunch(exec[par], s) != hipSuccess) {
         cleanup();
         return STFD_EHIP;
       }
@@ -3298,11 +3889,9 @@ static int pcg_run_streams(std::vector<PcgJob>& jobs, double rtol, int maxit, in
   int rc;
   for (PcgJob& J : jobs)
     if ((rc = pcg_init(J, flags, precision, rtol, J.P->job_stream))) return rc;
-  std::vector<IterationGraphs> G(graph && maxit > 0 ? nj : 0);
-  for (size_t j = 0; j < G.size(); ++j) {
-    std::vector<PcgJob> one(1, jobs[j]);
-    if ((rc = capture_iterations(one, precision, maxit, rtol, G[j]))) return rc;
-  }
+  std::vector<hipGraphExec_t*> G(graph && maxit > 0 ? nj : 0, nullptr);
+  for (size_t j = 0; j < G.size(); ++j)
+    if ((rc = cached_iterations(jobs[j], precision, maxit, rtol, &G[j]))) return rc;
   std::vector<int> launched(nj, 0);
   std::vector<char> active(nj, maxit > 0 ? 1 : 0);
   size_t n_active = maxit > 0 ? nj : 0;
@@ -3332,7 +3921,7 @@ static int pcg_run_streams(std::vector<PcgJob>& jobs, double rtol, int maxit, in
         continue;
       }
       if (graph) {
-        STFD_HIP(hipGraphLaunch(G[j].exec[k & 1], P->job_stream));
+        STFD_HIP(hipGraphLaunch(G[j][k & 1], P->job_stream));
       } else if ((rc = pcg_iteration(J, k & 1, precision, maxit, rtol, P->job_stream))) {
         return rc;
       }

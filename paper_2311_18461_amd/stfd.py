@@ -34,13 +34,16 @@ class SetupDesc(ctypes.Structure):
                 ("V_quad", ctypes.POINTER(ctypes.c_double)), ("n_quad", ctypes.c_int),
                 ("max_nrhs", ctypes.c_int), ("geometry", ctypes.c_int), ("geom", ctypes.c_double * 2),
                 ("precond", ctypes.c_int), ("matvec", ctypes.c_int), ("no_rhs_workspace", ctypes.c_int),
-                ("time_condition", ctypes.c_int), ("autotune", ctypes.c_int), ("precond_shift", ctypes.c_int)]
+                ("time_condition", ctypes.c_int), ("autotune", ctypes.c_int), ("precond_shift", ctypes.c_int),
+                ("fused_segment_length", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("autotuned", ctypes.c_int), ("mode_product_row_groups", (ctypes.c_int * 3) * 3),
                 ("time_segment_length", ctypes.c_int), ("time_transfers_in_kernel", ctypes.c_int),
-                ("tune_ms", ctypes.c_double), ("time_factors_in_kernel", ctypes.c_int)]
+                ("tune_ms", ctypes.c_double), ("time_factors_in_kernel", ctypes.c_int),
+                ("fused_time", ctypes.c_int), ("fused_segment_length", ctypes.c_int),
+                ("fused_factors_in_kernel", ctypes.c_int)]
 
 
 class PcgInfo(ctypes.Structure):
@@ -182,7 +185,8 @@ class Problem:
     def __init__(self, knots_t, knots_s, p_t: int, p_s: int, T: float = 1.0, nu: float = 1.0,
                  V_quad=None, n_quad: int = 0, max_nrhs: int = 1, geometry=GEOM_UNIT_CUBE, radii=(1.0, 2.0),
                  precond=PRECOND_AUTO, rhs_workspace: bool = True, matvec=MATVEC_AUTO,
-                 time_condition=TIME_INITIAL, autotune: bool = False, precond_shift=SHIFT_NONE):
+                 time_condition=TIME_INITIAL, autotune: bool = False, precond_shift=SHIFT_NONE,
+                 fused_segment_length: int = 0):
         d = len(knots_s)
         self._keep = [np.ascontiguousarray(knots_t, dtype=np.float64)]
         desc = SetupDesc()
@@ -210,6 +214,7 @@ class Problem:
         desc.time_condition = time_condition
         desc.autotune = 1 if autotune else 0
         desc.precond_shift = precond_shift
+        desc.fused_segment_length = fused_segment_length
         desc.matvec = matvec
         h = ctypes.c_void_p()
         self._h = None
@@ -251,7 +256,9 @@ class Problem:
                                             for k, name in enumerate(("fp64", "fp32", "bf16"))},
                 "time_segment_length": t.time_segment_length,
                 "time_transfers_in_kernel": bool(t.time_transfers_in_kernel),
-                "time_factors_in_kernel": bool(t.time_factors_in_kernel), "tune_ms": t.tune_ms}
+                "time_factors_in_kernel": bool(t.time_factors_in_kernel), "tune_ms": t.tune_ms,
+                "fused_time": bool(t.fused_time), "fused_segment_length": t.fused_segment_length,
+                "fused_factors_in_kernel": bool(t.fused_factors_in_kernel)}
 
     def set_mode_product_shapes(self, shapes):
         """stfd_set_tuning: {"fp64"|"fp32"|"bf16": [shape per direction]} (1, 2 = row groups per wave of
@@ -261,6 +268,14 @@ class Problem:
         for k, name in enumerate(("fp64", "fp32", "bf16")):
             for l, v in enumerate(shapes.get(name, [t.mode_product_row_groups[k][l] for l in range(self.d)])):
                 t.mode_product_row_groups[k][l] = int(v)
+        return _check(_lib().stfd_set_tuning(self._h, ctypes.byref(t)), "stfd_set_tuning")
+
+    def set_fused_time(self, on: bool):
+        """stfd_set_tuning: run the last direction's products and the time solves as one launch (on)
+        or as separate launches; the other fields are kept."""
+        t = Tuning()
+        _check(_lib().stfd_get_tuning(self._h, ctypes.byref(t)), "stfd_get_tuning")
+        t.fused_time = 1 if on else 0
         return _check(_lib().stfd_set_tuning(self._h, ctypes.byref(t)), "stfd_set_tuning")
 
     def get_pencil(self, l: int):

@@ -29,6 +29,14 @@ def _make(d, n_el, p, V, autotune, oracle=False):
     return lib, (OProblem(kt, ks, p, p, 1.0, V) if oracle else None)
 
 
+def _time_solve_key(t):
+    """What fixes the rounding of the time solves: the fused launch's segment length and form, or
+    the separate launch's."""
+    if t["fused_time"]:
+        return ("fused", t["fused_segment_length"], t["fused_factors_in_kernel"])
+    return ("separate", t["time_segment_length"], t["time_transfers_in_kernel"], t["time_factors_in_kernel"])
+
+
 @pytest.mark.parametrize("d,n_el,p,kind", [(2, 64, 3, "gauss"), (2, 16, 3, None), (3, 12, 3, "harm"),
                                            (3, 20, 4, None)])
 def test_tuned_shapes_valid_and_apply_matches_oracle(d, n_el, p, kind):
@@ -51,14 +59,15 @@ def test_tuned_shapes_valid_and_apply_matches_oracle(d, n_el, p, kind):
     torch.cuda.synchronize()
     s, s_ref = out.cpu().numpy(), FastDiagonalization(ref, precompute_inverse=False).apply(r)
     assert max_rel(s, s_ref) < 1e-11 and fiber_rel(s, s_ref, lib.n_t) < 1e-10
-    if (t["time_segment_length"], t["time_transfers_in_kernel"]) == (h["time_segment_length"],
-                                                                      h["time_transfers_in_kernel"]):
+    if _time_solve_key(t) == _time_solve_key(h):
         assert torch.equal(out, out_h)  # only the row groups differ: same arithmetic
     for prec in ("fp32", "bf16"):
         lib.apply_preconditioner(rd, out, precision=prec)
         heur.apply_preconditioner(rd, out_h, precision=prec)
         torch.cuda.synchronize()
-        assert max_rel(out.cpu().numpy(), out_h.cpu().numpy()) < (1e-5 if prec == "fp32" else 2e-2)
+        # two applies each within the FP32 bound of the oracle (2e-5; the time solves may differ in
+        # form, e.g. FP32 factor rows computed in the solve against FP32 copies of FP64 tables)
+        assert max_rel(out.cpu().numpy(), out_h.cpu().numpy()) < (4e-5 if prec == "fp32" else 2e-2)
 
 
 def test_tuned_pcg_matches_heuristic():
@@ -81,11 +90,13 @@ def test_every_shape_gives_the_same_apply(d, n_el, p, n_el_t):
     """Shapes 1, 2 (one column group per wave, 1 or 2 row groups) and 3 (every column group per wave,
     U' in LDS) accumulate every output over the same K steps in the same order: the applies agree
     bit for bit in every precision, and the FP64 one matches the oracle.  The PCG with the fused dot
-    products (whose partials depend on the shape) takes the same iteration count up to one."""
+    products (whose partials depend on the shape) takes the same iteration count up to one.  The
+    last direction runs as separate launches here, so that every direction takes every shape."""
     from paper_2311_18461_amd import stfd
     kt = inputs.uniform_open_knots(n_el_t, p)
     ks = [inputs.uniform_open_knots(n_el, p) for _ in range(d)]
     lib = stfd.Problem(kt, ks, p, p, 1.0, 1.0)
+    lib.set_fused_time(False)
     r = inputs.random_complex(lib.N, 61)
     rd = torch.from_numpy(r).to(DEV)
     outs = {}
