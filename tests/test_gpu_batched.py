@@ -99,3 +99,48 @@ def test_batched_argument_errors():
     assert ei.value.code == stfd.EINVAL
     rc, info = stfd.pcg_solve_batched([pr], [f], [u], [1])  # f = 0: u = 0 at once
     assert rc == 0 and info[0]["iters"] == 0 and torch.all(u == 0).item()
+
+
+def test_cached_graphs_replay_across_solves():
+    """Captured iterations are kept in the handle and replayed by later solves with the same
+    arguments: each replay (with eager work and host synchronisations between) equals the direct
+    solve of the data then in the buffers; new launch shapes drop the cache; more argument sets
+    than the cache holds evict the oldest."""
+    prob = _problem(16, V=inputs.gaussian_potential(2, 2000))
+    f = torch.empty(prob.N, dtype=torch.complex128, device=DEV)
+    u_ref, u = torch.empty_like(f), torch.empty_like(f)
+    extra = [torch.empty_like(f) for _ in range(5)]
+    for rep, seed in enumerate((12, 12, 13, 14)):
+        f.copy_(torch.from_numpy(inputs.random_complex(prob.N, seed)))
+        if rep == 3:
+            prob.set_mode_product_shapes({"fp64": [2, 2]})
+        rc1, i1 = prob.pcg_solve(f, u_ref, rtol=1e-9, maxit=1000)
+        torch.randn(1 << 20, device=DEV).mul_(2.0).sum().item()  # eager work between
+        rc2, i2 = prob.pcg_solve(f, u, rtol=1e-9, maxit=1000, graph=True)
+        torch.cuda.synchronize()
+        assert rc1 == rc2 == 0
+        assert i1[0]["iters"] == i2[0]["iters"] and torch.equal(u_ref, u), rep
+    for k, x in enumerate(extra + extra[:2]):  # seven argument sets through a cache of four
+        rc, info = prob.pcg_solve(f, x, rtol=1e-9, maxit=1000, graph=True)
+        assert rc == 0 and torch.equal(x, u_ref), k
+
+
+def test_batched_graph_replay_equals_streams():
+    """The batched driver with cached per-job graphs, called twice, gives the direct batched result."""
+    stfd = _stfd()
+    work = {n: ps[:3] for n, ps in inputs.batched_2d_workload().items() if n <= 32}
+    probs, fs, nr = [], [], []
+    for n_el, packets in work.items():
+        pr = _problem(n_el, max_nrhs=len(packets))
+        probs.append(pr)
+        fs.append(_rhs(pr, packets))
+        nr.append(len(packets))
+    us = [torch.empty_like(f) for f in fs]
+    rc, info = stfd.pcg_solve_batched(probs, fs, us, nr, rtol=1e-8, maxit=200)
+    assert rc == 0
+    for rep in range(2):
+        ug = [torch.empty_like(f) for f in fs] if rep == 0 else ug
+        torch.randn(1 << 20, device=DEV).mul_(2.0).sum().item()
+        rcg, infog = stfd.pcg_solve_batched(probs, fs, ug, nr, rtol=1e-8, maxit=200, graph=True)
+        assert rcg == 0 and all(torch.equal(a, b) for a, b in zip(us, ug)), rep
+        assert [a["iters"] for a in info] == [b["iters"] for b in infog]
