@@ -243,6 +243,21 @@ def precision_3d_section(stream, cases=((48, 3), (32, 4)), bf16_maxit=300):
             err = float(torch.linalg.vector_norm(z - z64) / torch.linalg.vector_norm(z64))
             row[prec] = {"apply_ms": round(ms, 4), "apply_mdofs": round(prob.N / (ms * 1e-3) / 1e6, 1),
                          "apply_relerr_vs_fp64": float(f"{err:.3e}")}
+        # the fused last-direction launch (x_d products and time solves in one kernel), where it
+        # fits: apply time and agreement with the separate launches the tuning kept
+        t = row["tuning"]
+        if t["fused_segment_length"]:
+            fz = {}
+            for prec in ("fp64", "fp32"):
+                prob.set_fused_time(True)
+                prob.apply_preconditioner(r, z, precision=prec, stream=stream)
+                ms = time_events(lambda: prob.apply_preconditioner(r, z, precision=prec, stream=stream), 10, stream)
+                prob.set_fused_time(t["fused_time"])
+                zs = torch.empty_like(z)
+                prob.apply_preconditioner(r, zs, precision=prec, stream=stream)
+                d_sep = float(torch.max(torch.abs(z - zs)) / torch.max(torch.abs(zs)))
+                fz[prec] = {"apply_ms": round(ms, 4), "max_rel_diff_vs_kept": float(f"{d_sep:.3e}")}
+            row["fused_last_direction"] = {"segment_length": t["fused_segment_length"], **fz}
         row["matvec_ms"] = round(time_events(lambda: prob.matvec(r, z, stream=stream), 10, stream), 4)
         # FP64 mode products timed one by one (HIP events on the launch stream), and the whole apply
         # against its roof
@@ -383,8 +398,9 @@ def main():
     ap.add_argument("--profile", nargs="?", const="2d", choices=["2d", "3d48", "3d32"],
                     help="short run for rocprofv3 on one workload (2d: the 2D p=3 64^3 Gaussian-potential step; "
                          "3d48 / 3d32: the 3D harmonic workloads p=3 48^4 / p=4 32^4): one solve, 20 applies per "
-                         "precision, 20 matvecs, and a device copy of known size (64 MiB read + 64 MiB written) "
-                         "to calibrate FETCH_SIZE / WRITE_SIZE")
+                         "precision (3D: and 20 FP64 applies with the fused last-direction launch), 20 matvecs, "
+                         "and a device copy of known size (64 MiB read + 64 MiB written) to calibrate FETCH_SIZE / "
+                         "WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
@@ -432,6 +448,12 @@ def main():
         for prec in ("fp64", "fp32", "bf16"):
             for _ in range(20):
                 prob.apply_preconditioner(r, s, precision=prec, stream=stream)
+        if args.profile != "2d" and prob.get_tuning()["fused_segment_length"]:
+            # the fused last-direction launch (off by default): 20 FP64 applies
+            prob.set_fused_time(True)
+            for _ in range(20):
+                prob.apply_preconditioner(r, s, precision="fp64", stream=stream)
+            prob.set_fused_time(False)
         for _ in range(20):
             prob.matvec(r, s, stream=stream)
         src = torch.ones(8 << 20, dtype=torch.float64, device=dev)

@@ -3,7 +3,8 @@
 For every key (d, n_s, n_t, p) of the workloads and every precision of the FD apply, sets the
 problem up twice (heuristic launch shapes, and autotune = 1, which times the candidate shapes on
 the device), prints the chosen shapes (mode-product row groups per direction, time-solve segment
-length and transfer mode) and the apply time of both as a Markdown table.
+length and transfer mode, whether the fused last-direction launch was kept) and the apply time of
+both, with the fused launch's own apply time, as a Markdown table.
 
     python -m paper_2311_18461_amd.autotune_sweep [--reps 20]
 """
@@ -58,8 +59,8 @@ def main():
     args = ap.parse_args()
     print("| workload | d | n_s | n_t | p | precision | row groups (heuristic -> tuned) | time segment "
           "(heuristic -> tuned) | time-solve form (heuristic -> tuned) | apply us heuristic | "
-          "apply us tuned | tune ms |")
-    print("|---|---|---|---|---|---|---|---|---|---|---|---|")
+          "apply us tuned | fused last direction: tuned, us | tune ms |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|")
     for label, d, n_el, p, kind in WORKLOADS:
         V = _potential(kind, d)
         kt = inputs.uniform_open_knots(n_el, p)
@@ -71,11 +72,19 @@ def main():
         for prec in ("fp64", "fp32", "bf16"):
             uh = _apply_us(heur, prec, args.reps, torch)
             ut = _apply_us(tuned, prec, args.reps, torch)
+            fz = "n/a"
+            if tt["fused_segment_length"] and prec != "bf16":
+                # the fused launch (segment length, form) on the tuned handle, whether kept or not
+                tuned.set_fused_time(True)
+                uf = _apply_us(tuned, prec, args.reps, torch)
+                tuned.set_fused_time(tt["fused_time"])
+                fz = (f"{'on' if tt['fused_time'] else 'off'} (segment {tt['fused_segment_length']}, "
+                      f"{'factor' if tt['fused_factors_in_kernel'] else 'tables'}), {uf:.1f}")
             print(f"| {label} | {d} | {heur.n_s[0]} | {heur.n_t} | {p} | {prec} | "
                   f"{th['mode_product_row_groups'][prec]} -> {tt['mode_product_row_groups'][prec]} | "
                   f"{th['time_segment_length']} -> {tt['time_segment_length']} | "
                   f"{_form(th)} -> {_form(tt)} | "
-                  f"{uh:.1f} | {ut:.1f} | {tt['tune_ms']:.0f} |", flush=True)
+                  f"{uh:.1f} | {ut:.1f} | {fz} | {tt['tune_ms']:.0f} |", flush=True)
         heur.close()
         tuned.close()
 
