@@ -18,6 +18,7 @@ timing) and the CPU oracle timed on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -64,7 +65,7 @@ def time_events(fn, reps, stream):
     return start.elapsed_time(end) / reps  # ms
 
 
-def batched_section(dev, stream, reps=3):
+def batched_section(dev, stream, reps=5):
     """64 wave-packet systems (V = 0, p = 3) dealt over the grids 16^3 .. 64^3: one batched call
     (one stream per grid; also with each grid's iteration replayed from a captured graph) vs the same
     systems solved grid by grid and one by one."""
@@ -85,13 +86,18 @@ def batched_section(dev, stream, reps=3):
     total = sum(pr.N * n for pr, n in zip(probs, nr))
 
     def timed(fn):
+        # median of individually synchronised calls after one untimed call (a host-side pause, such
+        # as the garbage collector freeing an earlier section's buffers, then moves one sample only)
+        gc.collect()
         fn()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        ts = []
         for _ in range(reps):
+            t0 = time.perf_counter()
             out = fn()
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / reps * 1e3, out
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts)), out
 
     t_batch, (rc, info) = timed(lambda: stfd.pcg_solve_batched(probs, fs, us, nr, rtol=1e-8, maxit=1000,
                                                                 stream=stream))
@@ -107,12 +113,40 @@ def batched_section(dev, stream, reps=3):
                              stream=stream)
     t_one, _ = timed(one_by_one)
     its = [i["iters"] for i in info]
+    # one FD apply of all 64 systems: every grid's stacked apply on its own stream (default
+    # priority), against the same applies one grid after the other, and the HBM roof of Algorithm
+    # 1 steps 2-4 (96 bytes per dof: three passes of the complex FP64 tensor)
+    rs = [torch.from_numpy(inputs.random_complex(pr.N * n, 77)).to(dev) for pr, n in zip(probs, nr)]
+    zs = [torch.empty_like(r) for r in rs]
+    side = [torch.cuda.Stream() for _ in probs]
+
+    def apply_all(concurrent):
+        if concurrent:
+            ev = torch.cuda.Event()
+            ev.record(stream)
+            for pr, r, z, n, st in zip(probs, rs, zs, nr, side):
+                st.wait_event(ev)
+                pr.apply_preconditioner(r, z, nrhs=n, stream=st)
+            for st in side:
+                stream.wait_stream(st)
+        else:
+            for pr, r, z, n in zip(probs, rs, zs, nr):
+                pr.apply_preconditioner(r, z, nrhs=n, stream=stream)
+
+    apply_all(True)
+    apply_all(False)
+    ms_conc = time_events(lambda: apply_all(True), 20, stream)
+    ms_seq = time_events(lambda: apply_all(False), 20, stream)
+    roof_us = 96 * total / (PEAK_HBM_GBS * 1e9) * 1e6
     return {"systems": len(its), "grids": list(work.keys()), "systems_per_grid": nr, "total_dofs": total,
             "batched_ms": round(t_batch, 3), "batched_mdofs": round(total / (t_batch * 1e-3) / 1e6, 2),
             "batched_graph_ms": round(t_batch_graph, 3),
             "grid_by_grid_ms": round(t_grid, 3), "one_by_one_ms": round(t_one, 3),
             "iterations_min_max": [min(its), max(its)],
-            "max_true_rel_res": float(f"{max(i['true_rel_res'] for i in info):.3e}")}
+            "max_true_rel_res": float(f"{max(i['true_rel_res'] for i in info):.3e}"),
+            "apply_fp64": {"concurrent_us": round(ms_conc * 1e3, 1), "grid_by_grid_us": round(ms_seq * 1e3, 1),
+                           "mdofs": round(total / (ms_conc * 1e-3) / 1e6, 1), "hbm_roof_us": round(roof_us, 1),
+                           "frac": round(roof_us / (ms_conc * 1e3), 4)}}
 
 
 WARMSTART_WEIGHTS = os.path.join(ROOT, "paper_2311_18461_amd", "data", "warmstart_annulus_p4_n64.npz")

@@ -89,6 +89,14 @@ def test_fused_pcg_matches_separate():
         assert rc == 0
         sols.append(u.cpu().numpy())
         its.append(info[0]["iters"])
+        if fused:
+            # replayed from captured iterations (twice: capture, then the cached graphs)
+            ug = torch.empty_like(fd)
+            for _ in range(2):
+                ug.fill_(float("nan"))
+                rcg, infog = lib.pcg_solve(fd, ug, rtol=1e-10, maxit=500, graph=True)
+                torch.cuda.synchronize()
+                assert rcg == 0 and infog[0]["iters"] == its[-1] and torch.equal(ug, u)
     x = sols[0]
     res = np.linalg.norm(f - ref.matvec(x)) / np.linalg.norm(f)
     print(f"fused PCG: {its[0]} iterations (separate {its[1]}), residual {res:.2e}", flush=True)

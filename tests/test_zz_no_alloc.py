@@ -49,6 +49,23 @@ def test_static_apply_matches_apply_twice(prec):
         assert torch.equal(got, want), prec
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_static_apply_with_the_fused_last_direction(prec):
+    """The fused last-direction launch works in place in the scratch's intermediate: the static
+    apply equals the regular one with the fused form on, twice (3D 13 x 14 x 15 x 11, then 9^3 x 8)."""
+    print(f"static apply {prec} with the fused last direction", flush=True)
+    for n_el, seed in ((12, 52), (8, 53)):
+        prob = _problem(3, n_el, 3)
+        prob.set_fused_time(True)
+        r = torch.from_numpy(inputs.random_complex(prob.N, seed)).to(DEV)
+        want = torch.empty_like(r)
+        got = torch.full_like(r, float("nan"))
+        prob.apply_preconditioner(r, want, precision=prec)
+        assert _call_static(prob, r, got, 1, prec) == 0
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), (prec, n_el)
+
+
 def test_static_apply_rejects_sizes_above_the_scratch():
     from paper_2311_18461_amd import stfd
     prob = _problem(2, 64, 3)
