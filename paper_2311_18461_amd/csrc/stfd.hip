@@ -3752,7 +3752,8 @@ static int capture_iterations(const std::vector<PcgJob>& jobs, int precision, in
 // Captured iterations of one job, from the handle's cache or captured now and cached (at most
 // kGraphCache per handle; the least recently used is dropped).  The graphs hold the job's buffers,
 // sizes, precision and stopping parameters; anything else they depend on (launch shapes, potential,
-// timing) drops the whole cache when it changes (graph_cache_clear).
+// timing) drops the whole cache when it changes (graph_cache_clear).  *out points into the cache:
+// valid until the next lookup or clear on this handle (one lookup per handle and solve).
 constexpr size_t kGraphCache = 4;
 static void graph_cache_clear(stfd_problem* P) {
   for (auto& g : P->graphs)
