@@ -189,8 +189,12 @@ int stfd_quad_points(const double *knots, int n_knots, int degree, int n_quad, d
  *  - the spatial factors S_1 = M_s, S_2 = nu^2 B_s - nu (K_V + K_V^T) + M_{V^2},
  *    S_3 = nu L_s + M_V of A = sum_k S_k (x) T_k, T = (L_t, M_t, W_t + W_t^*).
  * Everything is computed in FP64 on the host and uploaded once.
- * Errors: STFD_EINVAL (see stfd_setup_desc), STFD_ENOTSPD, STFD_ENOMEM, STFD_EHIP.
- * On success *out owns all host and device data of the problem. */
+ * Sizes: n_l <= 128 and n_t <= 128 for d = 2, 3; for d = 1, n_1 <= 1024 and n_t <= 2048 (long
+ * axes: the mode product walks its K steps in chunks, the matvec sums each entry's neighbours
+ * directly, and time axes longer than 64 segments of the compiled lengths are solved by one lane
+ * per mode, reported as time_segment_length = 0 by stfd_get_tuning).
+ * Errors: STFD_EINVAL (see stfd_setup_desc; sizes beyond the above), STFD_ENOTSPD, STFD_ENOMEM,
+ * STFD_EHIP.  On success *out owns all host and device data of the problem. */
 int stfd_setup(const stfd_setup_desc *desc, stfd_problem **out);
 
 /* Replace the potential of a set-up problem (same conventions as V_quad in
@@ -349,7 +353,8 @@ int stfd_timing_end(stfd_problem *P, double *total_ms, int64_t *launches);
 typedef struct {
   int autotuned;
   int mode_product_row_groups[3][3]; /* [precision STFD_FP64/FP32/BF16][direction], 0 past d */
-  int time_segment_length;
+  int time_segment_length;           /* rows per lane of the segmented time solve; 0: one lane per
+                                        mode over the whole time axis (axes longer than 64 segments) */
   int time_transfers_in_kernel;      /* 1: computed in the solve, 0: read from tables */
   double tune_ms;
   int time_factors_in_kernel;        /* 1: the rows of L and 1/D are factorised in the solve from a

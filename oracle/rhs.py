@@ -263,6 +263,25 @@ def full_coefficients(G, x_free, n_s, n_t):
     return C
 
 
+def errors_separable(knots_t, knots_s, p_t, p_s, C, nu, space_factors, time_u, time_f, q_extra=1):
+    """errors() for one space dimension (V = 0) and an exact solution given as a finite series
+    u = sum_k a_k(t) e_k(x), S u = f = sum_k c_k(t) e_k(x): space_factors(x) -> e_k(x_q) (Q_x x M),
+    time_u(t) / time_f(t) -> a_k(t_q) / c_k(t_q) (Q_t x M).  The exact values on the tensor grid
+    are the products E_x A_t^T and E_x C_t^T; everything else is errors().
+    """
+    assert len(knots_s) == 1
+    stb = SpaceTimeBasis(knots_t, knots_s, p_t, p_s, q=max(p_t, p_s) + 1 + q_extra)
+    uh, Suh = evaluate(stb, C, nu, None)
+    Ex = space_factors(stb.pts[0])
+    W = stb.weights()
+    e = Ex @ time_u(stb.pts[1]).T - uh
+    l2 = np.sqrt(np.sum(W * np.abs(e) ** 2))
+    del e
+    Se = Ex @ time_f(stb.pts[1]).T - Suh
+    vn = np.sqrt(l2 ** 2 + np.sum(W * np.abs(Se) ** 2))
+    return l2, vn
+
+
 def errors(knots_t, knots_s, p_t, p_s, C, nu, exact_u, exact_f, V=None, q_extra=1):
     """L2(Q) error and V-norm error ||e||_V^2 = ||e||^2 + ||S_V e||^2 (Section 2.1).
 

@@ -195,6 +195,13 @@ namespace {
 
 int grid_for(int64_t total) { return int(std::min<int64_t>((total + 255) / 256, 8192)); }
 
+// dynamic LDS beyond the default per-block limit (long time axes: the time-direction kernels stage
+// one point's time line) is granted per kernel before the launch
+int allow_lds(const void* fn, size_t bytes) {
+  if (bytes <= 64 * 1024) return 0;
+  return int(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+}
+
 template <typename T>
 int plan_upload(LoadPlan& plan, T** dst, const std::vector<T>& src) {
   void* p = nullptr;
@@ -967,6 +974,9 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
     int64_t npts = 1;
     for (int a = 1; a < na; ++a) npts *= plan.Q[a];
     const int m0 = plan.m[0], Q0 = plan.Q[0], n0 = plan.n[0];
+    if ((rc = allow_lds(reinterpret_cast<const void*>(&time_expand_kernel), 2 * m0 * sizeof(double2))) ||
+        (rc = allow_lds(reinterpret_cast<const void*>(&time_load_kernel), Q0 * sizeof(double2))))
+      return rc;
     hipLaunchKernelGGL(time_expand_kernel, dim3(static_cast<unsigned>(npts)), dim3(256), 2 * m0 * sizeof(double2), s,
                        (const double2*)A0, (const double2*)A2, (const double2*)f_q, (double2*)R, plan.tband_eval[0],
                        plan.tband_eval[1], plan.eval_lo[0], plan.tband_ew, m0, Q0);
@@ -1037,6 +1047,7 @@ int ultraweak_rhs_device(const HostProblem& hp, const LoadPlan& plan, const doub
   int rc;
   // time: X0[o][i_t] = sum_q w_q b_{i_t}(t_q) f(t_q, x_o) (free time rows of W_h)
   if (f_q) {
+    if ((rc = allow_lds(reinterpret_cast<const void*>(&time_load_kernel), Q0 * sizeof(double2)))) return rc;
     hipLaunchKernelGGL(time_load_kernel, dim3(static_cast<unsigned>(npts)), dim3(128), Q0 * sizeof(double2), s,
                        (const double2*)f_q, (double2*)X0, (double2*)w.A2, plan.tband_load[0], plan.tband_load[1],
                        plan.load_lo[0], plan.tband_lw, Q0, n0, (const double*)nullptr, (const double*)nullptr);

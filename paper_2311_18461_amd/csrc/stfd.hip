@@ -343,6 +343,109 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Mode product for long directions (n > kMaxModeN, one spatial direction): the one-group form
+// with one 16-row group per wave and the K steps walked in chunks of kLongChunk (each chunk's
+// operand loads in one batch, then its MFMA chain), so the register footprint does not grow with
+// n.  Same block layout, K-step order and epilogue as mode_product_kernel.
+// ---------------------------------------------------------------------------
+constexpr int kLongChunk = 16;
+
+template <int PREC, typename Tin, typename Tout, bool DOT>
+__global__ __launch_bounds__(64) void mode_product_long_kernel(ModeProductArgs a, int KS) {
+  using Tr = MPTraits<PREC>;
+  using op_t = typename Tr::op_t;
+  using u_t = typename Tr::u_t;
+  constexpr int K = Tr::K;
+  constexpr int E = K / 4;
+  const int n = a.n;
+  const int64_t per_rhs = int64_t(a.groups) * a.tiles_pad;
+  const int64_t lb = int64_t(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
+  const int64_t rhs = lb / per_rhs;
+  if (a.done && a.done[rhs]) return;
+  const int64_t rem = lb - rhs * per_rhs;
+  const int64_t tile = rem / a.groups;
+  const int cg = int(rem - tile * a.groups);
+  const int lane = threadIdx.x;
+  double dot_a = 0.0, dot_b = 0.0;
+  if (tile < a.tiles_per_rhs) {
+    const int64_t o = rhs * a.outer_per_rhs + tile / a.n_row_tiles;
+    const int64_t row0 = (tile % a.n_row_tiles) * 16;
+    const int rows_here = int(min<int64_t>(16, a.inner - row0));
+    const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
+    Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
+    const int a0 = cg * 16;
+    const int col = lane & 15, grp = lane >> 4;
+    const int rc = min(col, rows_here - 1);
+    const u_t* Up = static_cast<const u_t*>(a.U) + (int64_t(cg) * KS * 64 + lane) * E;
+    typename Tr::acc_t acc = typename Tr::acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < KS; k0 += kLongChunk) {
+      u_t ur[kLongChunk][E];
+      Tin xr[kLongChunk][E];
+#pragma unroll
+      for (int c = 0; c < kLongChunk; ++c) {
+        const int kc = min(k0 + c, KS - 1);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int jc = min(kc * K + E * grp + e, n - 1);
+          ur[c][e] = Up[int64_t(kc) * 64 * E + e];
+          xr[c][e] = src[int64_t(jc) * a.inner + rc];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int c = 0; c < kLongChunk; ++c) {
+        if (k0 + c < KS) {  // uniform
+          op_t ua[E], xb[E];
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            ua[e] = to_op<PREC>(ur[c][e]);
+            xb[e] = to_op<PREC>((k0 + c) * K + E * grp + e < n ? xr[c][e] : Tin(0));
+          }
+          if constexpr (PREC == MP_F64) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[0], xb[0], acc, 0, 0, 0);
+          } else if constexpr (PREC == MP_F32) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[0], xb[0], acc, 0, 0, 0);
+          } else {
+            s4_t av, bv;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              av[e] = ua[e];
+              bv[e] = xb[e];
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (col < rows_here) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int aa = a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
+        if (aa < n) {
+          const int64_t off = int64_t(aa) * a.inner + col;
+          const Tout val = Tout(acc[v]);
+          dst[off] = val;
+          if constexpr (DOT) {
+            const int64_t g = o * int64_t(n) * a.inner + row0 + off;
+            const double rv = a.dot_r[g];
+            dot_a += rv * double(val);
+            dot_b += rv * a.dot_z[g];
+          }
+        }
+      }
+    }
+  }
+  if constexpr (DOT) {
+    dot_a = wave_sum(dot_a);
+    dot_b = wave_sum(dot_b);
+    if (lane == 0) {
+      a.part_a[lb] = dot_a;
+      a.part_b[lb] = dot_b;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Mode product, wide form (large launches with one operand): a wave computes all G = ceil(n / 16)
 // column groups of a 16-row tile, so every In fragment it loads feeds G MFMA chains instead of one,
 // and the packed operand U' of all groups is staged in LDS once per block of 4 waves.  A block
@@ -1226,6 +1329,136 @@ __global__ __launch_bounds__(NW * 64) void fused_time_kernel(FusedTimeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Time solves on time axes longer than the segmented layouts hold (more than 64 segments of the
+// longest compiled length): one lane per mode runs the banded forward and backward substitutions
+// over the whole axis, L D L^H x = y with the host factors in their mode-fastest layout
+// Lfac[t][k-1][mode] (complex) and 1/D[t][mode] (loads coalesced across the lanes).  Dependent
+// chain 2 n_t steps; used for the long time axes of the one-dimensional problems only.
+// ---------------------------------------------------------------------------
+template <typename T, int P>
+__global__ __launch_bounds__(256) void time_solve_seq_kernel(T* y, const T* Lfac, const T* Dinv, int n_t,
+                                                             int64_t N_s, const int* done) {
+  using T2 = typename TsVec<T>::t;
+  const int64_t rhs = blockIdx.y;
+  if (done && done[rhs]) return;
+  const int64_t mode = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (mode >= N_s) return;
+  T2* yb = reinterpret_cast<T2*>(y) + (rhs * N_s + mode) * int64_t(n_t);
+  const T2* L = reinterpret_cast<const T2*>(Lfac);
+  T hr[P], hi[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) hr[k] = hi[k] = T(0);
+  // z_t = y_t - sum_k L[t][t-k] z_{t-k}; w_t = z_t / D_t in place (h[k-1] = z_{t-k})
+  for (int t = 0; t < n_t; ++t) {
+    const T2 yv = yb[t];
+    T zr = yv.x, zi = yv.y;
+#pragma unroll
+    for (int k = P; k >= 1; --k) {
+      const T2 l = t - k >= 0 ? L[(int64_t(t) * P + (k - 1)) * N_s + mode] : T2{T(0), T(0)};
+      zr = fma(-l.x, hr[k - 1], zr);
+      zr = fma(l.y, hi[k - 1], zr);
+      zi = fma(-l.x, hi[k - 1], zi);
+      zi = fma(-l.y, hr[k - 1], zi);
+    }
+#pragma unroll
+    for (int k = P - 1; k >= 1; --k) {
+      hr[k] = hr[k - 1];
+      hi[k] = hi[k - 1];
+    }
+    hr[0] = zr;
+    hi[0] = zi;
+    const T d = Dinv[int64_t(t) * N_s + mode];
+    T2 w;
+    w.x = zr * d;
+    w.y = zi * d;
+    yb[t] = w;
+  }
+  // x_t = w_t - sum_k conj(L[t+k][t]) x_{t+k} (h[k-1] = x_{t+k})
+#pragma unroll
+  for (int k = 0; k < P; ++k) hr[k] = hi[k] = T(0);
+  for (int t = n_t - 1; t >= 0; --t) {
+    const T2 wv = yb[t];
+    T xr = wv.x, xi = wv.y;
+#pragma unroll
+    for (int k = P; k >= 1; --k) {
+      const T2 l = t + k < n_t ? L[(int64_t(t + k) * P + (k - 1)) * N_s + mode] : T2{T(0), T(0)};
+      xr = fma(-l.x, hr[k - 1], xr);
+      xr = fma(-l.y, hi[k - 1], xr);
+      xi = fma(-l.x, hi[k - 1], xi);
+      xi = fma(l.y, hr[k - 1], xi);
+    }
+#pragma unroll
+    for (int k = P - 1; k >= 1; --k) {
+      hr[k] = hr[k - 1];
+      hi[k] = hi[k - 1];
+    }
+    hr[0] = xr;
+    hi[0] = xi;
+    T2 xo;
+    xo.x = xr;
+    xo.y = xi;
+    yb[t] = xo;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Matvec of one-dimensional problems with long time axes (the stencil kernel stages a whole
+// time line per point in LDS, which bounds n_t): one lane per (x_1 point, t) entry sums the
+// (2 p_s + 1)(2 p_t + 1) neighbours of eq. syst_mat directly,
+//   Y(t, i) = sum_s sum_dt (S_1[i][s] L_t + S_2[i][s] M_t + i S_3[i][s] K_t)[t][dt] X(t + dt - p_t, i + s - p_s),
+// neighbours through L1 / L2 (consecutive lanes read consecutive t), and one partial of
+// Re <x, y> per block.
+// ---------------------------------------------------------------------------
+constexpr int kMvLongBlock = 256;
+__global__ __launch_bounds__(kMvLongBlock) void matvec_long1d_kernel(const double* x, double* y, const double* Sc,
+                                                                    const double* TbL, int n_t, int pt, int n1,
+                                                                    int ps, int64_t blocks_per_rhs,
+                                                                    double* partial, const int* done) {
+  __shared__ double red[kMvLongBlock / 64];
+  const int64_t rhs = blockIdx.y;
+  if (done && done[rhs]) return;
+  const int64_t N = int64_t(n1) * n_t;
+  const int64_t e = int64_t(blockIdx.x) * kMvLongBlock + threadIdx.x;
+  const bool active = e < N;
+  const int64_t ec = active ? e : N - 1;
+  const int i = int(ec / n_t), t = int(ec - int64_t(i) * n_t);
+  const int ws = 2 * ps + 1, wt = 2 * pt + 1;
+  const double2* X = reinterpret_cast<const double2*>(x) + rhs * N;
+  double yr = 0.0, yi = 0.0;
+  for (int s = 0; s < ws; ++s) {
+    const int j = i + s - ps;
+    if (j < 0 || j >= n1) continue;
+    const double c1 = Sc[(int64_t(i) * ws + s) * 3], c2 = Sc[(int64_t(i) * ws + s) * 3 + 1],
+                 c3 = Sc[(int64_t(i) * ws + s) * 3 + 2];
+    for (int dt = 0; dt < wt; ++dt) {
+      const int tt = t + dt - pt;
+      if (tt < 0 || tt >= n_t) continue;
+      const double* tb = TbL + (int64_t(t) * wt + dt) * 4;
+      const double ar = fma(c1, tb[0], c2 * tb[1]), ai = c3 * tb[2];  // S_1 L_t + S_2 M_t + i S_3 K_t
+      const double2 xv = X[int64_t(j) * n_t + tt];
+      yr = fma(ar, xv.x, fma(-ai, xv.y, yr));
+      yi = fma(ar, xv.y, fma(ai, xv.x, yi));
+    }
+  }
+  double part = 0.0;
+  if (active) {
+    reinterpret_cast<double2*>(y)[rhs * N + e] = make_double2(yr, yi);
+    const double2 xe = X[e];
+    part = xe.x * yr + xe.y * yi;
+  }
+  if (partial) {
+    part = wave_sum(part);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t2 = 0.0;
+      for (int w = 0; w < kMvLongBlock / 64; ++w) t2 += red[w];
+      partial[rhs * blocks_per_rhs + blockIdx.x] = t2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Matrix-free system matvec (Section 5.3, eq. syst_mat with potential terms):
 //   Y = sum_k T_k X S_k^T, X viewed as n_t x N_s (time fastest).
 // Lanes run over the flat (spatial point, t) index of X, so that no lane idles
@@ -1242,7 +1475,11 @@ __global__ __launch_bounds__(NW * 64) void fused_time_kernel(FusedTimeArgs a) {
 //          the bands from LDS, zero outside 0 <= t + dt < n_t.
 // Optionally writes one partial of Re <x, y> per block (PCG's <p, A p>).
 // ---------------------------------------------------------------------------
-constexpr int kMvMaxNt = 128;      // longest time axis accepted at setup
+constexpr int kMvMaxNt = 128;      // longest time axis of the stencil and sum-factorised matvecs
+// one-dimensional problems beyond those limits (long axes): the chunked mode product, the
+// sequential time solve and the direct matvec
+constexpr int kLongMaxN = 1024;    // n_1 at most
+constexpr int kLongMaxNt = 2048;   // n_t at most
 constexpr int kMvLanes = 512;      // lanes per matvec block at most
 constexpr size_t kMvLds = 48 * 1024;  // LDS per block for coefficients / Z (several blocks per CU)
 constexpr uint32_t kMvBadOffset = 1u << 30;  // neighbour outside the grid (beyond any buffer)
@@ -1913,12 +2150,15 @@ struct stfd_problem {
   stfd::PcgScalars* sc_host_dev = nullptr;  // device address of sc_host
   int64_t mp_last_blocks[3] = {0, 0, 0};  // per precision: blocks per rhs of the last mode product (dot partials)
   int mp_rt[3][3] = {};                   // [precision][direction]: row groups per wave of the mode products
-  int ts_mode = 0;                        // time solve: 0 tables, 1 transfers computed, 2 factor computed
+  int ts_mode = 0;                        // time solve: 0 tables, 1 transfers computed, 2 factor computed,
+                                          // 3 one lane per mode over the whole axis (TsL / TsD hold the
+                                          // host factors in their mode-fastest layout)
   bool autotuned = false;
   double tune_ms = 0.0;                   // device time spent by the setup's tuning runs
   int64_t u_slice0 = 0;                  // per-mode pencils along x_1 (mapped domain): n_1^2, else 0
   int64_t mv_blocks = 0;
   int mv_points = 1;  // spatial points per matvec block
+  bool mv_long = false;  // one-dimensional problem with a long time axis: matvec_long1d_kernel
   size_t max_lds = 65536;  // per-block LDS limit of the device used at setup
   int n_cus = 256;         // compute units of the device used at setup
   stfd::LoadPlan load;     // basis matrices on the Gauss grids (right-hand side assembly)
@@ -2138,8 +2378,8 @@ template <int PREC, typename Tin, typename Tout>
 static int launch_mode_product(const void* in, void* out, const void* U, int n, int64_t inner, int64_t outer,
                                int64_t outer_per_rhs, const int* done, hipStream_t s,
                                const DotEpilogue& ep = DotEpilogue(), int64_t u_slice_stride = 0, int rt = 0) {
-  if (n < 1 || n > kMaxModeN || outer_per_rhs < 1 || rt < 0 || rt > kMpWide || (rt >= 2 && n > 80) ||
-      (rt == kMpWide && u_slice_stride != 0))
+  if (n < 1 || n > kLongMaxN || outer_per_rhs < 1 || rt < 0 || rt > kMpWide || (rt >= 2 && n > 80) ||
+      (rt == kMpWide && u_slice_stride != 0) || (n > kMaxModeN && (rt > 1 || u_slice_stride != 0)))
     return STFD_EINVAL;
   if (rt == kMpWide) return launch_mode_product_wide<PREC, Tin, Tout>(in, out, U, n, inner, outer, outer_per_rhs, done, s, ep);
   ModeProductArgs a;
@@ -2168,6 +2408,20 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   if (blocks <= 0) return STFD_OK;
   if (blocks % kXcds != 0 || blocks > int64_t(UINT32_MAX)) return STFD_EINVAL;  // the kernel's XCD remap needs it
   const dim3 grid(static_cast<unsigned>(blocks)), block(64);
+  if (n > kMaxModeN) {
+    // long direction: K steps in chunks (the operand is packed with mode_product_ks steps)
+    const int ks = mode_product_ks(PREC, n);
+    if constexpr (std::is_same<Tout, double>::value) {
+      if (a.part_a) {
+        hipLaunchKernelGGL((mode_product_long_kernel<PREC, Tin, Tout, true>), grid, block, 0, s, a, ks);
+        STFD_HIP(hipGetLastError());
+        return STFD_OK;
+      }
+    }
+    hipLaunchKernelGGL((mode_product_long_kernel<PREC, Tin, Tout, false>), grid, block, 0, s, a, ks);
+    STFD_HIP(hipGetLastError());
+    return STFD_OK;
+  }
   // FP64: one instantiation per K-step count; FP32 (K = 4): buckets of 4 steps; BF16 (K = 16): exact
 #define STFD_MP(B)                                                                                      \
   case B:                                                                                               \
@@ -2234,6 +2488,22 @@ static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* don
     L = P->TsL32, D = P->TsD32, Tf = P->TsTf32, Tb = P->TsTb32, S = P->TsS32, H = P->TsH32, Mu = P->TsMu32;
   }
   const int mode = P->ts_mode;
+  if (mode == 3) {
+    if (nrhs < 1) return STFD_OK;
+    const dim3 sgrid(unsigned((hp.N_s + 255) / 256), unsigned(nrhs));
+    switch (hp.p_t) {
+#define STFD_TSQ(PV)                                                                                          \
+  case PV:                                                                                                    \
+    hipLaunchKernelGGL((time_solve_seq_kernel<T, PV>), sgrid, dim3(256), 0, s, y, L, D, hp.n_t, hp.N_s, done); \
+    break;
+      STFD_TSQ(1) STFD_TSQ(2) STFD_TSQ(3) STFD_TSQ(4) STFD_TSQ(5) STFD_TSQ(6)
+#undef STFD_TSQ
+      default:
+        return STFD_EINVAL;
+    }
+    STFD_HIP(hipGetLastError());
+    return STFD_OK;
+  }
 #define STFD_TS(PV, LV)                                                                                        \
   if (hp.p_t == PV && P->ts_len == LV) {                                                                       \
     if (mode == 0)                                                                                             \
@@ -2849,6 +3119,13 @@ static int matvec_dispatch(stfd_problem* P, const double* x, double* y, int64_t 
     return STFD_OK;
   }
   const HostProblem& hp = P->hp;
+  if (P->mv_long) {
+    if (nrhs < 1) return STFD_OK;
+    hipLaunchKernelGGL(matvec_long1d_kernel, dim3(unsigned(P->mv_blocks), unsigned(nrhs)), dim3(kMvLongBlock), 0, s,
+                       x, y, P->Sc, P->TbL, hp.n_t, hp.p_t, hp.n_s[0], hp.p_s, P->mv_blocks, partial, done);
+    STFD_HIP(hipGetLastError());
+    return STFD_OK;
+  }
   MatvecArgs a;
   a.x = x;
   a.y = y;
@@ -3027,17 +3304,27 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   if (desc->fused_segment_length < 0) return STFD_EINVAL;
   if (desc->time_condition == STFD_TIME_FINAL && geom.kind != GEOM_UNIT) return STFD_EINVAL;
   v.time_final = desc->time_condition == STFD_TIME_FINAL;
+  // sizes from the knot counts (m = knots - degree - 1 functions; the reduced bases drop two in
+  // space and one in time), checked before the host setup spends time on them
+  {
+    const int64_t n_t = int64_t(desc->n_knots_t) - desc->p_t - 2;
+    const bool one_d = desc->d == 1;
+    if (n_t > (one_d ? kLongMaxNt : kMvMaxNt)) return STFD_EINVAL;
+    for (int l = 0; l < desc->d; ++l)
+      if (int64_t(desc->n_knots_s[l]) - desc->p_s - 3 > (one_d ? kLongMaxN : kMaxModeN)) return STFD_EINVAL;
+  }
   stfd_problem* P = new (std::nothrow) stfd_problem;
   if (!P) return STFD_ENOMEM;
   int rc = host_setup(v, P->hp);
   if (rc == 0) {
     const HostProblem& hp = P->hp;
+    const bool long1d = hp.d == 1 && hp.n_s[0] <= kLongMaxN && hp.n_t <= kLongMaxNt;
     for (int l = 0; l < hp.d; ++l)
-      if (hp.n_s[l] > kMaxModeN) rc = -1;
+      if (hp.n_s[l] > kMaxModeN && !long1d) rc = -1;
     if (hp.p_t > 6) rc = -1;
     bool mv_ok = (hp.d == 1 && hp.p_s <= 6) || (hp.d == 2 && hp.p_s <= 5) || (hp.d == 3 && hp.p_s <= 4);
     if (!mv_ok) rc = -1;
-    if (hp.n_t > 128) rc = -1;
+    if (hp.n_t > kMvMaxNt && !long1d) rc = -1;
   }
   if (rc) {
     delete P;
@@ -3125,7 +3412,9 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
       P->n_cus = cus;
     P->ts_len = time_segment_length(hp.n_t, hp.p_t);
-    if (P->ts_len == 0 || hp.n_t > kMvMaxNt || hp.N_s * hp.n_t * 16 >= int64_t(kMvBadOffset)) {
+    P->mv_long = hp.d == 1 && hp.n_t > kMvMaxNt;
+    if ((P->ts_len == 0 && hp.d != 1) || (hp.n_t > kMvMaxNt && !P->mv_long) ||
+        hp.N_s * hp.n_t * 16 >= int64_t(kMvBadOffset)) {
       stfd_destroy(P);
       return STFD_EINVAL;
     }
@@ -3135,8 +3424,12 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
     TimeSolvePlan tp;
     // all tables where one right-hand side's grid holds at most one wave per SIMD (the solve is
     // bound by its dependent chain), else the factor-in-kernel form (bound by table traffic)
-    const int mpb = 64 / ((hp.n_t + P->ts_len - 1) / P->ts_len);  // modes per block
-    P->ts_mode = (hp.N_s + mpb - 1) / mpb <= 4 * int64_t(P->n_cus) ? 0 : 2;
+    if (P->ts_len == 0) {
+      P->ts_mode = 3;  // no segmented layout holds the axis: one lane per mode
+    } else {
+      const int mpb = 64 / ((hp.n_t + P->ts_len - 1) / P->ts_len);  // modes per block
+      P->ts_mode = (hp.N_s + mpb - 1) / mpb <= 4 * int64_t(P->n_cus) ? 0 : 2;
+    }
     if (desc->autotune) {
       const auto t0 = std::chrono::steady_clock::now();
       TuneClock C;
@@ -3147,7 +3440,15 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
       P->tune_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       P->autotuned = true;
     }
-    if (time_tables(hp, P->ts_len, P->ts_mode, tp) != 0) {
+    if (P->ts_mode == 3) {
+      // the host factors as they are: Lfac[t][k-1][mode] (complex) and 1/D[t][mode]
+      tp.Lf.resize(hp.Lfac.size() * 2);
+      for (size_t k = 0; k < hp.Lfac.size(); ++k) {
+        tp.Lf[2 * k] = hp.Lfac[k].real();
+        tp.Lf[2 * k + 1] = hp.Lfac[k].imag();
+      }
+      tp.Df = hp.Dinv;
+    } else if (time_tables(hp, P->ts_len, P->ts_mode, tp) != 0) {
       stfd_destroy(P);
       return STFD_EINVAL;
     }
@@ -3238,6 +3539,7 @@ int stfd_setup(const stfd_setup_desc* desc, stfd_problem** out) {
   } else {
     P->mv_points = matvec_points_per_block(hp, P->n_cus);
     P->mv_blocks = (hp.N_s + P->mv_points - 1) / P->mv_points;
+    if (P->mv_long) P->mv_blocks = (hp.N + kMvLongBlock - 1) / kMvLongBlock;
   }
   // row groups of every product from the heuristic (the autotune below may change them); the dot
   // partials are sized for one row group, the largest block count

@@ -237,6 +237,27 @@ class HighModeSeries1D:
     def u0(self, x):
         return np.zeros(np.shape(x), dtype=np.complex128)
 
+    # the same series through its per-mode factors, for tensor grids too fine to sample point by
+    # point: u = sum_k a_k(t) e_k(x), f = sum_k c_k(t) e_k(x)
+    def space_factors(self, x):
+        """e_k(x_q) for the points x (array of length Q): shape (Q, M)."""
+        k = np.arange(1, self.M + 1, dtype=np.float64)
+        return np.sqrt(2.0) * np.sin(np.pi * np.outer(np.asarray(x, dtype=np.float64), k))
+
+    def time_factors_u(self, t):
+        k = np.arange(1, self.M + 1, dtype=np.float64)
+        t = np.asarray(t, dtype=np.float64)[:, None]
+        return -1j * t / k * np.exp(1j * (np.pi * k) ** 2 * t)
+
+    def time_factors_f(self, t):
+        k = np.arange(1, self.M + 1, dtype=np.float64)
+        t = np.asarray(t, dtype=np.float64)[:, None]
+        return (1.0 / k) * np.exp(1j * (np.pi * k) ** 2 * t)
+
+    def f_grid(self, t, x):
+        """f on the tensor grid t x x, shape (len(x), len(t)) (time fastest)."""
+        return self.space_factors(x) @ self.time_factors_f(t).T
+
 
 # ----------------------------------------------------------------------------
 # workloads

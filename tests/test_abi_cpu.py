@@ -97,13 +97,18 @@ def test_setup_rejects_bad_d_and_nrhs():
         stfd.Problem(kn, [kn], 2, 2, max_nrhs=0)
 
 
-def test_setup_rejects_direction_above_mode_product_limit():
-    """The MFMA mode product keeps one 16-column block of U_l per wave for n_l <= 128."""
+def test_setup_rejects_sizes_above_the_limits():
+    """n_l, n_t <= 128 for d = 2, 3 (one 16-column block of U_l per wave, one time line per point in
+    the matvec's LDS); n_1 <= 1024 and n_t <= 2048 for d = 1 (the long-axis kernels).  Rejected from
+    the knot counts, before any host or device work."""
     stfd = _lib()
-    kn = inputs.uniform_open_knots(130, 2)
-    with pytest.raises(stfd.StfdError) as ei:
-        stfd.Problem(inputs.uniform_open_knots(4, 2), [kn], 2, 2)
-    assert ei.value.code == stfd.EINVAL
+    for kt, ks in ((inputs.uniform_open_knots(4, 2), [inputs.uniform_open_knots(130, 2)] * 2),
+                   (inputs.uniform_open_knots(130, 2), [inputs.uniform_open_knots(4, 2)] * 2),
+                   (inputs.uniform_open_knots(4, 2), [inputs.uniform_open_knots(1030, 2)]),
+                   (inputs.uniform_open_knots(2050, 2), [inputs.uniform_open_knots(4, 2)])):
+        with pytest.raises(stfd.StfdError) as ei:
+            stfd.Problem(kt, ks, 2, 2)
+        assert ei.value.code == stfd.EINVAL
 
 
 def test_handle_entry_points_reject_null_handle():

@@ -61,3 +61,24 @@ def test_section61_data_satisfy_the_equation(name):
     assert err < (1e-8 if name == "gaussian" else 1e-4), err
     if name == "high_mode":
         assert np.max(np.abs(m.u(0.0, x))) == 0.0 and np.max(np.abs(m.u(t, 0.0 * x))) < 1e-12
+
+
+def test_separable_errors_equal_pointwise_errors():
+    """errors_separable (the exact series through its per-mode factors on the tensor grid) against
+    errors (the series evaluated point by point) for the high-mode data with M = 40 on a coarse
+    solve, and the separable sampling of f against f itself."""
+    from oracle.rhs import errors_separable
+    p, n, T = 3, 6, 2.0
+    m = HighModeSeries1D(M=40)
+    kt, ks = uniform_open_knots(2 * n, p, T), [uniform_open_knots(n, p)]
+    pr = Problem(kt, ks, p, p, 1.0, None)
+    fb, G = assemble_rhs(SpaceTimeBasis(kt, ks, p, p), 1.0, f=m.f, u0=m.u0, dirichlet=m.u)
+    x, info = pcg(pr.matvec, FastDiagonalization(pr).apply, fb, tol=1e-12, maxit=300)
+    C = full_coefficients(G, x, pr.n_s, pr.n_t)
+    l2, vn = errors(kt, ks, p, p, C, 1.0, m.u, m.f)
+    l2s, vns = errors_separable(kt, ks, p, p, C, 1.0, m.space_factors, m.time_factors_u, m.time_factors_f)
+    assert abs(l2s - l2) <= 1e-12 * l2 and abs(vns - vn) <= 1e-12 * vn
+    rng = np.random.default_rng(6)
+    t, xx = rng.uniform(0.0, T, 7), rng.uniform(0.0, 1.0, 5)
+    want = m.f(t[None, :], xx[:, None])
+    assert np.max(np.abs(m.f_grid(t, xx) - want)) <= 1e-12 * np.max(np.abs(want))
