@@ -1335,6 +1335,25 @@ __global__ __launch_bounds__(NW * 64) void fused_time_kernel(FusedTimeArgs a) {
 // Lfac[t][k-1][mode] (complex) and 1/D[t][mode] (loads coalesced across the lanes).  Dependent
 // chain 2 n_t steps; used for the long time axes of the one-dimensional problems only.
 // ---------------------------------------------------------------------------
+// [rhs][mode][t] <-> [rhs][t][mode] through 32 x 32 LDS tiles (both sides coalesced).
+template <typename T2>
+__global__ __launch_bounds__(256) void time_transpose_kernel(const T2* in, T2* out, int64_t rows, int64_t cols) {
+  __shared__ T2 tile[32][33];
+  const int64_t rhs = blockIdx.z;
+  const T2* src = in + rhs * rows * cols;
+  T2* dst = out + rhs * rows * cols;
+  const int64_t r0 = int64_t(blockIdx.y) * 32, c0 = int64_t(blockIdx.x) * 32;
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + threadIdx.x;
+    if (r < rows && c < cols) tile[k][threadIdx.x] = src[r * cols + c];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + threadIdx.x;
+    if (r < rows && c < cols) dst[c * rows + r] = tile[threadIdx.x][k];
+  }
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(256) void time_solve_seq_kernel(T* y, const T* Lfac, const T* Dinv, int n_t,
                                                              int64_t N_s, const int* done) {
@@ -1343,7 +1362,13 @@ __global__ __launch_bounds__(256) void time_solve_seq_kernel(T* y, const T* Lfac
   if (done && done[rhs]) return;
   const int64_t mode = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (mode >= N_s) return;
-  T2* yb = reinterpret_cast<T2*>(y) + (rhs * N_s + mode) * int64_t(n_t);
+  // y of one right-hand side transposed to [t][mode] (time_transpose_kernel): the lanes' rows are
+  // adjacent in memory
+  struct Rows {
+    T2* p;
+    int64_t s;
+    __device__ T2& operator[](int t) const { return p[int64_t(t) * s]; }
+  } yb{reinterpret_cast<T2*>(y) + rhs * N_s * int64_t(n_t) + mode, N_s};
   const T2* L = reinterpret_cast<const T2*>(Lfac);
   T hr[P], hi[P];
 #pragma unroll
@@ -2477,7 +2502,7 @@ static int64_t mp_last_blocks_bound(const stfd_problem* P) {
 
 // FP64 storage: FP64 solve; FP32 storage: FP32 solve with the FP32 tables
 template <typename T>
-static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* done, hipStream_t s) {
+static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* done, hipStream_t s, T* tmp) {
   const HostProblem& hp = P->hp;
   const int64_t bpr = P->ts_blocks;
   const dim3 grid(unsigned(bpr * nrhs)), block(kTsLanes);
@@ -2489,18 +2514,28 @@ static int launch_time_solve(stfd_problem* P, T* y, int64_t nrhs, const int* don
   }
   const int mode = P->ts_mode;
   if (mode == 3) {
+    // y transposed into tmp (the apply's other intermediate), solved there, transposed back
+    using T2 = typename TsVec<T>::t;
     if (nrhs < 1) return STFD_OK;
+    if (!tmp || nrhs > 65535) return STFD_EINVAL;
+    const dim3 tb(32, 8);
+    const dim3 tg_fwd(unsigned((hp.n_t + 31) / 32), unsigned((hp.N_s + 31) / 32), unsigned(nrhs));
+    const dim3 tg_bwd(unsigned((hp.N_s + 31) / 32), unsigned((hp.n_t + 31) / 32), unsigned(nrhs));
+    hipLaunchKernelGGL(time_transpose_kernel<T2>, tg_fwd, tb, 0, s, reinterpret_cast<const T2*>(y),
+                       reinterpret_cast<T2*>(tmp), hp.N_s, int64_t(hp.n_t));
     const dim3 sgrid(unsigned((hp.N_s + 255) / 256), unsigned(nrhs));
     switch (hp.p_t) {
 #define STFD_TSQ(PV)                                                                                          \
   case PV:                                                                                                    \
-    hipLaunchKernelGGL((time_solve_seq_kernel<T, PV>), sgrid, dim3(256), 0, s, y, L, D, hp.n_t, hp.N_s, done); \
+    hipLaunchKernelGGL((time_solve_seq_kernel<T, PV>), sgrid, dim3(256), 0, s, tmp, L, D, hp.n_t, hp.N_s, done); \
     break;
       STFD_TSQ(1) STFD_TSQ(2) STFD_TSQ(3) STFD_TSQ(4) STFD_TSQ(5) STFD_TSQ(6)
 #undef STFD_TSQ
       default:
         return STFD_EINVAL;
     }
+    hipLaunchKernelGGL(time_transpose_kernel<T2>, tg_bwd, tb, 0, s, reinterpret_cast<const T2*>(tmp),
+                       reinterpret_cast<T2*>(y), int64_t(hp.n_t), hp.N_s);
     STFD_HIP(hipGetLastError());
     return STFD_OK;
   }
@@ -2716,7 +2751,7 @@ static int apply_impl(stfd_problem* P, const double* r, double* s_out, int64_t n
     if constexpr (PREC != MP_BF16)
       rc = launch_fused_time<PREC, TY>(P, static_cast<TY*>(bufs[cur]), static_cast<TY*>(bufs[cur]), nrhs, done, s);
   } else {
-    rc = launch_time_solve<TY>(P, static_cast<TY*>(bufs[cur]), nrhs, done, s);
+    rc = launch_time_solve<TY>(P, static_cast<TY*>(bufs[cur]), nrhs, done, s, static_cast<TY*>(bufs[cur ^ 1]));
   }
   if (rc) return rc;
   // step 4: s = (U_s (x) I) x in reverse order, the last product writes FP64 output
@@ -2906,7 +2941,7 @@ static int tune_time_solve(stfd_problem* P, TuneClock& C) {
         P->ts_mpb = tp.mpb;
         P->ts_blocks = tp.blocks;
         float ms = 0.0f;
-        rc = C.median([&]() { return launch_time_solve<double>(P, y, 1, nullptr, C.s); }, &ms);
+        rc = C.median([&]() { return launch_time_solve<double>(P, y, 1, nullptr, C.s, nullptr); }, &ms);
         if (rc == STFD_OK && (!have || ms < best)) {
           have = true;
           best = ms;
