@@ -429,12 +429,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D precision section")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--profile", nargs="?", const="2d", choices=["2d", "3d48", "3d32"],
+    ap.add_argument("--profile", nargs="?", const="2d", choices=["2d", "3d48", "3d32", "long1d"],
                     help="short run for rocprofv3 on one workload (2d: the 2D p=3 64^3 Gaussian-potential step; "
                          "3d48 / 3d32: the 3D harmonic workloads p=3 48^4 / p=4 32^4): one solve, 20 applies per "
                          "precision (3D: and 20 FP64 applies with the fused last-direction launch), 20 matvecs, "
                          "and a device copy of known size (64 MiB read + 64 MiB written) to calibrate FETCH_SIZE / "
-                         "WRITE_SIZE")
+                         "WRITE_SIZE; long1d: the Section 6.1 high-mode series on 512 x 1024 elements, p = 4 "
+                         "(long axes), solved to 1e-10")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
@@ -462,7 +463,18 @@ def main():
         return solve(prec)
 
     if args.profile:
-        if args.profile != "2d":
+        if args.profile == "long1d":
+            prob.close()
+            p, n = 4, 512
+            series = inputs.HighModeSeries1D(625)
+            prob = stfd.Problem(inputs.uniform_open_knots(2 * n, p), [inputs.uniform_open_knots(n, p)], p, p, 2.0, 1.0)
+            N = prob.N
+            f = torch.empty(N, dtype=torch.complex128, device=dev)
+            u = torch.empty_like(f)
+            fq = series.f_grid(prob.quad[0][0], prob.quad[1][0]).ravel()
+            prob.load_vector(f, f_q=torch.from_numpy(fq).to(dev), stream=stream)
+            rc, info = prob.pcg_solve(f, u, rtol=1e-10, maxit=1000, stream=stream)
+        elif args.profile != "2d":
             prob.close()
             n_el, p = (48, 3) if args.profile == "3d48" else (32, 4)
             w3 = inputs.harmonic_3d_workload(0, n_el=n_el, p=p, with_potential=True)
