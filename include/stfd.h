@@ -335,6 +335,17 @@ int stfd_pcg_solve_batched(const stfd_problem *const *probs, int count, const vo
 int stfd_timing_begin(stfd_problem *P, int capacity);
 int stfd_timing_end(stfd_problem *P, double *total_ms, int64_t *launches);
 
+/* Kernel timing for measurement: the forward mode product of `direction` (Algorithm 1 step 2)
+ * for one right-hand side, in the launch shape the applies use, launched `reps` times back to back
+ * on the stream after two untimed launches, from one of the handle's work buffers into the other
+ * (their contents are overwritten); *avg_ms = HIP-event time between the first and the last
+ * launch divided by reps (back-to-back launches overlap the dispatch of one launch with the
+ * previous kernel, as in an apply).  precision FP64: FP64 operand and output (the first product of
+ * an FP64 apply); FP32 / BF16: FP32 operand and output.  Synchronises with the stream.
+ * Errors: STFD_EINVAL (NULL handle or avg_ms, reps < 1, direction outside 0..d-1, unknown
+ * precision), STFD_EHIP. */
+int stfd_time_mode_product(stfd_problem *P, int direction, int precision, int reps, void *stream, double *avg_ms);
+
 /* Launch shapes of a problem.  With stfd_setup_desc.autotune = 1 the setup timed on the device
  * (2 untimed and 5 timed launches per candidate on a private stream, median kept):
  *   the shape of every mode product, per precision and direction, for directions with n_l <= 80:

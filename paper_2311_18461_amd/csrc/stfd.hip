@@ -3856,6 +3856,52 @@ int stfd_timing_end(stfd_problem* P, double* total_ms, int64_t* launches) {
   return rc;
 }
 
+int stfd_time_mode_product(stfd_problem* P, int direction, int precision, int reps, void* stream, double* avg_ms) {
+  if (!P || !avg_ms || reps < 1 || direction < 0 || direction >= P->hp.d || precision < STFD_FP64 ||
+      precision > STFD_BF16)
+    return STFD_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const HostProblem& hp = P->hp;
+  const int l = direction, n = hp.n_s[l];
+  const int64_t inner = mp_inner(hp, l), outer = mp_outer(hp, l);
+  const int64_t slice = l == 0 ? P->upk_slice[precision] : 0;
+  // the forward product of one right-hand side in the applies' shape, from one work buffer into the
+  // other (FP64: FP64 in and out, as the first product of an FP64 apply; otherwise FP32 in and out)
+  auto launch = [&]() -> int {
+    const int rt = P->mp_rt[precision][l];
+    if (precision == STFD_FP64)
+      return launch_mode_product<MP_F64, double, double>(P->work64[0], P->work64[1], P->Upk_fwd[MP_F64][l], n, inner,
+                                                         outer, outer, nullptr, s, DotEpilogue(), slice, rt);
+    if (precision == STFD_FP32)
+      return launch_mode_product<MP_F32, float, float>(P->work32[0], P->work32[1], P->Upk_fwd[MP_F32][l], n, inner,
+                                                       outer, outer, nullptr, s, DotEpilogue(), slice, rt);
+    return launch_mode_product<MP_BF16, float, float>(P->work32[0], P->work32[1], P->Upk_fwd[MP_BF16][l], n, inner,
+                                                      outer, outer, nullptr, s, DotEpilogue(), slice, rt);
+  };
+  int rc;
+  for (int w = 0; w < 2; ++w)
+    if ((rc = launch())) return rc;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  rc = STFD_OK;
+  for (int k = 0; k < reps && e == hipSuccess && rc == STFD_OK; ++k) rc = launch();
+  if (e == hipSuccess && rc == STFD_OK) e = hipEventRecord(b, s);
+  if (e == hipSuccess && rc == STFD_OK) e = hipEventSynchronize(b);
+  float ms = 0.0f;
+  if (e == hipSuccess && rc == STFD_OK) e = hipEventElapsedTime(&ms, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (rc) return rc;
+  if (e != hipSuccess) {
+    g_last_hip_error = int(e);
+    return STFD_EHIP;
+  }
+  *avg_ms = double(ms) / reps;
+  return STFD_OK;
+}
+
 int stfd_apply_preconditioner(const stfd_problem* Pc, const void* r_dev, void* s_dev, int64_t nrhs, int precision,
                               void* stream) {
   stfd_problem* P = const_cast<stfd_problem*>(Pc);

@@ -89,6 +89,8 @@ SIGNATURES = {
     "stfd_set_lift_max_iterations": (ctypes.c_int, [_VP, ctypes.c_int]),
     "stfd_timing_begin": (ctypes.c_int, [_VP, ctypes.c_int]),
     "stfd_timing_end": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "stfd_time_mode_product": (ctypes.c_int, [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, _VP,
+                                              ctypes.POINTER(ctypes.c_double)]),
     "stfd_fno_create": (ctypes.c_int, [ctypes.POINTER(FnoDesc), ctypes.POINTER(_VP)]),
     "stfd_fno_num_params": (ctypes.c_int, [_VP, ctypes.POINTER(_I64)]),
     "stfd_fno_get_params": (ctypes.c_int, [_VP, _FP]),
@@ -380,6 +382,15 @@ class Problem:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(_lib().stfd_timing_end(self._h, ctypes.byref(ms), ctypes.byref(n)), "stfd_timing_end")
         return ms.value, n.value
+
+    def time_mode_product(self, direction: int = 0, precision=FP64, reps: int = 200, stream=None):
+        """stfd_time_mode_product: average ms per launch of the forward mode product of one
+        direction, launched reps times back to back."""
+        precision = PRECISIONS.get(precision, precision)
+        ms = ctypes.c_double()
+        _check(_lib().stfd_time_mode_product(self._h, int(direction), precision, int(reps), _stream_ptr(stream),
+                                             ctypes.byref(ms)), "stfd_time_mode_product")
+        return ms.value
 
     def set_lift_max_iterations(self, max_iter: int):
         """stfd_set_lift_max_iterations: iteration limit of the lifting CG in load_vector."""

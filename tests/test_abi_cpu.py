@@ -180,3 +180,9 @@ def test_precond_shift_rejected_where_it_does_not_apply():
     with pytest.raises(stfd.StfdError) as ei:
         stfd.Problem(kn, [kn], 3, 3, precond_shift=3)
     assert ei.value.code == stfd.EINVAL
+
+
+def test_time_mode_product_rejects_null_handle():
+    stfd = _lib()
+    ms = ctypes.c_double()
+    assert stfd._lib().stfd_time_mode_product(None, 0, 0, 10, None, ctypes.byref(ms)) == stfd.EINVAL

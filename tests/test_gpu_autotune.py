@@ -135,3 +135,32 @@ def test_set_tuning_rejects_invalid_shapes():
     with pytest.raises(stfd.StfdError):
         lib.set_mode_product_shapes({"fp64": [1, 4]})
     lib.set_mode_product_shapes({"fp64": [1, 3]})
+
+
+def test_time_mode_product_measures_and_checks_arguments():
+    """stfd_time_mode_product: a positive average per launch for every direction and precision,
+    no longer than one launch bracketed by its own events (which also enclose the dispatch), and
+    argument errors.  The applies afterwards are unchanged (it only uses the work buffers)."""
+    from paper_2311_18461_amd import stfd
+    kt = inputs.uniform_open_knots(16, 3)
+    lib = stfd.Problem(kt, [kt, kt], 3, 3)
+    r = torch.from_numpy(inputs.random_complex(lib.N, 63)).to(DEV)
+    before, after = torch.empty_like(r), torch.empty_like(r)
+    lib.apply_preconditioner(r, before)
+    for l in range(2):
+        for prec in ("fp64", "fp32", "bf16"):
+            ms = lib.time_mode_product(l, prec, reps=50)
+            assert 0.0 < ms < 1.0, (l, prec, ms)
+    lib.timing_begin(capacity=8)
+    lib.apply_preconditioner(r, after)
+    tot, n = lib.timing_end()
+    assert n == 4 and lib.time_mode_product(0, "fp64", reps=200) <= 1.5 * tot / n
+    lib.apply_preconditioner(r, after)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+    for bad in ((2, "fp64"), (-1, "fp64"), (0, 7)):
+        with pytest.raises(stfd.StfdError) as ei:
+            lib.time_mode_product(bad[0], bad[1], reps=5)
+        assert ei.value.code == stfd.EINVAL
+    with pytest.raises(stfd.StfdError):
+        lib.time_mode_product(0, "fp64", reps=0)
