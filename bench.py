@@ -44,7 +44,7 @@ PEAK_HBM_GBS = 8000.0
 # (stfd_time_mode_product: per launch, the kernel plus what its dispatch does not overlap with the
 # previous one); the events around each single launch of an apply (library timing hooks) enclose the
 # whole dispatch as well and are reported beside it.
-MODE_PRODUCT_KERNEL = "mode_product_kernel<0, double, double, 17, 1, false>"
+MODE_PRODUCT_KERNEL = "mode_product_kernel<0, double, double, 17, 1, false, 0>"
 MODE_PRODUCT_TRAFFIC_BYTES = 9.43e6
 MODE_PRODUCT_MFMA_FLOPS = 9.77e7
 def build_workload(sample=0, n_el=64, p=3):

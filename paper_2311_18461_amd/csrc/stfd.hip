@@ -213,7 +213,37 @@ __device__ __forceinline__ typename MPTraits<PREC>::op_t to_op(float v) {
   else return f32_to_bf16(v);
 }
 
-template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT>
+// Remainder columns.  Where n = 16 g + r with g >= 1 and r <= 2, the last r output columns would
+// take a 16-column MFMA group of their own, at least 14/16 of it padding (n = 65 in 2D and 49 in
+// 3D at p = 3: 20 and 25% of the MFMA work and of the narrow form's waves).  Instead they are
+// computed with vector FMAs from the In values the wave already holds: a lane sums
+// U'[j][a] In[j][row] over its own K rows j = ks K + E grp + e in K-step order, and two butterfly
+// rounds over the four lane groups complete the sum in every lane.  Operands are rounded as the
+// MFMA rounds them (FP32, BF16) and summed in its accumulator type.  The narrow and the wide form
+// run this same sequence, so they still agree bit for bit.
+template <int PREC>
+using rem_acc_t = typename std::conditional<PREC == MP_F64, double, float>::type;
+__device__ __forceinline__ float bf16_round(float v) {
+  return __uint_as_float(uint32_t(uint16_t(f32_to_bf16(v))) << 16);
+}
+template <int PREC, typename U, typename X>
+__device__ __forceinline__ rem_acc_t<PREC> rem_step(U u, X x, bool in_k, rem_acc_t<PREC> s) {
+  if constexpr (PREC == MP_F64) {
+    return __builtin_fma(double(u), in_k ? double(x) : 0.0, s);
+  } else if constexpr (PREC == MP_F32) {
+    return __builtin_fmaf(float(u), in_k ? float(x) : 0.0f, s);
+  } else {
+    return __builtin_fmaf(bf16_round(float(u)), in_k ? bf16_round(float(x)) : 0.0f, s);
+  }
+}
+template <typename A>
+__device__ __forceinline__ A rem_finish(A s) {
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  return s;
+}
+
+template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT, int RC>
 __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
   using Tr = MPTraits<PREC>;
   using op_t = typename Tr::op_t;
@@ -249,6 +279,35 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
     int rc[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) rc[t] = min(16 * t + col, rows_here - 1);
+    // remainder columns 16 groups + c, c < RC (computed by the waves of the last MFMA group): this
+    // lane's U' values of them are lane grp * 16 + c of the packed group after the last MFMA group;
+    // loaded first, so that waiting for the first In fragment covers them
+    const bool rem_wave = RC > 0 && cg == a.groups - 1;
+    u_t urm[RC > 0 ? RC : 1][KS][E];
+    double rrm[RT][RC > 0 ? RC : 1], zrm[RT][RC > 0 ? RC : 1];
+    if constexpr (RC > 0) {
+      if (rem_wave) {
+        const u_t* Ur = static_cast<const u_t*>(a.U) +
+                        (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0) +
+                        (int64_t(a.groups) * KS * 64 + grp * 16) * E;
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int e = 0; e < E; ++e) urm[c][ks][e] = Ur[(ks * 64 + c) * E + e];
+        if constexpr (DOT) {
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < RC; ++c) {
+              const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(16 * a.groups + c) * a.inner + rc[t];
+              rrm[t][c] = a.dot_r[g];
+              zrm[t][c] = a.dot_z[g];
+            }
+        }
+      }
+    }
     u_t ur[KS][E];
     Tin xr[RT][KS][E];
 #pragma unroll
@@ -328,6 +387,30 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
             }
           }
         }
+      }
+    }
+    if constexpr (RC > 0) {
+      if (rem_wave) {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int c = 0; c < RC; ++c) {
+            rem_acc_t<PREC> sum = 0;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+              for (int e = 0; e < E; ++e)
+                sum = rem_step<PREC>(urm[c][ks][e], xr[t][ks][e], ks * K + E * grp + e < n, sum);
+            sum = rem_finish(sum);
+            if (grp == 0 && 16 * t + col < rows_here) {
+              const Tout val = Tout(sum);
+              dst[int64_t(16 * a.groups + c) * a.inner + 16 * t + col] = val;
+              if constexpr (DOT) {
+                dot_a += rrm[t][c] * double(val);
+                dot_b += rrm[t][c] * zrm[t][c];
+              }
+            }
+          }
       }
     }
   }
@@ -454,14 +537,25 @@ __global__ __launch_bounds__(64) void mode_product_long_kernel(ModeProductArgs a
 // memory pipeline moves 1/G of the In bytes and none of the U' bytes of the one-group form.
 // Grid (blocks_per_rhs, nrhs); the fused dot products write one partial pair per block.
 // ---------------------------------------------------------------------------
-template <int PREC, typename Tin, typename Tout, int KS, bool DOT>
-__global__ __launch_bounds__(256) void mode_product_wide_kernel(ModeProductArgs a, int64_t blocks_per_rhs) {
+// Waves per SIMD asked of the compiler: the grid is kMpWideBlocks blocks of 4 waves, so 4 blocks
+// per CU hold it in one round; with 3 the last quarter of the blocks runs alone after the rest
+// (3D p = 3 48^4, n = 49: 41 us per product at 3 waves).  Asked only where the compiler's resource
+// report shows 4 waves (128 registers, accumulators in VGPRs) without spilling; elsewhere its own
+// choice stands.
+template <int PREC, int KS, bool DOT, int RC>
+constexpr int mode_product_wide_waves() {
+  return (PREC == MP_F64 && !DOT && (KS <= 10 || (KS == 12 && RC == 0) || (KS == 13 && RC == 1))) ? 4 : 1;
+}
+template <int PREC, typename Tin, typename Tout, int KS, bool DOT, int RC>
+__global__ __launch_bounds__(256, (mode_product_wide_waves<PREC, KS, DOT, RC>())) void mode_product_wide_kernel(
+    ModeProductArgs a, int64_t blocks_per_rhs) {
   using Tr = MPTraits<PREC>;
   using op_t = typename Tr::op_t;
   using u_t = typename Tr::u_t;
   constexpr int K = Tr::K;
   constexpr int E = K / 4;
   constexpr int G = PREC == MP_BF16 ? KS : (KS + 3) / 4;  // column groups of the packed operand
+  constexpr int GM = RC > 0 ? G - 1 : G;                   // of them computed by MFMA chains
   __shared__ u_t Us[G * KS * 64 * E];
   __shared__ double red[2][4];
   const int64_t rhs = blockIdx.y;
@@ -490,10 +584,11 @@ __global__ __launch_bounds__(256) void mode_product_wide_kernel(ModeProductArgs 
       for (int e = 0; e < E; ++e) xr[ks][e] = src[int64_t(min(ks * K + E * grp + e, n - 1)) * a.inner + rc];
     // operands of the fused dot products, in the same batch as In (loaded after the stores they
     // would wait behind every store: the compiler cannot tell that r, z_old and Out do not overlap)
-    double rv[DOT ? G : 1][4], zv[DOT ? G : 1][4];
+    double rv[DOT ? GM : 1][4], zv[DOT ? GM : 1][4];
+    double rrm[RC > 0 ? RC : 1], zrm[RC > 0 ? RC : 1];
     if constexpr (DOT) {
 #pragma unroll
-      for (int g = 0; g < G; ++g)
+      for (int g = 0; g < GM; ++g)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int aa = min(16 * g + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
@@ -501,18 +596,27 @@ __global__ __launch_bounds__(256) void mode_product_wide_kernel(ModeProductArgs 
           rv[g][v] = a.dot_r[off];
           zv[g][v] = a.dot_z[off];
         }
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        const int64_t off = base + int64_t(16 * GM + c) * a.inner + rc;
+        rrm[c] = a.dot_r[off];
+        zrm[c] = a.dot_z[off];
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
-    typename Tr::acc_t acc[G];
+    typename Tr::acc_t acc[GM];
 #pragma unroll
-    for (int g = 0; g < G; ++g) acc[g] = typename Tr::acc_t{0, 0, 0, 0};
+    for (int g = 0; g < GM; ++g) acc[g] = typename Tr::acc_t{0, 0, 0, 0};
+    rem_acc_t<PREC> rsum[RC > 0 ? RC : 1];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) rsum[c] = 0;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       op_t xb[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) xb[e] = to_op<PREC>(ks * K + E * grp + e < n ? xr[ks][e] : Tin(0));
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
+      for (int g = 0; g < GM; ++g) {
         op_t ua[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) ua[e] = to_op<PREC>(Us[((g * KS + ks) * 64 + lane) * E + e]);
@@ -530,10 +634,20 @@ __global__ __launch_bounds__(256) void mode_product_wide_kernel(ModeProductArgs 
           acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[g], 0, 0, 0);
         }
       }
+      // remainder columns 16 GM + c: vector FMAs beside the MFMA chains (U' of packed group GM,
+      // lane grp * 16 + c, an LDS broadcast)
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          rsum[c] = rem_step<PREC>(Us[((GM * KS + ks) * 64 + grp * 16 + c) * E + e], xr[ks][e],
+                                   ks * K + E * grp + e < n, rsum[c]);
     }
+#pragma unroll
+    for (int c = 0; c < RC; ++c) rsum[c] = rem_finish(rsum[c]);
     if (col < rows_here) {
 #pragma unroll
-      for (int g = 0; g < G; ++g)
+      for (int g = 0; g < GM; ++g)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int aa = 16 * g + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v);
@@ -547,6 +661,17 @@ __global__ __launch_bounds__(256) void mode_product_wide_kernel(ModeProductArgs 
             }
           }
         }
+      if (grp == 0) {
+#pragma unroll
+        for (int c = 0; c < RC; ++c) {
+          const Tout val = Tout(rsum[c]);
+          dst[int64_t(16 * GM + c) * a.inner + col] = val;
+          if constexpr (DOT) {
+            dot_a += rrm[c] * double(val);
+            dot_b += rrm[c] * zrm[c];
+          }
+        }
+      }
     }
   }
   if constexpr (DOT) {
@@ -2249,6 +2374,21 @@ static int upload(stfd_problem* P, T** ptr, const T* src, size_t count) {
 // -> 375 us; 2D 64^3 (2960 waves) 38.7 -> 41.8 us, hence the threshold.  Depends on per-rhs
 // sizes only, so every precision writes the same dot partials.
 constexpr int64_t kMpTwoGroupMinWaves = 16384;
+// Output columns computed by vector FMAs instead of an MFMA group of their own (the kernels'
+// remainder columns): the last r of n = 16 g + r, g >= 1, r <= 2, in launches large enough to keep
+// the chip busy with the fewer waves (as for two row groups); none for the long directions.  In a
+// small launch the longer waves of the last group set the time (2D 64^3: 6.8 -> 7.3 us per
+// product), in a large one the saved MFMA work does (3D 48^4: 41 -> 37 us).  Depends on per-rhs
+// sizes only, so every shape and every batch size computes the same way.
+static int mode_product_rem(int n, int64_t inner, int64_t outer_per_rhs) {
+  const int r = n - 16 * ((n + 15) / 16 - 1);
+  const int64_t waves1 = int64_t((n + 15) / 16) * outer_per_rhs * ((inner + 15) / 16);
+  return (n > 16 && n <= kMaxModeN && r <= 2 && waves1 >= kMpTwoGroupMinWaves) ? r : 0;
+}
+// 16-column groups computed by MFMA chains
+static int mode_product_groups(int n, int64_t inner, int64_t outer_per_rhs) {
+  return (n + 15) / 16 - (mode_product_rem(n, inner, outer_per_rhs) > 0 ? 1 : 0);
+}
 static int mode_product_row_groups(int n, int64_t inner, int64_t outer_per_rhs) {
   const int64_t waves1 = int64_t((n + 15) / 16) * outer_per_rhs * ((inner + 15) / 16);
   return (n <= 80 && waves1 >= kMpTwoGroupMinWaves) ? 2 : 1;
@@ -2269,7 +2409,7 @@ static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_p
   if (rt == kMpWide) return mode_product_wide_blocks(inner, outer_per_rhs);
   const int rows = 16 * (rt > 0 ? rt : mode_product_row_groups(n, inner, outer_per_rhs));
   const int64_t tiles = outer_per_rhs * ((inner + rows - 1) / rows);
-  return int64_t((n + 15) / 16) * ((tiles + kXcds - 1) / kXcds * kXcds);
+  return int64_t(mode_product_groups(n, inner, outer_per_rhs)) * ((tiles + kXcds - 1) / kXcds * kXcds);
 }
 
 // K steps of one mode-product instantiation: exact for FP64 (K = 4) and BF16 (K = 16), buckets
@@ -2303,29 +2443,47 @@ static void pack_mode_operand(const double* Uop, int n, int nsl, int K, int E, i
           }
 }
 
-// launch with RT row groups per wave; the two-group variant exists only for the K-step counts of
-// n <= 80 (mode_product_row_groups never asks for it beyond)
-template <int PREC, typename Tin, typename Tout, int KS, bool DOT>
-static void launch_mode_product_rt_dot(int rt, dim3 grid, dim3 block, hipStream_t s, const ModeProductArgs& a) {
-  constexpr bool kTwo = (PREC == MP_BF16) ? (KS <= 5) : (KS <= 20);
-  if constexpr (kTwo) {
-    if (rt == 2) {
-      hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, 2, DOT>), grid, block, 0, s, a);
-      return;
+// K-step counts of the instantiations whose n can have remainder columns: n = 16 g + 1 or 2 gives
+// KS = 4 g + 1 (FP64), 4 (g + 1) (FP32), g + 1 (BF16)
+template <int PREC, int KS>
+constexpr bool mode_product_has_rem() {
+  return PREC == MP_F64 ? (KS % 4 == 1 && KS >= 5) : PREC == MP_F32 ? (KS % 4 == 0 && KS >= 8) : KS >= 2;
+}
+// launch with RT row groups and RC remainder columns per wave (false: no such instantiation)
+template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT>
+static bool launch_mode_product_rc(int rc, dim3 grid, dim3 block, hipStream_t s, const ModeProductArgs& a) {
+  if constexpr (mode_product_has_rem<PREC, KS>()) {
+    if (rc == 1) {
+      hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, RT, DOT, 1>), grid, block, 0, s, a);
+      return true;
+    }
+    if (rc == 2) {
+      hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, RT, DOT, 2>), grid, block, 0, s, a);
+      return true;
     }
   }
-  hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, 1, DOT>), grid, block, 0, s, a);
+  if (rc != 0) return false;
+  hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, RT, DOT, 0>), grid, block, 0, s, a);
+  return true;
+}
+// the two-row-group variant exists only for the K-step counts of n <= 80
+// (mode_product_row_groups never asks for it beyond)
+template <int PREC, typename Tin, typename Tout, int KS, bool DOT>
+static bool launch_mode_product_rt_dot(int rt, int rc, dim3 grid, dim3 block, hipStream_t s,
+                                       const ModeProductArgs& a) {
+  constexpr bool kTwo = (PREC == MP_BF16) ? (KS <= 5) : (KS <= 20);
+  if constexpr (kTwo) {
+    if (rt == 2) return launch_mode_product_rc<PREC, Tin, Tout, KS, 2, DOT>(rc, grid, block, s, a);
+  }
+  return launch_mode_product_rc<PREC, Tin, Tout, KS, 1, DOT>(rc, grid, block, s, a);
 }
 // the fused dot products exist only for the FP64 output of the last backward product
 template <int PREC, typename Tin, typename Tout, int KS>
-static void launch_mode_product_rt(int rt, dim3 grid, dim3 block, hipStream_t s, const ModeProductArgs& a) {
+static bool launch_mode_product_rt(int rt, int rc, dim3 grid, dim3 block, hipStream_t s, const ModeProductArgs& a) {
   if constexpr (std::is_same<Tout, double>::value) {
-    if (a.part_a) {
-      launch_mode_product_rt_dot<PREC, Tin, Tout, KS, true>(rt, grid, block, s, a);
-      return;
-    }
+    if (a.part_a) return launch_mode_product_rt_dot<PREC, Tin, Tout, KS, true>(rt, rc, grid, block, s, a);
   }
-  launch_mode_product_rt_dot<PREC, Tin, Tout, KS, false>(rt, grid, block, s, a);
+  return launch_mode_product_rt_dot<PREC, Tin, Tout, KS, false>(rt, rc, grid, block, s, a);
 }
 
 struct DotEpilogue {
@@ -2350,7 +2508,7 @@ static int launch_mode_product_wide(const void* in, void* out, const void* U, in
   a.n_row_tiles = (inner + 15) / 16;
   a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
   a.tiles_pad = a.tiles_per_rhs;
-  a.groups = (n + 15) / 16;
+  a.groups = mode_product_groups(n, inner, outer_per_rhs);
   a.done = done;
   a.dot_r = ep.r;
   a.dot_z = ep.zold;
@@ -2363,16 +2521,28 @@ static int launch_mode_product_wide(const void* in, void* out, const void* U, in
   const dim3 grid(static_cast<unsigned>(bpr), static_cast<unsigned>(nrhs)), block(256);
   const int ks = mode_product_ks(PREC, n);
   const bool dot = ep.part_a != nullptr;
-#define STFD_MPW(KV)                                                                                       \
-  case KV:                                                                                                 \
-    if constexpr (std::is_same<Tout, double>::value) {                                                     \
-      if (dot) {                                                                                           \
-        hipLaunchKernelGGL((mode_product_wide_kernel<PREC, Tin, Tout, KV, true>), grid, block, 0, s, a, bpr); \
-        break;                                                                                             \
-      }                                                                                                    \
-    }                                                                                                      \
-    hipLaunchKernelGGL((mode_product_wide_kernel<PREC, Tin, Tout, KV, false>), grid, block, 0, s, a, bpr);  \
-    break;
+  const int rc = mode_product_rem(n, inner, outer_per_rhs);
+#define STFD_MPW_RC(KV, RCV)                                                                                     \
+  if constexpr (std::is_same<Tout, double>::value) {                                                            \
+    if (dot) {                                                                                                  \
+      hipLaunchKernelGGL((mode_product_wide_kernel<PREC, Tin, Tout, KV, true, RCV>), grid, block, 0, s, a, bpr); \
+      break;                                                                                                    \
+    }                                                                                                           \
+  }                                                                                                             \
+  hipLaunchKernelGGL((mode_product_wide_kernel<PREC, Tin, Tout, KV, false, RCV>), grid, block, 0, s, a, bpr);    \
+  break;
+#define STFD_MPW(KV)                                          \
+  case KV:                                                    \
+    if constexpr (mode_product_has_rem<PREC, KV>()) {         \
+      if (rc == 1) {                                          \
+        STFD_MPW_RC(KV, 1)                                    \
+      }                                                       \
+      if (rc == 2) {                                          \
+        STFD_MPW_RC(KV, 2)                                    \
+      }                                                       \
+    }                                                         \
+    if (rc != 0) return STFD_EINVAL;                          \
+    STFD_MPW_RC(KV, 0)
   if constexpr (PREC == MP_F64) {
     switch (ks) {
       STFD_MPW(1) STFD_MPW(2) STFD_MPW(3) STFD_MPW(4) STFD_MPW(5) STFD_MPW(6) STFD_MPW(7) STFD_MPW(8)
@@ -2395,6 +2565,7 @@ static int launch_mode_product_wide(const void* in, void* out, const void* U, in
     }
   }
 #undef STFD_MPW
+#undef STFD_MPW_RC
   STFD_HIP(hipGetLastError());
   return STFD_OK;
 }
@@ -2420,7 +2591,8 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   a.n_row_tiles = (inner + 16 * RTn - 1) / (16 * RTn);
   a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
   a.tiles_pad = (a.tiles_per_rhs + kXcds - 1) / kXcds * kXcds;
-  a.groups = (n + 15) / 16;
+  a.groups = mode_product_groups(n, inner, outer_per_rhs);
+  const int rc = mode_product_rem(n, inner, outer_per_rhs);
   a.done = done;
   a.dot_r = ep.r;
   a.dot_z = ep.zold;
@@ -2448,9 +2620,10 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
     return STFD_OK;
   }
   // FP64: one instantiation per K-step count; FP32 (K = 4): buckets of 4 steps; BF16 (K = 16): exact
-#define STFD_MP(B)                                                                                      \
-  case B:                                                                                               \
-    launch_mode_product_rt<PREC, Tin, Tout, (PREC == MP_F32 ? 4 * B : B)>(RTn, grid, block, s, a);      \
+#define STFD_MP(B)                                                                                         \
+  case B:                                                                                                  \
+    if (!launch_mode_product_rt<PREC, Tin, Tout, (PREC == MP_F32 ? 4 * B : B)>(RTn, rc, grid, block, s, a)) \
+      return STFD_EINVAL;                                                                                  \
     break;
   const int sel = PREC == MP_F32 ? (nks + 3) / 4 : nks;
   if ((PREC == MP_F32 ? 4 * sel : sel) != mode_product_ks(PREC, n)) return STFD_EINVAL;  // packing must match
