@@ -218,22 +218,18 @@ __device__ __forceinline__ typename MPTraits<PREC>::op_t to_op(float v) {
 // 3D at p = 3: 20 and 25% of the MFMA work and of the narrow form's waves).  Instead they are
 // computed with vector FMAs from the In values the wave already holds: a lane sums
 // U'[j][a] In[j][row] over its own K rows j = ks K + E grp + e in K-step order, and two butterfly
-// rounds over the four lane groups complete the sum in every lane.  Operands are rounded as the
-// MFMA rounds them (FP32, BF16) and summed in its accumulator type.  The narrow and the wide form
-// run this same sequence, so they still agree bit for bit.
+// rounds over the four lane groups complete the sum in every lane.  FP64 and FP32 products only
+// (operands rounded as the MFMA rounds them, summed in its accumulator type); BF16 keeps the MFMA
+// group.  The narrow and the wide form run this same sequence, so they still agree bit for bit.
 template <int PREC>
 using rem_acc_t = typename std::conditional<PREC == MP_F64, double, float>::type;
-__device__ __forceinline__ float bf16_round(float v) {
-  return __uint_as_float(uint32_t(uint16_t(f32_to_bf16(v))) << 16);
-}
 template <int PREC, typename U, typename X>
 __device__ __forceinline__ rem_acc_t<PREC> rem_step(U u, X x, bool in_k, rem_acc_t<PREC> s) {
+  static_assert(PREC != MP_BF16, "no remainder columns in BF16 products");
   if constexpr (PREC == MP_F64) {
     return __builtin_fma(double(u), in_k ? double(x) : 0.0, s);
-  } else if constexpr (PREC == MP_F32) {
-    return __builtin_fmaf(float(u), in_k ? float(x) : 0.0f, s);
   } else {
-    return __builtin_fmaf(bf16_round(float(u)), in_k ? bf16_round(float(x)) : 0.0f, s);
+    return __builtin_fmaf(float(u), in_k ? float(x) : 0.0f, s);
   }
 }
 template <typename A>
@@ -636,12 +632,14 @@ __global__ __launch_bounds__(256, (mode_product_wide_waves<PREC, KS, DOT, RC>())
       }
       // remainder columns 16 GM + c: vector FMAs beside the MFMA chains (U' of packed group GM,
       // lane grp * 16 + c, an LDS broadcast)
+      if constexpr (RC > 0) {
 #pragma unroll
-      for (int c = 0; c < RC; ++c)
+        for (int c = 0; c < RC; ++c)
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-          rsum[c] = rem_step<PREC>(Us[((GM * KS + ks) * 64 + grp * 16 + c) * E + e], xr[ks][e],
-                                   ks * K + E * grp + e < n, rsum[c]);
+          for (int e = 0; e < E; ++e)
+            rsum[c] = rem_step<PREC>(Us[((GM * KS + ks) * 64 + grp * 16 + c) * E + e], xr[ks][e],
+                                     ks * K + E * grp + e < n, rsum[c]);
+      }
     }
 #pragma unroll
     for (int c = 0; c < RC; ++c) rsum[c] = rem_finish(rsum[c]);
@@ -2375,19 +2373,21 @@ static int upload(stfd_problem* P, T** ptr, const T* src, size_t count) {
 // sizes only, so every precision writes the same dot partials.
 constexpr int64_t kMpTwoGroupMinWaves = 16384;
 // Output columns computed by vector FMAs instead of an MFMA group of their own (the kernels'
-// remainder columns): the last r of n = 16 g + r, g >= 1, r <= 2, in launches large enough to keep
-// the chip busy with the fewer waves (as for two row groups); none for the long directions.  In a
-// small launch the longer waves of the last group set the time (2D 64^3: 6.8 -> 7.3 us per
-// product), in a large one the saved MFMA work does (3D 48^4: 41 -> 37 us).  Depends on per-rhs
-// sizes only, so every shape and every batch size computes the same way.
-static int mode_product_rem(int n, int64_t inner, int64_t outer_per_rhs) {
+// remainder columns): the last r of n = 16 g + r, g >= 1, r <= 2, in FP64 and FP32 launches large
+// enough to keep the chip busy with the fewer waves (as for two row groups); none for the long
+// directions.  In a small launch the longer waves of the last group set the time (2D 64^3: 6.8 ->
+// 7.3 us per product), in a large one the saved MFMA work does (3D 48^4 FP64 apply 461 -> 420 us,
+// FP32 308 -> 288 us).  BF16 keeps the MFMA group: its MFMA is cheap and rounding the operands to
+// BF16 on the vector units is not (3D 48^4 apply 262 -> 283 us).  Depends on the precision and
+// per-rhs sizes only, so every shape and every batch size computes the same way.
+static int mode_product_rem(int prec, int n, int64_t inner, int64_t outer_per_rhs) {
   const int r = n - 16 * ((n + 15) / 16 - 1);
   const int64_t waves1 = int64_t((n + 15) / 16) * outer_per_rhs * ((inner + 15) / 16);
-  return (n > 16 && n <= kMaxModeN && r <= 2 && waves1 >= kMpTwoGroupMinWaves) ? r : 0;
+  return (prec != MP_BF16 && n > 16 && n <= kMaxModeN && r <= 2 && waves1 >= kMpTwoGroupMinWaves) ? r : 0;
 }
 // 16-column groups computed by MFMA chains
-static int mode_product_groups(int n, int64_t inner, int64_t outer_per_rhs) {
-  return (n + 15) / 16 - (mode_product_rem(n, inner, outer_per_rhs) > 0 ? 1 : 0);
+static int mode_product_groups(int prec, int n, int64_t inner, int64_t outer_per_rhs) {
+  return (n + 15) / 16 - (mode_product_rem(prec, n, inner, outer_per_rhs) > 0 ? 1 : 0);
 }
 static int mode_product_row_groups(int n, int64_t inner, int64_t outer_per_rhs) {
   const int64_t waves1 = int64_t((n + 15) / 16) * outer_per_rhs * ((inner + 15) / 16);
@@ -2405,11 +2405,11 @@ static int64_t mode_product_wide_blocks(int64_t inner, int64_t outer_per_rhs) {
   const int64_t tiles = outer_per_rhs * ((inner + 15) / 16);
   return std::min<int64_t>((tiles + 3) / 4, kMpWideBlocks);
 }
-static int64_t mode_product_blocks_per_rhs(int n, int64_t inner, int64_t outer_per_rhs, int rt = 0) {
+static int64_t mode_product_blocks_per_rhs(int prec, int n, int64_t inner, int64_t outer_per_rhs, int rt = 0) {
   if (rt == kMpWide) return mode_product_wide_blocks(inner, outer_per_rhs);
   const int rows = 16 * (rt > 0 ? rt : mode_product_row_groups(n, inner, outer_per_rhs));
   const int64_t tiles = outer_per_rhs * ((inner + rows - 1) / rows);
-  return int64_t(mode_product_groups(n, inner, outer_per_rhs)) * ((tiles + kXcds - 1) / kXcds * kXcds);
+  return int64_t(mode_product_groups(prec, n, inner, outer_per_rhs)) * ((tiles + kXcds - 1) / kXcds * kXcds);
 }
 
 // K steps of one mode-product instantiation: exact for FP64 (K = 4) and BF16 (K = 16), buckets
@@ -2444,10 +2444,10 @@ static void pack_mode_operand(const double* Uop, int n, int nsl, int K, int E, i
 }
 
 // K-step counts of the instantiations whose n can have remainder columns: n = 16 g + 1 or 2 gives
-// KS = 4 g + 1 (FP64), 4 (g + 1) (FP32), g + 1 (BF16)
+// KS = 4 g + 1 (FP64), 4 (g + 1) (FP32); none in BF16
 template <int PREC, int KS>
 constexpr bool mode_product_has_rem() {
-  return PREC == MP_F64 ? (KS % 4 == 1 && KS >= 5) : PREC == MP_F32 ? (KS % 4 == 0 && KS >= 8) : KS >= 2;
+  return PREC == MP_F64 ? (KS % 4 == 1 && KS >= 5) : PREC == MP_F32 ? (KS % 4 == 0 && KS >= 8) : false;
 }
 // launch with RT row groups and RC remainder columns per wave (false: no such instantiation)
 template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT>
@@ -2508,7 +2508,7 @@ static int launch_mode_product_wide(const void* in, void* out, const void* U, in
   a.n_row_tiles = (inner + 15) / 16;
   a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
   a.tiles_pad = a.tiles_per_rhs;
-  a.groups = mode_product_groups(n, inner, outer_per_rhs);
+  a.groups = mode_product_groups(PREC, n, inner, outer_per_rhs);
   a.done = done;
   a.dot_r = ep.r;
   a.dot_z = ep.zold;
@@ -2521,7 +2521,7 @@ static int launch_mode_product_wide(const void* in, void* out, const void* U, in
   const dim3 grid(static_cast<unsigned>(bpr), static_cast<unsigned>(nrhs)), block(256);
   const int ks = mode_product_ks(PREC, n);
   const bool dot = ep.part_a != nullptr;
-  const int rc = mode_product_rem(n, inner, outer_per_rhs);
+  const int rc = mode_product_rem(PREC, n, inner, outer_per_rhs);
 #define STFD_MPW_RC(KV, RCV)                                                                                     \
   if constexpr (std::is_same<Tout, double>::value) {                                                            \
     if (dot) {                                                                                                  \
@@ -2591,8 +2591,8 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   a.n_row_tiles = (inner + 16 * RTn - 1) / (16 * RTn);
   a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
   a.tiles_pad = (a.tiles_per_rhs + kXcds - 1) / kXcds * kXcds;
-  a.groups = mode_product_groups(n, inner, outer_per_rhs);
-  const int rc = mode_product_rem(n, inner, outer_per_rhs);
+  a.groups = mode_product_groups(PREC, n, inner, outer_per_rhs);
+  const int rc = mode_product_rem(PREC, n, inner, outer_per_rhs);
   a.done = done;
   a.dot_r = ep.r;
   a.dot_z = ep.zold;
@@ -2665,12 +2665,13 @@ static int mp_last_dir(const stfd_problem* P) { return P->u_slice0 ? P->hp.d - 1
 static void set_last_blocks(stfd_problem* P) {
   const int l = mp_last_dir(P);
   for (int prec = MP_F64; prec <= MP_BF16; ++prec)
-    P->mp_last_blocks[prec] = mode_product_blocks_per_rhs(P->hp.n_s[l], mp_inner(P->hp, l), mp_outer(P->hp, l),
+    P->mp_last_blocks[prec] = mode_product_blocks_per_rhs(prec, P->hp.n_s[l], mp_inner(P->hp, l), mp_outer(P->hp, l),
                                                           P->mp_rt[prec][l]);
 }
 static int64_t mp_last_blocks_bound(const stfd_problem* P) {
   const int l = mp_last_dir(P);
-  return mode_product_blocks_per_rhs(P->hp.n_s[l], mp_inner(P->hp, l), mp_outer(P->hp, l), 1);
+  // BF16 has no remainder columns: the most column groups, hence blocks, of any precision
+  return mode_product_blocks_per_rhs(MP_BF16, P->hp.n_s[l], mp_inner(P->hp, l), mp_outer(P->hp, l), 1);
 }
 
 // FP64 storage: FP64 solve; FP32 storage: FP32 solve with the FP32 tables
