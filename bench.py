@@ -33,19 +33,19 @@ METRIC = "FD precond apply Mdof/s + PCG time to 1e-8: FP64 vs mixed/batched/warm
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector and matrix peak
 PEAK_HBM_GBS = 8000.0
 # Dominant kernel of the step: the FP64 mode product of the FD apply (Algorithm 1 steps 2 and 4;
-# rocprofv3 kernel statistics of `bench.py --profile 2d`: 26.8% of kernel time, plus 10.2% for its
+# rocprofv3 kernel statistics of `bench.py --profile 2d`: 24.4% of kernel time, plus 9.8% for its
 # variant with the fused PCG dot products).  Per launch on this workload (2D p=3 64^3, n = 65 per
 # direction), from profiles/fd_apply_2d_p3_n64_gauss.md (mean of its two launch shapes):
 #   HBM traffic: FETCH_SIZE x 1.999 + WRITE_SIZE x 1.000 (factors: what the counters read for a
-#   64 MiB device copy in the same run) = 9.43e6 bytes (algorithmic: 32 bytes per dof = 8.92e6);
+#   64 MiB device copy in the same run) = 9.44e6 bytes (algorithmic: 32 bytes per dof = 8.92e6);
 #   MFMA work: SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 = 9.77e7 flops (algorithmic 4 n = 260 flops per
 #   dof = 7.25e7; the rest is the padding of n = 65 to 68 rows of K and 80 output columns).
 # The bench times the launch with HIP events on its stream around 500 back-to-back launches
 # (stfd_time_mode_product: per launch, the kernel plus what its dispatch does not overlap with the
 # previous one); the events around each single launch of an apply (library timing hooks) enclose the
 # whole dispatch as well and are reported beside it.
-MODE_PRODUCT_KERNEL = "mode_product_kernel<0, double, double, 17, 1, false, 0>"
-MODE_PRODUCT_TRAFFIC_BYTES = 9.43e6
+MODE_PRODUCT_KERNEL = "mode_product_kernel<0, double, double, 17, 1, false, 0, true>"
+MODE_PRODUCT_TRAFFIC_BYTES = 9.44e6
 MODE_PRODUCT_MFMA_FLOPS = 9.77e7
 def build_workload(sample=0, n_el=64, p=3):
     from paper_2311_18461_amd import inputs, stfd

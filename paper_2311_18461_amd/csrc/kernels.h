@@ -35,7 +35,7 @@ struct ModeProductArgs {
   int64_t outer_per_rhs;
   int64_t n_row_tiles;    // row tiles (16 RT rows, RT = 1 or 2) per outer slice, ceil(inner / (16 RT))
   int64_t tiles_per_rhs;  // outer_per_rhs * n_row_tiles
-  int64_t tiles_pad;      // tiles_per_rhs rounded up to a multiple of the XCD count
+  int64_t tiles_pad;      // blocks per column group (row tiles, or groups of row tiles), padded to the XCD count
   int groups;             // 16-column groups computed by MFMA chains (mode_product_groups)
   const int* done;     // per right-hand side "converged" flags or nullptr
   // optional epilogue (FP64 output only): per-block partials of <r, out> and <r, zold>

@@ -148,21 +148,22 @@ __device__ __forceinline__ void sum_partials3(const double* a, int na, const dou
 
 // ---------------------------------------------------------------------------
 // Mode product (Algorithm 1 steps 2 and 4): Out[o][a][r] = sum_j U'[j][a] In[o][j][r].
-// One block = one wave = one group of 16 rows r of one outer slice o and one
-// group of 16 output columns a.  Every operand goes straight from global memory
-// into registers in one batch of loads (the U' fragments of the column group, packed
-// at setup in the order the lanes read them, and the In fragments of the row group
-// for all KS = ceil(n / K) K steps), then one
-// MFMA chain and the stores: no LDS staging, no barrier.  KS is exact per
-// instantiation for FP64 (padded K steps cost full MFMAs; a skipping branch
-// breaks the load batch).  Block order: workgroups are dealt out round-robin over
-// the XCDs, so logical block lb = (b % X)(grid / X) + b / X (the grid is a
-// multiple of X) gives each XCD a contiguous range of (right-hand side, row tile,
-// column group), column group fastest: the column groups of a tile, which read
-// the same In fragments, and neighbouring tiles, whose 16-row fragments straddle
-// the same cache lines when a row is not a multiple of 128 bytes, share one L2.
-// Tiles are padded to a multiple of X per right-hand side; padding blocks only
-// write zero dot partials.  Dot partials are stored at the logical index.
+// One wave = one group of 16 rows r of one outer slice o and one group of 16 output
+// columns a; a block = kMpWaves waves on consecutive row tiles of one column group.
+// The block stages the column group's U' fragments (packed at setup in the order the
+// lanes read them) in LDS, and every wave loads the In fragments of its row group for
+// all KS = ceil(n / K) K steps straight into registers in one batch, then runs one
+// MFMA chain (U' from LDS) and the stores.  KS is exact per instantiation for FP64
+// (padded K steps cost full MFMAs; a skipping branch breaks the load batch).  Block
+// order: workgroups are dealt out round-robin over the XCDs, so logical block
+// lb = (b % X)(grid / X) + b / X (the grid is a multiple of X) gives each XCD a
+// contiguous range of (right-hand side, tile group, column group), column group
+// fastest: the column groups of a tile, which read the same In fragments, and
+// neighbouring tiles, whose 16-row fragments straddle the same cache lines when a row
+// is not a multiple of 128 bytes, share one L2.  Tile groups are padded to a multiple
+// of X per right-hand side; waves past the last tile only stage U' and write zero dot
+// partials.  One dot partial pair per block, stored at the logical index.  The long
+// directions keep one-wave blocks (one tile each) and read U' from global memory.
 // MFMA computes C^T = U'^T A^T so that the 16 rows of a result fragment are
 // contiguous in memory (coalesced stores).
 //   FP64: v_mfma_f64_16x16x4f64, K step 4
@@ -239,103 +240,136 @@ __device__ __forceinline__ A rem_finish(A s) {
   return s;
 }
 
-template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT, int RC>
-__global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
+// Row tiles per block of the one-group form: the waves of a block take consecutive row tiles of one
+// column group, so the block stages that group's packed U' in LDS once and every wave reads its
+// fragments there instead of from global memory (half of the form's vector memory instructions).
+constexpr int kMpWaves = 4;
+template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT, int RC, bool LDSU>
+__global__ __launch_bounds__(64 * kMpWaves) void mode_product_kernel(ModeProductArgs a) {
   using Tr = MPTraits<PREC>;
   using op_t = typename Tr::op_t;
+  using u_t = typename Tr::u_t;
   constexpr int K = Tr::K;
   constexpr int E = K / 4;
+  constexpr int NT = 64 * kMpWaves;
+  constexpr int UG = KS * 64 * E;                             // packed U' values of one column group
+  constexpr int US = LDSU ? (RC > 0 ? 2 : 1) * UG : 1;        // staged: the group (and the remainder's)
+  constexpr int UPT = LDSU ? (US + NT - 1) / NT : 1;          // staged values per thread
+  __shared__ u_t Us[US];
+  __shared__ double red[2][kMpWaves];
   const int n = a.n;
   const int64_t per_rhs = int64_t(a.groups) * a.tiles_pad;
   const int64_t lb = int64_t(blockIdx.x % kXcds) * (gridDim.x / kXcds) + blockIdx.x / kXcds;
   const int64_t rhs = lb / per_rhs;
-  if (a.done && a.done[rhs]) return;
+  if (a.done && a.done[rhs]) return;  // uniform per block
   STFD_STAMP(1, 4);
-  const int64_t rem = lb - rhs * per_rhs;
-  const int64_t tile = rem / a.groups;
-  const int cg = int(rem - tile * a.groups);
-  const int lane = threadIdx.x;
+  const int64_t remb = lb - rhs * per_rhs;
+  const int64_t tgrp = remb / a.groups;
+  const int cg = int(remb - tgrp * a.groups);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t tile = tgrp * kMpWaves + wave;
+  const bool active = tile < a.tiles_per_rhs;
+  // remainder columns 16 groups + c, c < RC, computed by the waves of the last MFMA group; their
+  // U' values are the packed group after the last MFMA group
+  const bool rem_wave = RC > 0 && cg == a.groups - 1;
+  // staging loads first: waiting for them before the LDS writes then leaves the In loads in flight
+  u_t stg[UPT];
+  if constexpr (LDSU) {
+    const u_t* Ug = static_cast<const u_t*>(a.U) + int64_t(cg) * UG;
+    const int cnt = rem_wave ? US : UG;
+#pragma unroll
+    for (int u = 0; u < UPT; ++u) {
+      const int i = u * NT + int(threadIdx.x);
+      stg[u] = i < cnt ? Ug[i] : u_t(0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
   double dot_a = 0.0, dot_b = 0.0;
-  if (tile < a.tiles_per_rhs) {
-    // a tile is RT adjacent 16-row groups: one U' fragment load serves RT MFMA chains and a row of
-    // In is read as 16 RT consecutive values
-    const int64_t o = rhs * a.outer_per_rhs + tile / a.n_row_tiles;
-    const int64_t row0 = (tile % a.n_row_tiles) * (16 * RT);
-    const int rows_here = int(min<int64_t>(16 * RT, a.inner - row0));
-    const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
-    Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
-    const int a0 = cg * 16;
-    const int col = lane & 15, grp = lane >> 4;
-    using u_t = typename Tr::u_t;
-    // U' packed in fragment order (see pack_mode_operand): this lane's KS x E values, zero past n
-    const u_t* Up = static_cast<const u_t*>(a.U) + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0) +
-                    (int64_t(cg) * KS * 64 + lane) * E;
-    // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row 16 t + col), k = j; In
-    // addresses are clamped into the operand and values past n replaced by zeros
-    int rc[RT];
+  // a tile is RT adjacent 16-row groups: one U' fragment serves RT MFMA chains and a row of In is
+  // read as 16 RT consecutive values
+  const int64_t ti = active ? tile : 0;
+  const int64_t o = rhs * a.outer_per_rhs + ti / a.n_row_tiles;
+  const int64_t row0 = (ti % a.n_row_tiles) * (16 * RT);
+  const int rows_here = int(min<int64_t>(16 * RT, a.inner - row0));
+  const Tin* src = static_cast<const Tin*>(a.in) + o * int64_t(n) * a.inner + row0;
+  Tout* dst = static_cast<Tout*>(a.out) + o * int64_t(n) * a.inner + row0;
+  const int a0 = cg * 16;
+  const int col = lane & 15, grp = lane >> 4;
+  // operand fragments: A = U'^T (m = column a0 + col), B = In (n = row 16 t + col), k = j; In
+  // addresses are clamped into the operand and values past n replaced by zeros
+  int rc[RT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t) rc[t] = min(16 * t + col, rows_here - 1);
-    // remainder columns 16 groups + c, c < RC (computed by the waves of the last MFMA group): this
-    // lane's U' values of them are lane grp * 16 + c of the packed group after the last MFMA group;
-    // loaded first, so that waiting for the first In fragment covers them
-    const bool rem_wave = RC > 0 && cg == a.groups - 1;
-    u_t urm[RC > 0 ? RC : 1][KS][E];
-    double rrm[RT][RC > 0 ? RC : 1], zrm[RT][RC > 0 ? RC : 1];
-    if constexpr (RC > 0) {
-      if (rem_wave) {
-        const u_t* Ur = static_cast<const u_t*>(a.U) +
-                        (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0) +
-                        (int64_t(a.groups) * KS * 64 + grp * 16) * E;
+  for (int t = 0; t < RT; ++t) rc[t] = min(16 * t + col, rows_here - 1);
+  // without LDS staging (one operand per outer slice): this lane's U' values from global memory
+  // (packed in fragment order, see pack_mode_operand; zero past n)
+  const u_t* Up = static_cast<const u_t*>(a.U) + (a.u_slice_stride ? (o % a.outer_per_rhs) * a.u_slice_stride : 0) +
+                  int64_t(cg) * UG + lane * E;
+  u_t ur[LDSU ? 1 : KS][E];
+  u_t urm[(RC > 0 && !LDSU) ? RC : 1][LDSU ? 1 : KS][E];
+  double rrm[RT][RC > 0 ? RC : 1], zrm[RT][RC > 0 ? RC : 1];
+  if constexpr (RC > 0 && !LDSU) {
+    if (rem_wave) {
+      const u_t* Ur = Up - lane * E + UG + grp * 16 * E;
 #pragma unroll
-        for (int c = 0; c < RC; ++c)
+      for (int c = 0; c < RC; ++c)
 #pragma unroll
-          for (int ks = 0; ks < KS; ++ks)
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int e = 0; e < E; ++e) urm[c][ks][e] = Ur[(ks * 64 + c) * E + e];
-        if constexpr (DOT) {
+          for (int e = 0; e < E; ++e) urm[c][ks][e] = Ur[(ks * 64 + c) * E + e];
+    }
+  }
+  if constexpr (RC > 0 && DOT) {
+    if (rem_wave) {
 #pragma unroll
-          for (int t = 0; t < RT; ++t)
+      for (int t = 0; t < RT; ++t)
 #pragma unroll
-            for (int c = 0; c < RC; ++c) {
-              const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(16 * a.groups + c) * a.inner + rc[t];
-              rrm[t][c] = a.dot_r[g];
-              zrm[t][c] = a.dot_z[g];
-            }
+        for (int c = 0; c < RC; ++c) {
+          const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(16 * a.groups + c) * a.inner + rc[t];
+          rrm[t][c] = a.dot_r[g];
+          zrm[t][c] = a.dot_z[g];
         }
+    }
+  }
+  Tin xr[RT][KS][E];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int jc = min(ks * K + E * grp + e, n - 1);
+      if constexpr (!LDSU) ur[ks][e] = Up[ks * 64 * E + e];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) xr[t][ks][e] = src[int64_t(jc) * a.inner + rc[t]];
+    }
+  // operands of the fused dot products (last backward product of a PCG iteration; a template
+  // switch, so that no branch separates these loads from the operand loads)
+  double rv[RT][4], zv[RT][4];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if constexpr (DOT) {
+        const int aa = min(a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
+        const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(aa) * a.inner + rc[t];
+        rv[t][v] = a.dot_r[g];
+        zv[t][v] = a.dot_z[g];
+      } else {
+        rv[t][v] = 0.0;
+        zv[t][v] = 0.0;
       }
     }
-    u_t ur[KS][E];
-    Tin xr[RT][KS][E];
+  // keep every load above the MFMA chains (the scheduler would otherwise interleave them to save
+  // registers, turning one memory latency into several); masking and conversion happen below
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (LDSU) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int jc = min(ks * K + E * grp + e, n - 1);
-        ur[ks][e] = Up[ks * 64 * E + e];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) xr[t][ks][e] = src[int64_t(jc) * a.inner + rc[t]];
-      }
-    // operands of the fused dot products (last backward product of a PCG iteration; a template
-    // switch, so that no branch separates these loads from the operand loads)
-    double rv[RT][4], zv[RT][4];
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if constexpr (DOT) {
-          const int aa = min(a0 + (PREC == MP_F64 ? 4 * v + grp : 4 * grp + v), n - 1);
-          const int64_t g = o * int64_t(n) * a.inner + row0 + int64_t(aa) * a.inner + rc[t];
-          rv[t][v] = a.dot_r[g];
-          zv[t][v] = a.dot_z[g];
-        } else {
-          rv[t][v] = 0.0;
-          zv[t][v] = 0.0;
-        }
-      }
-    // keep every load above the MFMA chains (the scheduler would otherwise interleave them to save
-    // registers, turning one memory latency into several); masking and conversion happen below
-    __builtin_amdgcn_sched_barrier(0);
-    STFD_STAMP(1, 5);
+    for (int u = 0; u < UPT; ++u) {
+      const int i = u * NT + int(threadIdx.x);
+      if (i < US) Us[i] = stg[u];
+    }
+    __syncthreads();
+  }
+  STFD_STAMP(1, 5);
+  if (active) {
     typename Tr::acc_t acc[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc[t] = typename Tr::acc_t{0, 0, 0, 0};
@@ -343,7 +377,10 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
     for (int ks = 0; ks < KS; ++ks) {
       op_t ua[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) ua[e] = to_op<PREC>(ur[ks][e]);
+      for (int e = 0; e < E; ++e) {
+        if constexpr (LDSU) ua[e] = to_op<PREC>(Us[(ks * 64 + lane) * E + e]);
+        else ua[e] = to_op<PREC>(ur[ks][e]);
+      }
 #pragma unroll
       for (int t = 0; t < RT; ++t) {
         op_t xb[E];
@@ -395,8 +432,12 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-              for (int e = 0; e < E; ++e)
-                sum = rem_step<PREC>(urm[c][ks][e], xr[t][ks][e], ks * K + E * grp + e < n, sum);
+              for (int e = 0; e < E; ++e) {
+                u_t um;
+                if constexpr (LDSU) um = Us[UG + (ks * 64 + grp * 16 + c) * E + e];
+                else um = urm[c][ks][e];
+                sum = rem_step<PREC>(um, xr[t][ks][e], ks * K + E * grp + e < n, sum);
+              }
             sum = rem_finish(sum);
             if (grp == 0 && 16 * t + col < rows_here) {
               const Tout val = Tout(sum);
@@ -411,11 +452,23 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
     }
   }
   if constexpr (DOT) {
+    // one partial pair per block, stored at the logical block index (waves in order)
     dot_a = wave_sum(dot_a);
     dot_b = wave_sum(dot_b);
     if (lane == 0) {
-      a.part_a[lb] = dot_a;
-      a.part_b[lb] = dot_b;
+      red[0][wave] = dot_a;
+      red[1][wave] = dot_b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sa = 0.0, sb = 0.0;
+#pragma unroll
+      for (int w = 0; w < kMpWaves; ++w) {
+        sa += red[0][w];
+        sb += red[1][w];
+      }
+      a.part_a[lb] = sa;
+      a.part_b[lb] = sb;
     }
   }
   STFD_STAMP(1, 7);
@@ -425,7 +478,8 @@ __global__ __launch_bounds__(64) void mode_product_kernel(ModeProductArgs a) {
 // Mode product for long directions (n > kMaxModeN, one spatial direction): the one-group form
 // with one 16-row group per wave and the K steps walked in chunks of kLongChunk (each chunk's
 // operand loads in one batch, then its MFMA chain), so the register footprint does not grow with
-// n.  Same block layout, K-step order and epilogue as mode_product_kernel.
+// n.  One wave per block (one row tile) and U' read from global memory; K-step order and
+// epilogue as in mode_product_kernel.
 // ---------------------------------------------------------------------------
 constexpr int kLongChunk = 16;
 
@@ -2409,7 +2463,9 @@ static int64_t mode_product_blocks_per_rhs(int prec, int n, int64_t inner, int64
   if (rt == kMpWide) return mode_product_wide_blocks(inner, outer_per_rhs);
   const int rows = 16 * (rt > 0 ? rt : mode_product_row_groups(n, inner, outer_per_rhs));
   const int64_t tiles = outer_per_rhs * ((inner + rows - 1) / rows);
-  return int64_t(mode_product_groups(prec, n, inner, outer_per_rhs)) * ((tiles + kXcds - 1) / kXcds * kXcds);
+  // one-group form: kMpWaves row tiles per block; long directions: one per block
+  const int64_t units = n > kMaxModeN ? tiles : (tiles + kMpWaves - 1) / kMpWaves;
+  return int64_t(mode_product_groups(prec, n, inner, outer_per_rhs)) * ((units + kXcds - 1) / kXcds * kXcds);
 }
 
 // K steps of one mode-product instantiation: exact for FP64 (K = 4) and BF16 (K = 16), buckets
@@ -2449,21 +2505,29 @@ template <int PREC, int KS>
 constexpr bool mode_product_has_rem() {
   return PREC == MP_F64 ? (KS % 4 == 1 && KS >= 5) : PREC == MP_F32 ? (KS % 4 == 0 && KS >= 8) : false;
 }
-// launch with RT row groups and RC remainder columns per wave (false: no such instantiation)
+// launch with RT row groups and RC remainder columns per wave (false: no such instantiation), U'
+// staged in LDS unless the operand differs per outer slice
+template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT, int RC>
+static void launch_mode_product_lds(dim3 grid, dim3 block, hipStream_t s, const ModeProductArgs& a) {
+  if (a.u_slice_stride == 0)
+    hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, RT, DOT, RC, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, RT, DOT, RC, false>), grid, block, 0, s, a);
+}
 template <int PREC, typename Tin, typename Tout, int KS, int RT, bool DOT>
 static bool launch_mode_product_rc(int rc, dim3 grid, dim3 block, hipStream_t s, const ModeProductArgs& a) {
   if constexpr (mode_product_has_rem<PREC, KS>()) {
     if (rc == 1) {
-      hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, RT, DOT, 1>), grid, block, 0, s, a);
+      launch_mode_product_lds<PREC, Tin, Tout, KS, RT, DOT, 1>(grid, block, s, a);
       return true;
     }
     if (rc == 2) {
-      hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, RT, DOT, 2>), grid, block, 0, s, a);
+      launch_mode_product_lds<PREC, Tin, Tout, KS, RT, DOT, 2>(grid, block, s, a);
       return true;
     }
   }
   if (rc != 0) return false;
-  hipLaunchKernelGGL((mode_product_kernel<PREC, Tin, Tout, KS, RT, DOT, 0>), grid, block, 0, s, a);
+  launch_mode_product_lds<PREC, Tin, Tout, KS, RT, DOT, 0>(grid, block, s, a);
   return true;
 }
 // the two-row-group variant exists only for the K-step counts of n <= 80
@@ -2590,7 +2654,11 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   const int RTn = rt > 0 ? rt : mode_product_row_groups(n, inner, outer_per_rhs);
   a.n_row_tiles = (inner + 16 * RTn - 1) / (16 * RTn);
   a.tiles_per_rhs = outer_per_rhs * a.n_row_tiles;
-  a.tiles_pad = (a.tiles_per_rhs + kXcds - 1) / kXcds * kXcds;
+  // blocks per (right-hand side, column group), padded to a multiple of the XCD count: groups of
+  // kMpWaves row tiles (one-group form), single tiles (long directions)
+  const bool long_dir = n > kMaxModeN;
+  const int64_t units = long_dir ? a.tiles_per_rhs : (a.tiles_per_rhs + kMpWaves - 1) / kMpWaves;
+  a.tiles_pad = (units + kXcds - 1) / kXcds * kXcds;
   a.groups = mode_product_groups(PREC, n, inner, outer_per_rhs);
   const int rc = mode_product_rem(PREC, n, inner, outer_per_rhs);
   a.done = done;
@@ -2604,7 +2672,7 @@ static int launch_mode_product(const void* in, void* out, const void* U, int n, 
   const int64_t blocks = (outer / outer_per_rhs) * a.groups * a.tiles_pad;
   if (blocks <= 0) return STFD_OK;
   if (blocks % kXcds != 0 || blocks > int64_t(UINT32_MAX)) return STFD_EINVAL;  // the kernel's XCD remap needs it
-  const dim3 grid(static_cast<unsigned>(blocks)), block(64);
+  const dim3 grid(static_cast<unsigned>(blocks)), block(long_dir ? 64 : 64 * kMpWaves);
   if (n > kMaxModeN) {
     // long direction: K steps in chunks (the operand is packed with mode_product_ks steps)
     const int ks = mode_product_ks(PREC, n);
