@@ -31,6 +31,7 @@
 namespace stfd {
 
 constexpr int kContractBatch = 8;
+constexpr int kLiftBatch = 24;
 
 // out[o][i][r] = alpha * sum_{k in [lo_i, hi_i)} M[i * ld + k] in[o][k][r]  (+ out if accumulate)
 __global__ void __launch_bounds__(256) axis_contract_kernel(const double2* __restrict__ in, double2* __restrict__ out,
@@ -348,6 +349,9 @@ __global__ void __launch_bounds__(64 * kLiftMvWaves) lift_matvec_kernel(LiftArgs
 
 // One axis of the face-wise inverse: out[F][loc] = sum_j Minv[ax][i_s][j] in_F(loc with i_s := j),
 // in_F read from the fixed-set vector r (step 0) or from the packed buffer `in` (later steps).
+// One thread per face entry and a dense row of the 1D inverse (m_l values) per entry: the launch
+// holds a few hundred waves, so the row is read in batches of kLiftBatch loads (3 batches for
+// m_l = 67 instead of 9), each batch one memory round trip (two at step 0: index, then value).
 __global__ void __launch_bounds__(256) lift_prec_axis_kernel(LiftArgs A, int step, const double2* __restrict__ r,
                                                              const double2* __restrict__ in,
                                                              double2* __restrict__ out,
@@ -379,37 +383,37 @@ __global__ void __launch_bounds__(256) lift_prec_axis_kernel(LiftArgs A, int ste
       for (int k = 0; k < F.n_tan; ++k)
         if (k != step) g += int64_t(li[k]) * A.fc.stride[F.tan_axis[k]];
       const int64_t sg = A.fc.stride[ax];
-      for (int jb = 0; jb < mm; jb += kContractBatch) {
-        int pj[kContractBatch];
-        double c[kContractBatch];
+      for (int jb = 0; jb < mm; jb += kLiftBatch) {
+        int pj[kLiftBatch];
+        double c[kLiftBatch];
 #pragma unroll
-        for (int u = 0; u < kContractBatch; ++u) {
+        for (int u = 0; u < kLiftBatch; ++u) {
           const int j = min(jb + u, mm - 1);
           pj[u] = A.pos[g + j * sg];
           c[u] = jb + u < mm ? row[j] : 0.0;
         }
-        double2 v[kContractBatch];
+        double2 v[kLiftBatch];
 #pragma unroll
-        for (int u = 0; u < kContractBatch; ++u) v[u] = r[pj[u]];
+        for (int u = 0; u < kLiftBatch; ++u) v[u] = r[pj[u]];
 #pragma unroll
-        for (int u = 0; u < kContractBatch; ++u) {
+        for (int u = 0; u < kLiftBatch; ++u) {
           sr = fma(c[u], v[u].x, sr);
           si = fma(c[u], v[u].y, si);
         }
       }
     } else {
       const double2* src = in + F.offset + (loc - int64_t(li[step]) * lstride[step]);
-      for (int jb = 0; jb < mm; jb += kContractBatch) {
-        double c[kContractBatch];
-        double2 v[kContractBatch];
+      for (int jb = 0; jb < mm; jb += kLiftBatch) {
+        double c[kLiftBatch];
+        double2 v[kLiftBatch];
 #pragma unroll
-        for (int u = 0; u < kContractBatch; ++u) {
+        for (int u = 0; u < kLiftBatch; ++u) {
           const int j = min(jb + u, mm - 1);
           c[u] = jb + u < mm ? row[j] : 0.0;
           v[u] = src[j * lstride[step]];
         }
 #pragma unroll
-        for (int u = 0; u < kContractBatch; ++u) {
+        for (int u = 0; u < kLiftBatch; ++u) {
           sr = fma(c[u], v[u].x, sr);
           si = fma(c[u], v[u].y, si);
         }
@@ -493,18 +497,23 @@ __global__ void __launch_bounds__(256) lift_p_kernel(double2* __restrict__ p, co
 
 enum { LIFT_RESET = 0, LIFT_INIT = 1, LIFT_ALPHA = 2, LIFT_BETA = 3 };
 
-// Scalar step of the lifting CG (one thread): partials are summed in block order.
-__global__ void lift_scalar_kernel(int mode, const double* __restrict__ pa, const double* __restrict__ pb, int nparts,
-                                   LiftState* __restrict__ st, int* __restrict__ status_out, int max_iter) {
+// Scalar step of the lifting CG (one block of kLiftScalarThreads; thread 0 updates the state).
+constexpr int kLiftScalarThreads = 256;
+__global__ void __launch_bounds__(kLiftScalarThreads) lift_scalar_kernel(int mode, const double* __restrict__ pa,
+                                                                         const double* __restrict__ pb, int nparts,
+                                                                         LiftState* __restrict__ st,
+                                                                         int* __restrict__ status_out, int max_iter) {
+  __shared__ double red[2][kLiftScalarThreads / 64];
   if (blockIdx.x != 0) return;
-  // partial sums: lane l adds the partials l, l + 64, ... (in batches of loads), then a fixed-order
-  // wave reduction
+  // partial sums: thread l adds the partials l, l + T, ... (in batches of 8 loads: the matvec's
+  // few thousand partials in three memory round trips), then a fixed-order block reduction
+  constexpr int T = kLiftScalarThreads;
   double a = 0.0, b = 0.0;
-  for (int k0 = 0; k0 < nparts; k0 += 64 * 8) {
+  for (int k0 = 0; k0 < nparts; k0 += T * 8) {
     double va[8], vb[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int k = k0 + u * 64 + int(threadIdx.x);
+      const int k = k0 + u * T + int(threadIdx.x);
       va[u] = (pa && k < nparts) ? pa[k] : 0.0;
       vb[u] = (pb && k < nparts) ? pb[k] : 0.0;
     }
@@ -516,7 +525,18 @@ __global__ void lift_scalar_kernel(int mode, const double* __restrict__ pa, cons
   }
   a = wave_sum64(a);
   b = wave_sum64(b);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = a;
+    red[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  a = 0.0;
+  b = 0.0;
+  for (int w = 0; w < T / 64; ++w) {
+    a += red[0][w];
+    b += red[1][w];
+  }
   LiftState s = *st;
   if (mode == LIFT_RESET) {
     s.bn = s.rz = s.alpha = s.beta = s.rn = 0.0;
@@ -838,8 +858,8 @@ int lifting_device(const LoadPlan& plan, const double* u0_q, const double* const
   int rc;
   const int64_t mvb = (nf + kLiftMvWaves - 1) / kLiftMvWaves;  // lifting-matvec blocks (one partial each)
   auto scalar = [&](int mode, const double* pa, const double* pb, int nparts = 0) -> int {
-    hipLaunchKernelGGL(lift_scalar_kernel, dim3(1), dim3(64), 0, s, mode, pa, pb, nparts > 0 ? nparts : nb, w.st,
-                       status_dev, max_iter);
+    hipLaunchKernelGGL(lift_scalar_kernel, dim3(1), dim3(kLiftScalarThreads), 0, s, mode, pa, pb,
+                       nparts > 0 ? nparts : nb, w.st, status_dev, max_iter);
     return int(hipGetLastError());
   };
   if ((rc = scalar(LIFT_RESET, nullptr, nullptr))) return rc;
