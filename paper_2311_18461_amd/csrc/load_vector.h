@@ -65,6 +65,7 @@ struct LoadPlan {
   LiftFaces faces;
   int64_t n_fixed = 0, n_full = 0;
   int64_t* fixed = nullptr;   // [n_fixed] global index
+  int* fixed_idx = nullptr;   // [n_fixed][4] its index along each axis (decoded once, on the host)
   int* pos = nullptr;         // [n_full] fixed position or -1
   double* Mband[4] = {};      // [m][2p + 1]
   double* Minv[4] = {};       // [m][m]

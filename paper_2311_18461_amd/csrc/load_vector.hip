@@ -256,6 +256,7 @@ struct LiftState {
 struct LiftArgs {
   LiftFaces fc;
   const int64_t* fixed;
+  const int* fixed_idx;  // [n_fixed][4]
   const int* pos;
   int64_t n_fixed;
   const double* Mband[4];
@@ -276,12 +277,17 @@ __device__ __forceinline__ double block_sum256(double v, double* lds) {
   return t;
 }
 
-__device__ __forceinline__ void decode_index(int64_t g, const LiftFaces& fc, int* idx) {
-  for (int a = 0; a < fc.na; ++a) idx[a] = int((g / fc.stride[a]) % fc.m[a]);
+// Index along each axis of fixed unknown i (decoded on the host: one 16-byte load instead of 64-bit
+// divisions per axis).
+__device__ __forceinline__ void fixed_index(const LiftArgs& A, int64_t i, int* idx) {
+  const int4 v = reinterpret_cast<const int4*>(A.fixed_idx)[i];
+  idx[0] = v.x;
+  idx[1] = v.y;
+  idx[2] = v.z;
+  idx[3] = v.w;
 }
 
-// y = (sum_F P_F^T M_F P_F) x on the fixed set, and per-block partials of Re <x, y>.
-// y = (sum_F P_F^T M_F P_F) x on the fixed set, partials of <x, y> per block.  One wave per fixed
+// y = (sum_F P_F^T M_F P_F) x on the fixed set, partials of Re <x, y> per block.  One wave per fixed
 // unknown, lanes over the (flattened) tangent window of each face that contains it, so that a
 // face costs one round of gathers and a wave reduction.
 constexpr int kLiftMvWaves = 4;
@@ -297,7 +303,7 @@ __global__ void __launch_bounds__(64 * kLiftMvWaves) lift_matvec_kernel(LiftArgs
   if (i < A.n_fixed) {
     const int64_t g = A.fixed[i];
     int idx[4];
-    decode_index(g, A.fc, idx);
+    fixed_index(A, i, idx);
     double yr = 0.0, yi = 0.0;
     for (int f = 0; f < A.fc.count; ++f) {
       const LiftFace& F = A.fc.f[f];
@@ -434,7 +440,7 @@ __global__ void __launch_bounds__(256) lift_prec_sum_kernel(LiftArgs A, const do
   double arr = 0.0, arz = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < A.n_fixed; i += int64_t(gridDim.x) * blockDim.x) {
     int idx[4];
-    decode_index(A.fixed[i], A.fc, idx);
+    fixed_index(A, i, idx);
     double zr = 0.0, zi = 0.0;
     for (int f = 0; f < A.fc.count; ++f) {
       const LiftFace& F = A.fc.f[f];
@@ -647,6 +653,7 @@ LiftArgs lift_args(const LoadPlan& plan) {
   LiftArgs A;
   A.fc = plan.faces;
   A.fixed = plan.fixed;
+  A.fixed_idx = plan.fixed_idx;
   A.pos = plan.pos;
   A.n_fixed = plan.n_fixed;
   for (int a = 0; a < 4; ++a) {
@@ -835,7 +842,11 @@ int load_plan_build(const HostProblem& hp, LoadPlan& plan) {
   }
   plan.n_fixed = int64_t(fixed.size());
   plan.lift_blocks = int(std::min<int64_t>((plan.n_fixed + 255) / 256, 1024));
+  std::vector<int> fixed_idx(size_t(plan.n_fixed) * 4, 0);
+  for (size_t i = 0; i < fixed.size(); ++i)
+    for (int a = 0; a < fc.na; ++a) fixed_idx[i * 4 + a] = int((fixed[i] / fc.stride[a]) % fc.m[a]);
   if (int rc = plan_upload(plan, &plan.fixed, fixed)) return rc;
+  if (int rc = plan_upload(plan, &plan.fixed_idx, fixed_idx)) return rc;
   if (int rc = plan_upload(plan, &plan.pos, pos)) return rc;
   return 0;
 }
