@@ -84,6 +84,41 @@ __global__ void __launch_bounds__(256) axis_contract_kernel(const double2* __res
 //   (both matrices as transposed bands band[u][row] = M[row][lo_row + u]);
 //   time_load:   X0[o][i] = sum_q L0[i][q] R[o][q],  X1[o][i] = sum_q L1[i][q] R[o][q],
 //                Y[o][i] = J[o] (-i X1 + V[o] X0)  (V == nullptr drops the term, J == nullptr: 1).
+// R at time Gauss point q of one spatial point, from the point's A and C (tl[0..m), tl[m..2m)).
+__device__ __forceinline__ double2 time_expand_at(const double2* tl, int m, int q, int Q, const double* E0b,
+                                                  const double* E1b, const int* lo, int ew) {
+  double ar = 0.0, ai = 0.0, cr = 0.0, ci = 0.0;
+  const int k0 = lo[q];
+  for (int u = 0; u < ew; ++u) {
+    const int k = min(k0 + u, m - 1);  // slots past the row's band carry zero weights
+    const double e0 = E0b[int64_t(u) * Q + q], e1 = E1b[int64_t(u) * Q + q];
+    const double2 a = tl[k], c = tl[m + k];
+    ar = fma(e1, a.x, ar);
+    ai = fma(e1, a.y, ai);
+    cr = fma(e0, c.x, cr);
+    ci = fma(e0, c.y, ci);
+  }
+  return make_double2(ai + cr, ci - ar);  // -i (ar + i ai) + (cr + i ci)
+}
+// X0 and Y at free time row i of one spatial point, from the point's R (tl[0..Q)).
+__device__ __forceinline__ void time_load_at(const double2* tl, int Q, int i, int n, const double* L0b,
+                                             const double* L1b, const int* lo, int lw, double v, double jac,
+                                             double2& x0, double2& y) {
+  double x0r = 0.0, x0i = 0.0, x1r = 0.0, x1i = 0.0;
+  const int q0 = lo[i];
+  for (int u = 0; u < lw; ++u) {
+    const int q = min(q0 + u, Q - 1);  // slots past the row's band carry zero weights
+    const double l0 = L0b[int64_t(u) * n + i], l1 = L1b[int64_t(u) * n + i];
+    const double2 r = tl[q];
+    x0r = fma(l0, r.x, x0r);
+    x0i = fma(l0, r.y, x0i);
+    x1r = fma(l1, r.x, x1r);
+    x1i = fma(l1, r.y, x1i);
+  }
+  x0 = make_double2(x0r, x0i);
+  y = make_double2(jac * (x1i + v * x0r), jac * (v * x0i - x1r));
+}
+
 __global__ void __launch_bounds__(256) time_expand_kernel(const double2* __restrict__ A, const double2* __restrict__ C,
                                                           const double2* __restrict__ f, double2* __restrict__ R,
                                                           const double* __restrict__ E0b, const double* __restrict__ E1b,
@@ -96,18 +131,7 @@ __global__ void __launch_bounds__(256) time_expand_kernel(const double2* __restr
   }
   __syncthreads();
   for (int q = threadIdx.x; q < Q; q += blockDim.x) {
-    double ar = 0.0, ai = 0.0, cr = 0.0, ci = 0.0;
-    const int k0 = lo[q];
-    for (int u = 0; u < ew; ++u) {
-      const int k = min(k0 + u, m - 1);  // slots past the row's band carry zero weights
-      const double e0 = E0b[int64_t(u) * Q + q], e1 = E1b[int64_t(u) * Q + q];
-      const double2 a = tl[k], c = tl[m + k];
-      ar = fma(e1, a.x, ar);
-      ai = fma(e1, a.y, ai);
-      cr = fma(e0, c.x, cr);
-      ci = fma(e0, c.y, ci);
-    }
-    double2 res = make_double2(ai + cr, ci - ar);  // -i (ar + i ai) + (cr + i ci)
+    double2 res = time_expand_at(tl, m, q, Q, E0b, E1b, lo, ew);
     if (f) {
       const double2 fv = f[o * Q + q];
       res.x += fv.x;
@@ -127,21 +151,43 @@ __global__ void __launch_bounds__(256) time_load_kernel(const double2* __restric
   for (int q = threadIdx.x; q < Q; q += blockDim.x) tl[q] = R[o * Q + q];
   __syncthreads();
   const double v = V ? V[o] : 0.0, jac = J ? J[o] : 1.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double x0r = 0.0, x0i = 0.0, x1r = 0.0, x1i = 0.0;
-    const int q0 = lo[i];
-    for (int u = 0; u < lw; ++u) {
-      const int q = min(q0 + u, Q - 1);  // slots past the row's band carry zero weights
-      const double l0 = L0b[int64_t(u) * n + i], l1 = L1b[int64_t(u) * n + i];
-      const double2 r = tl[q];
-      x0r = fma(l0, r.x, x0r);
-      x0i = fma(l0, r.y, x0i);
-      x1r = fma(l1, r.x, x1r);
-      x1i = fma(l1, r.y, x1i);
-    }
-    X0[o * n + i] = make_double2(x0r, x0i);
-    Y[o * n + i] = make_double2(jac * (x1i + v * x0r), jac * (v * x0i - x1r));
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    time_load_at(tl, Q, i, n, L0b, L1b, lo, lw, v, jac, X0[o * n + i], Y[o * n + i]);
+}
+
+// time_expand and time_load in one launch where a point's A, C and R fit in LDS: R stays in LDS
+// instead of a round trip of the whole space-time Gauss grid through memory (268 MB at 64^3); the
+// same arithmetic in the same order, so the same results.
+constexpr size_t kTimeRhsMaxLds = 64 * 1024;
+__global__ void __launch_bounds__(256) time_rhs_kernel(const double2* __restrict__ A, const double2* __restrict__ C,
+                                                       const double2* __restrict__ f, const double* __restrict__ E0b,
+                                                       const double* __restrict__ E1b, const int* __restrict__ elo,
+                                                       int ew, int m, int Q, double2* __restrict__ X0,
+                                                       double2* __restrict__ Y, const double* __restrict__ L0b,
+                                                       const double* __restrict__ L1b, const int* __restrict__ llo,
+                                                       int lw, int n, const double* __restrict__ V,
+                                                       const double* __restrict__ J) {
+  extern __shared__ double2 tl[];  // [2][m]: A and C of this point, then [Q]: its R
+  double2* Rs = tl + 2 * m;
+  const int64_t o = blockIdx.x;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) {
+    tl[k] = A[o * m + k];
+    tl[m + k] = C[o * m + k];
   }
+  __syncthreads();
+  for (int q = threadIdx.x; q < Q; q += blockDim.x) {
+    double2 res = time_expand_at(tl, m, q, Q, E0b, E1b, elo, ew);
+    if (f) {
+      const double2 fv = f[o * Q + q];
+      res.x += fv.x;
+      res.y += fv.y;
+    }
+    Rs[q] = res;
+  }
+  __syncthreads();
+  const double v = V ? V[o] : 0.0, jac = J ? J[o] : 1.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    time_load_at(Rs, Q, i, n, L0b, L1b, llo, lw, v, jac, X0[o * n + i], Y[o * n + i]);
 }
 
 // out[x][t] = J[x] (alpha A[x][t] + beta V[x] B[x][t])  (t fastest, n_time entries per x;
@@ -1000,22 +1046,39 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
   // free time rows: one pass each over the space-time grid, one block per spatial grid point
   double* X0 = A0;
   double* X1 = A2;
+  double* S = R;  // scratch for the c_k J X0 products below
   int64_t xs = plan.n[0];
   {
     int64_t npts = 1;
     for (int a = 1; a < na; ++a) npts *= plan.Q[a];
     const int m0 = plan.m[0], Q0 = plan.Q[0], n0 = plan.n[0];
-    if ((rc = allow_lds(reinterpret_cast<const void*>(&time_expand_kernel), 2 * m0 * sizeof(double2))) ||
-        (rc = allow_lds(reinterpret_cast<const void*>(&time_load_kernel), Q0 * sizeof(double2))))
-      return rc;
-    hipLaunchKernelGGL(time_expand_kernel, dim3(static_cast<unsigned>(npts)), dim3(256), 2 * m0 * sizeof(double2), s,
-                       (const double2*)A0, (const double2*)A2, (const double2*)f_q, (double2*)R, plan.tband_eval[0],
-                       plan.tband_eval[1], plan.eval_lo[0], plan.tband_ew, m0, Q0);
-    if ((rc = int(hipGetLastError()))) return rc;
-    hipLaunchKernelGGL(time_load_kernel, dim3(static_cast<unsigned>(npts)), dim3(128), Q0 * sizeof(double2), s,
-                       (const double2*)R, (double2*)X0, (double2*)X1, plan.tband_load[0], plan.tband_load[1],
-                       plan.load_lo[0], plan.tband_lw, Q0, n0, plan.Vq, plan.Jq);
-    if ((rc = int(hipGetLastError()))) return rc;
+    const size_t fused_lds = (2 * size_t(m0) + size_t(Q0)) * sizeof(double2);
+    if (fused_lds <= kTimeRhsMaxLds && 2 * n0 <= Q0) {
+      // one launch, R kept in LDS: X0 and X1 go to the (unused) R buffer, since a block's outputs
+      // would overwrite inputs of other blocks in A0 and A2; A0 is then the scratch
+      X0 = R;
+      X1 = R + 2 * int64_t(n0) * npts;
+      S = A0;
+      if ((rc = allow_lds(reinterpret_cast<const void*>(&time_rhs_kernel), fused_lds))) return rc;
+      hipLaunchKernelGGL(time_rhs_kernel, dim3(static_cast<unsigned>(npts)), dim3(256), fused_lds, s,
+                         (const double2*)A0, (const double2*)A2, (const double2*)f_q, plan.tband_eval[0],
+                         plan.tband_eval[1], plan.eval_lo[0], plan.tband_ew, m0, Q0, (double2*)X0, (double2*)X1,
+                         plan.tband_load[0], plan.tband_load[1], plan.load_lo[0], plan.tband_lw, n0, plan.Vq,
+                         plan.Jq);
+      if ((rc = int(hipGetLastError()))) return rc;
+    } else {
+      if ((rc = allow_lds(reinterpret_cast<const void*>(&time_expand_kernel), 2 * m0 * sizeof(double2))) ||
+          (rc = allow_lds(reinterpret_cast<const void*>(&time_load_kernel), Q0 * sizeof(double2))))
+        return rc;
+      hipLaunchKernelGGL(time_expand_kernel, dim3(static_cast<unsigned>(npts)), dim3(256), 2 * m0 * sizeof(double2),
+                         s, (const double2*)A0, (const double2*)A2, (const double2*)f_q, (double2*)R,
+                         plan.tband_eval[0], plan.tband_eval[1], plan.eval_lo[0], plan.tband_ew, m0, Q0);
+      if ((rc = int(hipGetLastError()))) return rc;
+      hipLaunchKernelGGL(time_load_kernel, dim3(static_cast<unsigned>(npts)), dim3(128), Q0 * sizeof(double2), s,
+                         (const double2*)R, (double2*)X0, (double2*)X1, plan.tband_load[0], plan.tband_load[1],
+                         plan.load_lo[0], plan.tband_lw, Q0, n0, plan.Vq, plan.Jq);
+      if ((rc = int(hipGetLastError()))) return rc;
+    }
     xs *= npts;
   }
   auto load_chain = [&](const double* src0, const int* ord, double ar, bool accumulate) -> int {
@@ -1036,14 +1099,14 @@ int load_vector_device(const HostProblem& hp, const LoadPlan& plan, const double
     return 0;
   };
   if ((rc = load_chain(X1, nullptr, 1.0, false))) return rc;
-  // - nu sum_k (D^k phi_I, c_k J X0): R is free again and holds c_k J X0
+  // - nu sum_k (D^k phi_I, c_k J X0): the scratch S holds c_k J X0
   for (int k = 0; k < plan.n_lap; ++k) {
     const double* src = X0;
     if (plan.lap_cJ[k]) {
       hipLaunchKernelGGL(scale_add_kernel, dim3(grid_for(xs)), dim3(256), 0, s, (const double2*)X0, plan.lap_cJ[k],
-                         (double2*)R, int64_t(plan.n[0]), xs, 1.0, 0);
+                         (double2*)S, int64_t(plan.n[0]), xs, 1.0, 0);
       if ((rc = int(hipGetLastError()))) return rc;
-      src = R;
+      src = S;
     }
     if ((rc = load_chain(src, plan.lap_ord[k], -nu, true))) return rc;
   }
