@@ -417,9 +417,11 @@ __global__ void __launch_bounds__(256) lift_prec_axis_kernel(LiftArgs A, int ste
     int li[3] = {0, 0, 0};
     int64_t lstride[3] = {1, 1, 1};
     {
-      int64_t rr = loc, ls = 1;
+      // a face holds at most a few million entries (the setup size limits): 32-bit division
+      int rr = int(loc);
+      int64_t ls = 1;
       for (int k = 0; k < F.n_tan; ++k) {
-        li[k] = int(rr % F.dims[k]);
+        li[k] = rr % F.dims[k];
         rr /= F.dims[k];
         lstride[k] = ls;
         ls *= F.dims[k];
