@@ -349,9 +349,11 @@ int stfd_time_mode_product(stfd_problem *P, int direction, int precision, int re
 /* Launch shapes of a problem.  With stfd_setup_desc.autotune = 1 the setup timed on the device
  * (2 untimed and 5 timed launches per candidate on a private stream, median kept):
  *   the shape of every mode product, per precision and direction, for directions with n_l <= 80:
- *   1 or 2 = one 16-column group per wave with 1 or 2 sixteen-row groups; 3 = the wide form (every
- *   column group of a 16-row tile in one wave, the packed operand staged in LDS per block; not for
- *   the per-mode operand of a mapped domain's x_1);
+ *   1 or 2 = one 16-column group per wave with 1 or 2 sixteen-row groups (four waves per block on
+ *   consecutive row tiles of one column group, its packed operand staged in LDS per block, read
+ *   from global memory instead for the per-mode operand of a mapped domain's x_1); 3 = the wide
+ *   form (every column group of a 16-row tile in one wave, the packed operand staged in LDS per
+ *   block; not for the per-mode operand);
  *   the segment length of the time solve and its form (every table read; rows of L and 1/D read and
  *   the segment transfers computed; or all of them computed, the factor rows from the last P rows
  *   before each segment), every form for problems with N_s n_t <= 2^21, the last form only for
