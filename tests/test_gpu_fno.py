@@ -22,7 +22,7 @@ def _stfd():
     return stfd
 
 
-CONFIGS = [
+NET_SHAPES = [
     dict(H=12, W=10, c_in=3, width=6, modes1=4, modes2=6, layers=2, proj=8, c_out=5),
     dict(H=18, W=18, c_in=5, width=8, modes1=6, modes2=6, layers=4, proj=16, c_out=10),
 ]
@@ -52,7 +52,7 @@ def _blocks(spec):
 
 @pytest.mark.parametrize("ci", [0, 1])
 def test_forward_backward_vs_oracle(ci):
-    cfg = CONFIGS[ci]
+    cfg = NET_SHAPES[ci]
     batch = 3
     net, spec = _pair(cfg, batch, seed=11 + ci)
     theta = net.get_params().astype(np.float64)
@@ -89,7 +89,7 @@ def test_rel_l2_and_adam_vs_oracle():
     assert abs(loss - loss_ref) < 1e-5 * loss_ref
     assert np.linalg.norm(dyd.cpu().numpy().reshape(B, n) - g_ref) < 1e-5 * np.linalg.norm(g_ref)
     # Adam: three steps with fixed gradients from one backward
-    cfg = CONFIGS[0]
+    cfg = NET_SHAPES[0]
     net, spec = _pair(cfg, 2, seed=3)
     x = torch.from_numpy(rng.standard_normal(2 * net.n_in).astype(np.float32)).to(DEV)
     out = torch.empty(2 * net.n_out, dtype=torch.float32, device=DEV)
