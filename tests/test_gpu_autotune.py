@@ -85,13 +85,16 @@ def test_tuned_pcg_matches_heuristic():
 
 
 @pytest.mark.parametrize("d,n_el,p,n_el_t", [(2, 64, 3, 64), (2, 15, 3, 21), (3, 16, 2, 11), (3, 31, 3, 7),
-                                             (3, 48, 3, 9)])
+                                             (3, 48, 3, 9), (3, 32, 4, 35)])
 def test_every_shape_gives_the_same_apply(d, n_el, p, n_el_t):
     """Shapes 1, 2 (one column group per wave, 1 or 2 row groups) and 3 (every column group per wave,
     U' in LDS) accumulate every output over the same K steps in the same order: the applies agree
     bit for bit in every precision, and the FP64 one matches the oracle.  The PCG with the fused dot
     products (whose partials depend on the shape) takes the same iteration count up to one.  The
-    last direction runs as separate launches here, so that every direction takes every shape."""
+    last direction runs as separate launches here, so that every direction takes every shape.
+    48 x 48 x 48 x 9 (n = 49) has one remainder column in x_1, 32^3 x 35 at p = 4 (n = 34, n_t = 38)
+    two in every direction: launches of at least 16,384 one-group waves compute them with vector
+    FMAs, by the same sequence in every shape (FP64 and FP32; BF16 keeps its MFMA group)."""
     from paper_2311_18461_amd import stfd
     kt = inputs.uniform_open_knots(n_el_t, p)
     ks = [inputs.uniform_open_knots(n_el, p) for _ in range(d)]
