@@ -347,6 +347,8 @@ __global__ void __launch_bounds__(64 * kLiftMvWaves) lift_matvec_kernel(LiftArgs
   const int64_t i = int64_t(blockIdx.x) * kLiftMvWaves + wave;
   double acc_xy = 0.0;
   if (i < A.n_fixed) {
+    // x[i] (for <x, y>) is loaded with the index: it does not wait for the gathers
+    const double2 xv = x[i];
     const int64_t g = A.fixed[i];
     int idx[4];
     fixed_index(A, i, idx);
@@ -386,7 +388,6 @@ __global__ void __launch_bounds__(64 * kLiftMvWaves) lift_matvec_kernel(LiftArgs
     yi = wave_sum64(yi);
     if (lane == 0) {
       y[i] = make_double2(yr, yi);
-      const double2 xv = x[i];
       acc_xy = xv.x * yr + xv.y * yi;
     }
   }
