@@ -441,7 +441,7 @@ def main():
                          "(long axes), solved to 1e-10")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on one GPU per process; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
