@@ -1,7 +1,7 @@
 """The library's host setup code (host_setup.cpp, spatial.cpp) built with g++ under
 AddressSanitizer and UndefinedBehaviorSanitizer and run over small problems by
 tests/host/sanitize_driver.cpp (no GPU, no HIP): any out-of-bounds access, use after free, leak,
-signed overflow or misaligned access aborts the driver.  The driver also checks what the host code
+signed overflow or misaligned access aborts the test program.  It also checks what the host code
 computes: finite results, the weighted-form mass stencil against the Kronecker-assembled one, the
 time factors against H_i, and the lane slots of every time-solve plan."""
 import os
